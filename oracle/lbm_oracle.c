@@ -1,0 +1,550 @@
+/*
+ * CPU FP64 oracle for the vectorial lattice Boltzmann shallow-water scheme of
+ * F. Dubois, "Simulation of strong nonlinear waves with vectorial lattice
+ * Boltzmann schemes" (D1Q3Q2 in Sec. 2, D2Q5Q4Q4 in Sec. 3).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is loaded by the test-suite, by the
+ * smoke check and by the benchmark's CPU-baseline leg; the GPU library never
+ * links, includes or calls it and shares no code with it.
+ *
+ * The oracle runs the paper's scheme literally, node by node, in double
+ * precision:
+ *   - it carries the rest population f_0 of the paper's schemes, so a > 0 gives
+ *     D1Q3Q2 / D2Q5Q4Q4 and a = 0 gives D1Q2 / D2Q4 per component exactly
+ *     (f_0^eq = a K theta vanishes and f_0 stays identically zero);
+ *   - state at level n = the post-collision distribution f*(n); the initial
+ *     pre-collision state is the equilibrium of the initial conserved fields;
+ *   - relaxation is either BGK in distribution space or the literal
+ *     moment-space MRT of eq. 2-relaxation with the paper's moment bases and
+ *     equilibrium moments (Sec. 2 and Sec. 3), used as a cross-check;
+ *   - the discrete adjoint (exact transpose of one step, derived by hand)
+ *     gives gradients of sum_x (h(T) - hhat)^2 with respect to the initial
+ *     height and the relaxation rate; a complex-step copy of the forward
+ *     program (same source, REAL = double _Complex) pins it.
+ *
+ * Readings where the paper is silent or garbled are listed in the design notes
+ * of the repository: cell-centred nodes, equilibrium initial state, mirror
+ * ghost walls, equilibrium inflow ghost, g = 1 unless stated, a = 0 on the hot
+ * path, and the corrected equilibrium moment eps_rho^eq (factor a restored).
+ *
+ * Parity pins live in tests/ (conservation, lake at rest, equilibrium moments,
+ * s = 1 Lax-Friedrichs, BGK = MRT, Stoker dam break, wall reflection, D4
+ * symmetry, complex-step adjoint).
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_NPMAX 13
+enum { ORC_BC_PERIODIC = 0, ORC_BC_NEUMANN = 1, ORC_BC_WALL = 2, ORC_BC_INFLOW = 3 };
+
+typedef struct {
+    int dim;              /* 1 or 2 */
+    int nx, ny;           /* ny = 1 in 1D */
+    double lambda;        /* lattice velocity dx/dt */
+    double s;             /* BGK relaxation rate */
+    double g;             /* gravity: p = (g/2) h^2 */
+    double a;             /* rest-particle weight; 0 = D1Q2 / D2Q4 per component */
+    int bc[4];            /* faces x-, x+, y-, y+ */
+    double inflow[4][3];  /* (h, qx, qy) of inflow faces */
+    int mrt;              /* 0 = BGK, 1 = moment-space MRT with the rates below */
+    double rates[10];     /* 1D: (J_rho, eps_rho, J_q); 2D: (Jx, Jy, eps, XX_rho,
+                             f_xx, f_xy, XX_u, f_yx, f_yy, XX_v) */
+} orc_params;
+
+static int orc_npop(int dim) { return dim == 1 ? 5 : 13; }
+
+/* 1D populations: 0 f0, 1 f+, 2 f-, 3 g+, 4 g-.
+ * 2D populations: 0 f0, 1..4 f_j, 5..8 gx_j, 9..12 gy_j with
+ * e_1 = (1,0), e_2 = (0,1), e_3 = (-1,0), e_4 = (0,-1) (eq. 3-stencil-d2q5). */
+static int orc_dir2d(int p) { return p == 0 ? 0 : ((p - 1) % 4) + 1; }
+
+static int orc_ex(int dim, int p)
+{
+    if (dim == 1) {
+        static const int ex1[5] = {0, 1, -1, 1, -1};
+        return ex1[p];
+    }
+    static const int exj[5] = {0, 1, 0, -1, 0};
+    return exj[orc_dir2d(p)];
+}
+
+static int orc_ey(int dim, int p)
+{
+    if (dim == 1) return 0;
+    static const int eyj[5] = {0, 0, 1, 0, -1};
+    return eyj[orc_dir2d(p)];
+}
+
+static int orc_comp(int dim, int p)
+{
+    if (dim == 1) return p <= 2 ? 0 : 1;
+    return p <= 4 ? 0 : (p <= 8 ? 1 : 2);
+}
+
+static int orc_opposite(int dim, int p)
+{
+    if (dim == 1) {
+        static const int op1[5] = {0, 2, 1, 4, 3};
+        return op1[p];
+    }
+    if (p == 0) return 0;
+    int base = p <= 4 ? 1 : (p <= 8 ? 5 : 9);
+    int j = p - base; /* 0..3 */
+    return base + (j + 2) % 4;
+}
+
+/* ---- instantiate the generic core twice -------------------------------- */
+#define REAL double
+#define FN(name) name##_d
+#include "oracle_core.inc"
+#undef REAL
+#undef FN
+
+#define REAL double _Complex
+#define FN(name) name##_c
+#include "oracle_core.inc"
+#undef REAL
+#undef FN
+
+/* Literal moment-space relaxation, eq. 2-relaxation, with the paper's moment
+ * bases and equilibrium moments.
+ *   1D (Sec. 2): rho = f0+f++f-, J_rho = lambda (f+ - f-),
+ *        eps_rho = lambda^2 (f+ + f- - 2 f0), q = g+ + g-, J_q = lambda (g+ - g-).
+ *        Equilibria: J_rho^eq = q, J_q^eq = q^2/rho + p (the physical fluxes),
+ *        eps_rho^eq = lambda^2 (rho - 3 a K theta).
+ *   2D (Sec. 3): rho, J_x = lambda (f1 - f3), J_y = lambda (f2 - f4),
+ *        eps = f1+f2+f3+f4 - 4 f0, XX = f1 - f2 + f3 - f4, and for g_x:
+ *        q_x, f_xx = lambda (gx1 - gx3), f_xy = lambda (gx2 - gx4),
+ *        XX_u = gx1 - gx2 + gx3 - gx4 (g_y likewise).
+ *        Equilibria (Sec. 3 table, with the factor a of eps restored):
+ *        J^eq = q, eps^eq = (1 - 5a/2) rho + (5a/4)(u^2+v^2)/g, XX^eq = 0,
+ *        f_xx^eq = rho u^2 + p, f_xy^eq = f_yx^eq = rho u v, f_yy^eq = rho v^2 + p. */
+static void collide_mrt_node(const orc_params *P, double s_unused, const double *f, double *fs)
+{
+    (void)s_unused;
+    const double lam = P->lambda, g = P->g, K = 0.5 / g;
+    const double *r = P->rates;
+    if (P->dim == 1) {
+        double rho = f[0] + f[1] + f[2];
+        double J = lam * (f[1] - f[2]);
+        double eps = lam * lam * (f[1] + f[2] - 2.0 * f[0]);
+        double q = f[3] + f[4];
+        double Jq = lam * (f[3] - f[4]);
+        double u = q / rho;
+        double p = 0.5 * g * rho * rho;
+        double theta = g * rho - 0.5 * u * u;
+        double J_eq = q;
+        double eps_eq = lam * lam * (rho - 3.0 * P->a * K * theta);
+        double Jq_eq = q * u + p;
+        J += r[0] * (J_eq - J);
+        eps += r[1] * (eps_eq - eps);
+        Jq += r[2] * (Jq_eq - Jq);
+        /* invert the moment map */
+        double f0 = (rho - eps / (lam * lam)) / 3.0;
+        double S = rho - f0;
+        fs[0] = f0;
+        fs[1] = 0.5 * (S + J / lam);
+        fs[2] = 0.5 * (S - J / lam);
+        fs[3] = 0.5 * (q + Jq / lam);
+        fs[4] = 0.5 * (q - Jq / lam);
+        return;
+    }
+    double rho = f[0] + f[1] + f[2] + f[3] + f[4];
+    double Jx = lam * (f[1] - f[3]);
+    double Jy = lam * (f[2] - f[4]);
+    double eps = f[1] + f[2] + f[3] + f[4] - 4.0 * f[0];
+    double XX = f[1] - f[2] + f[3] - f[4];
+    double qx = f[5] + f[6] + f[7] + f[8];
+    double fxx = lam * (f[5] - f[7]);
+    double fxy = lam * (f[6] - f[8]);
+    double XXu = f[5] - f[6] + f[7] - f[8];
+    double qy = f[9] + f[10] + f[11] + f[12];
+    double fyx = lam * (f[9] - f[11]);
+    double fyy = lam * (f[10] - f[12]);
+    double XXv = f[9] - f[10] + f[11] - f[12];
+    double u = qx / rho, v = qy / rho;
+    double p = 0.5 * g * rho * rho;
+    double m_eq[10] = {
+        qx, qy,
+        (1.0 - 2.5 * P->a) * rho + 1.25 * P->a * (u * u + v * v) / g,
+        0.0,
+        rho * u * u + p, rho * u * v, 0.0,
+        rho * u * v, rho * v * v + p, 0.0};
+    double m[10] = {Jx, Jy, eps, XX, fxx, fxy, XXu, fyx, fyy, XXv};
+    for (int l = 0; l < 10; ++l) m[l] += r[l] * (m_eq[l] - m[l]);
+    Jx = m[0]; Jy = m[1]; eps = m[2]; XX = m[3];
+    fxx = m[4]; fxy = m[5]; XXu = m[6]; fyx = m[7]; fyy = m[8]; XXv = m[9];
+    double f0 = (rho - eps) / 5.0;
+    double S = rho - f0;
+    double A = 0.5 * (S + XX), B = 0.5 * (S - XX);
+    fs[0] = f0;
+    fs[1] = 0.5 * (A + Jx / lam);
+    fs[3] = 0.5 * (A - Jx / lam);
+    fs[2] = 0.5 * (B + Jy / lam);
+    fs[4] = 0.5 * (B - Jy / lam);
+    A = 0.5 * (qx + XXu); B = 0.5 * (qx - XXu);
+    fs[5] = 0.5 * (A + fxx / lam);
+    fs[7] = 0.5 * (A - fxx / lam);
+    fs[6] = 0.5 * (B + fxy / lam);
+    fs[8] = 0.5 * (B - fxy / lam);
+    A = 0.5 * (qy + XXv); B = 0.5 * (qy - XXv);
+    fs[9] = 0.5 * (A + fyx / lam);
+    fs[11] = 0.5 * (A - fyx / lam);
+    fs[10] = 0.5 * (B + fyy / lam);
+    fs[12] = 0.5 * (B - fyy / lam);
+}
+
+static void collide_node_d(const orc_params *P, double s, const double *f, double *fs)
+{
+    if (P->mrt)
+        collide_mrt_node(P, s, f, fs);
+    else
+        collide_bgk_node_d(P, s, f, fs);
+}
+
+static void collide_node_c(const orc_params *P, double _Complex s, const double _Complex *f,
+                           double _Complex *fs)
+{
+    collide_bgk_node_c(P, s, f, fs);
+}
+
+/* ---- buffers ------------------------------------------------------------ */
+typedef struct {
+    int np;
+    long n;
+    double *mem;
+    double *p[ORC_NPMAX];
+} orc_field;
+
+static int field_alloc(orc_field *F, int np, long n)
+{
+    F->np = np;
+    F->n = n;
+    F->mem = (double *)malloc(sizeof(double) * (size_t)np * (size_t)n);
+    if (!F->mem) return -1;
+    for (int q = 0; q < ORC_NPMAX; ++q) F->p[q] = q < np ? F->mem + (long)q * n : NULL;
+    return 0;
+}
+
+static void field_free(orc_field *F) { free(F->mem); F->mem = NULL; }
+
+static int check_params(const orc_params *P)
+{
+    if (!P) return -1;
+    if (P->dim != 1 && P->dim != 2) return -1;
+    if (P->nx < 1 || P->ny < 1) return -1;
+    if (P->dim == 1 && P->ny != 1) return -1;
+    if (!(P->lambda > 0) || !(P->g > 0)) return -1;
+    for (int face = 0; face < 4; ++face) {
+        if (P->bc[face] < 0 || P->bc[face] > 3) return -1;
+        if (P->dim == 1 && face >= 2) continue;
+        int other = face ^ 1;
+        if ((P->bc[face] == ORC_BC_PERIODIC) != (P->bc[other] == ORC_BC_PERIODIC)) return -1;
+    }
+    return 0;
+}
+
+static void collide_field(const orc_params *P, double s, const orc_field *f, orc_field *fs)
+{
+    int np = f->np;
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < f->n; ++i) {
+        double fl[ORC_NPMAX], fsl[ORC_NPMAX];
+        for (int q = 0; q < np; ++q) fl[q] = f->p[q][i];
+        collide_node_d(P, s, fl, fsl);
+        for (int q = 0; q < np; ++q) fs->p[q][i] = fsl[q];
+    }
+}
+
+/* ---- exported API ------------------------------------------------------- */
+
+int orc_npop_of(int dim) { return orc_npop(dim); }
+
+/* Equilibrium distribution of one state W = (h, qx, qy) (qy ignored in 1D).
+ * out receives orc_npop(dim) values in the population order above. */
+int orc_feq(const orc_params *P, double h, double qx, double qy, double *out)
+{
+    if (!P || !out) return -1;
+    double W[3] = {h, qx, qy};
+    feq_node_d(P, W, out);
+    return 0;
+}
+
+/* Collide one node (BGK or MRT according to P->mrt). */
+int orc_collide(const orc_params *P, const double *f, double *fs)
+{
+    if (!P || !f || !fs) return -1;
+    collide_node_d(P, P->s, f, fs);
+    return 0;
+}
+
+/* Run nsteps steps from the equilibrium of (h0, qx0, qy0) (qx0/qy0 may be NULL
+ * for zero).  fstar_out (npop*n, population-major) receives the post-collision
+ * state f*(nsteps); fpre_out, if non-NULL, the pre-collision state f(nsteps). */
+int orc_run(const orc_params *P, const double *h0, const double *qx0, const double *qy0,
+            long nsteps, double *fstar_out, double *fpre_out)
+{
+    if (check_params(P) || !h0 || !fstar_out || nsteps < 0) return -1;
+    int np = orc_npop(P->dim);
+    long n = (long)P->nx * P->ny;
+    orc_field a, b, fs;
+    if (field_alloc(&a, np, n) || field_alloc(&b, np, n) || field_alloc(&fs, np, n)) return -2;
+    init_eq_d(P, h0, qx0, qy0, a.p);
+    orc_field *cur = &a, *nxt = &b;
+    for (long t = 0; t < nsteps; ++t) {
+        step_d(P, P->s, cur->p, fs.p, nxt->p);
+        orc_field *tmp = cur; cur = nxt; nxt = tmp;
+    }
+    if (fpre_out) memcpy(fpre_out, cur->mem, sizeof(double) * (size_t)np * (size_t)n);
+    collide_field(P, P->s, cur, &fs);
+    memcpy(fstar_out, fs.mem, sizeof(double) * (size_t)np * (size_t)n);
+    field_free(&a); field_free(&b); field_free(&fs);
+    return 0;
+}
+
+/* Advance a post-collision state by nsteps steps in place: stream, then
+ * collide (the convention of a post-collision state at every level). */
+int orc_advance(const orc_params *P, double *fstar, long nsteps)
+{
+    if (check_params(P) || !fstar || nsteps < 0) return -1;
+    int np = orc_npop(P->dim);
+    long n = (long)P->nx * P->ny;
+    orc_field cur, pre;
+    if (field_alloc(&pre, np, n)) return -2;
+    cur.np = np; cur.n = n; cur.mem = fstar;
+    for (int q = 0; q < ORC_NPMAX; ++q) cur.p[q] = q < np ? fstar + (long)q * n : NULL;
+    for (long t = 0; t < nsteps; ++t) {
+        /* stream the post-collision field, then collide: f*(t+1) = C(S(f*(t))) */
+        double feq_in[4 * ORC_NPMAX];
+        for (int face = 0; face < 4; ++face)
+            if (P->bc[face] == ORC_BC_INFLOW) {
+                double Win[3] = {P->inflow[face][0], P->inflow[face][1], P->inflow[face][2]};
+                feq_node_d(P, Win, feq_in + face * ORC_NPMAX);
+            }
+#pragma omp parallel for schedule(static)
+        for (int y = 0; y < P->ny; ++y)
+            for (int x = 0; x < P->nx; ++x)
+                for (int q = 0; q < np; ++q)
+                    pre.p[q][(long)y * P->nx + x] = pull_d(P, cur.p, feq_in, q, x, y);
+        collide_field(P, P->s, &pre, &cur);
+    }
+    field_free(&pre);
+    return 0;
+}
+
+/* Conserved fields of a distribution (population-major npop*n array). */
+int orc_moments(const orc_params *P, const double *f, double *h, double *qx, double *qy)
+{
+    if (!P || !f) return -1;
+    int np = orc_npop(P->dim);
+    long n = (long)P->nx * P->ny;
+    for (long i = 0; i < n; ++i) {
+        double fl[ORC_NPMAX], W[3];
+        for (int q = 0; q < np; ++q) fl[q] = f[(long)q * n + i];
+        moments_node_d(P->dim, fl, W);
+        if (h) h[i] = W[0];
+        if (qx) qx[i] = W[1];
+        if (qy && P->dim == 2) qy[i] = W[2];
+    }
+    return 0;
+}
+
+/* ---- discrete adjoint (a = 0, BGK, 2D, periodic) --------------------------
+ * Forward, post-collision state u: u^0 = C(f^eq(W0)), u^{n+1} = C(S(u^n)),
+ * C(v) = (1-s) v + s f^eq(W(v)), S the pull-stream, loss
+ * L = sum_x (h(u^T)(x) - hhat(x))^2.  With lam^{n} = dL/du^n:
+ *   v(x) = S(u^n)(x);  mu_k(x) = sum_q lam^{n+1}_q(x) d f^eq_q / d W_k (W(v(x)));
+ *   vt_p(x) = (1-s) lam^{n+1}_p(x) + s mu_{comp(p)}(x);
+ *   lam^n_p(x - e_p) = vt_p(x)          (transpose of the pull-stream);
+ *   dL/ds += sum_x sum_p lam^{n+1}_p(x) (f^eq_p(W(v(x))) - v_p(x));
+ *   dL/dW0(x) = J(W0(x))^T lam^0(x),   J = d f^eq / d W.
+ * Partial derivatives of the 2D equilibrium at a = 0 (u = qx/h, v = qy/h):
+ *   d/dh   : f_j 1/4;  gx: (gh - u^2) c on 1,3 (signed), -uv c on 2,4;
+ *            gy: -uv c on 1,3, (gh - v^2) c on 2,4
+ *   d/dqx  : f_{1,3} +-c; gx 1/4 plus 2u c (1,3), v c (2,4); gy v c (1,3)
+ *   d/dqy  : f_{2,4} +-c; gy 1/4 plus u c (1,3), 2v c (2,4); gx u c (2,4)
+ * with c = 1/(2 lambda) and the sign of e_j along the flux direction. */
+static void adj_mu_2d(const orc_params *P, const double *W, const double *lam, double *mu)
+{
+    const double c = 0.5 / P->lambda, g = P->g;
+    double h = W[0], u = W[1] / h, v = W[2] / h;
+    double L0h = lam[1] + lam[2] + lam[3] + lam[4];
+    double Lxh = lam[1] - lam[3], Lyh = lam[2] - lam[4];
+    double L0x = lam[5] + lam[6] + lam[7] + lam[8];
+    double Lxx = lam[5] - lam[7], Lyx = lam[6] - lam[8];
+    double L0y = lam[9] + lam[10] + lam[11] + lam[12];
+    double Lxy = lam[9] - lam[11], Lyy = lam[10] - lam[12];
+    mu[0] = 0.25 * L0h + c * (Lxx * (g * h - u * u) - Lyx * u * v - Lxy * u * v + Lyy * (g * h - v * v));
+    mu[1] = c * Lxh + 0.25 * L0x + c * (2.0 * u * Lxx + v * Lyx + v * Lxy);
+    mu[2] = c * Lyh + 0.25 * L0y + c * (2.0 * v * Lyy + u * Lxy + u * Lyx);
+}
+
+static int adj_supported(const orc_params *P)
+{
+    if (check_params(P)) return 0;
+    if (P->dim != 2 || P->a != 0.0 || P->mrt) return 0;
+    for (int f = 0; f < 4; ++f) if (P->bc[f] != ORC_BC_PERIODIC) return 0;
+    return 1;
+}
+
+/* One adjoint step: given the forward post-collision state u^n and lam^{n+1},
+ * write lam^n and add this step's contribution to *dLds (all arrays
+ * population-major, 13 populations; the rest population's adjoint is carried
+ * for exactness but never reaches the gradients at a = 0). */
+int orc_adjoint_step(const orc_params *P, const double *un, const double *lam_np1,
+                     double *lam_n, double *dLds)
+{
+    if (!adj_supported(P) || !un || !lam_np1 || !lam_n) return -1;
+    const int np = 13, nx = P->nx, ny = P->ny;
+    const long n = (long)nx * ny;
+    const double s = P->s;
+    double acc = 0.0;
+    double *row_acc = (double *)calloc((size_t)ny, sizeof(double));
+    if (!row_acc) return -2;
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < ny; ++y) {
+        double racc = 0.0;
+        for (int x = 0; x < nx; ++x) {
+            long i = (long)y * nx + x;
+            double v[13], lam[13], W[3], feq[13], mu[3];
+            for (int q = 0; q < np; ++q) {
+                int sx = (x - orc_ex(2, q) + nx) % nx, sy = (y - orc_ey(2, q) + ny) % ny;
+                v[q] = un[(long)q * n + (long)sy * nx + sx];
+                lam[q] = lam_np1[(long)q * n + i];
+            }
+            moments_node_d(2, v, W);
+            feq2d_d(P, W[0], W[1], W[2], feq);
+            adj_mu_2d(P, W, lam, mu);
+            for (int q = 0; q < np; ++q) {
+                racc += lam[q] * (feq[q] - v[q]);
+                double vt = (1.0 - s) * lam[q] + s * mu[orc_comp(2, q)];
+                int tx = (x - orc_ex(2, q) + nx) % nx, ty = (y - orc_ey(2, q) + ny) % ny;
+                lam_n[(long)q * n + (long)ty * nx + tx] = vt;
+            }
+        }
+        row_acc[y] = racc;
+    }
+    for (int y = 0; y < ny; ++y) acc += row_acc[y];
+    free(row_acc);
+    if (dLds) *dLds += acc;
+    return 0;
+}
+
+/* Loss and gradients for the adjoint workload: W0 = (h0, 0, 0), T steps,
+ * L = sum (h(u^T) - hhat)^2.  Forward states are checkpointed every K steps
+ * and recomputed segment by segment in the backward sweep.
+ * grad_h0 (n) and *grad_s receive dL/dh0 and dL/ds; *loss the loss. */
+int orc_loss_grad_2d(const orc_params *P, const double *h0, const double *hhat, long T, int K,
+                     double *loss, double *grad_h0, double *grad_s)
+{
+    if (!adj_supported(P) || !h0 || !hhat || T < 0 || K < 1) return -1;
+    const int np = 13;
+    const long n = (long)P->nx * P->ny;
+    const size_t bytes = sizeof(double) * (size_t)np * (size_t)n;
+    long nck = T / K + 1;
+    double *ck = (double *)malloc(bytes * (size_t)nck);
+    double *seg = (double *)malloc(bytes * (size_t)(K + 1));
+    double *lamA = (double *)malloc(bytes), *lamB = (double *)malloc(bytes);
+    double *cur = (double *)malloc(bytes);
+    if (!ck || !seg || !lamA || !lamB || !cur) {
+        free(ck); free(seg); free(lamA); free(lamB); free(cur);
+        return -2;
+    }
+    /* u^0 = C(f^eq(W0)) */
+    {
+        orc_field f0, fs;
+        field_alloc(&f0, np, n);
+        fs.np = np; fs.n = n; fs.mem = cur;
+        for (int q = 0; q < ORC_NPMAX; ++q) fs.p[q] = cur + (long)q * n;
+        init_eq_d(P, h0, NULL, NULL, f0.p);
+        collide_field(P, P->s, &f0, &fs);
+        field_free(&f0);
+    }
+    memcpy(ck, cur, bytes);
+    for (long t = 0; t < T; ++t) {
+        orc_advance(P, cur, 1);
+        if ((t + 1) % K == 0 && (t + 1) / K < nck) memcpy(ck + (size_t)((t + 1) / K) * np * n, cur, bytes);
+    }
+    /* terminal adjoint */
+    double L = 0.0;
+    memset(lamA, 0, bytes);
+    for (long i = 0; i < n; ++i) {
+        double fl[13], W[3];
+        for (int q = 0; q < np; ++q) fl[q] = cur[(long)q * n + i];
+        moments_node_d(2, fl, W);
+        double r = W[0] - hhat[i];
+        L += r * r;
+        for (int q = 0; q <= 4; ++q) lamA[(long)q * n + i] = 2.0 * r;
+    }
+    double gs = 0.0;
+    double *lam_hi = lamA, *lam_lo = lamB;
+    for (long seg0 = ((T - 1) / K) * K; T > 0 && seg0 >= 0; seg0 -= K) {
+        long seg1 = seg0 + K < T ? seg0 + K : T; /* states seg0 .. seg1-1 needed */
+        memcpy(seg, ck + (size_t)(seg0 / K) * np * n, bytes);
+        for (long t = seg0 + 1; t < seg1; ++t) {
+            memcpy(seg + (size_t)(t - seg0) * np * n, seg + (size_t)(t - seg0 - 1) * np * n, bytes);
+            orc_advance(P, seg + (size_t)(t - seg0) * np * n, 1);
+        }
+        for (long t = seg1 - 1; t >= seg0; --t) {
+            orc_adjoint_step(P, seg + (size_t)(t - seg0) * np * n, lam_hi, lam_lo, &gs);
+            double *tmp = lam_hi; lam_hi = lam_lo; lam_lo = tmp;
+        }
+    }
+    /* dL/dh0 = mu_h(lam^0; W0) */
+    for (long i = 0; i < n; ++i) {
+        double lam[13], W[3] = {h0[i], 0.0, 0.0}, mu[3];
+        for (int q = 0; q < np; ++q) lam[q] = lam_hi[(long)q * n + i];
+        adj_mu_2d(P, W, lam, mu);
+        if (grad_h0) grad_h0[i] = mu[0];
+    }
+    if (loss) *loss = L;
+    if (grad_s) *grad_s = gs;
+    free(ck); free(seg); free(lamA); free(lamB); free(cur);
+    return 0;
+}
+
+/* Loss of the same workload evaluated in complex arithmetic at
+ * (h0 + i eps dh0, s + i eps ds): the complex-step directional derivative
+ * Im(L)/eps of the forward program, independent of the hand-derived adjoint.
+ * Periodic 2D or any supported BC; small grids only (no checkpointing). */
+int orc_loss_cs_2d(const orc_params *P, const double *h0, const double *dh0, double ds,
+                   const double *hhat, long T, double eps, double *loss, double *dloss)
+{
+    if (check_params(P) || P->dim != 2 || P->mrt || !h0 || !hhat) return -1;
+    const int np = 13;
+    const long n = (long)P->nx * P->ny;
+    double _Complex *mem = (double _Complex *)malloc(sizeof(double _Complex) * 3 * np * (size_t)n);
+    double _Complex *hc = (double _Complex *)malloc(sizeof(double _Complex) * (size_t)n);
+    if (!mem || !hc) { free(mem); free(hc); return -2; }
+    double _Complex *A[ORC_NPMAX], *B[ORC_NPMAX], *S[ORC_NPMAX];
+    for (int q = 0; q < np; ++q) {
+        A[q] = mem + (long)q * n;
+        B[q] = mem + (long)(np + q) * n;
+        S[q] = mem + (long)(2 * np + q) * n;
+    }
+    for (long i = 0; i < n; ++i) hc[i] = h0[i] + I * (eps * (dh0 ? dh0[i] : 0.0));
+    double _Complex s = P->s + I * (eps * ds);
+    init_eq_c(P, hc, NULL, NULL, A);
+    /* u^0 = C(f^eq(W0)), then u^{n+1} = C(S(u^n)); implemented as pre-collision
+     * iteration f(n+1) = S(C(f(n))) followed by a final collision. */
+    double _Complex **cur = A, **nxt = B;
+    for (long t = 0; t < T; ++t) {
+        step_c(P, s, cur, S, nxt);
+        double _Complex **tmp = cur; cur = nxt; nxt = tmp;
+    }
+    double _Complex L = 0.0;
+    for (long i = 0; i < n; ++i) {
+        double _Complex fl[13], fs[13], W[3];
+        for (int q = 0; q < np; ++q) fl[q] = cur[q][i];
+        collide_node_c(P, s, fl, fs);
+        moments_node_c(2, fs, W);
+        double _Complex r = W[0] - hhat[i];
+        L += r * r;
+    }
+    if (loss) *loss = creal(L);
+    if (dloss) *dloss = cimag(L) / eps;
+    free(mem); free(hc);
+    return 0;
+}
