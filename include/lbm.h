@@ -1,0 +1,218 @@
+/*
+ * lbm.h -- C ABI of liblbm.so, the MI355X (gfx950) hot path of the vectorial
+ * lattice Boltzmann scheme for the shallow-water equations of F. Dubois,
+ * "Simulation of strong nonlinear waves with vectorial lattice Boltzmann
+ * schemes" (Sec. 1-3), in its a = 0 form: one D1Q2 (1D) or D2Q4 (2D) particle
+ * set per conserved component (h, qx = h u, qy = h v).
+ *
+ * What one time step computes (Sec. 1 eq. 1-hyp-N-vconserv, Sec. 2
+ * eq. 2-relaxation, Sec. 3):
+ *   W^k = sum_j f_j^k per node; f^eq from the kinetic decomposition of the dual
+ *   entropy, closed form at a = 0 with c = 1/(2 lambda):
+ *     1D: f_+- = h/2 +- q c,        g_+- = q/2 +- (q^2/h + p) c
+ *     2D: f_{1,3} = h/4 +- qx c,    f_{2,4} = h/4 +- qy c,
+ *         gx_{1,3} = qx/4 +- Fxx c, gx_{2,4} = qx/4 +- Fxy c,
+ *         gy_{1,3} = qy/4 +- Fxy c, gy_{2,4} = qy/4 +- Fyy c,
+ *     p = (g/2) h^2, Fxx = qx^2/h + p, Fxy = qx qy/h, Fyy = qy^2/h + p;
+ *   relaxation (BGK, one rate s on every non-conserved moment)
+ *     f* = f + s (f^eq - f);
+ *   streaming one cell per step along e_j (lambda = dx/dt, Sec. 2), walls by
+ *   bounce-back / anti-bounce-back (Sec. 3, last paragraph).
+ *
+ * Conventions
+ *   - Device memory for states, fields and adjoints is allocated and owned by
+ *     the caller; the library only borrows pointers and never frees them.  The
+ *     library owns its host context and a few small device scratch buffers
+ *     (reduction partials, flags), freed by lbm_destroy / lbm_batch_destroy.
+ *   - Every call is ordered on the caller's HIP stream (lbm_params.stream;
+ *     NULL = the default stream).  Calls that return host values synchronise
+ *     that stream.
+ *   - State layout (one buffer): n_planes SoA planes, plane p at element offset
+ *     p * plane_stride, each plane row-major [y][x] with row stride nx.
+ *     2D planes: (h: e1..e4, qx: e1..e4, qy: e1..e4), e1 = +x, e2 = +y,
+ *     e3 = -x, e4 = -y (Sec. 3 eq. 3-stencil-d2q5).  1D planes: (h: +, -;
+ *     q: +, -).  Elements are double (LBM_F64) or float (LBM_F32);
+ *     arithmetic is always double.  plane_stride >= nx*ny (padding breaks
+ *     power-of-two plane strides); query it with lbm_layout.
+ *   - State at level n = the post-collision distribution f*(n).  Level 0 is the
+ *     collision of the equilibrium of the initial fields.  Moments of the state
+ *     are the conserved fields W(n).
+ *   - Return codes: LBM_OK (0), LBM_WARN_SUBCHAR (> 0, non-fatal), or a
+ *     negative error; lbm_last_error() gives a thread-local message.  No
+ *     exception crosses the ABI.  Asynchronous device faults surface as
+ *     LBM_EDEVICE at the next synchronising call.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+typedef struct lbm_batch lbm_batch;
+
+enum lbm_status {
+    LBM_OK = 0,
+    LBM_WARN_SUBCHAR = 1, /* lambda below the monotonicity bound of the lattice:
+                             max(|u| + sqrt(g h)) (1D), 2 max(|u| + sqrt(g h)) (2D) */
+    LBM_EINVAL = -1,      /* bad argument (null pointer, size, rate, depth, BC) */
+    LBM_EDEVICE = -2,     /* HIP runtime error */
+    LBM_ESTATE = -3,      /* call out of order (e.g. step before init) */
+    LBM_EDIVERGED = -4    /* a check found h <= 0 or a non-finite value */
+};
+
+enum lbm_lattice { LBM_D1Q2x2 = 1, LBM_D2Q4x3 = 2 };
+enum lbm_storage { LBM_F64 = 64, LBM_F32 = 32 };
+enum lbm_bc {
+    LBM_BC_PERIODIC = 0, /* wrap around (both faces of an axis must be periodic) */
+    LBM_BC_NEUMANN = 1,  /* zero-gradient ghost: the node's own post-collision value */
+    LBM_BC_WALL = 2,     /* mirror ghost: bounce-back for h and the tangential
+                            momentum, anti-bounce-back for the normal momentum */
+    LBM_BC_INFLOW = 3    /* ghost held at f^eq of the face's inflow state */
+};
+
+typedef struct {
+    int lattice;          /* lbm_lattice */
+    int storage;          /* lbm_storage */
+    int nx, ny;           /* nodes; ny = 1 in 1D; nx, ny >= 2 in 2D, nx >= 2 in 1D */
+    double lambda;        /* lattice velocity dx/dt > 0 */
+    double s;             /* relaxation rate in (0, 2) */
+    double g;             /* gravity > 0, p = (g/2) h^2 */
+    int bc[4];            /* lbm_bc of faces x-, x+, y-, y+ (y faces ignored in 1D) */
+    double inflow[4][3];  /* (h, qx, qy) of LBM_BC_INFLOW faces, h > 0 */
+    int check_every;      /* 0 = off; else lbm_step checks the state every that
+                             many steps and returns LBM_EDIVERGED on failure */
+    int block;            /* threads per workgroup: 64, 128, 256 (default), 512 */
+    int nodes_per_thread; /* 1 (default), 2 or 4 nodes per thread along x */
+    long plane_pad;       /* extra elements between planes; < 0 = library default */
+    void *f_a, *f_b;      /* caller-owned device state buffers (ping-pong) */
+    void *stream;         /* hipStream_t; NULL = default stream */
+} lbm_params;
+
+/* Size of one state buffer for the given parameters (only lattice, storage, nx,
+ * ny and plane_pad are read).  Outputs may be NULL.  LBM_EINVAL on bad sizes. */
+int lbm_layout(const lbm_params *p, long *plane_stride, int *n_planes, size_t *bytes);
+
+/* Validate p, create a context and write the level-0 state into p->f_a:
+ * f*(0) = C(f^eq(W0)).  h0, qx0, qy0: device double arrays of nx*ny values
+ * row-major [y][x] (qx0 / qy0 may be NULL for zero; qy0 ignored in 1D).
+ * Synchronises the stream once to check min h0 > 0 (else LBM_EINVAL) and the
+ * monotonicity bound (LBM_WARN_SUBCHAR, context still created). */
+int lbm_init(const lbm_params *p, const double *h0, const double *qx0, const double *qy0,
+             lbm_ctx **out);
+
+/* Advance nsteps fused pull-stream + collide steps (ping-pong between f_a and
+ * f_b).  Stream-ordered; with check_every > 0 it synchronises at each check. */
+int lbm_step(lbm_ctx *ctx, long nsteps);
+
+/* One step from src into dst (both caller-owned buffers in the context's
+ * layout; must not alias).  Does not touch the context's own buffers. */
+int lbm_step_buffers(lbm_ctx *ctx, const void *src, void *dst);
+
+/* Pointer to the buffer holding the current level and the number of steps done. */
+int lbm_current(lbm_ctx *ctx, void **state, long *steps_done);
+
+/* Copy the current state to dst / overwrite it from src (device, same layout). */
+int lbm_export(lbm_ctx *ctx, void *dst);
+int lbm_import(lbm_ctx *ctx, const void *src);
+
+/* Conserved fields of a state (W^k = sum_j f_j^k, eq. 1-hyp-N-vconserv) into
+ * device double arrays h, qx, qy (nx*ny each, any may be NULL; qy ignored in
+ * 1D).  state = NULL means the current state.  totals_host (may be NULL)
+ * receives (sum h, sum qx, sum qy) in double, by a deterministic two-stage
+ * reduction; that synchronises the stream. */
+int lbm_moments(lbm_ctx *ctx, const void *state, double *h, double *qx, double *qy,
+                double *totals_host);
+
+/* Discrete adjoint of one step (2D, periodic faces only).  With C the
+ * collision, S the pull-stream and u^{n+1} = C(S(u^n)):
+ *   v = S(f_n); mu = (d f^eq / d W (W(v)))^T lam_np1 per node;
+ *   vt = (1 - s) lam_np1 + s mu (mu broadcast over each component's planes);
+ *   lam_n = S^T vt (push to x - e_j);
+ *   dLds_partials[b] += sum over block b of lam_np1 . (f^eq(W(v)) - v).
+ * f_n, lam_np1, lam_n: caller buffers in the state layout and storage type
+ * (lam_n must not alias the others).  dLds_partials: device double array of
+ * lbm_adjoint_partials(ctx) entries, accumulated (zero it before the first
+ * step).  LBM_EINVAL for 1D or non-periodic contexts. */
+int lbm_adjoint_step(lbm_ctx *ctx, const void *f_n, const void *lam_np1, void *lam_n,
+                     double *dLds_partials);
+long lbm_adjoint_partials(lbm_ctx *ctx);
+
+/* Terminal adjoint for a loss of the final height: lam_T = dL/dh broadcast to
+ * the four h planes, zero on the momentum planes.  dLdh: device doubles, nx*ny. */
+int lbm_adjoint_terminal(lbm_ctx *ctx, const double *dLdh, void *lam_T);
+
+/* Gradient with respect to the initial fields: (dL/dh0, dL/dqx0, dL/dqy0) =
+ * J(W0)^T lam0 per node, J = d f^eq / d W.  Outputs may be NULL. */
+int lbm_adjoint_grad_w0(lbm_ctx *ctx, const void *lam0, const double *h0, const double *qx0,
+                        const double *qy0, double *grad_h0, double *grad_qx0, double *grad_qy0);
+
+/* Deterministic sum of n device doubles into *out_host (synchronises). */
+int lbm_sum(lbm_ctx *ctx, const double *partials, long n, double *out_host);
+
+/* Release the context (NULL-safe; never frees caller memory). */
+void lbm_destroy(lbm_ctx *ctx);
+
+/* ---- batched form: many independent problems in one persistent launch ---- */
+
+typedef struct {
+    int lattice;          /* lbm_lattice */
+    int nx, ny;           /* ny = 1 in 1D */
+    double lambda, s, g;
+    int bc[4];            /* as lbm_params.bc */
+    double inflow[4][3];
+    long state_offset;    /* set by lbm_batch_layout: element offset of the
+                             instance's planes inside each batch buffer */
+    long node_offset;     /* set by lbm_batch_layout: offset of the instance's
+                             nodes in packed field arrays (h0, moments) */
+} lbm_instance;
+
+typedef struct {
+    int block;            /* threads per workgroup (64..1024, multiple of 64) */
+    int tile_nodes;       /* target nodes per work tile (>= block) */
+    int grid;             /* persistent workgroups; 0 = fill the device */
+} lbm_batch_tuning;
+
+/* Assign state_offset / node_offset to n instances (in place) for the given
+ * storage; *bytes receives the size of one batch state buffer and *nodes the
+ * total node count. */
+int lbm_batch_layout(lbm_instance *inst, int n, int storage, size_t *bytes, long *nodes);
+
+/* Create a batch over caller-owned buffers f_a, f_b (lbm_batch_layout sizes).
+ * tuning may be NULL (defaults).  The instances are copied. */
+int lbm_batch_create(const lbm_instance *inst, int n, int storage, void *f_a, void *f_b,
+                     void *stream, const lbm_batch_tuning *tuning, lbm_batch **out);
+
+/* Level-0 state of every instance from packed device double fields (node_offset). */
+int lbm_batch_init(lbm_batch *b, const double *h0, const double *qx0, const double *qy0);
+
+/* Advance every instance by nsteps in ONE persistent kernel launch (replayed
+ * from a captured HIP graph).  Tiles of each instance advance as soon as their
+ * neighbours have finished the previous step; no grid-wide barrier. */
+int lbm_batch_run(lbm_batch *b, long nsteps);
+
+/* Packed conserved fields of every instance (device doubles, may be NULL). */
+int lbm_batch_moments(lbm_batch *b, double *h, double *qx, double *qy);
+
+/* Current state buffer of the batch. */
+int lbm_batch_current(lbm_batch *b, void **state, long *steps_done);
+
+/* Number of work tiles and of persistent workgroups the batch launches. */
+int lbm_batch_info(lbm_batch *b, int *ntiles, int *grid);
+
+void lbm_batch_destroy(lbm_batch *b);
+
+/* Thread-local message describing the last failure (never NULL). */
+const char *lbm_last_error(void);
+
+/* Library version string. */
+const char *lbm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,74 @@
+"""Gradients of a final-height misfit through the lattice Boltzmann rollout.
+
+``rollout(h0, s, T, ...)`` returns h(T) as a differentiable function of the
+initial height field h0 and the relaxation rate s.  Forward: T steps of the
+fused stream + collide kernel, keeping a copy of the state every K steps.
+Backward: for each K-step segment in reverse, recompute its states from the
+checkpoint (one extra forward step per adjoint step), then apply the
+hand-written adjoint kernel step by step (``lbm_adjoint_step``), accumulating
+dL/ds in FP64 per workgroup; finally dL/dh0 = J(W0)^T lam^0.
+
+Only the 2D lattice with periodic faces has an adjoint.  Initial momentum is
+zero (the adjoint workload); the state storage may be FP64 or FP32 (the adjoint
+is stored like the state, arithmetic and the s-gradient stay FP64).
+"""
+from __future__ import annotations
+
+import math
+
+import torch
+
+from .lbm import Solver
+
+
+class _Rollout(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, h0, s, T, K, lam, g, storage, block):
+        n = h0.shape
+        solver = Solver(2, n[1], n[0], lam=lam, s=float(s), g=g, h0=h0.detach(),
+                        storage=storage, block=block)
+        cks = {0: solver.current()[0].clone()}
+        for t in range(T):
+            solver.step(1)
+            if (t + 1) % K == 0 and (t + 1) < T:
+                cks[t + 1] = solver.current()[0].clone()
+        hT = solver.moments()[0]
+        ctx.solver = solver
+        ctx.cks = cks
+        ctx.T, ctx.K = T, K
+        ctx.save_for_backward(h0)
+        return hT
+
+    @staticmethod
+    def backward(ctx, grad_hT):
+        solver, cks, T, K = ctx.solver, ctx.cks, ctx.T, ctx.K
+        lam_hi = solver.new_state()
+        lam_lo = solver.new_state()
+        solver.adjoint_terminal(grad_hT.contiguous(), lam_hi)
+        partials = solver.adjoint_partials()
+        seg_starts = sorted(cks)
+        seg = [solver.new_state() for _ in range(K)]
+        for s0 in reversed(seg_starts):
+            s1 = min(s0 + K, T)
+            seg[0].copy_(cks[s0])
+            for t in range(s0 + 1, s1):
+                solver.step_buffers(seg[t - s0 - 1], seg[t - s0])
+            for t in range(s1 - 1, s0 - 1, -1):
+                solver.adjoint_step(seg[t - s0], lam_hi, lam_lo, partials)
+                lam_hi, lam_lo = lam_lo, lam_hi
+        gh0 = solver.adjoint_grad_w0(lam_hi)[0]
+        gs = solver.sum(partials)
+        ctx.solver = None
+        ctx.cks = None
+        grad_s = torch.tensor(gs, dtype=torch.float64, device=gh0.device)
+        return gh0, grad_s, None, None, None, None, None, None
+
+
+def rollout(h0: torch.Tensor, s: torch.Tensor, T: int, K: int | None = None, lam: float = 3.0,
+            g: float = 1.0, storage: str = "f64", block: int = 256) -> torch.Tensor:
+    """h(T) from W0 = (h0, 0, 0) on the periodic unit square; differentiable in
+    h0 (2D float64 CUDA tensor) and s (0-dim float64 tensor).  K defaults to
+    about sqrt(T)."""
+    if K is None:
+        K = max(1, int(round(math.sqrt(T))))
+    return _Rollout.apply(h0, s, int(T), int(K), float(lam), float(g), storage, int(block))

@@ -1,0 +1,433 @@
+// Host side of liblbm.so: argument validation, layout, ping-pong buffers,
+// HIP-graph replay of step chunks, reductions and error reporting.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "../../include/lbm.h"
+#include "internal.h"
+
+using namespace lbm;
+
+// ------------------------------------------------------------------ errors ----
+static thread_local char g_err[512] = "no error";
+
+static int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(LBM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+    } while (0)
+
+extern "C" const char *lbm_last_error(void) { return g_err; }
+
+// Used by the other translation units of the library to report an error.
+int lbm_set_error(int code, const char *msg)
+{
+    snprintf(g_err, sizeof g_err, "%s", msg);
+    return code;
+}
+extern "C" const char *lbm_version(void) { return "liblbm 1.0 (gfx950, D1Q2x2 / D2Q4x3)"; }
+
+// ------------------------------------------------------------------ layout ----
+static const long kAlign = 64;        // elements: planes start on 512 B / 256 B boundaries
+static const long kDefaultPad = 128;  // elements between planes (breaks power-of-two strides)
+
+static int nplanes_of(int lattice) { return lattice == LBM_D1Q2x2 ? 4 : 12; }
+static size_t elem_of(int storage) { return storage == LBM_F32 ? 4 : 8; }
+
+static int layout_of(int lattice, int storage, int nx, int ny, long pad, long *ps, int *np,
+                     size_t *bytes)
+{
+    if (lattice != LBM_D1Q2x2 && lattice != LBM_D2Q4x3)
+        return fail(LBM_EINVAL, "lattice must be LBM_D1Q2x2 or LBM_D2Q4x3 (got %d)", lattice);
+    if (storage != LBM_F64 && storage != LBM_F32)
+        return fail(LBM_EINVAL, "storage must be LBM_F64 or LBM_F32 (got %d)", storage);
+    if (lattice == LBM_D1Q2x2 && (nx < 2 || ny != 1))
+        return fail(LBM_EINVAL, "1D needs nx >= 2 and ny == 1 (got %d x %d)", nx, ny);
+    if (lattice == LBM_D2Q4x3 && (nx < 2 || ny < 2))
+        return fail(LBM_EINVAL, "2D needs nx, ny >= 2 (got %d x %d)", nx, ny);
+    const long n = (long)nx * ny;
+    if (n > (1L << 31) / 16) return fail(LBM_EINVAL, "grid too large (%ld nodes)", n);
+    if (pad < 0) pad = kDefaultPad;
+    const long stride = ((n + kAlign - 1) / kAlign) * kAlign + ((pad + kAlign - 1) / kAlign) * kAlign;
+    if (ps) *ps = stride;
+    if (np) *np = nplanes_of(lattice);
+    if (bytes) *bytes = (size_t)stride * nplanes_of(lattice) * elem_of(storage);
+    return LBM_OK;
+}
+
+extern "C" int lbm_layout(const lbm_params *p, long *plane_stride, int *n_planes, size_t *bytes)
+{
+    if (!p) return fail(LBM_EINVAL, "null params");
+    return layout_of(p->lattice, p->storage, p->nx, p->ny, p->plane_pad, plane_stride, n_planes,
+                     bytes);
+}
+
+static int check_bcs(int dim, const int *bc, const double (*inflow)[3])
+{
+    const int nface = dim == 1 ? 2 : 4;
+    for (int f = 0; f < nface; ++f) {
+        if (bc[f] < LBM_BC_PERIODIC || bc[f] > LBM_BC_INFLOW)
+            return fail(LBM_EINVAL, "bad boundary code %d on face %d", bc[f], f);
+        if ((bc[f] == LBM_BC_PERIODIC) != (bc[f ^ 1] == LBM_BC_PERIODIC))
+            return fail(LBM_EINVAL, "faces %d and %d: periodic must be paired", f, f ^ 1);
+        if (bc[f] == LBM_BC_INFLOW &&
+            (!(inflow[f][0] > 0.0) || !isfinite(inflow[f][0]) || !isfinite(inflow[f][1]) ||
+             !isfinite(inflow[f][2])))
+            return fail(LBM_EINVAL, "inflow state of face %d needs finite values and h > 0", f);
+    }
+    return LBM_OK;
+}
+
+static int check_phys(double lambda, double s, double g)
+{
+    if (!(lambda > 0.0) || !isfinite(lambda)) return fail(LBM_EINVAL, "lambda must be > 0");
+    if (!(s > 0.0 && s < 2.0)) return fail(LBM_EINVAL, "relaxation rate s must be in (0, 2)");
+    if (!(g > 0.0) || !isfinite(g)) return fail(LBM_EINVAL, "g must be > 0");
+    return LBM_OK;
+}
+
+static void fill_geo_phys(int dim, int nx, int ny, long ps, double lambda, double s, double g,
+                          const int *bc, const double (*inflow)[3], Geo &G, Phys &P)
+{
+    G.nx = nx;
+    G.ny = ny;
+    G.ps = ps;
+    for (int f = 0; f < 4; ++f) {
+        G.bc[f] = (dim == 1 && f >= 2) ? BC_PERIODIC : bc[f];
+        for (int k = 0; k < 3; ++k) G.win[f][k] = inflow[f][k];
+    }
+    P.c = 0.5 / lambda;
+    P.s = s;
+    P.hg = 0.5 * g;
+    P.g = g;
+}
+
+// --------------------------------------------------------------- context ----
+struct lbm_ctx {
+    lbm_params p;
+    int dim;
+    bool f32;
+    long ps;
+    int np;
+    size_t bytes;
+    Geo G;
+    Phys P;
+    Launch L;
+    void *buf[2];
+    int cur;
+    long steps;
+    hipStream_t st;
+    // library-owned scratch
+    unsigned long long *d_speed;
+    int *d_flag;
+    double *d_partials;  // moments partials (3 per block)
+    double *d_totals;    // 3 doubles
+    // captured step chunks, one per starting buffer
+    hipStream_t cap;
+    hipGraphExec_t chunk[2];
+    int chunk_len;
+};
+
+static const int kChunk = 32;  // steps per captured graph (even: parity preserved)
+
+extern "C" void lbm_destroy(lbm_ctx *c)
+{
+    if (!c) return;
+    for (int i = 0; i < 2; ++i)
+        if (c->chunk[i]) (void)hipGraphExecDestroy(c->chunk[i]);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
+    (void)hipFree(c->d_speed);
+    (void)hipFree(c->d_flag);
+    (void)hipFree(c->d_partials);
+    (void)hipFree(c->d_totals);
+    delete c;
+}
+
+extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0,
+                        const double *qy0, lbm_ctx **out)
+{
+    if (!out) return fail(LBM_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (!p) return fail(LBM_EINVAL, "null params");
+    if (!h0) return fail(LBM_EINVAL, "null h0");
+    if (!p->f_a || !p->f_b) return fail(LBM_EINVAL, "null state buffer");
+    if (p->f_a == p->f_b) return fail(LBM_EINVAL, "f_a and f_b must be distinct buffers");
+    long ps;
+    int np;
+    size_t bytes;
+    int rc = layout_of(p->lattice, p->storage, p->nx, p->ny, p->plane_pad, &ps, &np, &bytes);
+    if (rc) return rc;
+    if ((rc = check_phys(p->lambda, p->s, p->g))) return rc;
+    const int dim = p->lattice == LBM_D1Q2x2 ? 1 : 2;
+    if ((rc = check_bcs(dim, p->bc, p->inflow))) return rc;
+    const int block = p->block ? p->block : 256;
+    if (block != 64 && block != 128 && block != 256 && block != 512)
+        return fail(LBM_EINVAL, "block must be 64, 128, 256 or 512 (got %d)", block);
+    const int npt = p->nodes_per_thread ? p->nodes_per_thread : 1;
+    if (npt != 1 && npt != 2 && npt != 4)
+        return fail(LBM_EINVAL, "nodes_per_thread must be 1, 2 or 4 (got %d)", npt);
+    if (p->check_every < 0) return fail(LBM_EINVAL, "check_every must be >= 0");
+
+    lbm_ctx *c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(LBM_EDEVICE, "out of host memory");
+    c->p = *p;
+    c->dim = dim;
+    c->f32 = p->storage == LBM_F32;
+    c->ps = ps;
+    c->np = np;
+    c->bytes = bytes;
+    fill_geo_phys(dim, p->nx, p->ny, ps, p->lambda, p->s, p->g, p->bc, p->inflow, c->G, c->P);
+    c->L.block = block;
+    c->L.npt = npt;
+    c->buf[0] = p->f_a;
+    c->buf[1] = p->f_b;
+    c->cur = 0;
+    c->steps = 0;
+    c->st = (hipStream_t)p->stream;
+    c->chunk_len = kChunk;
+
+    hipError_t e;
+    const int nmb = moments_blocks(c->G);
+    if ((e = hipMalloc(&c->d_speed, sizeof(unsigned long long))) != hipSuccess ||
+        (e = hipMalloc(&c->d_flag, 2 * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&c->d_partials, sizeof(double) * 3 * (size_t)nmb)) != hipSuccess ||
+        (e = hipMalloc(&c->d_totals, sizeof(double) * 4)) != hipSuccess) {
+        lbm_destroy(c);
+        return fail(LBM_EDEVICE, "hipMalloc of scratch failed: %s", hipGetErrorString(e));
+    }
+    unsigned long long speed_bits = 0;
+    int bad = 0;
+    if ((e = hipMemsetAsync(c->d_speed, 0, sizeof(unsigned long long), c->st)) != hipSuccess ||
+        (e = hipMemsetAsync(c->d_flag, 0, 2 * sizeof(int), c->st)) != hipSuccess ||
+        (e = launch_init(dim, c->f32, c->buf[0], h0, qx0, qy0, c->G, c->P, c->L, c->d_speed,
+                         c->d_flag, c->st)) != hipSuccess ||
+        (e = hipMemcpyAsync(&speed_bits, c->d_speed, sizeof speed_bits, hipMemcpyDeviceToHost,
+                            c->st)) != hipSuccess ||
+        (e = hipMemcpyAsync(&bad, c->d_flag, sizeof bad, hipMemcpyDeviceToHost, c->st)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(c->st)) != hipSuccess) {
+        lbm_destroy(c);
+        return fail(LBM_EDEVICE, "initialisation failed: %s", hipGetErrorString(e));
+    }
+    if (bad) {
+        lbm_destroy(c);
+        return fail(LBM_EINVAL, "initial fields need h > 0 and finite values everywhere");
+    }
+    *out = c;
+    double speed;
+    memcpy(&speed, &speed_bits, sizeof speed);
+    const double need = (dim == 1 ? 1.0 : 2.0) * speed;
+    if (p->lambda < need)
+        return fail(LBM_WARN_SUBCHAR,
+                    "lambda = %g is below the monotonicity bound %g of the %s lattice "
+                    "(max |u| + sqrt(g h) = %g); the run may diverge",
+                    p->lambda, need, dim == 1 ? "D1Q2" : "D2Q4", speed);
+    return LBM_OK;
+}
+
+static int check_ctx(lbm_ctx *c)
+{
+    if (!c) return fail(LBM_ESTATE, "null context");
+    return LBM_OK;
+}
+
+static int check_state(lbm_ctx *c, long at_step)
+{
+    int flag = 0;
+    HIP_TRY(hipMemsetAsync(c->d_flag, 0, sizeof(int), c->st));
+    HIP_TRY(launch_check(c->dim, c->f32, c->buf[c->cur], c->G, c->d_flag, c->st));
+    HIP_TRY(hipMemcpyAsync(&flag, c->d_flag, sizeof flag, hipMemcpyDeviceToHost, c->st));
+    HIP_TRY(hipStreamSynchronize(c->st));
+    if (flag)
+        return fail(LBM_EDIVERGED, "state diverged (h <= 0 or non-finite) at step %ld", at_step);
+    return LBM_OK;
+}
+
+// Capture kChunk steps starting from buffer `from` into a graph (once).
+static int ensure_chunk(lbm_ctx *c, int from)
+{
+    if (c->chunk[from]) return LBM_OK;
+    if (!c->cap) HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    int cur = from;
+    hipError_t le = hipSuccess;
+    for (int k = 0; k < c->chunk_len && le == hipSuccess; ++k) {
+        le = launch_step(c->dim, c->f32, c->buf[cur], c->buf[cur ^ 1], c->G, c->P, c->L, c->cap);
+        cur ^= 1;
+    }
+    hipError_t ee = hipStreamEndCapture(c->cap, &g);
+    if (le != hipSuccess || ee != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(LBM_EDEVICE, "graph capture failed: %s",
+                    hipGetErrorString(le != hipSuccess ? le : ee));
+    }
+    hipError_t ie = hipGraphInstantiate(&c->chunk[from], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+        c->chunk[from] = nullptr;
+        return fail(LBM_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(ie));
+    }
+    return LBM_OK;
+}
+
+extern "C" int lbm_step(lbm_ctx *c, long nsteps)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+    long done = 0;
+    while (done < nsteps) {
+        long todo = nsteps - done;
+        if (c->p.check_every > 0) {
+            const long to_check = c->p.check_every - (c->steps % c->p.check_every);
+            if (todo > to_check) todo = to_check;
+        }
+        // whole chunks through the captured graph, the rest launch by launch
+        while (todo >= c->chunk_len) {
+            if ((rc = ensure_chunk(c, c->cur))) return rc;
+            HIP_TRY(hipGraphLaunch(c->chunk[c->cur], c->st));
+            todo -= c->chunk_len;
+            done += c->chunk_len;
+            c->steps += c->chunk_len;  // chunk length is even: c->cur unchanged
+        }
+        for (; todo > 0; --todo) {
+            HIP_TRY(launch_step(c->dim, c->f32, c->buf[c->cur], c->buf[c->cur ^ 1], c->G, c->P,
+                                c->L, c->st));
+            c->cur ^= 1;
+            ++done;
+            ++c->steps;
+        }
+        if (c->p.check_every > 0 && c->steps % c->p.check_every == 0)
+            if ((rc = check_state(c, c->steps))) return rc;
+    }
+    return LBM_OK;
+}
+
+extern "C" int lbm_step_buffers(lbm_ctx *c, const void *src, void *dst)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!src || !dst) return fail(LBM_EINVAL, "null buffer");
+    if (src == dst) return fail(LBM_EINVAL, "src and dst must not alias");
+    HIP_TRY(launch_step(c->dim, c->f32, src, dst, c->G, c->P, c->L, c->st));
+    return LBM_OK;
+}
+
+extern "C" int lbm_current(lbm_ctx *c, void **state, long *steps_done)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (state) *state = c->buf[c->cur];
+    if (steps_done) *steps_done = c->steps;
+    return LBM_OK;
+}
+
+extern "C" int lbm_export(lbm_ctx *c, void *dst)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!dst) return fail(LBM_EINVAL, "null destination");
+    HIP_TRY(hipMemcpyAsync(dst, c->buf[c->cur], c->bytes, hipMemcpyDeviceToDevice, c->st));
+    return LBM_OK;
+}
+
+extern "C" int lbm_import(lbm_ctx *c, const void *src)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!src) return fail(LBM_EINVAL, "null source");
+    HIP_TRY(hipMemcpyAsync(c->buf[c->cur], src, c->bytes, hipMemcpyDeviceToDevice, c->st));
+    return LBM_OK;
+}
+
+extern "C" int lbm_moments(lbm_ctx *c, const void *state, double *h, double *qx, double *qy,
+                           double *totals_host)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    const void *s = state ? state : c->buf[c->cur];
+    int nb = 0;
+    HIP_TRY(launch_moments(c->dim, c->f32, s, h, qx, qy, totals_host ? c->d_partials : nullptr,
+                           c->G, c->st, &nb));
+    if (totals_host) {
+        HIP_TRY(launch_sum(c->d_partials, nb, 3, 3, c->d_totals, c->st));
+        HIP_TRY(hipMemcpyAsync(totals_host, c->d_totals, 3 * sizeof(double),
+                               hipMemcpyDeviceToHost, c->st));
+        HIP_TRY(hipStreamSynchronize(c->st));
+        if (c->dim == 1) totals_host[2] = 0.0;
+    }
+    return LBM_OK;
+}
+
+static int check_adjoint_ctx(lbm_ctx *c)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (c->dim != 2) return fail(LBM_EINVAL, "the adjoint is implemented for the 2D lattice");
+    for (int f = 0; f < 4; ++f)
+        if (c->G.bc[f] != BC_PERIODIC)
+            return fail(LBM_EINVAL, "the adjoint is implemented for periodic faces only");
+    return LBM_OK;
+}
+
+extern "C" long lbm_adjoint_partials(lbm_ctx *c) { return c ? adjoint_blocks(c->G) : 0; }
+
+extern "C" int lbm_adjoint_step(lbm_ctx *c, const void *f_n, const void *lam_np1, void *lam_n,
+                                double *dLds_partials)
+{
+    int rc = check_adjoint_ctx(c);
+    if (rc) return rc;
+    if (!f_n || !lam_np1 || !lam_n || !dLds_partials) return fail(LBM_EINVAL, "null argument");
+    if (lam_n == f_n || lam_n == lam_np1)
+        return fail(LBM_EINVAL, "lam_n must not alias f_n or lam_np1");
+    HIP_TRY(launch_adjoint(c->f32, f_n, lam_np1, lam_n, dLds_partials, c->G, c->P, c->st));
+    return LBM_OK;
+}
+
+extern "C" int lbm_adjoint_terminal(lbm_ctx *c, const double *dLdh, void *lam_T)
+{
+    int rc = check_adjoint_ctx(c);
+    if (rc) return rc;
+    if (!dLdh || !lam_T) return fail(LBM_EINVAL, "null argument");
+    HIP_TRY(launch_adjoint_terminal(c->f32, dLdh, lam_T, c->G, c->st));
+    return LBM_OK;
+}
+
+extern "C" int lbm_adjoint_grad_w0(lbm_ctx *c, const void *lam0, const double *h0,
+                                   const double *qx0, const double *qy0, double *grad_h0,
+                                   double *grad_qx0, double *grad_qy0)
+{
+    int rc = check_adjoint_ctx(c);
+    if (rc) return rc;
+    if (!lam0 || !h0) return fail(LBM_EINVAL, "null argument");
+    HIP_TRY(launch_adjoint_grad_w0(c->f32, lam0, h0, qx0, qy0, grad_h0, grad_qx0, grad_qy0,
+                                   c->G, c->P, c->st));
+    return LBM_OK;
+}
+
+extern "C" int lbm_sum(lbm_ctx *c, const double *partials, long n, double *out_host)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!partials || !out_host || n < 0) return fail(LBM_EINVAL, "bad argument");
+    HIP_TRY(launch_sum(partials, n, 1, 1, c->d_totals + 3, c->st));
+    HIP_TRY(hipMemcpyAsync(out_host, c->d_totals + 3, sizeof(double), hipMemcpyDeviceToHost,
+                           c->st));
+    HIP_TRY(hipStreamSynchronize(c->st));
+    return LBM_OK;
+}

@@ -1,0 +1,502 @@
+// Batched form: many independent 1D / 2D problems of uneven size advanced in
+// ONE persistent kernel launch.
+//
+// Work decomposition
+//   Every instance is cut into tiles of about `tile_nodes` nodes: runs of
+//   consecutive nodes in 1D, bands of whole rows in 2D.  A tile's pull-stream
+//   reads only its own nodes and one node (1D) or one row (2D) of each of its
+//   two neighbour tiles, so tile t can take step n as soon as t and its
+//   neighbours have finished step n-1 -- both for the data it reads and because
+//   then nobody still reads the buffer region it overwrites (ping-pong).
+//
+// Scheduling
+//   Work items (step n, tile t) are handed out by one atomic counter in
+//   step-major order w = n * T + t.  Every dependency of item w has a smaller
+//   index, so it was handed out earlier to a running workgroup; the smallest
+//   unfinished item therefore never waits, and the launch cannot deadlock
+//   whatever the number of resident workgroups.  There is no grid-wide
+//   barrier: fast regions run ahead of slow ones by as many steps as their
+//   neighbourhoods allow.  Completion of (n, t) is published by a per-tile
+//   counter with agent-scope release / acquire, after every wave of the
+//   workgroup has made its stores visible at agent scope.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "internal.h"
+
+namespace lbm {
+
+struct InstDev {
+    int dim;
+    int allper;  // all faces periodic
+    long off;    // element offset of the instance's planes in the batch buffer
+    Geo G;
+    Phys P;
+};
+
+struct TileDev {
+    int inst;
+    int begin, end;  // 1D: node range; 2D: row range
+    int nb0, nb1;    // neighbour tiles (-1: none)
+};
+
+__device__ __forceinline__ int wait_ge(int *done, int t, int n)
+{
+    if (t < 0) return 0;
+    while (__hip_atomic_load(done + t, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < n)
+        __builtin_amdgcn_s_sleep(1);
+    return 0;
+}
+
+template <typename T>
+__device__ __forceinline__ void tile_1d(const T *__restrict__ src, T *__restrict__ dst,
+                                        const InstDev &I, int b, int e)
+{
+    const T *s = src + I.off;
+    T *d = dst + I.off;
+    for (int x = b + (int)threadIdx.x; x < e; x += blockDim.x) {
+        double f[4];
+        pull1d(s, I.G, I.P, x, f);
+        collide1d(f, I.P);
+#pragma unroll
+        for (int pl = 0; pl < 4; ++pl) st(d + pl * I.G.ps + x, f[pl]);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void tile_2d(const T *__restrict__ src, T *__restrict__ dst,
+                                        const InstDev &I, int r0, int r1)
+{
+    const T *s = src + I.off;
+    T *d = dst + I.off;
+    const int nx = I.G.nx, ny = I.G.ny;
+    const long ps = I.G.ps;
+    const int cnt = (r1 - r0) * nx;
+    for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
+        const int y = r0 + k / nx;
+        const int x = k - (y - r0) * nx;
+        double f[12];
+        const bool interior = x > 0 && x < nx - 1 && y > 0 && y < ny - 1;
+        if (I.allper || interior) {
+            const long row = (long)y * nx;
+            const int xm = x == 0 ? nx - 1 : x - 1;
+            const int xp = x == nx - 1 ? 0 : x + 1;
+            const long rm = y == 0 ? (long)(ny - 1) * nx : row - nx;
+            const long rp = y == ny - 1 ? 0 : row + nx;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const T *b = s + (4 * c) * ps;
+                f[4 * c + 0] = ld(b + row + xm);
+                f[4 * c + 1] = ld(b + ps + rm + x);
+                f[4 * c + 2] = ld(b + 2 * ps + row + xp);
+                f[4 * c + 3] = ld(b + 3 * ps + rp + x);
+            }
+        } else {
+            pull2d_generic(s, I.G, I.P, x, y, f);
+        }
+        collide2d(f, I.P);
+        T *o = d + (long)y * nx + x;
+#pragma unroll
+        for (int pl = 0; pl < 12; ++pl) st(o + pl * ps, f[pl]);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024)
+    k_batch(const InstDev *__restrict__ inst, const TileDev *__restrict__ tiles, int ntiles,
+            unsigned long long nitems, int *done, unsigned long long *next, T *buf0, T *buf1,
+            int cur)
+{
+    __shared__ unsigned long long item;
+    for (;;) {
+        if (threadIdx.x == 0) item = atomicAdd(next, 1ull);
+        __syncthreads();
+        const unsigned long long w = item;
+        __syncthreads();
+        if (w >= nitems) break;
+        const int n = (int)(w / (unsigned long long)ntiles);
+        const int t = (int)(w - (unsigned long long)n * ntiles);
+        const TileDev td = tiles[t];
+        if (threadIdx.x == 0) {
+            wait_ge(done, t, n);
+            wait_ge(done, td.nb0, n);
+            wait_ge(done, td.nb1, n);
+        }
+        __syncthreads();
+        const InstDev I = inst[td.inst];
+        const bool odd = ((cur + n) & 1) != 0;
+        const T *src = odd ? buf1 : buf0;
+        T *dst = odd ? buf0 : buf1;
+        if (I.dim == 1)
+            tile_1d(src, dst, I, td.begin, td.end);
+        else
+            tile_2d(src, dst, I, td.begin, td.end);
+        // every wave publishes its own stores at agent scope, then one release
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_store(done + t, n + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Zero the per-tile counters and the work counter (a kernel, so that it can sit
+// in a captured graph).
+__global__ void k_batch_reset(int *done, int ntiles, unsigned long long *next)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ntiles) done[i] = 0;
+    if (i == 0) *next = 0ull;
+}
+
+} // namespace lbm
+
+using namespace lbm;
+
+// ----------------------------------------------------------------- host side ----
+static thread_local char b_err[512];
+extern "C" const char *lbm_last_error(void);
+int lbm_set_error(int code, const char *msg);  // api.hip
+
+static int bfail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(b_err, sizeof b_err, fmt, ap);
+    va_end(ap);
+    return lbm_set_error(code, b_err);
+}
+
+#define BHIP(expr)                                                                        \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return bfail(LBM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+struct lbm_batch {
+    std::vector<lbm_instance> inst;
+    int storage;
+    bool f32;
+    void *buf[2];
+    int cur;
+    long steps;
+    hipStream_t st;
+    lbm_batch_tuning tune;
+    int ntiles;
+    InstDev *d_inst;
+    TileDev *d_tiles;
+    int *d_done;
+    unsigned long long *d_next;
+    int grid;
+    // one captured graph per (nsteps, starting buffer); the last one is kept
+    hipGraphExec_t gexec;
+    long g_nsteps;
+    int g_cur;
+    hipStream_t cap;
+    std::vector<Geo> geo;
+    std::vector<Phys> phys;
+};
+
+static long round_up(long v, long a) { return ((v + a - 1) / a) * a; }
+
+extern "C" int lbm_batch_layout(lbm_instance *inst, int n, int storage, size_t *bytes,
+                                long *nodes)
+{
+    if (!inst || n <= 0) return bfail(LBM_EINVAL, "need at least one instance");
+    if (storage != LBM_F64 && storage != LBM_F32) return bfail(LBM_EINVAL, "bad storage");
+    long off = 0, noff = 0;
+    for (int i = 0; i < n; ++i) {
+        lbm_instance &I = inst[i];
+        const bool d1 = I.lattice == LBM_D1Q2x2;
+        if (I.lattice != LBM_D1Q2x2 && I.lattice != LBM_D2Q4x3)
+            return bfail(LBM_EINVAL, "instance %d: bad lattice", i);
+        if (I.nx < 2 || (d1 ? I.ny != 1 : I.ny < 2))
+            return bfail(LBM_EINVAL, "instance %d: bad size %d x %d", i, I.nx, I.ny);
+        const long nn = (long)I.nx * I.ny;
+        const long ps = round_up(nn, 64);
+        I.state_offset = off;
+        I.node_offset = noff;
+        off += ps * (d1 ? 4 : 12);
+        noff += nn;
+    }
+    if (bytes) *bytes = (size_t)off * (storage == LBM_F32 ? 4 : 8);
+    if (nodes) *nodes = noff;
+    return LBM_OK;
+}
+
+extern "C" void lbm_batch_destroy(lbm_batch *b)
+{
+    if (!b) return;
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    (void)hipFree(b->d_inst);
+    (void)hipFree(b->d_tiles);
+    (void)hipFree(b->d_done);
+    (void)hipFree(b->d_next);
+    delete b;
+}
+
+extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage, void *f_a,
+                                void *f_b, void *stream, const lbm_batch_tuning *tuning,
+                                lbm_batch **out)
+{
+    if (!out) return bfail(LBM_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (!inst_in || n <= 0) return bfail(LBM_EINVAL, "need at least one instance");
+    if (!f_a || !f_b || f_a == f_b) return bfail(LBM_EINVAL, "need two distinct buffers");
+    std::vector<lbm_instance> inst(inst_in, inst_in + n);
+    int rc = lbm_batch_layout(inst.data(), n, storage, nullptr, nullptr);
+    if (rc) return rc;
+    for (int i = 0; i < n; ++i) {
+        if (inst[i].state_offset != inst_in[i].state_offset ||
+            inst[i].node_offset != inst_in[i].node_offset)
+            return bfail(LBM_EINVAL, "instance %d: offsets differ from lbm_batch_layout", i);
+        const lbm_instance &I = inst[i];
+        if (!(I.lambda > 0) || !(I.s > 0 && I.s < 2) || !(I.g > 0))
+            return bfail(LBM_EINVAL, "instance %d: need lambda > 0, s in (0,2), g > 0", i);
+        const int nface = I.lattice == LBM_D1Q2x2 ? 2 : 4;
+        for (int f = 0; f < nface; ++f) {
+            if (I.bc[f] < 0 || I.bc[f] > 3) return bfail(LBM_EINVAL, "instance %d: bad bc", i);
+            if ((I.bc[f] == 0) != (I.bc[f ^ 1] == 0))
+                return bfail(LBM_EINVAL, "instance %d: periodic faces must be paired", i);
+            if (I.bc[f] == LBM_BC_INFLOW && !(I.inflow[f][0] > 0))
+                return bfail(LBM_EINVAL, "instance %d: inflow h must be > 0", i);
+        }
+    }
+    lbm_batch_tuning tune = {256, 4096, 0};
+    if (tuning) tune = *tuning;
+    if (tune.block < 64 || tune.block > 1024 || tune.block % 64)
+        return bfail(LBM_EINVAL, "tuning.block must be a multiple of 64 in [64, 1024]");
+    if (tune.tile_nodes < tune.block) return bfail(LBM_EINVAL, "tuning.tile_nodes < block");
+    if (tune.grid < 0) return bfail(LBM_EINVAL, "tuning.grid must be >= 0");
+
+    lbm_batch *b = new (std::nothrow) lbm_batch();
+    if (!b) return bfail(LBM_EDEVICE, "out of host memory");
+    b->inst = inst;
+    b->storage = storage;
+    b->f32 = storage == LBM_F32;
+    b->buf[0] = f_a;
+    b->buf[1] = f_b;
+    b->st = (hipStream_t)stream;
+    b->tune = tune;
+
+    std::vector<InstDev> hi(n);
+    std::vector<TileDev> ht;
+    b->geo.resize(n);
+    b->phys.resize(n);
+    for (int i = 0; i < n; ++i) {
+        const lbm_instance &I = inst[i];
+        const int dim = I.lattice == LBM_D1Q2x2 ? 1 : 2;
+        InstDev &d = hi[i];
+        d.dim = dim;
+        d.off = I.state_offset;
+        d.G.nx = I.nx;
+        d.G.ny = I.ny;
+        d.G.ps = round_up((long)I.nx * I.ny, 64);
+        for (int f = 0; f < 4; ++f) {
+            d.G.bc[f] = (dim == 1 && f >= 2) ? BC_PERIODIC : I.bc[f];
+            for (int k = 0; k < 3; ++k) d.G.win[f][k] = I.inflow[f][k];
+        }
+        d.allper = d.G.bc[0] == 0 && d.G.bc[1] == 0 && d.G.bc[2] == 0 && d.G.bc[3] == 0;
+        d.P.c = 0.5 / I.lambda;
+        d.P.s = I.s;
+        d.P.hg = 0.5 * I.g;
+        d.P.g = I.g;
+        b->geo[i] = d.G;
+        b->phys[i] = d.P;
+        // tiles
+        const int first = (int)ht.size();
+        int nt;
+        if (dim == 1) {
+            nt = (int)std::max(1L, ((long)I.nx + tune.tile_nodes - 1) / tune.tile_nodes);
+            const int per = (I.nx + nt - 1) / nt;
+            for (int k = 0; k < nt; ++k) {
+                TileDev td;
+                td.inst = i;
+                td.begin = k * per;
+                td.end = std::min(I.nx, (k + 1) * per);
+                ht.push_back(td);
+            }
+        } else {
+            const int rows = std::max(1, tune.tile_nodes / I.nx);
+            nt = (I.ny + rows - 1) / rows;
+            const int per = (I.ny + nt - 1) / nt;
+            for (int k = 0; k < nt; ++k) {
+                TileDev td;
+                td.inst = i;
+                td.begin = k * per;
+                td.end = std::min(I.ny, (k + 1) * per);
+                ht.push_back(td);
+            }
+        }
+        // drop empty tiles that rounding may leave at the end
+        while ((int)ht.size() > first + 1 && ht.back().begin >= ht.back().end) ht.pop_back();
+        nt = (int)ht.size() - first;
+        const bool wrap = dim == 1 ? d.G.bc[0] == BC_PERIODIC : d.G.bc[2] == BC_PERIODIC;
+        for (int k = 0; k < nt; ++k) {
+            TileDev &td = ht[first + k];
+            int a = k - 1, c = k + 1;
+            if (a < 0) a = wrap ? nt - 1 : -1;
+            if (c >= nt) c = wrap ? 0 : -1;
+            td.nb0 = (a < 0 || a == k) ? -1 : first + a;
+            td.nb1 = (c < 0 || c == k || c == a) ? -1 : first + c;
+        }
+    }
+    b->ntiles = (int)ht.size();
+
+    hipError_t e;
+    if ((e = hipMalloc(&b->d_inst, sizeof(InstDev) * n)) != hipSuccess ||
+        (e = hipMalloc(&b->d_tiles, sizeof(TileDev) * ht.size())) != hipSuccess ||
+        (e = hipMalloc(&b->d_done, sizeof(int) * ht.size())) != hipSuccess ||
+        (e = hipMalloc(&b->d_next, sizeof(unsigned long long))) != hipSuccess ||
+        (e = hipMemcpy(b->d_inst, hi.data(), sizeof(InstDev) * n, hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (e = hipMemcpy(b->d_tiles, ht.data(), sizeof(TileDev) * ht.size(),
+                       hipMemcpyHostToDevice)) != hipSuccess) {
+        lbm_batch_destroy(b);
+        return bfail(LBM_EDEVICE, "batch setup failed: %s", hipGetErrorString(e));
+    }
+    // persistent grid: fill the device
+    int dev = 0, ncu = 0, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (b->f32)
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<float>, tune.block, 0);
+    else
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<double>, tune.block, 0);
+    if (ncu <= 0) ncu = 256;
+    if (per_cu <= 0) per_cu = 1;
+    b->grid = tune.grid > 0 ? tune.grid : ncu * per_cu;
+    *out = b;
+    return LBM_OK;
+}
+
+extern "C" int lbm_batch_init(lbm_batch *b, const double *h0, const double *qx0,
+                              const double *qy0)
+{
+    if (!b) return bfail(LBM_ESTATE, "null batch");
+    if (!h0) return bfail(LBM_EINVAL, "null h0");
+    unsigned long long *d_speed = nullptr;
+    int *d_bad = nullptr;
+    BHIP(hipMalloc(&d_speed, sizeof(unsigned long long)));
+    hipError_t e = hipMalloc(&d_bad, sizeof(int));
+    if (e != hipSuccess) {
+        (void)hipFree(d_speed);
+        return bfail(LBM_EDEVICE, "hipMalloc failed: %s", hipGetErrorString(e));
+    }
+    Launch L = {256, 1};
+    for (size_t i = 0; i < b->inst.size() && e == hipSuccess; ++i) {
+        const lbm_instance &I = b->inst[i];
+        const int dim = I.lattice == LBM_D1Q2x2 ? 1 : 2;
+        const size_t es = b->f32 ? 4 : 8;
+        void *dst = (char *)b->buf[0] + (size_t)I.state_offset * es;
+        const long no = I.node_offset;
+        e = hipMemsetAsync(d_bad, 0, sizeof(int), b->st);
+        if (e == hipSuccess)
+            e = launch_init(dim, b->f32, dst, h0 + no, qx0 ? qx0 + no : nullptr,
+                            qy0 ? qy0 + no : nullptr, b->geo[i], b->phys[i], L, d_speed, d_bad,
+                            b->st);
+    }
+    int bad = 0;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&bad, d_bad, sizeof bad, hipMemcpyDeviceToHost, b->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->st);
+    (void)hipFree(d_speed);
+    (void)hipFree(d_bad);
+    if (e != hipSuccess) return bfail(LBM_EDEVICE, "batch init failed: %s", hipGetErrorString(e));
+    b->cur = 0;
+    b->steps = 0;
+    if (bad) return bfail(LBM_EINVAL, "initial fields need h > 0 and finite values everywhere");
+    return LBM_OK;
+}
+
+static hipError_t enqueue_run(lbm_batch *b, long nsteps, hipStream_t st)
+{
+    const int rb = (b->ntiles + 255) / 256;
+    hipLaunchKernelGGL(k_batch_reset, dim3(rb), dim3(256), 0, st, b->d_done, b->ntiles,
+                       b->d_next);
+    const unsigned long long nitems = (unsigned long long)nsteps * (unsigned long long)b->ntiles;
+    if (b->f32)
+        hipLaunchKernelGGL(k_batch<float>, dim3(b->grid), dim3(b->tune.block), 0, st, b->d_inst,
+                           b->d_tiles, b->ntiles, nitems, b->d_done, b->d_next,
+                           (float *)b->buf[0], (float *)b->buf[1], b->cur);
+    else
+        hipLaunchKernelGGL(k_batch<double>, dim3(b->grid), dim3(b->tune.block), 0, st,
+                           b->d_inst, b->d_tiles, b->ntiles, nitems, b->d_done, b->d_next,
+                           (double *)b->buf[0], (double *)b->buf[1], b->cur);
+    return hipGetLastError();
+}
+
+extern "C" int lbm_batch_run(lbm_batch *b, long nsteps)
+{
+    if (!b) return bfail(LBM_ESTATE, "null batch");
+    if (nsteps < 0 || nsteps > (1L << 30)) return bfail(LBM_EINVAL, "bad nsteps");
+    if (nsteps == 0) return LBM_OK;
+    if (!b->gexec || b->g_nsteps != nsteps || b->g_cur != b->cur) {
+        if (b->gexec) {
+            (void)hipGraphExecDestroy(b->gexec);
+            b->gexec = nullptr;
+        }
+        if (!b->cap) BHIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        BHIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+        hipError_t le = enqueue_run(b, nsteps, b->cap);
+        hipError_t ee = hipStreamEndCapture(b->cap, &g);
+        if (le != hipSuccess || ee != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return bfail(LBM_EDEVICE, "batch graph capture failed: %s",
+                         hipGetErrorString(le != hipSuccess ? le : ee));
+        }
+        hipError_t ie = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) {
+            b->gexec = nullptr;
+            return bfail(LBM_EDEVICE, "batch graph instantiate failed: %s", hipGetErrorString(ie));
+        }
+        b->g_nsteps = nsteps;
+        b->g_cur = b->cur;
+    }
+    BHIP(hipGraphLaunch(b->gexec, b->st));
+    b->steps += nsteps;
+    b->cur = (int)((b->cur + nsteps) & 1);
+    return LBM_OK;
+}
+
+extern "C" int lbm_batch_moments(lbm_batch *b, double *h, double *qx, double *qy)
+{
+    if (!b) return bfail(LBM_ESTATE, "null batch");
+    const size_t es = b->f32 ? 4 : 8;
+    for (size_t i = 0; i < b->inst.size(); ++i) {
+        const lbm_instance &I = b->inst[i];
+        const int dim = I.lattice == LBM_D1Q2x2 ? 1 : 2;
+        const void *s = (const char *)b->buf[b->cur] + (size_t)I.state_offset * es;
+        const long no = I.node_offset;
+        BHIP(launch_moments(dim, b->f32, s, h ? h + no : nullptr, qx ? qx + no : nullptr,
+                            (qy && dim == 2) ? qy + no : nullptr, nullptr, b->geo[i], b->st,
+                            nullptr));
+    }
+    return LBM_OK;
+}
+
+extern "C" int lbm_batch_current(lbm_batch *b, void **state, long *steps_done)
+{
+    if (!b) return bfail(LBM_ESTATE, "null batch");
+    if (state) *state = b->buf[b->cur];
+    if (steps_done) *steps_done = b->steps;
+    return LBM_OK;
+}
+
+// Number of work tiles and persistent workgroups (for tuning reports).
+extern "C" int lbm_batch_info(lbm_batch *b, int *ntiles, int *grid)
+{
+    if (!b) return bfail(LBM_ESTATE, "null batch");
+    if (ntiles) *ntiles = b->ntiles;
+    if (grid) *grid = b->grid;
+    return LBM_OK;
+}

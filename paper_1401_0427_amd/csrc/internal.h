@@ -1,0 +1,41 @@
+// Internal declarations shared by the host-side sources of liblbm.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+#include "lbm_device.h"
+
+namespace lbm {
+
+// Launch shape of the plain forward / adjoint kernels.
+struct Launch {
+    int block;  // threads per workgroup
+    int npt;    // nodes per thread along x
+};
+
+// Kernel launchers (each returns the hipError_t of the launch).
+hipError_t launch_init(int dim, bool f32, void *dst, const double *h0, const double *qx0,
+                       const double *qy0, const Geo &G, const Phys &P, const Launch &L,
+                       unsigned long long *speed_bits, int *bad, hipStream_t st);
+hipError_t launch_step(int dim, bool f32, const void *src, void *dst, const Geo &G,
+                       const Phys &P, const Launch &L, hipStream_t st);
+hipError_t launch_moments(int dim, bool f32, const void *state, double *h, double *qx,
+                          double *qy, double *partials, const Geo &G, hipStream_t st,
+                          int *nblocks_out);
+hipError_t launch_sum(const double *in, long n, int stride, int ncomp, double *out,
+                      hipStream_t st);
+hipError_t launch_check(int dim, bool f32, const void *state, const Geo &G, int *flag,
+                        hipStream_t st);
+int moments_blocks(const Geo &G);
+
+hipError_t launch_adjoint(bool f32, const void *un, const void *lam1, void *lam0,
+                          double *partials, const Geo &G, const Phys &P, hipStream_t st);
+long adjoint_blocks(const Geo &G);
+hipError_t launch_adjoint_terminal(bool f32, const double *dLdh, void *lam, const Geo &G,
+                                   hipStream_t st);
+hipError_t launch_adjoint_grad_w0(bool f32, const void *lam0, const double *h0,
+                                  const double *qx0, const double *qy0, double *gh, double *gqx,
+                                  double *gqy, const Geo &G, const Phys &P, hipStream_t st);
+
+} // namespace lbm

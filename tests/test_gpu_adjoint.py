@@ -1,0 +1,129 @@
+"""GPU adjoint (lbm_adjoint_step and the checkpointed autograd rollout) against
+the oracle's adjoint and central finite differences.  Gate: relative error
+<= 1e-6 for the FP64 run; the FP32-storage gradient error is reported."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import gpu_solver, normwise_rel, say, smooth_random_2d, to_np
+from paper_1401_0427_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1401_0427_amd import lbm
+
+    lbm.load()
+
+
+def _with_rest(planes):
+    return np.concatenate([np.zeros((1,) + planes.shape[1:]), planes])
+
+
+def test_adjoint_step_matches_oracle():
+    import torch
+
+    case = smooth_random_2d(300, 24, seed=8, lam=5.0, s=1.6)
+    S = gpu_solver(case)
+    S.step(9)
+    un = to_np(S.planes()).copy()
+    rng = np.random.default_rng(9)
+    lam1 = rng.standard_normal(un.shape)
+    lam1_t = S.new_state()
+    S.planes(lam1_t).copy_(torch.as_tensor(lam1))
+    lam0_t = S.new_state()
+    partials = S.adjoint_partials()
+    S.adjoint_step(S.current()[0], lam1_t, lam0_t, partials)
+    gs = S.sum(partials)
+    P = oracle.params(2, case.nx, case.ny, lam=case.lam, s=case.s, g=case.g)
+    ref, gs_ref = oracle.adjoint_step(P, _with_rest(un), _with_rest(lam1))
+    err = max(normwise_rel(a, b) for a, b in zip(to_np(S.planes(lam0_t)), ref[1:]))
+    say(f"[adjoint step] lam rel err {err:.3e}, dL/ds {gs:.15e} vs {gs_ref:.15e}")
+    assert err <= 1e-12
+    assert abs(gs - gs_ref) <= 1e-12 * abs(gs_ref)
+
+
+def _problem(n, T, seed=0):
+    c, ht0 = W.adjoint_case(n=n, steps=T, seed=seed, width2=0.05)
+    P = oracle.params(2, n, n, lam=c.lam, s=c.s)
+    hhat = oracle.moments(P, oracle.run(P, ht0, None, None, T))[0]
+    return c, P, hhat
+
+
+def _gpu_grad(c, hhat, T, K, storage="f64"):
+    import torch
+
+    from paper_1401_0427_amd.adjoint import rollout
+
+    h0 = torch.tensor(c.h0, dtype=torch.float64, device="cuda", requires_grad=True)
+    s = torch.tensor(c.s, dtype=torch.float64, device="cuda", requires_grad=True)
+    hT = rollout(h0, s, T, K, lam=c.lam, storage=storage)
+    loss = ((hT - torch.as_tensor(hhat, device="cuda")) ** 2).sum()
+    loss.backward()
+    return float(loss), to_np(h0.grad), float(s.grad)
+
+
+@pytest.mark.parametrize("n,T,K", [(32, 60, 7), (48, 41, 41)])
+def test_rollout_gradient_matches_oracle_fp64(n, T, K):
+    c, P, hhat = _problem(n, T)
+    say(f"[rollout grad] n={n} T={T} K={K}")
+    loss, gh, gs = _gpu_grad(c, hhat, T, K)
+    l_ref, gh_ref, gs_ref = oracle.loss_grad_2d(P, c.h0, hhat, T, K=5)
+    e_h = normwise_rel(gh, gh_ref)
+    e_s = abs(gs - gs_ref) / abs(gs_ref)
+    say(f"  loss {loss:.15e} vs {l_ref:.15e}; grad_h0 rel {e_h:.3e}; grad_s rel {e_s:.3e}")
+    assert abs(loss - l_ref) <= 1e-12 * l_ref
+    assert e_h <= 1e-6 and e_s <= 1e-6
+
+
+def test_rollout_gradient_central_differences_fp64():
+    import torch
+
+    from paper_1401_0427_amd.adjoint import rollout
+
+    n, T = 24, 30
+    c, P, hhat = _problem(n, T, seed=2)
+    loss, gh, gs = _gpu_grad(c, hhat, T, 6)
+    rng = np.random.default_rng(4)
+    v = rng.standard_normal((n, n))
+    eps = 1e-6
+
+    def L(h0, s):
+        with torch.no_grad():
+            hT = rollout(torch.as_tensor(h0, device="cuda"), torch.tensor(s, dtype=torch.float64),
+                         T, 6, lam=c.lam)
+            return float(((hT - torch.as_tensor(hhat, device="cuda")) ** 2).sum())
+
+    fd_h = (L(c.h0 + eps * v, c.s) - L(c.h0 - eps * v, c.s)) / (2 * eps)
+    fd_s = (L(c.h0, c.s + eps) - L(c.h0, c.s - eps)) / (2 * eps)
+    ad_h = float((gh * v).sum())
+    say(f"[fd] <grad,v> {ad_h:.10e} vs {fd_h:.10e}; ds {gs:.10e} vs {fd_s:.10e}")
+    assert abs(ad_h - fd_h) <= 1e-6 * abs(fd_h)
+    assert abs(gs - fd_s) <= 1e-6 * abs(fd_s)
+
+
+def test_rollout_gradient_fp32_storage_reported():
+    n, T = 64, 80
+    c, P, hhat = _problem(n, T, seed=3)
+    loss, gh, gs = _gpu_grad(c, hhat, T, 9, storage="f32")
+    _, gh_ref, gs_ref = oracle.loss_grad_2d(P, c.h0, hhat, T, K=9)
+    e_h = normwise_rel(gh, gh_ref)
+    e_s = abs(gs - gs_ref) / abs(gs_ref)
+    say(f"[fp32 rollout grad] grad_h0 rel {e_h:.3e}; grad_s rel {e_s:.3e} (reported, not gated "
+        f"at 1e-6)")
+    assert e_h < 1e-2 and e_s < 1e-2
+
+
+def test_adjoint_rejects_non_periodic():
+    from paper_1401_0427_amd.lbm import LbmError
+
+    case = smooth_random_2d(40, 40, seed=1, bc=("wall", "wall", "periodic", "periodic"))
+    S = gpu_solver(case)
+    with pytest.raises(LbmError, match="periodic"):
+        S.adjoint_step(S.current()[0], S.new_state(), S.new_state(), S.adjoint_partials())

@@ -1,0 +1,184 @@
+"""GPU (gfx950) parity of the HIP path against the CPU FP64 oracle, through the
+C ABI.  Tolerances: FP64 storage -- normwise max relative error <= 1e-12 per
+plane (the arithmetic order is the same on both sides, so the results are
+expected to agree bit for bit); FP32 storage -- L1 relative error of h <= 1e-5
+against the FP64 oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import (gpu_solver, l1_rel, normwise_rel, orc_params, orc_state,
+                         per_plane_rel, say, smooth_random_2d, to_np)
+from paper_1401_0427_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32_L1 = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1401_0427_amd import lbm
+
+    lbm.load()
+
+
+def _compare(case, steps, storage="f64", **kw):
+    say(f"[parity] {case.name} steps={steps} storage={storage} {kw}")
+    S = gpu_solver(case, storage=storage, **kw)
+    S.step(steps)
+    got = to_np(S.planes())
+    ref, P = orc_state(case, steps)
+    return got, ref, S, P
+
+
+@pytest.mark.parametrize("launch", [dict(block=256, npt=1), dict(block=64, npt=4),
+                                    dict(block=512, npt=2), dict(block=128, npt=2)])
+def test_2d_periodic_fp64_matches_oracle(launch):
+    case = smooth_random_2d(300, 40, seed=1)  # 300 = 256 + ragged 44
+    got, ref, S, _ = _compare(case, 150, **launch)
+    err = per_plane_rel(got, ref)
+    say(f"  max plane rel err {err:.3e}, bitwise equal: {np.array_equal(got, ref)}")
+    assert err <= TOL64
+
+
+@pytest.mark.parametrize("bc,inflow", [
+    (("inflow", "neumann", "wall", "wall"), {0: (1.2, 0.3, 0.0)}),
+    (("wall", "wall", "periodic", "periodic"), {}),
+    (("periodic", "periodic", "neumann", "inflow"), {3: (0.9, 0.05, -0.2)}),
+])
+def test_2d_boundaries_fp64_matches_oracle(bc, inflow):
+    case = smooth_random_2d(70, 50, seed=2, bc=bc, inflow=inflow)
+    got, ref, _, _ = _compare(case, 120)
+    err = per_plane_rel(got, ref)
+    say(f"  {bc}: max plane rel err {err:.3e}")
+    assert err <= TOL64
+
+
+def test_1d_dam_break_fp64_matches_oracle():
+    case = W.dam_break_1d(1000)  # 1D Riemann workload: 1000 nodes, 400 steps, Neumann ends
+    got, ref, _, _ = _compare(case, case.steps)
+    err = per_plane_rel(got, ref)
+    say(f"  max plane rel err {err:.3e}")
+    assert err <= TOL64
+
+
+@pytest.mark.parametrize("s", [1.5, 1.9])
+def test_1d_wall_reflection_fp64_matches_oracle(s):
+    case = W.wall_reflection_1d(8192, s=s, steps=3000)
+    got, ref, _, _ = _compare(case, 3000, npt=2)
+    err = per_plane_rel(got, ref)
+    say(f"  s={s}: max plane rel err {err:.3e}")
+    assert err <= TOL64
+
+
+def test_1d_periodic_ragged_fp64():
+    rng = np.random.default_rng(3)
+    n = 777
+    h = 1 + 0.2 * rng.random(n)
+    case = W.Case(1, n, 1, 3.0, 1.7, 0, bc=("periodic",) * 4, h0=h, qx0=0.1 * rng.standard_normal(n))
+    got, ref, S, P = _compare(case, 250, block=64, npt=4)
+    assert per_plane_rel(got, ref) <= TOL64
+    (hh, qq), tot = S.moments(totals=True)
+    assert abs(tot[0] - math.fsum(h)) <= 1e-13 * math.fsum(h)
+
+
+def test_moments_and_totals_match_oracle():
+    case = smooth_random_2d(300, 40, seed=4)
+    S = gpu_solver(case)
+    S.step(77)
+    (h, qx, qy), tot = S.moments(totals=True)
+    ref, P = orc_state(case, 77)
+    full = np.concatenate([np.zeros((1,) + ref.shape[1:]), ref])
+    oh, oqx, oqy = oracle.moments(P, full)
+    for a, b in ((h, oh), (qx, oqx), (qy, oqy)):
+        assert normwise_rel(to_np(a), b) <= TOL64
+    for k, (t, b) in enumerate(zip(tot, (case.h0, case.qx0, case.qy0))):
+        assert abs(t - math.fsum(b.ravel())) <= 1e-12 * (math.fsum(np.abs(b).ravel()) + 1)
+
+
+def test_graph_chunks_equal_single_launches():
+    """lbm_step(70) (two captured 32-step graphs + 6 launches) = 70 x lbm_step(1)."""
+    case = smooth_random_2d(128, 36, seed=5)
+    A = gpu_solver(case)
+    B = gpu_solver(case)
+    A.step(70)
+    for _ in range(70):
+        B.step(1)
+    assert np.array_equal(to_np(A.planes()), to_np(B.planes()))
+    A.step(3)  # odd offset: the graph for the other starting buffer
+    A.step(64)
+    B.step(67)
+    assert np.array_equal(to_np(A.planes()), to_np(B.planes()))
+
+
+def test_step_buffers_export_import_roundtrip():
+    case = smooth_random_2d(64, 64, seed=6)
+    S = gpu_solver(case)
+    a = S.new_state()
+    b = S.new_state()
+    S.export(a)
+    S.step_buffers(a, b)
+    S.step(1)
+    assert np.array_equal(to_np(S.planes()), to_np(S.planes(b)))
+    S.import_(a)
+    S.step(1)
+    assert np.array_equal(to_np(S.planes()), to_np(S.planes(b)))
+
+
+def test_fp32_storage_l1_error_2d():
+    case = W.radial_dam_break_2d(256, lam=6.0, steps=500)
+    got, ref, S, P = _compare(case, 500, storage="f32")
+    (h, _, _) = S.moments()
+    full = np.concatenate([np.zeros((1,) + ref.shape[1:]), ref])
+    oh = oracle.moments(P, full)[0]
+    e = l1_rel(to_np(h), oh)
+    say(f"  FP32 storage 256^2 x 500: L1 rel error of h = {e:.3e}")
+    assert e <= TOL32_L1
+
+
+def test_fp32_storage_l1_error_1d_wall():
+    case = W.wall_reflection_1d(8192, s=1.9, steps=20000)
+    got, ref, S, P = _compare(case, 20000, storage="f32")
+    h = to_np(S.moments()[0])
+    full = np.concatenate([np.zeros((1,) + ref.shape[1:]), ref])
+    oh = oracle.moments(P, full)[0]
+    e = l1_rel(h, oh)
+    say(f"  FP32 storage 1D wall reflection 8192 x 20000: L1 rel error of h = {e:.3e}")
+    assert e <= TOL32_L1
+
+
+def test_divergence_detected():
+    """The radial dam break at the stated lambda = 3 satisfies the D2Q4 bound at
+    rest (2 sqrt(2) < 3) but the flow it develops does not, and it blows up; the
+    periodic check reports it."""
+    from paper_1401_0427_amd.lbm import LbmError
+
+    case = W.radial_dam_break_2d(256, lam=3.0)
+    S = gpu_solver(case, check_every=25)
+    with pytest.raises(LbmError, match="diverged"):
+        S.step(2000)
+
+
+def test_subchar_warning():
+    """lambda below 2 max(|u| + sqrt(g h)) at t = 0 warns (context still usable)."""
+    case = W.radial_dam_break_2d(64, lam=2.5)
+    with pytest.warns(RuntimeWarning, match="monotonicity bound"):
+        S = gpu_solver(case)
+    S.step(1)
+
+
+def test_init_rejects_nonpositive_depth():
+    from paper_1401_0427_amd.lbm import LbmError
+
+    case = smooth_random_2d(40, 40, seed=7)
+    case.h0[3, 5] = 0.0
+    with pytest.raises(LbmError, match="h > 0"):
+        gpu_solver(case)
