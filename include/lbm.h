@@ -88,6 +88,9 @@ typedef struct {
     int block;            /* threads per workgroup: 64, 128, 256 (default), 512 */
     int nodes_per_thread; /* 1 (default), 2 or 4 nodes per thread along x */
     long plane_pad;       /* extra elements between planes; < 0 = library default */
+    int mem_hints;        /* bit 0: non-temporal loads, bit 1: non-temporal stores,
+                             bit 2: plain workgroup order (no XCD-aware tile remap);
+                             < 0 = library default */
     void *f_a, *f_b;      /* caller-owned device state buffers (ping-pong) */
     void *stream;         /* hipStream_t; NULL = default stream */
 } lbm_params;
@@ -171,9 +174,10 @@ typedef struct {
 } lbm_instance;
 
 typedef struct {
-    int block;            /* threads per workgroup (64..1024, multiple of 64) */
+    int block;            /* threads per workgroup (64..512, multiple of 64) */
     int tile_nodes;       /* target nodes per work tile (>= block) */
     int grid;             /* persistent workgroups; 0 = fill the device */
+    int pass_nodes;       /* nodes per thread per pass: 1 or 2 (0 = 1) */
 } lbm_batch_tuning;
 
 /* Assign state_offset / node_offset to n instances (in place) for the given
@@ -193,6 +197,11 @@ int lbm_batch_init(lbm_batch *b, const double *h0, const double *qx0, const doub
  * from a captured HIP graph).  Tiles of each instance advance as soon as their
  * neighbours have finished the previous step; no grid-wide barrier. */
 int lbm_batch_run(lbm_batch *b, long nsteps);
+
+/* Synchronise the stream and report whether the last run completed: the
+ * persistent kernel bounds every dependency wait and, past that bound, stops
+ * all workgroups and flags the run (then LBM_EDEVICE; the state is invalid). */
+int lbm_batch_check(lbm_batch *b);
 
 /* Packed conserved fields of every instance (device doubles, may be NULL). */
 int lbm_batch_moments(lbm_batch *b, double *h, double *qx, double *qy);

@@ -324,10 +324,11 @@ int orc_advance(const orc_params *P, double *fstar, long nsteps)
                 feq_node_d(P, Win, feq_in + face * ORC_NPMAX);
             }
 #pragma omp parallel for schedule(static)
-        for (int y = 0; y < P->ny; ++y)
-            for (int x = 0; x < P->nx; ++x)
-                for (int q = 0; q < np; ++q)
-                    pre.p[q][(long)y * P->nx + x] = pull_d(P, cur.p, feq_in, q, x, y);
+        for (long i = 0; i < n; ++i) {
+            const int y = (int)(i / P->nx), x = (int)(i % P->nx);
+            for (int q = 0; q < np; ++q)
+                pre.p[q][i] = pull_d(P, cur.p, feq_in, q, x, y);
+        }
         collide_field(P, P->s, &pre, &cur);
     }
     field_free(&pre);

@@ -1,0 +1,148 @@
+"""Project autotuner: picks launch shapes by timing them on the device.
+
+* ``tune_forward``: workgroup size, nodes per thread, plane padding and memory
+  hints of the fused stream + collide kernel for one grid and storage type.
+* ``tune_batch``: workgroup size and tile size (and optionally the persistent
+  grid) of the batched launch for a manifest.
+
+Results are cached in ``paper_1401_0427_amd/tuning.json`` (read by bench.py):
+    {"forward": {"f64": {...}, "f32": {...}}, "batch": {...}, "sweeps": {...}}
+Run on a GPU:  python -m paper_1401_0427_amd.autotune [--steps 60]
+"""
+from __future__ import annotations
+
+import argparse
+import itertools
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(HERE, "tuning.json")
+
+
+def _timer(torch):
+    st = torch.cuda.current_stream()
+
+    def run(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(st)
+        fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    return run
+
+
+def tune_forward(n=4096, storage="f64", steps=60, blocks=(128, 256, 512), npts=(1, 2),
+                 pads=(0, 2048), hints=(2, 6), log=print):
+    import torch
+
+    from . import workloads as W
+    from .lbm import Solver
+
+    timer = _timer(torch)
+    c = W.radial_dam_break_2d(n, lam=6.0)
+    h0 = torch.as_tensor(c.h0, device="cuda")
+    z = torch.zeros_like(h0)
+    bpl = 192 if storage == "f64" else 96
+    rows = []
+    for block, npt, pad, hint in itertools.product(blocks, npts, pads, hints):
+        S = Solver(2, n, n, lam=c.lam, s=c.s, h0=h0, qx0=z, qy0=z, storage=storage, block=block,
+                   npt=npt, plane_pad=pad, mem_hints=hint)
+        S.step(4)
+        ms = timer(lambda: S.step(steps)) / steps
+        del S
+        torch.cuda.empty_cache()
+        r = dict(block=block, npt=npt, plane_pad=pad, mem_hints=hint, ms=ms,
+                 gbs=n * n * bpl / ms / 1e6)
+        rows.append(r)
+        log(json.dumps(r))
+    best = max(rows, key=lambda r: r["gbs"])
+    return best, rows
+
+
+def _manifest_dicts(man):
+    from . import workloads as W
+
+    out = []
+    for m in man:
+        h, qx, qy = m.initial()
+        bc = ("neumann", "neumann", "periodic", "periodic") if m.dim == 1 else ("periodic",) * 4
+        out.append(dict(dim=m.dim, nx=m.nx, ny=m.ny, lam=m.lam, s=m.s, g=W.G, bc=bc, h0=h,
+                        qx0=qx, qy0=qy))
+    return out
+
+
+def tune_batch(seed=0, steps=100, blocks=(256, 512), tiles=(4096, 8192, 16384, 32768),
+               grids=(0,), passes=(1, 2), storage="f32", log=print):
+    import torch
+
+    from . import workloads as W
+    from .lbm import Batch
+
+    timer = _timer(torch)
+    insts = _manifest_dicts(W.batched_manifest(seed))
+    rows = []
+    for block, tile, grid, npp in itertools.product(blocks, tiles, grids, passes):
+        if tile < block:
+            continue
+        B = Batch(insts, storage=storage, block=block, tile_nodes=tile, grid=grid, pass_nodes=npp)
+        B.run(4, check_done=True)
+        ms = timer(lambda: B.run(steps))
+        B.check()
+        nt, gr = B.info()
+        r = dict(block=block, tile_nodes=tile, grid=grid, pass_nodes=npp, grid_used=gr, tiles=nt,
+                 ms_per_step=ms / steps, mlups=B.nodes * steps / (ms * 1e-3) / 1e6)
+        del B
+        torch.cuda.empty_cache()
+        rows.append(r)
+        log(json.dumps(r))
+    best = max(rows, key=lambda r: r["mlups"])
+    return best, rows
+
+
+def save(update: dict):
+    data = json.load(open(CACHE)) if os.path.exists(CACHE) else {}
+    for k, v in update.items():
+        if isinstance(v, dict) and isinstance(data.get(k), dict):
+            data[k].update(v)
+        else:
+            data[k] = v
+    with open(CACHE, "w") as fh:
+        json.dump(data, fh, indent=1)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--skip-forward", action="store_true")
+    ap.add_argument("--skip-batch", action="store_true")
+    args = ap.parse_args()
+
+    def log(s):
+        print(s, flush=True)
+
+    out = {}
+    if not args.skip_forward:
+        fw = {}
+        sweeps = {}
+        for storage in ("f64", "f32"):
+            best, rows = tune_forward(storage=storage, steps=args.steps, log=log)
+            fw[storage] = {k: best[k] for k in ("block", "npt", "plane_pad", "mem_hints")}
+            fw[storage]["gbs"] = round(best["gbs"], 1)
+            sweeps["forward_" + storage] = rows
+        out["forward"] = fw
+        out["sweeps"] = sweeps
+    if not args.skip_batch:
+        best, rows = tune_batch(steps=args.steps, log=log)
+        out["batch"] = {k: best[k] for k in ("block", "tile_nodes", "grid", "pass_nodes")}
+        out.setdefault("sweeps", {})["batch"] = rows
+    save(out)
+    log(json.dumps({"saved": CACHE, "forward": out.get("forward"), "batch": out.get("batch")}))
+
+
+if __name__ == "__main__":
+    sys.exit(main())

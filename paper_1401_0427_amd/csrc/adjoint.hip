@@ -45,7 +45,7 @@ __global__ void __launch_bounds__(256) k_adj2d(const T *__restrict__ un,
                                                int tiles_x, int ntiles)
 {
     __shared__ double sh[256];
-    const int t = xcd_tile(blockIdx.x, ntiles);
+    const int t = xcd_tile(blockIdx.x, ntiles, false);  // plain order measured faster
     const int y = t / tiles_x;
     const int x = (t - y * tiles_x) * 256 + threadIdx.x;
     const int nx = G.nx, ny = G.ny;
@@ -78,10 +78,10 @@ __global__ void __launch_bounds__(256) k_adj2d(const T *__restrict__ un,
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             T *b = lam0 + (4 * k) * ps;
-            st(b + row + xm, oms * l[4 * k + 0] + P.s * mu[k]);
-            st(b + ps + rm + x, oms * l[4 * k + 1] + P.s * mu[k]);
-            st(b + 2 * ps + row + xp, oms * l[4 * k + 2] + P.s * mu[k]);
-            st(b + 3 * ps + rp + x, oms * l[4 * k + 3] + P.s * mu[k]);
+            sth<2>(b + row + xm, oms * l[4 * k + 0] + P.s * mu[k]);
+            sth<2>(b + ps + rm + x, oms * l[4 * k + 1] + P.s * mu[k]);
+            sth<2>(b + 2 * ps + row + xp, oms * l[4 * k + 2] + P.s * mu[k]);
+            sth<2>(b + 3 * ps + rp + x, oms * l[4 * k + 3] + P.s * mu[k]);
         }
     }
     sh[threadIdx.x] = acc;

@@ -17,8 +17,8 @@
 //   whatever the number of resident workgroups.  There is no grid-wide
 //   barrier: fast regions run ahead of slow ones by as many steps as their
 //   neighbourhoods allow.  Completion of (n, t) is published by a per-tile
-//   counter with agent-scope release / acquire, after every wave of the
-//   workgroup has made its stores visible at agent scope.
+//   counter: one agent-scope release store after a workgroup barrier, and one
+//   agent-scope acquire fence after the consumer's relaxed polls succeed.
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -46,112 +46,182 @@ struct TileDev {
     int nb0, nb1;    // neighbour tiles (-1: none)
 };
 
-__device__ __forceinline__ int wait_ge(int *done, int t, int n)
+// Spin (one lane) until tile t has completed n steps.  Polls are relaxed
+// agent-scope loads (they read the coherent copy without invalidating any
+// cache); the caller issues one acquire fence once every wait has succeeded.
+// The wait is bounded: after kSpinLimit polls, or once any workgroup has raised
+// the abort flag, it gives up and raises the flag, so every wave of the launch
+// always reaches the kernel's exit.  Returns 1 when aborting.
+static constexpr int kSpinLimit = 1 << 22;
+
+__device__ __forceinline__ int wait_ge(int *done, int t, int n, int *abort_flag)
 {
     if (t < 0) return 0;
-    while (__hip_atomic_load(done + t, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < n)
+    for (int k = 0;; ++k) {
+        if (__hip_atomic_load(done + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= n) return 0;
+        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return 1;
+        if (k >= kSpinLimit) {
+            __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return 1;
+        }
         __builtin_amdgcn_s_sleep(1);
-    return 0;
+    }
 }
 
+// One node of a 2D instance: pull (periodic fast path or boundary rules).
 template <typename T>
+__device__ __forceinline__ void pull_node2d(const T *__restrict__ s, const InstDev &I, int x, int y,
+                                            double *f)
+{
+    const int nx = I.G.nx, ny = I.G.ny;
+    const long ps = I.G.ps;
+    const bool interior = x > 0 && x < nx - 1 && y > 0 && y < ny - 1;
+    if (I.allper || interior) {
+        const long row = (long)y * nx;
+        const int xm = x == 0 ? nx - 1 : x - 1;
+        const int xp = x == nx - 1 ? 0 : x + 1;
+        const long rm = y == 0 ? (long)(ny - 1) * nx : row - nx;
+        const long rp = y == ny - 1 ? 0 : row + nx;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const T *b = s + (4 * c) * ps;
+            f[4 * c + 0] = ld(b + row + xm);
+            f[4 * c + 1] = ld(b + ps + rm + x);
+            f[4 * c + 2] = ld(b + 2 * ps + row + xp);
+            f[4 * c + 3] = ld(b + 3 * ps + rp + x);
+        }
+    } else {
+        pull2d_generic(s, I.G, I.P, x, y, f);
+    }
+}
+
+// Tiles: with NPP = 2 each thread takes two nodes per pass (both pulls issued
+// before either collision) for more loads in flight per thread, at the price
+// of registers (occupancy); NPP is a tuning choice.
+template <typename T, int NPP>
 __device__ __forceinline__ void tile_1d(const T *__restrict__ src, T *__restrict__ dst,
                                         const InstDev &I, int b, int e)
 {
     const T *s = src + I.off;
     T *d = dst + I.off;
-    for (int x = b + (int)threadIdx.x; x < e; x += blockDim.x) {
-        double f[4];
+    const int B = blockDim.x;
+    for (int x = b + (int)threadIdx.x; x < e; x += NPP * B) {
+        const int x2 = x + B;
+        const bool two = NPP == 2 && x2 < e;
+        double f[4], g[4];
         pull1d(s, I.G, I.P, x, f);
+        if (two) pull1d(s, I.G, I.P, x2, g);
         collide1d(f, I.P);
 #pragma unroll
-        for (int pl = 0; pl < 4; ++pl) st(d + pl * I.G.ps + x, f[pl]);
+        for (int pl = 0; pl < 4; ++pl) sth<2>(d + pl * I.G.ps + x, f[pl]);
+        if (two) {
+            collide1d(g, I.P);
+#pragma unroll
+            for (int pl = 0; pl < 4; ++pl) sth<2>(d + pl * I.G.ps + x2, g[pl]);
+        }
     }
 }
 
-template <typename T>
+template <typename T, int NPP>
 __device__ __forceinline__ void tile_2d(const T *__restrict__ src, T *__restrict__ dst,
                                         const InstDev &I, int r0, int r1)
 {
     const T *s = src + I.off;
     T *d = dst + I.off;
-    const int nx = I.G.nx, ny = I.G.ny;
+    const int nx = I.G.nx;
     const long ps = I.G.ps;
     const int cnt = (r1 - r0) * nx;
-    for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
-        const int y = r0 + k / nx;
-        const int x = k - (y - r0) * nx;
-        double f[12];
-        const bool interior = x > 0 && x < nx - 1 && y > 0 && y < ny - 1;
-        if (I.allper || interior) {
-            const long row = (long)y * nx;
-            const int xm = x == 0 ? nx - 1 : x - 1;
-            const int xp = x == nx - 1 ? 0 : x + 1;
-            const long rm = y == 0 ? (long)(ny - 1) * nx : row - nx;
-            const long rp = y == ny - 1 ? 0 : row + nx;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const T *b = s + (4 * c) * ps;
-                f[4 * c + 0] = ld(b + row + xm);
-                f[4 * c + 1] = ld(b + ps + rm + x);
-                f[4 * c + 2] = ld(b + 2 * ps + row + xp);
-                f[4 * c + 3] = ld(b + 3 * ps + rp + x);
-            }
-        } else {
-            pull2d_generic(s, I.G, I.P, x, y, f);
-        }
+    const int B = blockDim.x;
+    for (int k = threadIdx.x; k < cnt; k += NPP * B) {
+        const int k2 = k + B;
+        const bool two = NPP == 2 && k2 < cnt;
+        const int y = r0 + k / nx, x = k - (y - r0) * nx;
+        const int y2 = r0 + k2 / nx, x2 = k2 - (y2 - r0) * nx;
+        double f[12], g[12];
+        pull_node2d(s, I, x, y, f);
+        if (two) pull_node2d(s, I, x2, y2, g);
         collide2d(f, I.P);
         T *o = d + (long)y * nx + x;
 #pragma unroll
-        for (int pl = 0; pl < 12; ++pl) st(o + pl * ps, f[pl]);
+        for (int pl = 0; pl < 12; ++pl) sth<2>(o + pl * ps, f[pl]);
+        if (two) {
+            collide2d(g, I.P);
+            T *o2 = d + (long)y2 * nx + x2;
+#pragma unroll
+            for (int pl = 0; pl < 12; ++pl) sth<2>(o2 + pl * ps, g[pl]);
+        }
     }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(1024)
+// 64-bit value of lane 0, as a wave-uniform (scalar) value.
+__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v)
+{
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// The loop's control flow is uniform by construction: the work index is read
+// from LDS into a scalar register (readfirstlane), so the exit is a scalar
+// branch, and a barrier separates the release store of one item from the
+// dequeue of the next, so no lane-0-only code spans the loop's back edge.
+template <typename T, int NPP>
+__global__ void __launch_bounds__(512)
     k_batch(const InstDev *__restrict__ inst, const TileDev *__restrict__ tiles, int ntiles,
             unsigned long long nitems, int *done, unsigned long long *next, T *buf0, T *buf1,
-            int cur)
+            int cur, int *abort_flag)
 {
     __shared__ unsigned long long item;
+    __shared__ int stop;
     for (;;) {
-        if (threadIdx.x == 0) item = atomicAdd(next, 1ull);
+        if (threadIdx.x == 0) {
+            item = atomicAdd(next, 1ull);
+            stop = __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         __syncthreads();
-        const unsigned long long w = item;
-        __syncthreads();
-        if (w >= nitems) break;
+        const unsigned long long w = uniform_u64(item);
+        if (w >= nitems || __builtin_amdgcn_readfirstlane(stop) != 0) break;
         const int n = (int)(w / (unsigned long long)ntiles);
         const int t = (int)(w - (unsigned long long)n * ntiles);
         const TileDev td = tiles[t];
         if (threadIdx.x == 0) {
-            wait_ge(done, t, n);
-            wait_ge(done, td.nb0, n);
-            wait_ge(done, td.nb1, n);
+            int a = wait_ge(done, t, n, abort_flag);
+            if (!a) a = wait_ge(done, td.nb0, n, abort_flag);
+            if (!a) a = wait_ge(done, td.nb1, n, abort_flag);
+            stop = a;
+            // one acquire for all three waits: later loads of this workgroup see
+            // the neighbours' step n-1 results
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         __syncthreads();
+        if (__builtin_amdgcn_readfirstlane(stop) != 0) break;
         const InstDev I = inst[td.inst];
         const bool odd = ((cur + n) & 1) != 0;
         const T *src = odd ? buf1 : buf0;
         T *dst = odd ? buf0 : buf1;
         if (I.dim == 1)
-            tile_1d(src, dst, I, td.begin, td.end);
+            tile_1d<T, NPP>(src, dst, I, td.begin, td.end);
         else
-            tile_2d(src, dst, I, td.begin, td.end);
-        // every wave publishes its own stores at agent scope, then one release
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            tile_2d<T, NPP>(src, dst, I, td.begin, td.end);
+        // the barrier orders every wave's stores before thread 0's agent-scope
+        // release (fence cumulativity), which publishes the tile's completion
         __syncthreads();
         if (threadIdx.x == 0)
             __hip_atomic_store(done + t, n + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
     }
 }
 
 // Zero the per-tile counters and the work counter (a kernel, so that it can sit
 // in a captured graph).
-__global__ void k_batch_reset(int *done, int ntiles, unsigned long long *next)
+__global__ void k_batch_reset(int *done, int ntiles, unsigned long long *next, int *abort_flag)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < ntiles) done[i] = 0;
-    if (i == 0) *next = 0ull;
+    if (i == 0) {
+        *next = 0ull;
+        *abort_flag = 0;
+    }
 }
 
 } // namespace lbm
@@ -193,6 +263,7 @@ struct lbm_batch {
     TileDev *d_tiles;
     int *d_done;
     unsigned long long *d_next;
+    int *d_abort;
     int grid;
     // one captured graph per (nsteps, starting buffer); the last one is kept
     hipGraphExec_t gexec;
@@ -239,6 +310,7 @@ extern "C" void lbm_batch_destroy(lbm_batch *b)
     (void)hipFree(b->d_tiles);
     (void)hipFree(b->d_done);
     (void)hipFree(b->d_next);
+    (void)hipFree(b->d_abort);
     delete b;
 }
 
@@ -269,10 +341,13 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
                 return bfail(LBM_EINVAL, "instance %d: inflow h must be > 0", i);
         }
     }
-    lbm_batch_tuning tune = {256, 4096, 0};
+    lbm_batch_tuning tune = {256, 16384, 0, 1};
     if (tuning) tune = *tuning;
-    if (tune.block < 64 || tune.block > 1024 || tune.block % 64)
-        return bfail(LBM_EINVAL, "tuning.block must be a multiple of 64 in [64, 1024]");
+    if (tune.pass_nodes == 0) tune.pass_nodes = 1;
+    if (tune.pass_nodes != 1 && tune.pass_nodes != 2)
+        return bfail(LBM_EINVAL, "tuning.pass_nodes must be 1 or 2");
+    if (tune.block < 64 || tune.block > 512 || tune.block % 64)
+        return bfail(LBM_EINVAL, "tuning.block must be a multiple of 64 in [64, 512]");
     if (tune.tile_nodes < tune.block) return bfail(LBM_EINVAL, "tuning.tile_nodes < block");
     if (tune.grid < 0) return bfail(LBM_EINVAL, "tuning.grid must be >= 0");
 
@@ -355,6 +430,8 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
         (e = hipMalloc(&b->d_tiles, sizeof(TileDev) * ht.size())) != hipSuccess ||
         (e = hipMalloc(&b->d_done, sizeof(int) * ht.size())) != hipSuccess ||
         (e = hipMalloc(&b->d_next, sizeof(unsigned long long))) != hipSuccess ||
+        (e = hipMalloc(&b->d_abort, sizeof(int))) != hipSuccess ||
+        (e = hipMemset(b->d_abort, 0, sizeof(int))) != hipSuccess ||
         (e = hipMemcpy(b->d_inst, hi.data(), sizeof(InstDev) * n, hipMemcpyHostToDevice)) !=
             hipSuccess ||
         (e = hipMemcpy(b->d_tiles, ht.data(), sizeof(TileDev) * ht.size(),
@@ -366,10 +443,14 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
     int dev = 0, ncu = 0, per_cu = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (b->f32)
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<float>, tune.block, 0);
+    if (b->f32 && tune.pass_nodes == 2)
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<float, 2>, tune.block, 0);
+    else if (b->f32)
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<float, 1>, tune.block, 0);
+    else if (tune.pass_nodes == 2)
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<double, 2>, tune.block, 0);
     else
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<double>, tune.block, 0);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<double, 1>, tune.block, 0);
     if (ncu <= 0) ncu = 256;
     if (per_cu <= 0) per_cu = 1;
     b->grid = tune.grid > 0 ? tune.grid : ncu * per_cu;
@@ -390,7 +471,7 @@ extern "C" int lbm_batch_init(lbm_batch *b, const double *h0, const double *qx0,
         (void)hipFree(d_speed);
         return bfail(LBM_EDEVICE, "hipMalloc failed: %s", hipGetErrorString(e));
     }
-    Launch L = {256, 1};
+    Launch L = {256, 1, 0};
     for (size_t i = 0; i < b->inst.size() && e == hipSuccess; ++i) {
         const lbm_instance &I = b->inst[i];
         const int dim = I.lattice == LBM_D1Q2x2 ? 1 : 2;
@@ -420,16 +501,21 @@ static hipError_t enqueue_run(lbm_batch *b, long nsteps, hipStream_t st)
 {
     const int rb = (b->ntiles + 255) / 256;
     hipLaunchKernelGGL(k_batch_reset, dim3(rb), dim3(256), 0, st, b->d_done, b->ntiles,
-                       b->d_next);
+                       b->d_next, b->d_abort);
     const unsigned long long nitems = (unsigned long long)nsteps * (unsigned long long)b->ntiles;
-    if (b->f32)
-        hipLaunchKernelGGL(k_batch<float>, dim3(b->grid), dim3(b->tune.block), 0, st, b->d_inst,
-                           b->d_tiles, b->ntiles, nitems, b->d_done, b->d_next,
-                           (float *)b->buf[0], (float *)b->buf[1], b->cur);
+#define LBM_BATCH_LAUNCH(TT, NP)                                                               \
+    hipLaunchKernelGGL((k_batch<TT, NP>), dim3(b->grid), dim3(b->tune.block), 0, st, b->d_inst, \
+                       b->d_tiles, b->ntiles, nitems, b->d_done, b->d_next, (TT *)b->buf[0],    \
+                       (TT *)b->buf[1], b->cur, b->d_abort)
+    if (b->f32 && b->tune.pass_nodes == 2)
+        LBM_BATCH_LAUNCH(float, 2);
+    else if (b->f32)
+        LBM_BATCH_LAUNCH(float, 1);
+    else if (b->tune.pass_nodes == 2)
+        LBM_BATCH_LAUNCH(double, 2);
     else
-        hipLaunchKernelGGL(k_batch<double>, dim3(b->grid), dim3(b->tune.block), 0, st,
-                           b->d_inst, b->d_tiles, b->ntiles, nitems, b->d_done, b->d_next,
-                           (double *)b->buf[0], (double *)b->buf[1], b->cur);
+        LBM_BATCH_LAUNCH(double, 1);
+#undef LBM_BATCH_LAUNCH
     return hipGetLastError();
 }
 
@@ -465,6 +551,18 @@ extern "C" int lbm_batch_run(lbm_batch *b, long nsteps)
     BHIP(hipGraphLaunch(b->gexec, b->st));
     b->steps += nsteps;
     b->cur = (int)((b->cur + nsteps) & 1);
+    return LBM_OK;
+}
+
+extern "C" int lbm_batch_check(lbm_batch *b)
+{
+    if (!b) return bfail(LBM_ESTATE, "null batch");
+    int flag = 0;
+    BHIP(hipMemcpyAsync(&flag, b->d_abort, sizeof flag, hipMemcpyDeviceToHost, b->st));
+    BHIP(hipStreamSynchronize(b->st));
+    if (flag)
+        return bfail(LBM_EDEVICE, "batched run aborted: a tile dependency was not satisfied "
+                                  "within the scheduler's wait limit (state is invalid)");
     return LBM_OK;
 }
 

@@ -14,11 +14,12 @@
 namespace lbm {
 
 // ------------------------------------------------------------------ 2D step ----
-template <typename T, bool ALLPER, int NPT>
+template <typename T, bool ALLPER, int NPT, int H>
 __global__ void __launch_bounds__(512) k_step2d(const T *__restrict__ src, T *__restrict__ dst,
-                                                Geo G, Phys P, int tiles_x, int ntiles)
+                                                Geo G, Phys P, int tiles_x, int ntiles,
+                                                int remap)
 {
-    const int t = xcd_tile(blockIdx.x, ntiles);
+    const int t = xcd_tile(blockIdx.x, ntiles, remap != 0);
     const int y = t / tiles_x;
     const int tx = t - y * tiles_x;
     const int xb = tx * (int)(blockDim.x * NPT) + threadIdx.x;
@@ -40,10 +41,10 @@ __global__ void __launch_bounds__(512) k_step2d(const T *__restrict__ src, T *__
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const T *b = src + (4 * k) * ps;
-                f[i][4 * k + 0] = ld(b + row + xm);
-                f[i][4 * k + 1] = ld(b + ps + rm + x);
-                f[i][4 * k + 2] = ld(b + 2 * ps + row + xp);
-                f[i][4 * k + 3] = ld(b + 3 * ps + rp + x);
+                f[i][4 * k + 0] = ldh<H>(b + row + xm);
+                f[i][4 * k + 1] = ldh<H>(b + ps + rm + x);
+                f[i][4 * k + 2] = ldh<H>(b + 2 * ps + row + xp);
+                f[i][4 * k + 3] = ldh<H>(b + 3 * ps + rp + x);
             }
         } else {
             pull2d_generic(src, G, P, x, y, f[i]);
@@ -56,16 +57,16 @@ __global__ void __launch_bounds__(512) k_step2d(const T *__restrict__ src, T *__
         collide2d(f[i], P);
         T *o = dst + row + x;
 #pragma unroll
-        for (int pl = 0; pl < 12; ++pl) st(o + pl * ps, f[i][pl]);
+        for (int pl = 0; pl < 12; ++pl) sth<H>(o + pl * ps, f[i][pl]);
     }
 }
 
 // ------------------------------------------------------------------ 1D step ----
-template <typename T, int NPT>
+template <typename T, int NPT, int H>
 __global__ void __launch_bounds__(512) k_step1d(const T *__restrict__ src, T *__restrict__ dst,
-                                                Geo G, Phys P, int ntiles)
+                                                Geo G, Phys P, int ntiles, int remap)
 {
-    const int t = xcd_tile(blockIdx.x, ntiles);
+    const int t = xcd_tile(blockIdx.x, ntiles, remap != 0);
     const int xb = t * (int)(blockDim.x * NPT) + threadIdx.x;
     const long ps = G.ps;
     double f[NPT][4];
@@ -81,7 +82,7 @@ __global__ void __launch_bounds__(512) k_step1d(const T *__restrict__ src, T *__
         if (x >= G.nx) continue;
         collide1d(f[i], P);
 #pragma unroll
-        for (int pl = 0; pl < 4; ++pl) st(dst + pl * ps + x, f[i][pl]);
+        for (int pl = 0; pl < 4; ++pl) sth<H>(dst + pl * ps + x, f[i][pl]);
     }
 }
 
@@ -235,49 +236,67 @@ hipError_t launch_init(int dim, bool f32, void *dst, const double *h0, const dou
     return hipGetLastError();
 }
 
-template <typename T, int NPT>
-static void step2d_npt(bool allper, const void *src, void *dst, const Geo &G, const Phys &P,
-                       int block, hipStream_t st)
+template <typename T, int NPT, int H>
+static void step2d_h(bool allper, const void *src, void *dst, const Geo &G, const Phys &P,
+                     const Launch &L, hipStream_t st)
 {
-    const int span = block * NPT;
+    const int span = L.block * NPT;
     const int tiles_x = (G.nx + span - 1) / span;
     const int ntiles = tiles_x * G.ny;
+    const int remap = (L.hints & 4) ? 0 : 1;
     if (allper)
-        hipLaunchKernelGGL((k_step2d<T, true, NPT>), dim3(ntiles), dim3(block), 0, st,
-                           (const T *)src, (T *)dst, G, P, tiles_x, ntiles);
+        hipLaunchKernelGGL((k_step2d<T, true, NPT, H>), dim3(ntiles), dim3(L.block), 0, st,
+                           (const T *)src, (T *)dst, G, P, tiles_x, ntiles, remap);
     else
-        hipLaunchKernelGGL((k_step2d<T, false, NPT>), dim3(ntiles), dim3(block), 0, st,
-                           (const T *)src, (T *)dst, G, P, tiles_x, ntiles);
+        hipLaunchKernelGGL((k_step2d<T, false, NPT, 0>), dim3(ntiles), dim3(L.block), 0, st,
+                           (const T *)src, (T *)dst, G, P, tiles_x, ntiles, remap);
+}
+
+template <typename T, int NPT, int H>
+static void step1d_h(const void *src, void *dst, const Geo &G, const Phys &P, const Launch &L,
+                     hipStream_t st)
+{
+    const int span = L.block * NPT;
+    const int ntiles = (G.nx + span - 1) / span;
+    const int remap = (L.hints & 4) ? 0 : 1;
+    hipLaunchKernelGGL((k_step1d<T, NPT, H>), dim3(ntiles), dim3(L.block), 0, st,
+                       (const T *)src, (T *)dst, G, P, ntiles, remap);
 }
 
 template <typename T, int NPT>
-static void step1d_npt(const void *src, void *dst, const Geo &G, const Phys &P, int block,
-                       hipStream_t st)
+static void step_npt(int dim, bool allper, const void *src, void *dst, const Geo &G,
+                     const Phys &P, const Launch &L, hipStream_t st)
 {
-    const int span = block * NPT;
-    const int ntiles = (G.nx + span - 1) / span;
-    hipLaunchKernelGGL((k_step1d<T, NPT>), dim3(ntiles), dim3(block), 0, st, (const T *)src,
-                       (T *)dst, G, P, ntiles);
+    switch (L.hints & 3) {
+    case 1:
+        dim == 2 ? step2d_h<T, NPT, 1>(allper, src, dst, G, P, L, st)
+                 : step1d_h<T, NPT, 1>(src, dst, G, P, L, st);
+        break;
+    case 2:
+        dim == 2 ? step2d_h<T, NPT, 2>(allper, src, dst, G, P, L, st)
+                 : step1d_h<T, NPT, 2>(src, dst, G, P, L, st);
+        break;
+    case 3:
+        dim == 2 ? step2d_h<T, NPT, 3>(allper, src, dst, G, P, L, st)
+                 : step1d_h<T, NPT, 3>(src, dst, G, P, L, st);
+        break;
+    default:
+        dim == 2 ? step2d_h<T, NPT, 0>(allper, src, dst, G, P, L, st)
+                 : step1d_h<T, NPT, 0>(src, dst, G, P, L, st);
+        break;
+    }
 }
 
 template <typename T>
 static void step_t(int dim, const void *src, void *dst, const Geo &G, const Phys &P,
                    const Launch &L, hipStream_t st)
 {
-    if (dim == 2) {
-        const bool allper = G.bc[0] == BC_PERIODIC && G.bc[1] == BC_PERIODIC &&
-                            G.bc[2] == BC_PERIODIC && G.bc[3] == BC_PERIODIC;
-        switch (L.npt) {
-        case 2: step2d_npt<T, 2>(allper, src, dst, G, P, L.block, st); break;
-        case 4: step2d_npt<T, 4>(allper, src, dst, G, P, L.block, st); break;
-        default: step2d_npt<T, 1>(allper, src, dst, G, P, L.block, st); break;
-        }
-    } else {
-        switch (L.npt) {
-        case 2: step1d_npt<T, 2>(src, dst, G, P, L.block, st); break;
-        case 4: step1d_npt<T, 4>(src, dst, G, P, L.block, st); break;
-        default: step1d_npt<T, 1>(src, dst, G, P, L.block, st); break;
-        }
+    const bool allper = G.bc[0] == BC_PERIODIC && G.bc[1] == BC_PERIODIC &&
+                        G.bc[2] == BC_PERIODIC && G.bc[3] == BC_PERIODIC;
+    switch (L.npt) {
+    case 2: step_npt<T, 2>(dim, allper, src, dst, G, P, L, st); break;
+    case 4: step_npt<T, 4>(dim, allper, src, dst, G, P, L, st); break;
+    default: step_npt<T, 1>(dim, allper, src, dst, G, P, L, st); break;
     }
 }
 

@@ -12,6 +12,7 @@ namespace lbm {
 struct Launch {
     int block;  // threads per workgroup
     int npt;    // nodes per thread along x
+    int hints;  // bit 0 non-temporal loads, bit 1 non-temporal stores, bit 2 no XCD remap
 };
 
 // Kernel launchers (each returns the hipError_t of the launch).

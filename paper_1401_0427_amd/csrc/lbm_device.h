@@ -21,6 +21,32 @@ __device__ __forceinline__ double ld(const float *p) { return (double)*p; }
 __device__ __forceinline__ void st(double *p, double v) { *p = v; }
 __device__ __forceinline__ void st(float *p, double v) { *p = (float)v; }
 
+// Loads / stores with optional non-temporal hints (H bit 0: loads, bit 1: stores).
+template <int H>
+__device__ __forceinline__ double ldh(const double *p)
+{
+    if constexpr ((H & 1) != 0) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <int H>
+__device__ __forceinline__ double ldh(const float *p)
+{
+    if constexpr ((H & 1) != 0) return (double)__builtin_nontemporal_load(p);
+    else return (double)*p;
+}
+template <int H>
+__device__ __forceinline__ void sth(double *p, double v)
+{
+    if constexpr ((H & 2) != 0) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+template <int H>
+__device__ __forceinline__ void sth(float *p, double v)
+{
+    if constexpr ((H & 2) != 0) __builtin_nontemporal_store((float)v, p);
+    else *p = (float)v;
+}
+
 // ---- physics constants of one problem -----------------------------------------
 struct Phys {
     double c;   // 1 / (2 lambda)
@@ -99,9 +125,9 @@ __device__ __forceinline__ void collide2d(double *f, const Phys &P)
 // XCD b % 8).  Remapping b -> (b % 8) * (T / 8) + b / 8 gives each XCD one
 // contiguous range of tiles, so the cache lines shared by neighbouring tiles
 // (the x-shifted pulls) stay in one XCD's L2.
-__device__ __forceinline__ int xcd_tile(int b, int ntiles)
+__device__ __forceinline__ int xcd_tile(int b, int ntiles, bool remap = true)
 {
-    if ((ntiles & 7) != 0) return b;
+    if (!remap || (ntiles & 7) != 0) return b;
     return (b & 7) * (ntiles >> 3) + (b >> 3);
 }
 

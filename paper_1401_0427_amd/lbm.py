@@ -46,6 +46,7 @@ class LbmParams(ctypes.Structure):
         ("block", ctypes.c_int),
         ("nodes_per_thread", ctypes.c_int),
         ("plane_pad", ctypes.c_long),
+        ("mem_hints", ctypes.c_int),
         ("f_a", ctypes.c_void_p),
         ("f_b", ctypes.c_void_p),
         ("stream", ctypes.c_void_p),
@@ -68,7 +69,8 @@ class LbmInstance(ctypes.Structure):
 
 
 class LbmBatchTuning(ctypes.Structure):
-    _fields_ = [("block", ctypes.c_int), ("tile_nodes", ctypes.c_int), ("grid", ctypes.c_int)]
+    _fields_ = [("block", ctypes.c_int), ("tile_nodes", ctypes.c_int), ("grid", ctypes.c_int),
+                ("pass_nodes", ctypes.c_int)]
 
 
 EXPORTS = [
@@ -76,7 +78,8 @@ EXPORTS = [
     "lbm_import", "lbm_moments", "lbm_adjoint_step", "lbm_adjoint_partials",
     "lbm_adjoint_terminal", "lbm_adjoint_grad_w0", "lbm_sum", "lbm_destroy",
     "lbm_batch_layout", "lbm_batch_create", "lbm_batch_init", "lbm_batch_run",
-    "lbm_batch_moments", "lbm_batch_current", "lbm_batch_info", "lbm_batch_destroy",
+    "lbm_batch_moments", "lbm_batch_current", "lbm_batch_info", "lbm_batch_check",
+    "lbm_batch_destroy",
     "lbm_last_error", "lbm_version",
 ]
 
@@ -119,6 +122,7 @@ def load(path: str = LIB_PATH):
         "lbm_batch_moments": (ip, [vp, vp, vp, vp]),
         "lbm_batch_current": (ip, [vp, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_long)]),
         "lbm_batch_info": (ip, [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+        "lbm_batch_check": (ip, [vp]),
         "lbm_batch_destroy": (None, [vp]),
         "lbm_last_error": (ctypes.c_char_p, []),
         "lbm_version": (ctypes.c_char_p, []),
@@ -172,7 +176,7 @@ def _bc_codes(bc):
 
 
 def make_params(dim, nx, ny, lam, s, g=1.0, bc=("periodic",) * 4, inflow=None, storage="f64",
-                check_every=0, block=256, npt=1, plane_pad=-1) -> LbmParams:
+                check_every=0, block=256, npt=1, plane_pad=-1, mem_hints=-1) -> LbmParams:
     p = LbmParams()
     p.lattice = D1Q2x2 if dim == 1 else D2Q4x3
     p.storage = F32 if storage in ("f32", F32) else F64
@@ -188,6 +192,7 @@ def make_params(dim, nx, ny, lam, s, g=1.0, bc=("periodic",) * 4, inflow=None, s
     p.block = block
     p.nodes_per_thread = npt
     p.plane_pad = plane_pad
+    p.mem_hints = mem_hints
     return p
 
 
@@ -203,7 +208,7 @@ class Solver:
 
     def __init__(self, dim, nx, ny=1, lam=3.0, s=1.8, g=1.0, bc=("periodic",) * 4, inflow=None,
                  h0=None, qx0=None, qy0=None, storage="f64", check_every=0, block=256, npt=1,
-                 plane_pad=-1, device="cuda"):
+                 plane_pad=-1, mem_hints=-1, device="cuda"):
         import torch
 
         _require_gpu(torch)
@@ -212,7 +217,7 @@ class Solver:
         self.dim = dim
         self.nx, self.ny = nx, (ny if dim == 2 else 1)
         self.params = make_params(dim, nx, ny, lam, s, g, bc, inflow, storage, check_every, block,
-                                  npt, plane_pad)
+                                  npt, plane_pad, mem_hints)
         self.ps, self.nplanes, self.nbytes = layout(self.params)
         self.dtype = torch.float32 if self.params.storage == F32 else torch.float64
         self.device = torch.device(device)
@@ -328,7 +333,8 @@ class Solver:
 class Batch:
     """Many independent problems advanced in one persistent launch."""
 
-    def __init__(self, instances, storage="f32", block=256, tile_nodes=4096, grid=0, device="cuda"):
+    def __init__(self, instances, storage="f32", block=256, tile_nodes=16384, grid=0, pass_nodes=1,
+                 device="cuda"):
         """``instances``: iterable of dicts with keys dim, nx, ny, lam, s, g, bc,
         inflow, h0, qx0, qy0 (numpy arrays of the instance's nodes)."""
         import torch
@@ -374,7 +380,7 @@ class Batch:
                 qy0[o:o + m] = np.asarray(d["qy0"]).reshape(-1)
         f64 = dict(dtype=torch.float64, device=self.device)
         self.h0, self.qx0, self.qy0 = (torch.as_tensor(a, **f64) for a in (h0, qx0, qy0))
-        tune = LbmBatchTuning(block, tile_nodes, grid)
+        tune = LbmBatchTuning(block, tile_nodes, grid, pass_nodes)
         b = ctypes.c_void_p()
         check(L.lbm_batch_create(arr, n, self.storage, _ptr(self.fa), _ptr(self.fb),
                                  _stream_handle(torch), ctypes.byref(tune), ctypes.byref(b)),
@@ -382,8 +388,14 @@ class Batch:
         self.b = b
         check(L.lbm_batch_init(b, _ptr(self.h0), _ptr(self.qx0), _ptr(self.qy0)), "lbm_batch_init")
 
-    def run(self, nsteps):
+    def run(self, nsteps, check_done=False):
         check(load().lbm_batch_run(self.b, int(nsteps)), "lbm_batch_run")
+        if check_done:
+            self.check()
+
+    def check(self):
+        """Synchronise and raise if the last run was aborted by the scheduler."""
+        check(load().lbm_batch_check(self.b), "lbm_batch_check")
 
     def info(self):
         nt, gr = ctypes.c_int(), ctypes.c_int()
@@ -396,6 +408,7 @@ class Batch:
         h = torch.zeros(self.nodes, dtype=torch.float64, device=self.device)
         qx, qy = torch.zeros_like(h), torch.zeros_like(h)
         check(load().lbm_batch_moments(self.b, _ptr(h), _ptr(qx), _ptr(qy)), "lbm_batch_moments")
+        self.check()
         return h, qx, qy
 
     def instance_view(self, i, packed):

@@ -1,0 +1,233 @@
+"""Parity at the full sizes of the benchmark workloads, in the launch
+configuration bench.py times (library defaults / tuning.json).
+
+The oracle cannot run 4096^2 x 2000 steps node by node in test time, so:
+* sampled outputs: one node's value after n steps depends only on the initial
+  data within n nodes of it (one node per step along each axis), so the oracle
+  runs that window (cut faces get a zero-gradient rule whose errors travel one
+  node per step and never reach the centre) and its centre node is compared
+  with the GPU's -- all 12 (4) populations;
+* properties that hold at any size: exact D4 symmetry of the radial dam break,
+  conservation of the totals, positivity."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import (cone_window_1d, cone_window_2d_periodic, gpu_solver, l1_rel,
+                         normwise_rel, say, to_np)
+from paper_1401_0427_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TUNING = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                      "paper_1401_0427_amd", "tuning.json")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1401_0427_amd import lbm
+
+    lbm.load()
+
+
+def _launch(storage):
+    if os.path.exists(TUNING):
+        t = json.load(open(TUNING)).get("forward", {}).get(storage, {})
+        return dict(block=t.get("block", 256), npt=t.get("npt", 1),
+                    plane_pad=t.get("plane_pad", -1), mem_hints=t.get("mem_hints", -1))
+    return {}
+
+
+def _oracle_centre_2d(case, x, y, steps):
+    sub, cx, cy = cone_window_2d_periodic(case, x, y, steps)
+    P = oracle.params(2, sub.nx, sub.ny, lam=sub.lam, s=sub.s, g=sub.g, bc=sub.bc)
+    f = oracle.run(P, sub.h0, sub.qx0, sub.qy0, steps)
+    assert np.all(f[0] == 0.0)
+    return f[1:, cy, cx]
+
+
+def _oracle_centre_1d(case, x, steps):
+    sub, cx = cone_window_1d(case, x, steps)
+    P = oracle.params(1, sub.nx, lam=sub.lam, s=sub.s, g=sub.g, bc=sub.bc, inflow=sub.inflow)
+    f = oracle.run(P, sub.h0, sub.qx0, None, steps)
+    return f[1:, cx]
+
+
+SAMPLES_2D = [(0, 0), (4095, 4095), (2047, 2048), (2048, 2048), (2048 + 819, 2048),
+              (2048, 2048 - 820), (2048 + 580, 2048 + 580), (13, 3000), (4095, 7), (1000, 2222)]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_radial_4096_sampled_nodes_match_oracle(storage):
+    """4096^2 radial dam break (lambda = 6, s = 1.8), 200 steps: 10 sampled nodes
+    (corners, centre, disk edge, diagonal, interior), all 12 populations."""
+    import torch
+
+    steps = 200
+    case = W.radial_dam_break_2d(4096, lam=6.0)
+    say(f"[full] 4096^2 {storage} {steps} steps, launch {_launch(storage)}")
+    S = gpu_solver(case, storage=storage, **_launch(storage))
+    S.step(steps)
+    planes = S.planes()
+    worst = 0.0
+    for (x, y) in SAMPLES_2D:
+        got = planes[:, y, x].double().cpu().numpy()
+        ref = _oracle_centre_2d(case, x, y, steps)
+        e = np.abs(got - ref).max() / np.abs(ref).max()
+        worst = max(worst, e)
+    say(f"  worst sampled relative error {worst:.3e}")
+    assert worst <= (1e-12 if storage == "f64" else 1e-6)
+    del S
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_radial_4096_full_steps_invariants(storage):
+    """2000 steps at 4096^2: the state stays exactly D4-symmetric (transpose and
+    both reflections, bit for bit), the totals of h, qx, qy are conserved and h
+    stays positive and finite."""
+    import torch
+
+    case = W.radial_dam_break_2d(4096, lam=6.0)
+    S = gpu_solver(case, storage=storage, **_launch(storage))
+    S.step(2000)
+    (h, qx, qy), tot = S.moments(totals=True)
+    h, qx, qy = to_np(h), to_np(qx), to_np(qy)
+    mass0 = math.fsum(case.h0.ravel())
+    rel = abs(tot[0] - mass0) / mass0
+    say(f"[full] {storage} 2000 steps: mass rel change {rel:.3e}, max |q| {np.abs(qx).max():.3f}")
+    assert np.isfinite(h).all() and h.min() > 0
+    assert np.array_equal(h, h.T)
+    assert np.array_equal(h, h[:, ::-1]) and np.array_equal(h, h[::-1, :])
+    assert np.array_equal(qx, qy.T)
+    assert np.array_equal(qx, -qx[:, ::-1])
+    assert rel <= (1e-12 if storage == "f64" else 1e-5)
+    assert abs(tot[1]) <= 1e-9 * mass0 and abs(tot[2]) <= 1e-9 * mass0
+    del S
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("s,storage", [(1.9, "f64"), (1.5, "f64"), (1.9, "f32")])
+def test_wall_reflection_2pow20_sampled_after_20000_steps(s, storage):
+    """1D inflow toward a wall, 2^20 nodes, 20000 steps (the full run): nodes at
+    the inflow end, behind and ahead of the incident shock, in the middle and at
+    the wall, against the oracle's window runs."""
+    import torch
+
+    n, steps = 1 << 20, 20000
+    case = W.wall_reflection_1d(n, s=s, steps=steps)
+    S = gpu_solver(case, storage=storage, **_launch(storage))
+    S.step(steps)
+    planes = S.planes()
+    worst = 0.0
+    for x in (0, 3000, 9150, 9300, n // 2, n - 1):
+        got = planes[:, x].double().cpu().numpy()
+        ref = _oracle_centre_1d(case, x, steps)
+        e = np.abs(got - ref).max() / np.abs(ref).max()
+        worst = max(worst, e)
+    say(f"[full] 1D 2^20 x 20000 s={s} {storage}: worst sampled relative error {worst:.3e}")
+    assert worst <= (1e-12 if storage == "f64" else 1e-5)
+    h = to_np(S.moments()[0])
+    # incident shock front: ~ S t cells from the inflow end
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "riemann_exact.json")))
+    xs = gold["wall_reflection"]["incident_shock_speed"] * steps / case.lam  # in cells
+    front = np.nonzero(h > 0.5 * (1.0 + gold["wall_reflection"]["h_mid"]))[0].max()
+    assert abs(front - xs) < 20
+    del S
+    torch.cuda.empty_cache()
+
+
+def test_batched_full_manifest_matches_oracle_on_samples():
+    """The 256-instance manifest (seed 0), 1000 steps, FP32 storage, in the tuned
+    launch: sampled instances against the FP64 oracle (L1 of h <= 1e-5) and mass
+    conservation of every periodic 2D instance."""
+    import torch
+
+    from paper_1401_0427_amd.lbm import Batch
+
+    man = W.batched_manifest(0)
+    insts = []
+    for m in man:
+        h, qx, qy = m.initial()
+        bc = ("neumann", "neumann", "periodic", "periodic") if m.dim == 1 else ("periodic",) * 4
+        insts.append(dict(dim=m.dim, nx=m.nx, ny=m.ny, lam=m.lam, s=m.s, g=W.G, bc=bc, h0=h,
+                          qx0=qx, qy0=qy))
+    tune = {}
+    if os.path.exists(TUNING):
+        tune = json.load(open(TUNING)).get("batch", {})
+    say(f"[full batch] tuning {tune}")
+    B = Batch(insts, storage="f32", **tune)
+    B.run(1000, check_done=True)
+    hs = B.moments()[0]
+    order1 = sorted((i for i, d in enumerate(insts) if d["dim"] == 1), key=lambda i: insts[i]["nx"])
+    order2 = sorted((i for i, d in enumerate(insts) if d["dim"] == 2), key=lambda i: insts[i]["nx"])
+    picks = order1[:3] + order1[-1:] + order2[:2]
+    worst = 0.0
+    for i in picks:
+        d = insts[i]
+        P = oracle.params(d["dim"], d["nx"], d["ny"], lam=d["lam"], s=d["s"], bc=d["bc"])
+        ref = oracle.moments(P, oracle.run(P, d["h0"], d["qx0"], d["qy0"] if d["dim"] == 2 else None,
+                                           1000))[0]
+        worst = max(worst, l1_rel(to_np(B.instance_view(i, hs)), ref))
+    say(f"  sampled instances {picks}: worst L1 rel of h {worst:.3e}")
+    assert worst <= 1e-5
+    for i in order2:
+        got = to_np(B.instance_view(i, hs))
+        m0 = math.fsum(np.asarray(insts[i]["h0"]).ravel())
+        assert abs(math.fsum(got.ravel()) - m0) <= 1e-5 * m0
+    del B
+    torch.cuda.empty_cache()
+
+
+def test_adjoint_full_1024_fp64_matches_oracle_and_fd():
+    """Adjoint workload at full size: 1024^2, 500 steps, checkpoints every 23
+    steps; gradients of sum (h(T) - hhat)^2 w.r.t. h0 and s vs the FP64 oracle
+    gradient and a central difference of the GPU loss (rel <= 1e-6); the FP32
+    forward's gradient error vs the oracle is reported."""
+    import torch
+
+    from paper_1401_0427_amd.adjoint import rollout
+
+    n, T, K = 1024, 500, 23
+    c, ht0 = W.adjoint_case(n=n, steps=T)
+    P = oracle.params(2, n, n, lam=c.lam, s=c.s)
+    hhat = oracle.moments(P, oracle.run(P, ht0, None, None, T))[0]
+    l_ref, gh_ref, gs_ref = oracle.loss_grad_2d(P, c.h0, hhat, T, K=K)
+    target = torch.as_tensor(hhat, device="cuda")
+
+    def grads(storage):
+        h0 = torch.tensor(c.h0, dtype=torch.float64, device="cuda", requires_grad=True)
+        s = torch.tensor(c.s, dtype=torch.float64, device="cuda", requires_grad=True)
+        loss = ((rollout(h0, s, T, K, lam=c.lam, storage=storage) - target) ** 2).sum()
+        loss.backward()
+        return float(loss), to_np(h0.grad), float(s.grad)
+
+    loss, gh, gs = grads("f64")
+    e_h, e_s = normwise_rel(gh, gh_ref), abs(gs - gs_ref) / abs(gs_ref)
+    say(f"[full adjoint] FP64: loss {loss:.12e} vs {l_ref:.12e}; grad_h0 {e_h:.3e}; grad_s {e_s:.3e}")
+    assert e_h <= 1e-6 and e_s <= 1e-6
+    v = np.random.default_rng(7).standard_normal((n, n))
+    eps = 1e-6
+
+    def L(h0):
+        with torch.no_grad():
+            hT = rollout(torch.as_tensor(h0, device="cuda"), torch.tensor(c.s, dtype=torch.float64),
+                         T, K, lam=c.lam)
+            return float(((hT - target) ** 2).sum())
+
+    fd = (L(c.h0 + eps * v) - L(c.h0 - eps * v)) / (2 * eps)
+    ad = float((gh * v).sum())
+    say(f"  central difference along a random direction: {ad:.10e} vs {fd:.10e}")
+    assert abs(ad - fd) <= 1e-6 * abs(fd)
+    loss32, gh32, gs32 = grads("f32")
+    say(f"  FP32 forward: grad_h0 rel {normwise_rel(gh32, gh_ref):.3e}; grad_s rel "
+        f"{abs(gs32 - gs_ref) / abs(gs_ref):.3e} (reported)")
+    assert normwise_rel(gh32, gh_ref) < 1e-2
