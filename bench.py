@@ -39,6 +39,9 @@ def _parse():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--npt", type=int, default=0)
     ap.add_argument("--pad", type=int, default=-1)
+    ap.add_argument("--probe-copy", action="store_true",
+                    help="first run a plain device copy of 2^30 bytes (reference for counters)")
+    ap.add_argument("--storage", choices=("both", "f64", "f32"), default="both")
     return ap.parse_args()
 
 
@@ -176,6 +179,31 @@ def time_adjoint(torch, n=1024, T=500, K=23, storage="f32"):
                 grad_s=float(s.grad), grad_h0_norm=float(h0.grad.norm()))
 
 
+def _measured_traffic(n):
+    """HBM bytes per launch of the FP64 step kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, each scaled by what the counter
+    reads for a plain copy of known size), if it was taken for this grid and
+    the current kernel source; else None."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                        "k_step2d_fwd_4096_traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("n") != n or d.get("kernel_source_sha") != _kernel_sha():
+        return None
+    return d.get("traffic_bytes_per_launch_f64")
+
+
+def _kernel_sha():
+    import hashlib
+
+    root = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    for f in ("fwd.hip", "lbm_device.h"):
+        h.update(open(os.path.join(root, "paper_1401_0427_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def cpu_baseline(n):
     """The CPU oracle (as it stands) on a bounded sample of the headline workload:
     the full 4096^2 grid, a few steps, all host cores (OpenMP); the per-step time
@@ -220,11 +248,21 @@ def main():
                 args.pad if args.pad >= 0 else t.get("plane_pad", -1))
 
     n = args.n
-    log(f"[bench] forward FP64 {n}^2, {args.steps} steps, launch {launch('f64')}")
-    f64 = time_forward(torch, n, "f64", args.steps, args.warmup, *launch("f64"))
-    log(f"[bench] forward FP32 {n}^2, {args.steps} steps, launch {launch('f32')}")
-    f32 = time_forward(torch, n, "f32", args.steps, args.warmup, *launch("f32"))
-    forms = {"fp64": f64, "fp32": f32}
+    if args.probe_copy:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 2^30 bytes
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("[bench] copy probe: 2^30 bytes read, 2^30 bytes written")
+    forms = {}
+    if args.storage in ("both", "f64"):
+        log(f"[bench] forward FP64 {n}^2, {args.steps} steps, launch {launch('f64')}")
+        forms["fp64"] = time_forward(torch, n, "f64", args.steps, args.warmup, *launch("f64"))
+    if args.storage in ("both", "f32"):
+        log(f"[bench] forward FP32 {n}^2, {args.steps} steps, launch {launch('f32')}")
+        forms["fp32"] = time_forward(torch, n, "f32", args.steps, args.warmup, *launch("f32"))
+    f64 = forms.get("fp64") or forms["fp32"]
     if not args.quick and not args.no_batched:
         log("[bench] batched 256 instances x 1000 steps")
         forms["batched"] = time_batched(torch)
@@ -236,6 +274,9 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "kernel": "k_step2d<double> (fused pull-stream + BGK collide)",
             "bytes_per_launch": n * n * f64["bytes_per_lu"]}
+    traffic = _measured_traffic(n)
+    if traffic is not None:
+        roof["traffic"] = traffic
     cpu = None
     if not args.quick and not args.no_cpu:
         log("[bench] CPU oracle baseline")
@@ -259,6 +300,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "forms": forms,
+        "kernel_source_sha": _kernel_sha(),
     }
     print(json.dumps(out), flush=True)
 

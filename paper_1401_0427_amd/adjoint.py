@@ -28,10 +28,13 @@ class _Rollout(torch.autograd.Function):
         solver = Solver(2, n[1], n[0], lam=lam, s=float(s), g=g, h0=h0.detach(),
                         storage=storage, block=block)
         cks = {0: solver.current()[0].clone()}
-        for t in range(T):
-            solver.step(1)
-            if (t + 1) % K == 0 and (t + 1) < T:
-                cks[t + 1] = solver.current()[0].clone()
+        t = 0
+        while t < T:
+            k = min(K, T - t)
+            solver.step(k)
+            t += k
+            if t < T:
+                cks[t] = solver.current()[0].clone()
         hT = solver.moments()[0]
         ctx.solver = solver
         ctx.cks = cks

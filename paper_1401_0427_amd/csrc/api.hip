@@ -7,7 +7,7 @@
 
 #include <new>
 
-#include "../../include/lbm.h"
+#include "lbm.h"
 #include "internal.h"
 
 using namespace lbm;

@@ -27,7 +27,7 @@
 #include <new>
 #include <vector>
 
-#include "../../include/lbm.h"
+#include "lbm.h"
 #include "internal.h"
 
 namespace lbm {
