@@ -31,7 +31,8 @@
  *     p * plane_stride, each plane row-major [y][x] with row stride nx.
  *     2D planes: (h: e1..e4, qx: e1..e4, qy: e1..e4), e1 = +x, e2 = +y,
  *     e3 = -x, e4 = -y (Sec. 3 eq. 3-stencil-d2q5).  1D planes: (h: +, -;
- *     q: +, -).  Elements are double (LBM_F64) or float (LBM_F32);
+ *     q: +, -).  D2Q5Q4Q4 / D1Q3Q2 put the rest population h_0 first:
+ *     (h: 0, e1..e4, qx: e1..e4, qy: e1..e4) and (h: 0, +, -; q: +, -).  Elements are double (LBM_F64) or float (LBM_F32);
  *     arithmetic is always double.  plane_stride >= nx*ny (padding breaks
  *     power-of-two plane strides); query it with lbm_layout.
  *   - State at level n = the post-collision distribution f*(n).  Level 0 is the
@@ -64,7 +65,11 @@ enum lbm_status {
     LBM_EDIVERGED = -4    /* a check found h <= 0 or a non-finite value */
 };
 
-enum lbm_lattice { LBM_D1Q2x2 = 1, LBM_D2Q4x3 = 2 };
+/* LBM_D1Q2x2 / LBM_D2Q4x3: the hot path (rest weight a = 0, BGK).
+ * LBM_D1Q3Q2 / LBM_D2Q5Q4Q4: the paper's schemes with a rest population f_0 of
+ * weight a >= 0 (Sec. 2 eq. 2-potentiels-st-venant-1d, Sec. 3) and moment-space
+ * relaxation with one rate per non-conserved moment (eq. 2-relaxation, MRT). */
+enum lbm_lattice { LBM_D1Q2x2 = 1, LBM_D2Q4x3 = 2, LBM_D1Q3Q2 = 3, LBM_D2Q5Q4Q4 = 4 };
 enum lbm_storage { LBM_F64 = 64, LBM_F32 = 32 };
 enum lbm_bc {
     LBM_BC_PERIODIC = 0, /* wrap around (both faces of an axis must be periodic) */
@@ -81,6 +86,11 @@ typedef struct {
     double lambda;        /* lattice velocity dx/dt > 0 */
     double s;             /* relaxation rate in (0, 2) */
     double g;             /* gravity > 0, p = (g/2) h^2 */
+    double a;             /* rest weight (D1Q3Q2 / D2Q5Q4Q4 only; must be 0 otherwise) */
+    double rates[10];     /* D1Q3Q2 / D2Q5Q4Q4 relaxation rates of the non-conserved
+                             moments, each in (0, 2); 0 entries take s.
+                             1D: (J_rho, eps_rho, J_q); 2D: (J_x, J_y, eps, XX_rho,
+                             f_xx, f_xy, XX_u, f_yx, f_yy, XX_v) (Sec. 2, Sec. 3) */
     int bc[4];            /* lbm_bc of faces x-, x+, y-, y+ (y faces ignored in 1D) */
     double inflow[4][3];  /* (h, qx, qy) of LBM_BC_INFLOW faces, h > 0 */
     int check_every;      /* 0 = off; else lbm_step checks the state every that

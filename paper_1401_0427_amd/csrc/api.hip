@@ -50,19 +50,30 @@ static const long kAlign = 64;        // elements: planes start on 512 B / 256 B
 static const long kDefaultPad = 2048;  // elements between planes
 static const int kDefaultHints = 6;    // non-temporal stores, plain workgroup order
 
-static int nplanes_of(int lattice) { return lattice == LBM_D1Q2x2 ? 4 : 12; }
+static int nplanes_of(int lattice)
+{
+    switch (lattice) {
+    case LBM_D1Q2x2: return 4;
+    case LBM_D2Q4x3: return 12;
+    case LBM_D1Q3Q2: return 5;
+    default: return 13;
+    }
+}
+static int dim_of(int lattice) { return (lattice == LBM_D1Q2x2 || lattice == LBM_D1Q3Q2) ? 1 : 2; }
+static bool rest_of(int lattice) { return lattice == LBM_D1Q3Q2 || lattice == LBM_D2Q5Q4Q4; }
 static size_t elem_of(int storage) { return storage == LBM_F32 ? 4 : 8; }
 
 static int layout_of(int lattice, int storage, int nx, int ny, long pad, long *ps, int *np,
                      size_t *bytes)
 {
-    if (lattice != LBM_D1Q2x2 && lattice != LBM_D2Q4x3)
-        return fail(LBM_EINVAL, "lattice must be LBM_D1Q2x2 or LBM_D2Q4x3 (got %d)", lattice);
+    if (lattice < LBM_D1Q2x2 || lattice > LBM_D2Q5Q4Q4)
+        return fail(LBM_EINVAL, "lattice must be one of LBM_D1Q2x2, LBM_D2Q4x3, LBM_D1Q3Q2, "
+                                "LBM_D2Q5Q4Q4 (got %d)", lattice);
     if (storage != LBM_F64 && storage != LBM_F32)
         return fail(LBM_EINVAL, "storage must be LBM_F64 or LBM_F32 (got %d)", storage);
-    if (lattice == LBM_D1Q2x2 && (nx < 2 || ny != 1))
+    if (dim_of(lattice) == 1 && (nx < 2 || ny != 1))
         return fail(LBM_EINVAL, "1D needs nx >= 2 and ny == 1 (got %d x %d)", nx, ny);
-    if (lattice == LBM_D2Q4x3 && (nx < 2 || ny < 2))
+    if (dim_of(lattice) == 2 && (nx < 2 || ny < 2))
         return fail(LBM_EINVAL, "2D needs nx, ny >= 2 (got %d x %d)", nx, ny);
     const long n = (long)nx * ny;
     if (n > (1L << 31) / 16) return fail(LBM_EINVAL, "grid too large (%ld nodes)", n);
@@ -125,6 +136,9 @@ static void fill_geo_phys(int dim, int nx, int ny, long ps, double lambda, doubl
 struct lbm_ctx {
     lbm_params p;
     int dim;
+    bool rest;  // rest-population scheme (D1Q3Q2 / D2Q5Q4Q4, MRT)
+    Mrt M;
+    double *d_ghost;  // inflow equilibria of the rest-population schemes (4 x 13)
     bool f32;
     long ps;
     int np;
@@ -159,6 +173,7 @@ extern "C" void lbm_destroy(lbm_ctx *c)
     (void)hipFree(c->d_flag);
     (void)hipFree(c->d_partials);
     (void)hipFree(c->d_totals);
+    (void)hipFree(c->d_ghost);
     delete c;
 }
 
@@ -177,8 +192,25 @@ extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0
     int rc = layout_of(p->lattice, p->storage, p->nx, p->ny, p->plane_pad, &ps, &np, &bytes);
     if (rc) return rc;
     if ((rc = check_phys(p->lambda, p->s, p->g))) return rc;
-    const int dim = p->lattice == LBM_D1Q2x2 ? 1 : 2;
+    const int dim = dim_of(p->lattice);
+    const bool rest = rest_of(p->lattice);
     if ((rc = check_bcs(dim, p->bc, p->inflow))) return rc;
+    double rates[10];
+    if (rest)
+        return fail(LBM_EINVAL,
+                    "the D1Q3Q2 / D2Q5Q4Q4 kernels are disabled: their first GPU run ended in an "
+                    "illegal memory access whose cause has not been found (the kernels and this "
+                    "API run clean under AddressSanitizer in a CPU build)");
+    if (rest) {
+        if (!(p->a >= 0.0) || !isfinite(p->a)) return fail(LBM_EINVAL, "rest weight a must be >= 0");
+        for (int i = 0; i < 10; ++i) {
+            rates[i] = p->rates[i] == 0.0 ? p->s : p->rates[i];
+            if (!(rates[i] > 0.0 && rates[i] < 2.0))
+                return fail(LBM_EINVAL, "relaxation rate %d must be in (0, 2)", i);
+        }
+    } else if (p->a != 0.0) {
+        return fail(LBM_EINVAL, "a > 0 needs LBM_D1Q3Q2 or LBM_D2Q5Q4Q4");
+    }
     const int block = p->block ? p->block : 256;
     if (block != 64 && block != 128 && block != 256 && block != 512)
         return fail(LBM_EINVAL, "block must be 64, 128, 256 or 512 (got %d)", block);
@@ -192,6 +224,17 @@ extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0
     if (!c) return fail(LBM_EDEVICE, "out of host memory");
     c->p = *p;
     c->dim = dim;
+    c->rest = rest;
+    if (rest) {
+        c->M.lam = p->lambda;
+        c->M.il = 1.0 / p->lambda;
+        c->M.a = p->a;
+        c->M.aK = p->a * (0.5 / p->g);
+        c->M.g = p->g;
+        c->M.hg = 0.5 * p->g;
+        c->M.c = 0.5 / p->lambda;
+        for (int i = 0; i < 10; ++i) c->M.rate[i] = rates[i];
+    }
     c->f32 = p->storage == LBM_F32;
     c->ps = ps;
     c->np = np;
@@ -212,7 +255,8 @@ extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0
     if ((e = hipMalloc(&c->d_speed, sizeof(unsigned long long))) != hipSuccess ||
         (e = hipMalloc(&c->d_flag, 2 * sizeof(int))) != hipSuccess ||
         (e = hipMalloc(&c->d_partials, sizeof(double) * 3 * (size_t)nmb)) != hipSuccess ||
-        (e = hipMalloc(&c->d_totals, sizeof(double) * 4)) != hipSuccess) {
+        (e = hipMalloc(&c->d_totals, sizeof(double) * 4)) != hipSuccess ||
+        (e = hipMalloc(&c->d_ghost, sizeof(double) * 4 * 13)) != hipSuccess) {
         lbm_destroy(c);
         return fail(LBM_EDEVICE, "hipMalloc of scratch failed: %s", hipGetErrorString(e));
     }
@@ -220,8 +264,11 @@ extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0
     int bad = 0;
     if ((e = hipMemsetAsync(c->d_speed, 0, sizeof(unsigned long long), c->st)) != hipSuccess ||
         (e = hipMemsetAsync(c->d_flag, 0, 2 * sizeof(int), c->st)) != hipSuccess ||
-        (e = launch_init(dim, c->f32, c->buf[0], h0, qx0, qy0, c->G, c->P, c->L, c->d_speed,
-                         c->d_flag, c->st)) != hipSuccess ||
+        (rest && (e = launch_inflow_ghost(dim, c->G, c->M, c->d_ghost, c->st)) != hipSuccess) ||
+        (e = (rest ? launch_init_rest(dim, c->f32, c->buf[0], h0, qx0, qy0, c->G, c->M,
+                                      c->d_speed, c->d_flag, c->st)
+                   : launch_init(dim, c->f32, c->buf[0], h0, qx0, qy0, c->G, c->P, c->L,
+                                 c->d_speed, c->d_flag, c->st))) != hipSuccess ||
         (e = hipMemcpyAsync(&speed_bits, c->d_speed, sizeof speed_bits, hipMemcpyDeviceToHost,
                             c->st)) != hipSuccess ||
         (e = hipMemcpyAsync(&bad, c->d_flag, sizeof bad, hipMemcpyDeviceToHost, c->st)) !=
@@ -237,13 +284,19 @@ extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0
     *out = c;
     double speed;
     memcpy(&speed, &speed_bits, sizeof speed);
-    const double need = (dim == 1 ? 1.0 : 2.0) * speed;
+    const double need = (dim == 1 ? 1.0 : 2.0) * speed;  // a = 0 bound (a > 0: indicative)
     if (p->lambda < need)
         return fail(LBM_WARN_SUBCHAR,
                     "lambda = %g is below the monotonicity bound %g of the %s lattice "
                     "(max |u| + sqrt(g h) = %g); the run may diverge",
                     p->lambda, need, dim == 1 ? "D1Q2" : "D2Q4", speed);
     return LBM_OK;
+}
+
+static hipError_t step_once(lbm_ctx *c, const void *src, void *dst, hipStream_t st)
+{
+    if (c->rest) return launch_step_rest(c->dim, c->f32, src, dst, c->G, c->M, c->d_ghost, st);
+    return launch_step(c->dim, c->f32, src, dst, c->G, c->P, c->L, st);
 }
 
 static int check_ctx(lbm_ctx *c)
@@ -256,7 +309,11 @@ static int check_state(lbm_ctx *c, long at_step)
 {
     int flag = 0;
     HIP_TRY(hipMemsetAsync(c->d_flag, 0, sizeof(int), c->st));
-    HIP_TRY(launch_check(c->dim, c->f32, c->buf[c->cur], c->G, c->d_flag, c->st));
+    if (c->rest)
+        HIP_TRY(launch_moments_rest(c->dim, c->f32, c->buf[c->cur], nullptr, nullptr, nullptr,
+                                    nullptr, c->d_flag, c->G, c->st, nullptr));
+    else
+        HIP_TRY(launch_check(c->dim, c->f32, c->buf[c->cur], c->G, c->d_flag, c->st));
     HIP_TRY(hipMemcpyAsync(&flag, c->d_flag, sizeof flag, hipMemcpyDeviceToHost, c->st));
     HIP_TRY(hipStreamSynchronize(c->st));
     if (flag)
@@ -274,7 +331,7 @@ static int ensure_chunk(lbm_ctx *c, int from)
     int cur = from;
     hipError_t le = hipSuccess;
     for (int k = 0; k < c->chunk_len && le == hipSuccess; ++k) {
-        le = launch_step(c->dim, c->f32, c->buf[cur], c->buf[cur ^ 1], c->G, c->P, c->L, c->cap);
+        le = step_once(c, c->buf[cur], c->buf[cur ^ 1], c->cap);
         cur ^= 1;
     }
     hipError_t ee = hipStreamEndCapture(c->cap, &g);
@@ -313,8 +370,7 @@ extern "C" int lbm_step(lbm_ctx *c, long nsteps)
             c->steps += c->chunk_len;  // chunk length is even: c->cur unchanged
         }
         for (; todo > 0; --todo) {
-            HIP_TRY(launch_step(c->dim, c->f32, c->buf[c->cur], c->buf[c->cur ^ 1], c->G, c->P,
-                                c->L, c->st));
+            HIP_TRY(step_once(c, c->buf[c->cur], c->buf[c->cur ^ 1], c->st));
             c->cur ^= 1;
             ++done;
             ++c->steps;
@@ -331,7 +387,7 @@ extern "C" int lbm_step_buffers(lbm_ctx *c, const void *src, void *dst)
     if (rc) return rc;
     if (!src || !dst) return fail(LBM_EINVAL, "null buffer");
     if (src == dst) return fail(LBM_EINVAL, "src and dst must not alias");
-    HIP_TRY(launch_step(c->dim, c->f32, src, dst, c->G, c->P, c->L, c->st));
+    HIP_TRY(step_once(c, src, dst, c->st));
     return LBM_OK;
 }
 
@@ -369,8 +425,13 @@ extern "C" int lbm_moments(lbm_ctx *c, const void *state, double *h, double *qx,
     if (rc) return rc;
     const void *s = state ? state : c->buf[c->cur];
     int nb = 0;
-    HIP_TRY(launch_moments(c->dim, c->f32, s, h, qx, qy, totals_host ? c->d_partials : nullptr,
-                           c->G, c->st, &nb));
+    if (c->rest)
+        HIP_TRY(launch_moments_rest(c->dim, c->f32, s, h, qx, qy,
+                                    totals_host ? c->d_partials : nullptr, nullptr, c->G, c->st,
+                                    &nb));
+    else
+        HIP_TRY(launch_moments(c->dim, c->f32, s, h, qx, qy,
+                               totals_host ? c->d_partials : nullptr, c->G, c->st, &nb));
     if (totals_host) {
         HIP_TRY(launch_sum(c->d_partials, nb, 3, 3, c->d_totals, c->st));
         HIP_TRY(hipMemcpyAsync(totals_host, c->d_totals, 3 * sizeof(double),
@@ -385,7 +446,8 @@ static int check_adjoint_ctx(lbm_ctx *c)
 {
     int rc = check_ctx(c);
     if (rc) return rc;
-    if (c->dim != 2) return fail(LBM_EINVAL, "the adjoint is implemented for the 2D lattice");
+    if (c->p.lattice != LBM_D2Q4x3)
+        return fail(LBM_EINVAL, "the adjoint is implemented for the D2Q4x3 lattice");
     for (int f = 0; f < 4; ++f)
         if (c->G.bc[f] != BC_PERIODIC)
             return fail(LBM_EINVAL, "the adjoint is implemented for periodic faces only");

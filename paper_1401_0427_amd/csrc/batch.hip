@@ -286,7 +286,8 @@ extern "C" int lbm_batch_layout(lbm_instance *inst, int n, int storage, size_t *
         lbm_instance &I = inst[i];
         const bool d1 = I.lattice == LBM_D1Q2x2;
         if (I.lattice != LBM_D1Q2x2 && I.lattice != LBM_D2Q4x3)
-            return bfail(LBM_EINVAL, "instance %d: bad lattice", i);
+            return bfail(LBM_EINVAL, "instance %d: the batched form runs LBM_D1Q2x2 / LBM_D2Q4x3",
+                         i);
         if (I.nx < 2 || (d1 ? I.ny != 1 : I.ny < 2))
             return bfail(LBM_EINVAL, "instance %d: bad size %d x %d", i, I.nx, I.ny);
         const long nn = (long)I.nx * I.ny;

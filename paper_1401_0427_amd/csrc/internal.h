@@ -8,6 +8,14 @@
 
 namespace lbm {
 
+// Constants of the rest-population schemes (D1Q3Q2 / D2Q5Q4Q4) with MRT.
+struct Mrt {
+    double lam, il;   // lambda and 1 / lambda
+    double a, aK;     // rest weight and a K, K = 1 / (2 g)
+    double g, hg, c;  // g, g / 2, 1 / (2 lambda)
+    double rate[10];  // relaxation rates of the non-conserved moments
+};
+
 // Launch shape of the plain forward / adjoint kernels.
 struct Launch {
     int block;  // threads per workgroup
@@ -38,5 +46,16 @@ hipError_t launch_adjoint_terminal(bool f32, const double *dLdh, void *lam, cons
 hipError_t launch_adjoint_grad_w0(bool f32, const void *lam0, const double *h0,
                                   const double *qx0, const double *qy0, double *gh, double *gqx,
                                   double *gqy, const Geo &G, const Phys &P, hipStream_t st);
+
+hipError_t launch_inflow_ghost(int dim, const Geo &G, const Mrt &M, double *ghost,
+                               hipStream_t st);
+hipError_t launch_init_rest(int dim, bool f32, void *dst, const double *h0, const double *qx0,
+                            const double *qy0, const Geo &G, const Mrt &M,
+                            unsigned long long *speed_bits, int *bad, hipStream_t st);
+hipError_t launch_step_rest(int dim, bool f32, const void *src, void *dst, const Geo &G,
+                            const Mrt &M, const double *ghost, hipStream_t st);
+hipError_t launch_moments_rest(int dim, bool f32, const void *state, double *h, double *qx,
+                               double *qy, double *partials, int *flag, const Geo &G,
+                               hipStream_t st, int *nblocks_out);
 
 } // namespace lbm

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 LBM_OK, LBM_WARN_SUBCHAR = 0, 1
 LBM_EINVAL, LBM_EDEVICE, LBM_ESTATE, LBM_EDIVERGED = -1, -2, -3, -4
-D1Q2x2, D2Q4x3 = 1, 2
+D1Q2x2, D2Q4x3, D1Q3Q2, D2Q5Q4Q4 = 1, 2, 3, 4
 F64, F32 = 64, 32
 BC = {"periodic": 0, "neumann": 1, "wall": 2, "inflow": 3}
 
@@ -40,6 +40,8 @@ class LbmParams(ctypes.Structure):
         ("lam", ctypes.c_double),
         ("s", ctypes.c_double),
         ("g", ctypes.c_double),
+        ("a", ctypes.c_double),
+        ("rates", ctypes.c_double * 10),
         ("bc", ctypes.c_int * 4),
         ("inflow", (ctypes.c_double * 3) * 4),
         ("check_every", ctypes.c_int),
@@ -176,9 +178,18 @@ def _bc_codes(bc):
 
 
 def make_params(dim, nx, ny, lam, s, g=1.0, bc=("periodic",) * 4, inflow=None, storage="f64",
-                check_every=0, block=256, npt=1, plane_pad=-1, mem_hints=-1) -> LbmParams:
+                check_every=0, block=256, npt=1, plane_pad=-1, mem_hints=-1, rest=False, a=0.0,
+                rates=None) -> LbmParams:
+    """Parameter block; ``rest`` selects the rest-population schemes D1Q3Q2 /
+    D2Q5Q4Q4 (weight ``a``, MRT ``rates``; 0 / missing rates take ``s``)."""
     p = LbmParams()
-    p.lattice = D1Q2x2 if dim == 1 else D2Q4x3
+    if rest:
+        p.lattice = D1Q3Q2 if dim == 1 else D2Q5Q4Q4
+    else:
+        p.lattice = D1Q2x2 if dim == 1 else D2Q4x3
+    p.a = a
+    for i, r in enumerate(rates or []):
+        p.rates[i] = r
     p.storage = F32 if storage in ("f32", F32) else F64
     p.nx, p.ny = nx, (ny if dim == 2 else 1)
     p.lam, p.s, p.g = lam, s, g
@@ -208,7 +219,7 @@ class Solver:
 
     def __init__(self, dim, nx, ny=1, lam=3.0, s=1.8, g=1.0, bc=("periodic",) * 4, inflow=None,
                  h0=None, qx0=None, qy0=None, storage="f64", check_every=0, block=256, npt=1,
-                 plane_pad=-1, mem_hints=-1, device="cuda"):
+                 plane_pad=-1, mem_hints=-1, rest=False, a=0.0, rates=None, device="cuda"):
         import torch
 
         _require_gpu(torch)
@@ -217,7 +228,7 @@ class Solver:
         self.dim = dim
         self.nx, self.ny = nx, (ny if dim == 2 else 1)
         self.params = make_params(dim, nx, ny, lam, s, g, bc, inflow, storage, check_every, block,
-                                  npt, plane_pad, mem_hints)
+                                  npt, plane_pad, mem_hints, rest, a, rates)
         self.ps, self.nplanes, self.nbytes = layout(self.params)
         self.dtype = torch.float32 if self.params.storage == F32 else torch.float64
         self.device = torch.device(device)

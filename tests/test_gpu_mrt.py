@@ -1,0 +1,119 @@
+"""GPU kernels of the paper's rest-population schemes (D1Q3Q2, D2Q5Q4Q4) with
+moment-space MRT, against the oracle's literal moment-space relaxation.
+Tolerance: FP64 storage 1e-12 normwise per plane (the two sides evaluate the
+same formulas in different operation orders); FP32 storage L1 of h 1e-5."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import l1_rel, per_plane_rel, say, smooth_random_2d, to_np
+from paper_1401_0427_amd import workloads as W
+
+pytestmark = [
+    pytest.mark.gpu,
+    pytest.mark.skip(reason="D1Q3Q2 / D2Q5Q4Q4 GPU kernels disabled: their first GPU run ended in an "
+                            "illegal memory access whose cause is not found yet (clean under ASan "
+                            "in a CPU build); not run on the GPU again until a cause is shown"),
+]
+
+RATES2D = [1.7, 1.6, 1.2, 1.9, 1.5, 1.3, 1.1, 1.45, 1.55, 1.8]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1401_0427_amd import lbm
+
+    lbm.load()
+
+
+def _gpu_rest(case, a, rates, steps, storage="f64"):
+    from paper_1401_0427_amd.lbm import Solver
+
+    S = Solver(case.dim, case.nx, case.ny, lam=case.lam, s=case.s, g=case.g, bc=case.bc,
+               inflow=case.inflow, h0=case.h0, qx0=case.qx0,
+               qy0=case.qy0 if case.dim == 2 else None, storage=storage, rest=True, a=a,
+               rates=rates)
+    S.step(steps)
+    return S
+
+
+def _orc_rest(case, a, rates, steps):
+    P = oracle.params(case.dim, case.nx, case.ny, lam=case.lam, s=case.s, g=case.g, bc=case.bc,
+                      inflow=case.inflow, a=a, mrt=True, rates=rates)
+    return oracle.run(P, case.h0, case.qx0, case.qy0 if case.dim == 2 else None, steps), P
+
+
+@pytest.mark.parametrize("bc,inflow", [
+    (("periodic",) * 4, {}),
+    (("inflow", "neumann", "wall", "wall"), {0: (1.2, 0.3, 0.0)}),
+    (("wall", "wall", "periodic", "periodic"), {}),
+])
+def test_d2q5q4q4_mrt_matches_oracle(bc, inflow):
+    case = smooth_random_2d(300, 34, seed=11, lam=6.0, s=1.7, bc=bc, inflow=inflow)
+    say(f"[mrt 2D] {bc} a=0.05 rates={RATES2D}")
+    S = _gpu_rest(case, 0.05, RATES2D, 120)
+    got = to_np(S.planes())
+    ref, _ = _orc_rest(case, 0.05, RATES2D, 120)
+    err = per_plane_rel(got, ref)
+    say(f"  max plane rel err {err:.3e}")
+    assert got.shape == ref.shape == (13, 34, 300)
+    assert err <= 1e-12
+
+
+def test_d1q3q2_fig1_setup_matches_oracle():
+    """Sec. 2 experiment on the GPU: 80 points, a = 0.15, lambda = 8, s = 1.8."""
+    n = 80
+    x = W.cell_centres(n)
+    case = W.Case(1, n, 1, 8.0, 1.8, 96, bc=("neumann", "neumann", "periodic", "periodic"),
+                  h0=np.where(x < 0.5, 2.0, 0.5), qx0=np.zeros(n))
+    S = _gpu_rest(case, 0.15, [1.8, 1.8, 1.8], 96)
+    ref, P = _orc_rest(case, 0.15, [1.8, 1.8, 1.8], 96)
+    err = per_plane_rel(to_np(S.planes()), ref)
+    say(f"[mrt 1D fig1] max plane rel err {err:.3e}")
+    assert err <= 1e-12
+
+
+def test_d1q3q2_distinct_rates_walls_inflow():
+    case = W.wall_reflection_1d(4096, s=1.7, steps=2500)
+    rates = [1.7, 1.3, 1.9]
+    S = _gpu_rest(case, 0.1, rates, 2500)
+    ref, _ = _orc_rest(case, 0.1, rates, 2500)
+    err = per_plane_rel(to_np(S.planes()), ref)
+    say(f"[mrt 1D wall/inflow] max plane rel err {err:.3e}")
+    assert err <= 1e-12
+
+
+def test_rest_scheme_at_a0_equal_rates_is_the_hot_path():
+    """a = 0 with every rate equal to s reproduces the D2Q4x3 BGK kernel (the
+    rest population stays at rounding level)."""
+    from gpu_helpers import gpu_solver
+
+    case = smooth_random_2d(128, 96, seed=12)
+    R = _gpu_rest(case, 0.0, [case.s] * 10, 150)
+    H = gpu_solver(case)
+    H.step(150)
+    a, b = to_np(R.planes()), to_np(H.planes())
+    assert np.abs(a[0]).max() < 1e-14
+    assert per_plane_rel(a[1:], b) <= 1e-13
+
+
+def test_d2q5q4q4_fp32_storage_l1():
+    case = W.radial_dam_break_2d(192, lam=6.0)
+    S = _gpu_rest(case, 0.05, RATES2D, 300, storage="f32")
+    ref, P = _orc_rest(case, 0.05, RATES2D, 300)
+    e = l1_rel(to_np(S.moments()[0]), oracle.moments(P, ref)[0])
+    say(f"[mrt fp32] L1 rel of h {e:.3e}")
+    assert e <= 1e-5
+
+
+def test_adjoint_rejects_rest_lattice():
+    from paper_1401_0427_amd.lbm import LbmError
+
+    case = smooth_random_2d(40, 40, seed=1)
+    S = _gpu_rest(case, 0.05, RATES2D, 1)
+    with pytest.raises(LbmError, match="D2Q4x3"):
+        S.adjoint_step(S.current()[0], S.new_state(), S.new_state(), S.adjoint_partials())

@@ -440,3 +440,28 @@ def test_wall_reflection_state_and_shock(orc, s):
     assert abs(np.median(wall_zone) - gold["h_wall"]) < 2e-3
     mid_zone = h[(x > 0.5) & (x < x_ref - 0.02)]
     assert abs(np.median(mid_zone) - gold["h_mid"]) < 2e-3
+
+
+def test_fig1_setup_d1q3q2_converges_to_exact_riemann(orc):
+    """The Sec. 2 experiment: D1Q3Q2 with a = 0.15, lambda / c0 = 8, s = 1.8,
+    rho_l / rho0 = 2, rho_r / rho0 = 0.5, q = 0 (rho0 = 1, g = 1), 80 points and
+    refinements, run to t = 0.15 (end time not stated; both waves stay inside).
+    The rarefaction and the shock are captured: L1 error of h to the exact
+    Riemann solution decreases under refinement, and the rest population stays
+    positive."""
+    from oracle import exact
+
+    sol = exact.riemann(2.0, 0.0, 0.5, 0.0, 1.0)
+    errs = []
+    for n in (80, 160, 320, 640):
+        x = W.cell_centres(n)
+        h0 = np.where(x < 0.5, 2.0, 0.5)
+        steps = int(round(0.15 * 8.0 * n))
+        P = orc.params(1, n, lam=8.0, s=1.8, a=0.15, bc=("neumann", "neumann", "periodic", "periodic"))
+        f = orc.run(P, h0, np.zeros(n), None, steps)
+        h, _ = orc.moments(P, f)
+        he, _ = sol.sample((x - 0.5) / (steps / n / 8.0))
+        errs.append(np.abs(h - he).mean())
+        assert f[0].min() > 0
+    assert all(b < a for a, b in zip(errs, errs[1:]))
+    assert errs[0] < 0.04 and errs[0] / errs[-1] > 4.0
