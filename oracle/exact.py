@@ -142,3 +142,17 @@ def rh_residual_2d(A, B, g=1.0):
     r_mass = hA * unA - hB * unB
     r_mom = (hA * unA * np.array([uA, vA]) + pA * n) - (hB * unB * np.array([uB, vB]) + pB * n)
     return n, np.array([r_mass, r_mom[0], r_mom[1]])
+
+
+def oblique_shock_reflection(x, y, left, top, right, g=1.0):
+    """Exact stationary solution of the Sec. 4 reflection on [0, L] x [0, 1]
+    with the wall at y = 0: the incident shock runs from (0, 1) at angle -pi/4
+    (line y = 1 - x), the reflected shock leaves the wall at (1, 0) along the
+    normal computed from the top and right states (rh_residual_2d).  Returns the
+    depth h at the points (x, y)."""
+    n2, _ = rh_residual_2d(top, right, g)
+    slope = -n2[0] / n2[1]
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    h = np.where(y > 1.0 - x, top[0], left[0])
+    return np.where((x > 1.0) & (y < slope * (x - 1.0)), right[0], h)

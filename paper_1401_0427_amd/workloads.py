@@ -164,3 +164,30 @@ def adjoint_case(n=1024, lam=3.0, s=1.8, steps=500, sigma=0.1, seed=0, amp=0.3, 
     noise = np.random.default_rng(seed).standard_normal((n, n)) * sigma
     return Case(2, n, n, lam, s, steps, h0=h0, qx0=np.zeros((n, n)), qy0=np.zeros((n, n)),
                 name=f"adjoint_2d_n{n}"), h0 + noise
+
+
+# --- stationary oblique shock reflection (Sec. 4, first test case) -------------------
+
+OBLIQUE_STATES = {  # (h, u, v) printed in Sec. 4 (g = 1)
+    "left": (1.0, 1.59497132403753, 0.0),
+    "top": (1.17150636388320, 1.47822089880855, -0.116750425228984),
+    "right": (1.38196199044604, 1.33228286727232, 0.0),
+}
+
+
+def oblique_shock_2d(ny=20, lam=8.0, s=1.8, steps=None, aspect=1.75) -> Case:
+    """Domain [0, aspect] x [0, 1] with ny rows (the Sec. 4 meshes are 35 x 20,
+    70 x 40, 140 x 80).  The left state enters through the left face and the top
+    state through the top face (equilibrium inflow ghosts), the bottom face is a
+    wall, the right face a zero-gradient outflow.  Starts from the left state
+    everywhere; `steps` defaults to about ten crossings of the domain."""
+    nx = int(round(aspect * ny))
+    hl, ul, vl = OBLIQUE_STATES["left"]
+    ht, ut, vt = OBLIQUE_STATES["top"]
+    if steps is None:
+        steps = 120 * ny
+    h0 = np.full((ny, nx), hl)
+    return Case(2, nx, ny, lam, s, steps, bc=("inflow", "neumann", "wall", "inflow"),
+                inflow={0: (hl, hl * ul, hl * vl), 3: (ht, ht * ut, ht * vt)},
+                h0=h0, qx0=np.full((ny, nx), hl * ul), qy0=np.zeros((ny, nx)),
+                name=f"oblique_shock_{nx}x{ny}")

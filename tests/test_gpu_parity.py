@@ -182,3 +182,15 @@ def test_init_rejects_nonpositive_depth():
     case.h0[3, 5] = 0.0
     with pytest.raises(LbmError, match="h > 0"):
         gpu_solver(case)
+
+
+@pytest.mark.parametrize("ny", [20, 40, 80])
+def test_oblique_shock_reflection_fp64_matches_oracle(ny):
+    """Sec. 4 stationary reflection on the paper's meshes (35 x 20, 70 x 40,
+    140 x 80): inflow faces (left, top), wall (bottom), outflow (right), run to
+    steady state -- the GPU state equals the oracle's."""
+    case = W.oblique_shock_2d(ny)
+    got, ref, S, P = _compare(case, case.steps)
+    err = per_plane_rel(got, ref)
+    say(f"  {case.name} {case.steps} steps: max plane rel err {err:.3e}")
+    assert err <= TOL64

@@ -465,3 +465,27 @@ def test_fig1_setup_d1q3q2_converges_to_exact_riemann(orc):
         assert f[0].min() > 0
     assert all(b < a for a, b in zip(errs, errs[1:]))
     assert errs[0] < 0.04 and errs[0] / errs[-1] > 4.0
+
+
+def test_oblique_shock_reflection_converges_to_rankine_hugoniot(orc):
+    """Sec. 4 first test case with the printed states, on the paper's three
+    meshes (35 x 20, 70 x 40, 140 x 80): the steady state approaches the exact
+    piecewise-constant solution (L1 of h decreasing under refinement) and the
+    reflected plateau reaches the right state's depth."""
+    from oracle import exact
+
+    errs = []
+    for ny in (20, 40, 80):
+        c = W.oblique_shock_2d(ny)
+        P = orc.params(2, c.nx, c.ny, lam=c.lam, s=c.s, bc=c.bc, inflow=c.inflow)
+        f = orc.run(P, c.h0, c.qx0, c.qy0, c.steps)
+        h = orc.moments(P, f)[0]
+        x = (np.arange(c.nx) + 0.5) / ny
+        X, Y = np.meshgrid(x, (np.arange(ny) + 0.5) / ny)
+        he = exact.oblique_shock_reflection(X, Y, *(W.OBLIQUE_STATES[k] for k in ("left", "top", "right")))
+        errs.append(np.abs(h - he).mean())
+        f2 = orc.advance(P, f, 100)  # steady: 100 more steps change nothing visible
+        assert np.abs(orc.moments(P, f2)[0] - h).max() < 1e-5
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[0] / errs[2] > 2.5
+    assert abs(h.max() - W.OBLIQUE_STATES["right"][0]) < 2e-3
