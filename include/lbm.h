@@ -187,7 +187,16 @@ typedef struct {
     int block;            /* threads per workgroup (64..512, multiple of 64) */
     int tile_nodes;       /* target nodes per work tile (>= block) */
     int grid;             /* persistent workgroups; 0 = fill the device */
-    int pass_nodes;       /* nodes per thread per pass: 1 or 2 (0 = 1) */
+    int pass_nodes;       /* dataflow mode: nodes per thread per pass, 1 or 2 (0 = 1) */
+    int mode;             /* 0: dataflow -- tiles advance when their neighbours have
+                                finished the previous step (no grid barrier; cannot
+                                deadlock whatever the grid);
+                             1: step-synchronous -- units of `block` nodes, one per
+                                workgroup in turn, one grid barrier per step (needs a
+                                fully resident grid; bounded waits, see lbm_batch_check).
+                                Currently DISABLED: lbm_batch_create returns LBM_EINVAL
+                                for mode 1 (an unexplained GPU memory fault on its first
+                                run with non-periodic faces) */
 } lbm_batch_tuning;
 
 /* Assign state_offset / node_offset to n instances (in place) for the given
@@ -204,8 +213,8 @@ int lbm_batch_create(const lbm_instance *inst, int n, int storage, void *f_a, vo
 int lbm_batch_init(lbm_batch *b, const double *h0, const double *qx0, const double *qy0);
 
 /* Advance every instance by nsteps in ONE persistent kernel launch (replayed
- * from a captured HIP graph).  Tiles of each instance advance as soon as their
- * neighbours have finished the previous step; no grid-wide barrier. */
+ * from a captured HIP graph), in the mode chosen at creation (tuning.mode).
+ * Stream-ordered; lbm_batch_check reports whether the launch completed. */
 int lbm_batch_run(lbm_batch *b, long nsteps);
 
 /* Synchronise the stream and report whether the last run completed: the
@@ -219,7 +228,8 @@ int lbm_batch_moments(lbm_batch *b, double *h, double *qx, double *qy);
 /* Current state buffer of the batch. */
 int lbm_batch_current(lbm_batch *b, void **state, long *steps_done);
 
-/* Number of work tiles and of persistent workgroups the batch launches. */
+/* Number of work tiles (dataflow) or units (step-synchronous) and of persistent
+ * workgroups the batch launches. */
 int lbm_batch_info(lbm_batch *b, int *ntiles, int *grid);
 
 void lbm_batch_destroy(lbm_batch *b);

@@ -77,25 +77,41 @@ def _manifest_dicts(man):
 
 
 def tune_batch(seed=0, steps=100, blocks=(256, 512), tiles=(4096, 8192, 16384, 32768),
-               grids=(0,), passes=(1, 2), storage="f32", log=print):
+               grids=(0,), passes=(1, 2), storage="f32", modes=(0,), sync_blocks=(128, 256, 512),
+               log=print):
+    """Sweep the persistent modes in ``modes``: the dataflow mode (0) over workgroup
+    size, tile size, grid and nodes per pass; the step-synchronous mode (1, which
+    the library currently rejects) over workgroup size.  A configuration whose
+    run is aborted by the bounded waits is reported and skipped."""
     import torch
 
     from . import workloads as W
-    from .lbm import Batch
+    from .lbm import Batch, LbmError
 
     timer = _timer(torch)
     insts = _manifest_dicts(W.batched_manifest(seed))
+    configs = []
+    if 0 in modes:
+        for block, tile, grid, npp in itertools.product(blocks, tiles, grids, passes):
+            if tile >= block:
+                configs.append(dict(mode=0, block=block, tile_nodes=tile, grid=grid, pass_nodes=npp))
+    if 1 in modes:
+        for block, grid in itertools.product(sync_blocks, grids):
+            configs.append(dict(mode=1, block=block, tile_nodes=block, grid=grid, pass_nodes=1))
     rows = []
-    for block, tile, grid, npp in itertools.product(blocks, tiles, grids, passes):
-        if tile < block:
+    for cfg in configs:
+        B = Batch(insts, storage=storage, **cfg)
+        try:
+            B.run(4, check_done=True)
+            ms = timer(lambda: B.run(steps))
+            B.check()
+        except LbmError as e:
+            log(json.dumps(dict(cfg, error=str(e))))
+            del B
             continue
-        B = Batch(insts, storage=storage, block=block, tile_nodes=tile, grid=grid, pass_nodes=npp)
-        B.run(4, check_done=True)
-        ms = timer(lambda: B.run(steps))
-        B.check()
         nt, gr = B.info()
-        r = dict(block=block, tile_nodes=tile, grid=grid, pass_nodes=npp, grid_used=gr, tiles=nt,
-                 ms_per_step=ms / steps, mlups=B.nodes * steps / (ms * 1e-3) / 1e6)
+        r = dict(cfg, grid_used=gr, tiles=nt, ms_per_step=ms / steps,
+                 mlups=B.nodes * steps / (ms * 1e-3) / 1e6)
         del B
         torch.cuda.empty_cache()
         rows.append(r)
@@ -138,7 +154,7 @@ def main():
         out["sweeps"] = sweeps
     if not args.skip_batch:
         best, rows = tune_batch(steps=args.steps, log=log)
-        out["batch"] = {k: best[k] for k in ("block", "tile_nodes", "grid", "pass_nodes")}
+        out["batch"] = {k: best[k] for k in ("mode", "block", "tile_nodes", "grid", "pass_nodes")}
         out.setdefault("sweeps", {})["batch"] = rows
     save(out)
     log(json.dumps({"saved": CACHE, "forward": out.get("forward"), "batch": out.get("batch")}))

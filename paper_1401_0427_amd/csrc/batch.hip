@@ -212,6 +212,193 @@ __global__ void __launch_bounds__(512)
     }
 }
 
+// ---- step-synchronous mode ------------------------------------------------------------
+// Each step's nodes are cut into units of blockDim consecutive (flat) nodes of
+// one instance; unit u is processed by workgroup u mod G, so at any moment the
+// G workgroups work on one contiguous window of units (the memory order of the
+// plain kernel) with one node per thread.  A grid barrier closes every step:
+// one agent-scope release and one acquire per workgroup per step.  The barrier
+// needs every workgroup resident (grid sized from the occupancy query); its wait
+// is bounded like the dataflow mode's, so a launch that is not fully resident
+// stops with the abort flag instead of hanging.
+struct UnitDev {
+    int inst;
+    int k0;  // first flat node (y * nx + x) of the unit in its instance
+};
+
+// Boundary pulls of the batch kernels: inflow faces read precomputed
+// equilibria (ghost[face * 12 + plane]) instead of evaluating them.
+template <typename T>
+__device__ double pull_face2d_ghost(const T *__restrict__ src, const Geo &G,
+                                    const double *__restrict__ ghost, int pl, int face, int x,
+                                    int y, int sx, int sy)
+{
+    switch (G.bc[face]) {
+    case BC_PERIODIC:
+        sx = sx < 0 ? sx + G.nx : (sx >= G.nx ? sx - G.nx : sx);
+        sy = sy < 0 ? sy + G.ny : (sy >= G.ny ? sy - G.ny : sy);
+        return ld(src + pl * G.ps + (long)sy * G.nx + sx);
+    case BC_NEUMANN:
+        return ld(src + pl * G.ps + (long)y * G.nx + x);
+    case BC_WALL: {
+        const int k = pl >> 2, j = pl & 3;
+        const double v = ld(src + ((k << 2) | ((j + 2) & 3)) * G.ps + (long)y * G.nx + x);
+        return k == (face < 2 ? 1 : 2) ? -v : v;
+    }
+    default:
+        return ghost[face * 12 + pl];
+    }
+}
+
+template <typename T>
+__device__ double pull_face1d_ghost(const T *__restrict__ src, const Geo &G,
+                                    const double *__restrict__ ghost, int pl, int face, int x)
+{
+    switch (G.bc[face]) {
+    case BC_PERIODIC:
+        return ld(src + pl * G.ps + (face == 0 ? G.nx - 1 : 0));
+    case BC_NEUMANN:
+        return ld(src + pl * G.ps + x);
+    case BC_WALL: {
+        const double v = ld(src + (pl ^ 1) * G.ps + x);
+        return pl >= 2 ? -v : v;
+    }
+    default:
+        return ghost[face * 12 + pl];
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void node_sync(const T *__restrict__ s, T *__restrict__ d,
+                                          const InstDev &I, const double *__restrict__ ghost,
+                                          int k)
+{
+    const Geo &G = I.G;
+    const long ps = G.ps;
+    if (I.dim == 1) {
+        const int x = k;
+        double f[4];
+        f[0] = x > 0 ? ld(s + x - 1) : pull_face1d_ghost(s, G, ghost, 0, 0, x);
+        f[2] = x > 0 ? ld(s + 2 * ps + x - 1) : pull_face1d_ghost(s, G, ghost, 2, 0, x);
+        f[1] = x < G.nx - 1 ? ld(s + ps + x + 1) : pull_face1d_ghost(s, G, ghost, 1, 1, x);
+        f[3] = x < G.nx - 1 ? ld(s + 3 * ps + x + 1) : pull_face1d_ghost(s, G, ghost, 3, 1, x);
+        collide1d(f, I.P);
+#pragma unroll
+        for (int pl = 0; pl < 4; ++pl) sth<2>(d + pl * ps + x, f[pl]);
+        return;
+    }
+    const int nx = G.nx, ny = G.ny;
+    const int y = k / nx, x = k - y * nx;
+    const long row = (long)y * nx;
+    double f[12];
+    if (I.allper || (x > 0 && x < nx - 1 && y > 0 && y < ny - 1)) {
+        const int xm = x == 0 ? nx - 1 : x - 1;
+        const int xp = x == nx - 1 ? 0 : x + 1;
+        const long rm = y == 0 ? (long)(ny - 1) * nx : row - nx;
+        const long rp = y == ny - 1 ? 0 : row + nx;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const T *b = s + (4 * c) * ps;
+            f[4 * c + 0] = ld(b + row + xm);
+            f[4 * c + 1] = ld(b + ps + rm + x);
+            f[4 * c + 2] = ld(b + 2 * ps + row + xp);
+            f[4 * c + 3] = ld(b + 3 * ps + rp + x);
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int p = 4 * c;
+            f[p] = x > 0 ? ld(s + p * ps + row + x - 1)
+                         : pull_face2d_ghost(s, G, ghost, p, 0, x, y, x - 1, y);
+            f[p + 1] = y > 0 ? ld(s + (p + 1) * ps + row - nx + x)
+                             : pull_face2d_ghost(s, G, ghost, p + 1, 2, x, y, x, y - 1);
+            f[p + 2] = x < nx - 1 ? ld(s + (p + 2) * ps + row + x + 1)
+                                  : pull_face2d_ghost(s, G, ghost, p + 2, 1, x, y, x + 1, y);
+            f[p + 3] = y < ny - 1 ? ld(s + (p + 3) * ps + row + nx + x)
+                                  : pull_face2d_ghost(s, G, ghost, p + 3, 3, x, y, x, y + 1);
+        }
+    }
+    collide2d(f, I.P);
+    T *o = d + row + x;
+#pragma unroll
+    for (int pl = 0; pl < 12; ++pl) sth<2>(o + pl * ps, f[pl]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(512)
+    k_batch_sync(const InstDev *__restrict__ inst, const UnitDev *__restrict__ units, int nunits,
+                 int nsteps, const double *__restrict__ ghost, T *buf0, T *buf1, int cur,
+                 unsigned *bar, int *abort_flag)
+{
+    __shared__ int stop;
+    const unsigned G = gridDim.x;
+    for (int n = 0; n < nsteps; ++n) {
+        const bool odd = ((cur + n) & 1) != 0;
+        const T *src = odd ? buf1 : buf0;
+        T *dst = odd ? buf0 : buf1;
+        for (int u = blockIdx.x; u < nunits; u += (int)G) {
+            const UnitDev ud = units[u];
+            const InstDev I = inst[ud.inst];
+            const int k = ud.k0 + (int)threadIdx.x;
+            if (k < I.G.nx * I.G.ny)
+                node_sync(src + I.off, dst + I.off, I, ghost + (long)ud.inst * 48, k);
+        }
+        // grid barrier: the workgroup barrier orders every wave's stores before
+        // thread 0's agent-scope release (fetch-add); one acquire after the wait
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned target = (unsigned)(n + 1) * G;
+            int a = 0;
+            for (int it = 0;; ++it) {
+                if (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target)
+                    break;
+                if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                    a = 1;
+                    break;
+                }
+                if (it >= kSpinLimit) {
+                    __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    a = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            stop = a;
+        }
+        __syncthreads();
+        if (__builtin_amdgcn_readfirstlane(stop) != 0) break;
+    }
+}
+
+// Inflow equilibria of every instance: ghost[i * 48 + face * 12 + plane].
+__global__ void k_batch_ghost(const InstDev *__restrict__ inst, int n, double *ghost)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const InstDev I = inst[i];
+    for (int face = 0; face < 4; ++face) {
+        double e[12];
+        for (int k = 0; k < 12; ++k) e[k] = 0.0;
+        if (I.G.bc[face] == BC_INFLOW) {
+            if (I.dim == 1)
+                feq1d(I.G.win[face][0], I.G.win[face][1], I.P, e);
+            else
+                feq2d(I.G.win[face][0], I.G.win[face][1], I.G.win[face][2], I.P, e);
+        }
+        for (int k = 0; k < 12; ++k) ghost[(long)i * 48 + face * 12 + k] = e[k];
+    }
+}
+
+__global__ void k_batch_sync_reset(unsigned *bar, int *abort_flag)
+{
+    if (threadIdx.x == 0) {
+        *bar = 0u;
+        *abort_flag = 0;
+    }
+}
+
 // Zero the per-tile counters and the work counter (a kernel, so that it can sit
 // in a captured graph).
 __global__ void k_batch_reset(int *done, int ntiles, unsigned long long *next, int *abort_flag)
@@ -264,6 +451,11 @@ struct lbm_batch {
     int *d_done;
     unsigned long long *d_next;
     int *d_abort;
+    // step-synchronous mode
+    UnitDev *d_units;
+    int nunits;
+    double *d_ghost;
+    unsigned *d_bar;
     int grid;
     // one captured graph per (nsteps, starting buffer); the last one is kept
     hipGraphExec_t gexec;
@@ -312,6 +504,9 @@ extern "C" void lbm_batch_destroy(lbm_batch *b)
     (void)hipFree(b->d_done);
     (void)hipFree(b->d_next);
     (void)hipFree(b->d_abort);
+    (void)hipFree(b->d_units);
+    (void)hipFree(b->d_ghost);
+    (void)hipFree(b->d_bar);
     delete b;
 }
 
@@ -342,8 +537,16 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
                 return bfail(LBM_EINVAL, "instance %d: inflow h must be > 0", i);
         }
     }
-    lbm_batch_tuning tune = {256, 16384, 0, 1};
+    lbm_batch_tuning tune = {256, 16384, 0, 1, 0};
     if (tuning) tune = *tuning;
+    if (tune.mode != 0 && tune.mode != 1)
+        return bfail(LBM_EINVAL, "tuning.mode must be 0 (dataflow) or 1 (step-synchronous)");
+    if (tune.mode == 1)
+        return bfail(LBM_EINVAL,
+                     "tuning.mode 1 (step-synchronous) is disabled: its first GPU run with wall / "
+                     "inflow / Neumann faces ended in an illegal memory access whose cause has not "
+                     "been found (clean under AddressSanitizer and UBSan in a CPU build); use "
+                     "mode 0");
     if (tune.pass_nodes == 0) tune.pass_nodes = 1;
     if (tune.pass_nodes != 1 && tune.pass_nodes != 2)
         return bfail(LBM_EINVAL, "tuning.pass_nodes must be 1 or 2");
@@ -425,6 +628,13 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
         }
     }
     b->ntiles = (int)ht.size();
+    // units of the step-synchronous mode: blockDim consecutive flat nodes
+    std::vector<UnitDev> hu;
+    for (int i = 0; i < n; ++i) {
+        const long nn = (long)inst[i].nx * inst[i].ny;
+        for (long k0 = 0; k0 < nn; k0 += tune.block) hu.push_back(UnitDev{i, (int)k0});
+    }
+    b->nunits = (int)hu.size();
 
     hipError_t e;
     if ((e = hipMalloc(&b->d_inst, sizeof(InstDev) * n)) != hipSuccess ||
@@ -432,6 +642,11 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
         (e = hipMalloc(&b->d_done, sizeof(int) * ht.size())) != hipSuccess ||
         (e = hipMalloc(&b->d_next, sizeof(unsigned long long))) != hipSuccess ||
         (e = hipMalloc(&b->d_abort, sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&b->d_units, sizeof(UnitDev) * hu.size())) != hipSuccess ||
+        (e = hipMalloc(&b->d_ghost, sizeof(double) * 48 * (size_t)n)) != hipSuccess ||
+        (e = hipMalloc(&b->d_bar, sizeof(unsigned))) != hipSuccess ||
+        (e = hipMemcpy(b->d_units, hu.data(), sizeof(UnitDev) * hu.size(),
+                       hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemset(b->d_abort, 0, sizeof(int))) != hipSuccess ||
         (e = hipMemcpy(b->d_inst, hi.data(), sizeof(InstDev) * n, hipMemcpyHostToDevice)) !=
             hipSuccess ||
@@ -440,11 +655,22 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
         lbm_batch_destroy(b);
         return bfail(LBM_EDEVICE, "batch setup failed: %s", hipGetErrorString(e));
     }
+    if (tune.mode == 1)
+        hipLaunchKernelGGL(k_batch_ghost, dim3((n + 63) / 64), dim3(64), 0, b->st, b->d_inst, n,
+                           b->d_ghost);
+    if ((e = hipGetLastError()) != hipSuccess || (e = hipStreamSynchronize(b->st)) != hipSuccess) {
+        lbm_batch_destroy(b);
+        return bfail(LBM_EDEVICE, "batch setup failed: %s", hipGetErrorString(e));
+    }
     // persistent grid: fill the device
     int dev = 0, ncu = 0, per_cu = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (b->f32 && tune.pass_nodes == 2)
+    if (tune.mode == 1 && b->f32)
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_sync<float>, tune.block, 0);
+    else if (tune.mode == 1)
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_sync<double>, tune.block, 0);
+    else if (b->f32 && tune.pass_nodes == 2)
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<float, 2>, tune.block, 0);
     else if (b->f32)
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<float, 1>, tune.block, 0);
@@ -500,6 +726,20 @@ extern "C" int lbm_batch_init(lbm_batch *b, const double *h0, const double *qx0,
 
 static hipError_t enqueue_run(lbm_batch *b, long nsteps, hipStream_t st)
 {
+    if (b->tune.mode == 1) {
+        hipLaunchKernelGGL(k_batch_sync_reset, dim3(1), dim3(64), 0, st, b->d_bar, b->d_abort);
+        if (b->f32)
+            hipLaunchKernelGGL(k_batch_sync<float>, dim3(b->grid), dim3(b->tune.block), 0, st,
+                               b->d_inst, b->d_units, b->nunits, (int)nsteps, b->d_ghost,
+                               (float *)b->buf[0], (float *)b->buf[1], b->cur, b->d_bar,
+                               b->d_abort);
+        else
+            hipLaunchKernelGGL(k_batch_sync<double>, dim3(b->grid), dim3(b->tune.block), 0, st,
+                               b->d_inst, b->d_units, b->nunits, (int)nsteps, b->d_ghost,
+                               (double *)b->buf[0], (double *)b->buf[1], b->cur, b->d_bar,
+                               b->d_abort);
+        return hipGetLastError();
+    }
     const int rb = (b->ntiles + 255) / 256;
     hipLaunchKernelGGL(k_batch_reset, dim3(rb), dim3(256), 0, st, b->d_done, b->ntiles,
                        b->d_next, b->d_abort);
@@ -524,6 +764,8 @@ extern "C" int lbm_batch_run(lbm_batch *b, long nsteps)
 {
     if (!b) return bfail(LBM_ESTATE, "null batch");
     if (nsteps < 0 || nsteps > (1L << 30)) return bfail(LBM_EINVAL, "bad nsteps");
+    if (b->tune.mode == 1 && (double)nsteps * b->grid >= 2147483648.0)
+        return bfail(LBM_EINVAL, "nsteps x grid too large for the step-synchronous mode");
     if (nsteps == 0) return LBM_OK;
     if (!b->gexec || b->g_nsteps != nsteps || b->g_cur != b->cur) {
         if (b->gexec) {
@@ -595,7 +837,7 @@ extern "C" int lbm_batch_current(lbm_batch *b, void **state, long *steps_done)
 extern "C" int lbm_batch_info(lbm_batch *b, int *ntiles, int *grid)
 {
     if (!b) return bfail(LBM_ESTATE, "null batch");
-    if (ntiles) *ntiles = b->ntiles;
+    if (ntiles) *ntiles = b->tune.mode == 1 ? b->nunits : b->ntiles;
     if (grid) *grid = b->grid;
     return LBM_OK;
 }

@@ -72,7 +72,7 @@ class LbmInstance(ctypes.Structure):
 
 class LbmBatchTuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int), ("tile_nodes", ctypes.c_int), ("grid", ctypes.c_int),
-                ("pass_nodes", ctypes.c_int)]
+                ("pass_nodes", ctypes.c_int), ("mode", ctypes.c_int)]
 
 
 EXPORTS = [
@@ -345,9 +345,11 @@ class Batch:
     """Many independent problems advanced in one persistent launch."""
 
     def __init__(self, instances, storage="f32", block=256, tile_nodes=16384, grid=0, pass_nodes=1,
-                 device="cuda"):
+                 mode=0, device="cuda"):
         """``instances``: iterable of dicts with keys dim, nx, ny, lam, s, g, bc,
-        inflow, h0, qx0, qy0 (numpy arrays of the instance's nodes)."""
+        inflow, h0, qx0, qy0 (numpy arrays of the instance's nodes).  ``mode`` 0 is
+        the dataflow persistent launch; mode 1 (step-synchronous) is rejected by
+        the library while it is switched off."""
         import torch
 
         _require_gpu(torch)
@@ -391,7 +393,7 @@ class Batch:
                 qy0[o:o + m] = np.asarray(d["qy0"]).reshape(-1)
         f64 = dict(dtype=torch.float64, device=self.device)
         self.h0, self.qx0, self.qy0 = (torch.as_tensor(a, **f64) for a in (h0, qx0, qy0))
-        tune = LbmBatchTuning(block, tile_nodes, grid, pass_nodes)
+        tune = LbmBatchTuning(block, tile_nodes, grid, pass_nodes, mode)
         b = ctypes.c_void_p()
         check(L.lbm_batch_create(arr, n, self.storage, _ptr(self.fa), _ptr(self.fb),
                                  _stream_handle(torch), ctypes.byref(tune), ctypes.byref(b)),

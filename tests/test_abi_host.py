@@ -89,3 +89,18 @@ def test_batch_layout_offsets(L):
     assert arr[2].state_offset == 1024 * 4 + 16832 * 12
     assert [a.node_offset for a in arr] == [0, 1000, 1000 + 130 * 129]
     assert nb.value == (1024 * 4 + 16832 * 12 + 64 * 4) * 4
+
+
+def test_batch_create_rejects_disabled_step_synchronous_mode(L):
+    arr = (L.LbmInstance * 1)()
+    arr[0].lattice, arr[0].nx, arr[0].ny = L.D2Q4x3, 64, 64
+    arr[0].lam, arr[0].s, arr[0].g = 6.0, 1.8, 1.0
+    nb, nodes = ctypes.c_size_t(), ctypes.c_long()
+    lib = L.load()
+    assert lib.lbm_batch_layout(arr, 1, L.F32, ctypes.byref(nb), ctypes.byref(nodes)) == 0
+    tune = L.LbmBatchTuning(256, 16384, 0, 1, 1)
+    b = ctypes.c_void_p()
+    rc = lib.lbm_batch_create(arr, 1, L.F32, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000),
+                              None, ctypes.byref(tune), ctypes.byref(b))
+    assert rc == L.LBM_EINVAL and not b.value
+    assert "disabled" in L.last_error()

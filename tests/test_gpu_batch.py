@@ -20,51 +20,76 @@ def _gpu():
     lbm.load()
 
 
-def instance_dicts(manifest):
+def instance_dicts(manifest, mixed_bc=False):
+    """Neumann ends in 1D, periodic in 2D; with ``mixed_bc`` instance i instead
+    takes the i-th of a cycle of boundary sets covering every face kind."""
+    cyc1 = [("inflow", "wall"), ("wall", "neumann"), ("periodic", "periodic"), ("neumann", "inflow")]
+    cyc2 = [("inflow", "neumann", "wall", "inflow"), ("wall", "wall", "periodic", "periodic"),
+            ("periodic", "periodic", "inflow", "wall"), ("neumann", "inflow", "neumann", "wall")]
     out = []
-    for m in manifest:
+    for i, m in enumerate(manifest):
         h, qx, qy = m.initial()
         bc = ("neumann", "neumann", "periodic", "periodic") if m.dim == 1 else ("periodic",) * 4
-        out.append(dict(dim=m.dim, nx=m.nx, ny=m.ny, lam=m.lam, s=m.s, g=W.G, bc=bc, h0=h,
-                        qx0=qx, qy0=qy))
+        if mixed_bc:
+            bc = cyc1[i % 4] + ("periodic", "periodic") if m.dim == 1 else cyc2[i % 4]
+        inflow = {f: (m.hl, m.hl * m.ul, m.hl * m.vl if m.dim == 2 else 0.0)
+                  for f in range(4) if bc[f] == "inflow"}
+        out.append(dict(dim=m.dim, nx=m.nx, ny=m.ny, lam=m.lam, s=m.s, g=W.G, bc=bc,
+                        inflow=inflow, h0=h, qx0=qx, qy0=qy))
     return out
 
 
 def oracle_moments(d, steps):
-    P = oracle.params(d["dim"], d["nx"], d["ny"], lam=d["lam"], s=d["s"], g=d["g"], bc=d["bc"])
+    P = oracle.params(d["dim"], d["nx"], d["ny"], lam=d["lam"], s=d["s"], g=d["g"], bc=d["bc"],
+                      inflow=d.get("inflow"))
     f = oracle.run(P, d["h0"], d["qx0"], d["qy0"] if d["dim"] == 2 else None, steps)
     return oracle.moments(P, f)
 
 
-@pytest.mark.parametrize("tune", [dict(block=256, tile_nodes=256), dict(block=64, tile_nodes=100),
-                                  dict(block=512, tile_nodes=4096, grid=7)])
-def test_batch_small_manifest_fp64_matches_oracle(tune):
+MODE1_OFF = pytest.mark.skip(
+    reason="step-synchronous batch mode disabled: its first GPU run (block 256, mixed wall / "
+           "inflow / Neumann faces) ended in an illegal memory access whose cause is not found "
+           "yet (clean under ASan and UBSan in a CPU build); not run on the GPU again until a "
+           "cause is shown")
+
+TUNES = [dict(block=256, tile_nodes=256), dict(block=64, tile_nodes=100),
+         dict(block=512, tile_nodes=4096, grid=7),
+         pytest.param(dict(block=256, mode=1), marks=MODE1_OFF),
+         pytest.param(dict(block=64, mode=1, grid=5), marks=MODE1_OFF),
+         pytest.param(dict(block=512, mode=1), marks=MODE1_OFF)]
+
+
+@pytest.mark.parametrize("mixed_bc", [False, True])
+@pytest.mark.parametrize("tune", TUNES)
+def test_batch_small_manifest_fp64_matches_oracle(tune, mixed_bc):
     from paper_1401_0427_amd.lbm import Batch
 
-    insts = instance_dicts(W.small_manifest(seed=1))
+    insts = instance_dicts(W.small_manifest(seed=1), mixed_bc)
     steps = 157
-    say(f"[batch] {len(insts)} instances, {steps} steps, {tune}")
+    say(f"[batch] {len(insts)} instances, {steps} steps, {tune}, mixed_bc={mixed_bc}")
     B = Batch(insts, storage="f64", **tune)
     nt, grid = B.info()
     say(f"  tiles {nt}, grid {grid}")
     B.run(steps)
-    h, qx, qy = (to_np(t) for t in B.moments())
+    mom = [to_np(t) for t in B.moments()]
     worst = 0.0
     for i, d in enumerate(insts):
         ref = oracle_moments(d, steps)
-        got = [to_np(B.instance_view(i, t)) for t in B.moments()[: 2 if d["dim"] == 1 else 3]]
+        got = [B.instance_view(i, t) for t in mom[: 2 if d["dim"] == 1 else 3]]
         e = max(normwise_rel(a, b) for a, b in zip(got, ref))
         worst = max(worst, e)
     say(f"  worst instance rel err {worst:.3e}")
     assert worst <= 1e-12
 
 
-def test_batch_run_twice_equals_one_long_run():
+@pytest.mark.parametrize("mode", [0, pytest.param(1, marks=MODE1_OFF)])
+def test_batch_run_twice_equals_one_long_run(mode):
     from paper_1401_0427_amd.lbm import Batch
 
-    insts = instance_dicts(W.small_manifest(seed=2))
-    A = Batch(insts, storage="f64", tile_nodes=256)
-    B = Batch(insts, storage="f64", tile_nodes=256)
+    insts = instance_dicts(W.small_manifest(seed=2), mixed_bc=True)
+    say(f"[batch run twice] mode {mode}")
+    A = Batch(insts, storage="f64", tile_nodes=256, mode=mode)
+    B = Batch(insts, storage="f64", tile_nodes=256, mode=mode)
     A.run(51)
     A.run(50)
     B.run(101)
@@ -72,17 +97,19 @@ def test_batch_run_twice_equals_one_long_run():
         assert np.array_equal(to_np(a), to_np(b))
 
 
-def test_batch_fp32_l1():
+@pytest.mark.parametrize("mode", [0, pytest.param(1, marks=MODE1_OFF)])
+def test_batch_fp32_l1(mode):
     from paper_1401_0427_amd.lbm import Batch
 
     insts = instance_dicts(W.small_manifest(seed=3))
     steps = 300
-    B = Batch(insts, storage="f32", tile_nodes=512)
+    say(f"[batch fp32] mode {mode}")
+    B = Batch(insts, storage="f32", tile_nodes=512, mode=mode)
     B.run(steps)
     worst = 0.0
     hs = B.moments()[0]
     for i, d in enumerate(insts):
         ref = oracle_moments(d, steps)[0]
         worst = max(worst, l1_rel(to_np(B.instance_view(i, hs)), ref))
-    say(f"[batch fp32] worst L1 rel of h {worst:.3e}")
+    say(f"  worst L1 rel of h {worst:.3e}")
     assert worst <= 1e-5
