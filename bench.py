@@ -94,7 +94,8 @@ def time_batched(torch, steps=1000):
         tune = json.load(open(tpath)).get("batch", {})
     B = Batch(insts, storage="f32", **tune)
     nodes = B.nodes
-    B.run(10)
+    B.run(64, check_done=True)  # warm-up; captures the flat mode's graphs
+    B.run(steps)  # same length as the timed run: the dataflow graph is captured here
     torch.cuda.synchronize()
     st = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

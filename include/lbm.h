@@ -185,8 +185,8 @@ typedef struct {
 
 typedef struct {
     int block;            /* threads per workgroup (64..512, multiple of 64) */
-    int tile_nodes;       /* target nodes per work tile (>= block) */
-    int grid;             /* persistent workgroups; 0 = fill the device */
+    int tile_nodes;       /* dataflow mode: target nodes per work tile (>= block) */
+    int grid;             /* persistent modes: workgroups; 0 = fill the device */
     int pass_nodes;       /* dataflow mode: nodes per thread per pass, 1 or 2 (0 = 1) */
     int mode;             /* 0: dataflow -- tiles advance when their neighbours have
                                 finished the previous step (no grid barrier; cannot
@@ -196,7 +196,12 @@ typedef struct {
                                 fully resident grid; bounded waits, see lbm_batch_check).
                                 Currently DISABLED: lbm_batch_create returns LBM_EINVAL
                                 for mode 1 (an unexplained GPU memory fault on its first
-                                run with non-periodic faces) */
+                                run with non-periodic faces);
+                             2: flat -- one ordinary launch per step over all instances,
+                                one workgroup per unit of `block` nodes; the launch
+                                boundary is the step barrier; chunks of 32 steps replay
+                                a captured HIP graph.  tile_nodes, grid and pass_nodes
+                                are ignored. */
 } lbm_batch_tuning;
 
 /* Assign state_offset / node_offset to n instances (in place) for the given
@@ -212,9 +217,10 @@ int lbm_batch_create(const lbm_instance *inst, int n, int storage, void *f_a, vo
 /* Level-0 state of every instance from packed device double fields (node_offset). */
 int lbm_batch_init(lbm_batch *b, const double *h0, const double *qx0, const double *qy0);
 
-/* Advance every instance by nsteps in ONE persistent kernel launch (replayed
- * from a captured HIP graph), in the mode chosen at creation (tuning.mode).
- * Stream-ordered; lbm_batch_check reports whether the launch completed. */
+/* Advance every instance by nsteps in the mode chosen at creation (tuning.mode):
+ * dataflow -- ONE persistent kernel launch (replayed from a captured HIP graph);
+ * flat -- one launch per step (graph chunks of 32 steps).  Stream-ordered;
+ * lbm_batch_check reports whether a dataflow launch completed. */
 int lbm_batch_run(lbm_batch *b, long nsteps);
 
 /* Synchronise the stream and report whether the last run completed: the

@@ -2,8 +2,9 @@
 
 * ``tune_forward``: workgroup size, nodes per thread, plane padding and memory
   hints of the fused stream + collide kernel for one grid and storage type.
-* ``tune_batch``: workgroup size and tile size (and optionally the persistent
-  grid) of the batched launch for a manifest.
+* ``tune_batch``: mode (persistent dataflow or flat per-step launches),
+  workgroup size, tile size and nodes per pass of the batched launch for a
+  manifest.
 
 Results are cached in ``paper_1401_0427_amd/tuning.json`` (read by bench.py):
     {"forward": {"f64": {...}, "f32": {...}}, "batch": {...}, "sweeps": {...}}
@@ -77,12 +78,13 @@ def _manifest_dicts(man):
 
 
 def tune_batch(seed=0, steps=100, blocks=(256, 512), tiles=(4096, 8192, 16384, 32768),
-               grids=(0,), passes=(1, 2), storage="f32", modes=(0,), sync_blocks=(128, 256, 512),
-               log=print):
-    """Sweep the persistent modes in ``modes``: the dataflow mode (0) over workgroup
-    size, tile size, grid and nodes per pass; the step-synchronous mode (1, which
-    the library currently rejects) over workgroup size.  A configuration whose
-    run is aborted by the bounded waits is reported and skipped."""
+               grids=(0,), passes=(1, 2), storage="f32", modes=(0, 2),
+               unit_blocks=(128, 256, 512), log=print):
+    """Sweep the batch modes in ``modes``: the dataflow mode (0) over workgroup
+    size, tile size, grid and nodes per pass; the step-synchronous (1, which the
+    library currently rejects) and flat (2) modes over workgroup size (= nodes
+    per unit).  A configuration whose run is aborted by the bounded waits is
+    reported and skipped."""
     import torch
 
     from . import workloads as W
@@ -96,13 +98,16 @@ def tune_batch(seed=0, steps=100, blocks=(256, 512), tiles=(4096, 8192, 16384, 3
             if tile >= block:
                 configs.append(dict(mode=0, block=block, tile_nodes=tile, grid=grid, pass_nodes=npp))
     if 1 in modes:
-        for block, grid in itertools.product(sync_blocks, grids):
+        for block, grid in itertools.product(unit_blocks, grids):
             configs.append(dict(mode=1, block=block, tile_nodes=block, grid=grid, pass_nodes=1))
+    if 2 in modes:
+        for block in unit_blocks:
+            configs.append(dict(mode=2, block=block, tile_nodes=block, grid=0, pass_nodes=1))
     rows = []
     for cfg in configs:
         B = Batch(insts, storage=storage, **cfg)
         try:
-            B.run(4, check_done=True)
+            B.run(steps, check_done=True)  # also captures the graphs the timed run replays
             ms = timer(lambda: B.run(steps))
             B.check()
         except LbmError as e:

@@ -212,6 +212,49 @@ __global__ void __launch_bounds__(512)
     }
 }
 
+// Unit of the flat and step-synchronous modes: blockDim consecutive flat nodes
+// of one instance.
+struct UnitDev {
+    int inst;
+    int k0;  // first flat node (y * nx + x) of the unit in its instance
+};
+
+// ---- flat mode -------------------------------------------------------------------
+// One ordinary launch per step over every instance: workgroup u takes unit u
+// (blockDim consecutive flat nodes y * nx + x of one instance), one node per
+// thread, with the same pull / collide code as the tiles above.  The launch
+// boundary is the step barrier, so there are no counters, waits or fences;
+// the steps are replayed from a captured HIP graph.
+template <typename T>
+__global__ void __launch_bounds__(512)
+    k_batch_flat(const InstDev *__restrict__ inst, const UnitDev *__restrict__ units,
+                 const T *__restrict__ src, T *__restrict__ dst)
+{
+    const UnitDev ud = units[blockIdx.x];
+    const InstDev I = inst[ud.inst];
+    const int k = ud.k0 + (int)threadIdx.x;
+    const int nx = I.G.nx;
+    if (k >= nx * I.G.ny) return;
+    const long ps = I.G.ps;
+    const T *s = src + I.off;
+    T *d = dst + I.off;
+    if (I.dim == 1) {
+        double f[4];
+        pull1d(s, I.G, I.P, k, f);
+        collide1d(f, I.P);
+#pragma unroll
+        for (int pl = 0; pl < 4; ++pl) sth<2>(d + pl * ps + k, f[pl]);
+        return;
+    }
+    const int y = k / nx, x = k - y * nx;
+    double f[12];
+    pull_node2d(s, I, x, y, f);
+    collide2d(f, I.P);
+    T *o = d + k;
+#pragma unroll
+    for (int pl = 0; pl < 12; ++pl) sth<2>(o + pl * ps, f[pl]);
+}
+
 // ---- step-synchronous mode ------------------------------------------------------------
 // Each step's nodes are cut into units of blockDim consecutive (flat) nodes of
 // one instance; unit u is processed by workgroup u mod G, so at any moment the
@@ -221,10 +264,6 @@ __global__ void __launch_bounds__(512)
 // needs every workgroup resident (grid sized from the occupancy query); its wait
 // is bounded like the dataflow mode's, so a launch that is not fully resident
 // stops with the abort flag instead of hanging.
-struct UnitDev {
-    int inst;
-    int k0;  // first flat node (y * nx + x) of the unit in its instance
-};
 
 // Boundary pulls of the batch kernels: inflow faces read precomputed
 // equilibria (ghost[face * 12 + plane]) instead of evaluating them.
@@ -457,6 +496,8 @@ struct lbm_batch {
     double *d_ghost;
     unsigned *d_bar;
     int grid;
+    // flat mode: one captured graph of kFlatChunk steps per starting buffer
+    hipGraphExec_t fexec[2];
     // one captured graph per (nsteps, starting buffer); the last one is kept
     hipGraphExec_t gexec;
     long g_nsteps;
@@ -498,6 +539,8 @@ extern "C" void lbm_batch_destroy(lbm_batch *b)
 {
     if (!b) return;
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    for (int p = 0; p < 2; ++p)
+        if (b->fexec[p]) (void)hipGraphExecDestroy(b->fexec[p]);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     (void)hipFree(b->d_inst);
     (void)hipFree(b->d_tiles);
@@ -539,8 +582,9 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
     }
     lbm_batch_tuning tune = {256, 16384, 0, 1, 0};
     if (tuning) tune = *tuning;
-    if (tune.mode != 0 && tune.mode != 1)
-        return bfail(LBM_EINVAL, "tuning.mode must be 0 (dataflow) or 1 (step-synchronous)");
+    if (tune.mode < 0 || tune.mode > 2)
+        return bfail(LBM_EINVAL,
+                     "tuning.mode must be 0 (dataflow), 1 (step-synchronous) or 2 (flat)");
     if (tune.mode == 1)
         return bfail(LBM_EINVAL,
                      "tuning.mode 1 (step-synchronous) is disabled: its first GPU run with wall / "
@@ -552,7 +596,8 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
         return bfail(LBM_EINVAL, "tuning.pass_nodes must be 1 or 2");
     if (tune.block < 64 || tune.block > 512 || tune.block % 64)
         return bfail(LBM_EINVAL, "tuning.block must be a multiple of 64 in [64, 512]");
-    if (tune.tile_nodes < tune.block) return bfail(LBM_EINVAL, "tuning.tile_nodes < block");
+    if (tune.mode == 0 && tune.tile_nodes < tune.block)
+        return bfail(LBM_EINVAL, "tuning.tile_nodes < block");
     if (tune.grid < 0) return bfail(LBM_EINVAL, "tuning.grid must be >= 0");
 
     lbm_batch *b = new (std::nothrow) lbm_batch();
@@ -634,6 +679,10 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
         const long nn = (long)inst[i].nx * inst[i].ny;
         for (long k0 = 0; k0 < nn; k0 += tune.block) hu.push_back(UnitDev{i, (int)k0});
     }
+    if (hu.size() > (size_t)INT32_MAX) {
+        lbm_batch_destroy(b);
+        return bfail(LBM_EINVAL, "too many units for one launch: raise tuning.block");
+    }
     b->nunits = (int)hu.size();
 
     hipError_t e;
@@ -666,7 +715,9 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
     int dev = 0, ncu = 0, per_cu = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (tune.mode == 1 && b->f32)
+    if (tune.mode == 2)
+        per_cu = 1;  // ordinary launches: one workgroup per unit
+    else if (tune.mode == 1 && b->f32)
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_sync<float>, tune.block, 0);
     else if (tune.mode == 1)
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_sync<double>, tune.block, 0);
@@ -680,7 +731,7 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<double, 1>, tune.block, 0);
     if (ncu <= 0) ncu = 256;
     if (per_cu <= 0) per_cu = 1;
-    b->grid = tune.grid > 0 ? tune.grid : ncu * per_cu;
+    b->grid = tune.mode == 2 ? b->nunits : (tune.grid > 0 ? tune.grid : ncu * per_cu);
     *out = b;
     return LBM_OK;
 }
@@ -760,10 +811,62 @@ static hipError_t enqueue_run(lbm_batch *b, long nsteps, hipStream_t st)
     return hipGetLastError();
 }
 
+static void launch_flat(lbm_batch *b, int cur, hipStream_t st)
+{
+    void *src = b->buf[cur], *dst = b->buf[cur ^ 1];
+    if (b->f32)
+        hipLaunchKernelGGL(k_batch_flat<float>, dim3(b->nunits), dim3(b->tune.block), 0, st,
+                           b->d_inst, b->d_units, (const float *)src, (float *)dst);
+    else
+        hipLaunchKernelGGL(k_batch_flat<double>, dim3(b->nunits), dim3(b->tune.block), 0, st,
+                           b->d_inst, b->d_units, (const double *)src, (double *)dst);
+}
+
+// Flat mode: whole chunks of kFlatChunk steps (an even number, so the chunk
+// starts and ends on the same buffer) replay one captured graph per starting
+// buffer; the remaining steps are launched one by one.
+static constexpr long kFlatChunk = 32;
+
+static int run_flat(lbm_batch *b, long nsteps)
+{
+    long left = nsteps;
+    if (left >= kFlatChunk && !b->fexec[b->cur]) {
+        if (!b->cap) BHIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        BHIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+        for (long k = 0; k < kFlatChunk; ++k) launch_flat(b, (int)((b->cur + k) & 1), b->cap);
+        hipError_t le = hipGetLastError();
+        hipError_t ee = hipStreamEndCapture(b->cap, &g);
+        if (le != hipSuccess || ee != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return bfail(LBM_EDEVICE, "batch graph capture failed: %s",
+                         hipGetErrorString(le != hipSuccess ? le : ee));
+        }
+        hipError_t ie = hipGraphInstantiate(&b->fexec[b->cur], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) {
+            b->fexec[b->cur] = nullptr;
+            return bfail(LBM_EDEVICE, "batch graph instantiate failed: %s", hipGetErrorString(ie));
+        }
+    }
+    for (; left >= kFlatChunk; left -= kFlatChunk) {
+        BHIP(hipGraphLaunch(b->fexec[b->cur], b->st));
+        b->steps += kFlatChunk;
+    }
+    for (; left > 0; --left) {
+        launch_flat(b, b->cur, b->st);
+        BHIP(hipGetLastError());
+        b->cur ^= 1;
+        ++b->steps;
+    }
+    return LBM_OK;
+}
+
 extern "C" int lbm_batch_run(lbm_batch *b, long nsteps)
 {
     if (!b) return bfail(LBM_ESTATE, "null batch");
     if (nsteps < 0 || nsteps > (1L << 30)) return bfail(LBM_EINVAL, "bad nsteps");
+    if (b->tune.mode == 2) return run_flat(b, nsteps);
     if (b->tune.mode == 1 && (double)nsteps * b->grid >= 2147483648.0)
         return bfail(LBM_EINVAL, "nsteps x grid too large for the step-synchronous mode");
     if (nsteps == 0) return LBM_OK;
@@ -837,7 +940,7 @@ extern "C" int lbm_batch_current(lbm_batch *b, void **state, long *steps_done)
 extern "C" int lbm_batch_info(lbm_batch *b, int *ntiles, int *grid)
 {
     if (!b) return bfail(LBM_ESTATE, "null batch");
-    if (ntiles) *ntiles = b->tune.mode == 1 ? b->nunits : b->ntiles;
+    if (ntiles) *ntiles = b->tune.mode != 0 ? b->nunits : b->ntiles;
     if (grid) *grid = b->grid;
     return LBM_OK;
 }
