@@ -68,8 +68,11 @@ def lib():
         _lib.orc_loss_grad_2d.argtypes = [pp, dp, dp, ctypes.c_long, ctypes.c_int, dp, dp, dp]
         _lib.orc_loss_cs_2d.argtypes = [pp, dp, dp, ctypes.c_double, dp, ctypes.c_long,
                                         ctypes.c_double, dp, dp]
+        _lib.orc_entropy.argtypes = [pp, dp, dp, dp, ctypes.POINTER(ctypes.c_long)]
+        _lib.orc_entropy_pop.argtypes = [pp, ctypes.c_int, dp, dp, dp, dp]
         for name in ("orc_feq", "orc_collide", "orc_run", "orc_advance", "orc_moments",
-                     "orc_adjoint_step", "orc_loss_grad_2d", "orc_loss_cs_2d"):
+                     "orc_adjoint_step", "orc_loss_grad_2d", "orc_loss_cs_2d", "orc_entropy",
+                     "orc_entropy_pop"):
             getattr(_lib, name).restype = ctypes.c_int
     return _lib
 
@@ -198,6 +201,34 @@ def loss_complex_step_2d(P: OrcParams, h0, hhat, T, dh0=None, ds=0.0, eps=1e-30)
     if rc != 0:
         raise ValueError(f"orc_loss_cs_2d failed ({rc})")
     return loss.value, dl.value
+
+
+def entropy(P: OrcParams, f):
+    """Discrete microscopic entropy of a distribution (a = 0): returns
+    (per-node H, total H, number of populations outside the convexity domain)."""
+    f = _f64(f).reshape(-1)
+    n = P.nx * P.ny
+    hn = np.zeros(n)
+    tot = ctypes.c_double(0.0)
+    bad = ctypes.c_long(0)
+    rc = lib().orc_entropy(ctypes.byref(P), _dp(f), _dp(hn), ctypes.byref(tot), ctypes.byref(bad))
+    if rc != 0:
+        raise ValueError(f"orc_entropy failed ({rc})")
+    return (hn if P.dim == 1 else hn.reshape(P.ny, P.nx)), tot.value, bad.value
+
+
+def entropy_pop(P: OrcParams, j, F, W0):
+    """Entropy of one population j (1D: 0 = +, 1 = -; 2D: 0..3 = e_1..e_4) with
+    components F, Newton started from the entropy variables of W0.  Returns
+    (valid, h, phi)."""
+    F = _f64(F)
+    W0 = _f64(np.asarray(list(W0) + [0.0] * (3 - len(W0))))
+    h = ctypes.c_double(0.0)
+    phi = np.zeros(3)
+    rc = lib().orc_entropy_pop(ctypes.byref(P), int(j), _dp(F), _dp(W0), ctypes.byref(h), _dp(phi))
+    if rc < 0:
+        raise ValueError(f"orc_entropy_pop failed ({rc})")
+    return rc == 0, h.value, phi[: (2 if P.dim == 1 else 3)]
 
 
 def to_hotpath_planes(f):

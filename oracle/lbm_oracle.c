@@ -549,3 +549,228 @@ int orc_loss_cs_2d(const orc_params *P, const double *h0, const double *dh0, dou
     free(mem); free(hc);
     return 0;
 }
+
+/* ---- discrete microscopic entropy (Sec. 1, a = 0) --------------------------
+ * Perthame-Bouchut potentials of the hot-path lattices, from Sec. 2 (1D,
+ * eq. 2-potentiels-st-venant-1d-suite) and Sec. 3 (2D, eqs. 3-st-venant-
+ * contraintes-2 and 3-st-venant-enplus) at a = 0, with phi = (theta, U) the
+ * entropy variables, P = theta + |U|^2 / 2 and p = K P^2 (K = 1/(2g)):
+ *   h_j^*(phi) = p(phi) (alpha + e_j . U / (2 lambda)),
+ *   alpha = 1/2 (1D, e = +-1) or 1/4 (2D, e_j the four unit vectors).
+ * The microscopic entropy of population j with components F = (f_j, g_j ...)
+ * is the Legendre dual h_j(F) = sup_phi (phi . F - h_j^*(phi)), taken over the
+ * domain where h_j^* is convex: the stationary point grad h_j^*(phi) = F is
+ * found by Newton's method on the full system (Hessian of h_j^* as Jacobian),
+ * started from the entropy variables of the node's conserved fields, and is
+ * accepted only if the Hessian there is positive definite.  Outside that
+ * domain the entropy is reported as +infinity. */
+static void ent_pot(int dim, int j, double K, double lam, const double *phi, double *hs,
+                    double *grad, double hess[3][3])
+{
+    const int n = dim == 1 ? 2 : 3;
+    double e[2] = {0.0, 0.0};
+    double alpha;
+    if (dim == 1) {
+        e[0] = j == 0 ? 1.0 : -1.0;
+        alpha = 0.5;
+    } else {
+        static const double ex[4] = {1, 0, -1, 0}, ey[4] = {0, 1, 0, -1};
+        e[0] = ex[j];
+        e[1] = ey[j];
+        alpha = 0.25;
+    }
+    const double *U = phi + 1;
+    double U2 = 0.0, eU = 0.0;
+    for (int a = 0; a < n - 1; ++a) {
+        U2 += U[a] * U[a];
+        eU += e[a] * U[a];
+    }
+    const double P = phi[0] + 0.5 * U2;
+    const double p = K * P * P;
+    const double m = alpha + eU / (2.0 * lam);
+    double b[2];
+    for (int a = 0; a < n - 1; ++a) b[a] = e[a] / (2.0 * lam);
+    if (hs) *hs = p * m;
+    if (grad) {
+        grad[0] = 2.0 * K * P * m;
+        for (int a = 0; a < n - 1; ++a) grad[1 + a] = 2.0 * K * P * U[a] * m + p * b[a];
+    }
+    if (hess) {
+        hess[0][0] = 2.0 * K * m;
+        for (int a = 0; a < n - 1; ++a) {
+            hess[0][1 + a] = hess[1 + a][0] = 2.0 * K * U[a] * m + 2.0 * K * P * b[a];
+            for (int c = 0; c < n - 1; ++c)
+                hess[1 + a][1 + c] = 2.0 * K * U[a] * U[c] * m + (a == c ? 2.0 * K * P * m : 0.0) +
+                                     2.0 * K * P * (U[a] * b[c] + U[c] * b[a]);
+        }
+    }
+}
+
+/* Solve A x = r (n <= 3) by Gaussian elimination with partial pivoting. */
+static int ent_solve(int n, double A[3][3], const double *r, double *x)
+{
+    double M[3][4];
+    for (int i = 0; i < n; ++i) {
+        for (int k = 0; k < n; ++k) M[i][k] = A[i][k];
+        M[i][n] = r[i];
+    }
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int i = c + 1; i < n; ++i)
+            if (fabs(M[i][c]) > fabs(M[piv][c])) piv = i;
+        if (M[piv][c] == 0.0) return -1;
+        if (piv != c)
+            for (int k = 0; k <= n; ++k) {
+                double t = M[c][k]; M[c][k] = M[piv][k]; M[piv][k] = t;
+            }
+        for (int i = c + 1; i < n; ++i) {
+            double q = M[i][c] / M[c][c];
+            for (int k = c; k <= n; ++k) M[i][k] -= q * M[c][k];
+        }
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double s = M[i][n];
+        for (int k = i + 1; k < n; ++k) s -= M[i][k] * x[k];
+        x[i] = s / M[i][i];
+    }
+    return 0;
+}
+
+/* Positive definiteness by Cholesky. */
+static int ent_posdef(int n, double A[3][3])
+{
+    double L[3][3] = {{0}};
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k <= i; ++k) {
+            double s = A[i][k];
+            for (int m = 0; m < k; ++m) s -= L[i][m] * L[k][m];
+            if (i == k) {
+                if (!(s > 0.0)) return 0;
+                L[i][i] = sqrt(s);
+            } else {
+                L[i][k] = s / L[k][k];
+            }
+        }
+    return 1;
+}
+
+/* Entropy of one population: j = 0 (+) / 1 (-) in 1D, 0..3 (e_1..e_4) in 2D;
+ * F = its components (f, g) or (f, gx, gy); phi0 = starting entropy variables.
+ * Returns 0 and writes h and phi if the dual is attained in the convexity
+ * domain, 1 otherwise. */
+static int ent_pop(int dim, int j, double K, double lam, const double *F, const double *phi0,
+                   double *h_out, double *phi_out)
+{
+    const int n = dim == 1 ? 2 : 3;
+    double phi[3] = {phi0[0], phi0[1], dim == 2 ? phi0[2] : 0.0};
+    /* converged when the step is at rounding level, or has become small and
+     * stops shrinking (the rounding floor of a nearly singular Hessian close to
+     * the edge of the domain) */
+    int ok = 0;
+    double prev = INFINITY;
+    for (int it = 0; it < 100; ++it) {
+        double grad[3], H[3][3], r[3], d[3];
+        ent_pot(dim, j, K, lam, phi, NULL, grad, H);
+        for (int i = 0; i < n; ++i) r[i] = grad[i] - F[i];
+        if (ent_solve(n, H, r, d)) return 1;
+        double big = 0.0;
+        for (int i = 0; i < n; ++i) {
+            phi[i] -= d[i];
+            if (!isfinite(phi[i])) return 1;
+            double rel = fabs(d[i]) / (1.0 + fabs(phi[i]));
+            if (rel > big) big = rel;
+        }
+        if (big <= 1e-15 || (big < 1e-10 && big >= prev)) {
+            ok = 1;
+            break;
+        }
+        prev = big;
+    }
+    if (!ok) return 1;
+    double hs, H[3][3];
+    ent_pot(dim, j, K, lam, phi, &hs, NULL, H);
+    if (!ent_posdef(n, H)) return 1;
+    double dot = 0.0;
+    for (int i = 0; i < n; ++i) dot += phi[i] * F[i];
+    *h_out = dot - hs;
+    if (phi_out)
+        for (int i = 0; i < n; ++i) phi_out[i] = phi[i];
+    return 0;
+}
+
+/* Entropy variables (theta, u, v) of a conserved state: theta = g h - |u|^2/2. */
+static void ent_phi_of(const orc_params *P, const double *W, double *phi)
+{
+    const double h = W[0], u = W[1] / h, v = P->dim == 2 ? W[2] / h : 0.0;
+    phi[0] = P->g * h - 0.5 * (u * u + v * v);
+    phi[1] = u;
+    phi[2] = v;
+}
+
+/* Entropy of one population j with components F (exported for the tests);
+ * the Newton start is the entropy variables of W0 = (h, qx, qy). */
+int orc_entropy_pop(const orc_params *P, int j, const double *F, const double *W0,
+                    double *h_out, double *phi_out)
+{
+    if (!P || !F || !W0 || !h_out || P->a != 0.0 || !(W0[0] > 0.0)) return -1;
+    if (j < 0 || j >= (P->dim == 1 ? 2 : 4)) return -1;
+    double phi0[3];
+    ent_phi_of(P, W0, phi0);
+    return ent_pop(P->dim, j, 0.5 / P->g, P->lambda, F, phi0, h_out, phi_out);
+}
+
+/* H(f) = sum over nodes and populations of h_j.  h_node (optional) receives
+ * the per-node sums (+inf at a node with a population outside the domain),
+ * *total the sum over nodes in node order (+inf if any node is), *invalid the
+ * number of populations outside the domain.  a = 0 only; the rest population
+ * must be zero (its potential vanishes, so its dual is finite only at 0). */
+int orc_entropy(const orc_params *P, const double *f, double *h_node, double *total,
+                long *invalid)
+{
+    if (check_params(P) || !f || P->a != 0.0) return -1;
+    const int np = orc_npop(P->dim), nj = P->dim == 1 ? 2 : 4;
+    const long n = (long)P->nx * P->ny;
+    const double K = 0.5 / P->g;
+    double tot = 0.0;
+    long bad = 0;
+    for (long i = 0; i < n; ++i) {
+        double fl[ORC_NPMAX], W[3], phi0[3];
+        for (int q = 0; q < np; ++q) fl[q] = f[(long)q * n + i];
+        moments_node_d(P->dim, fl, W);
+        double Hn = 0.0;
+        int nodebad = 0;
+        if (fl[0] != 0.0) {
+            ++bad;
+            nodebad = 1;
+        }
+        if (!(W[0] > 0.0)) {
+            bad += nj;
+            nodebad = 1;
+        } else {
+            ent_phi_of(P, W, phi0);
+            for (int j = 0; j < nj; ++j) {
+                double F[3], hj;
+                if (P->dim == 1) {
+                    F[0] = fl[1 + j];
+                    F[1] = fl[3 + j];
+                } else {
+                    F[0] = fl[1 + j];
+                    F[1] = fl[5 + j];
+                    F[2] = fl[9 + j];
+                }
+                if (ent_pop(P->dim, j, K, P->lambda, F, phi0, &hj, NULL)) {
+                    ++bad;
+                    nodebad = 1;
+                } else {
+                    Hn += hj;
+                }
+            }
+        }
+        if (nodebad) Hn = INFINITY;
+        if (h_node) h_node[i] = Hn;
+        tot += Hn;
+    }
+    if (total) *total = tot;
+    if (invalid) *invalid = bad;
+    return 0;
+}
