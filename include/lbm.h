@@ -163,6 +163,21 @@ int lbm_adjoint_terminal(lbm_ctx *ctx, const double *dLdh, void *lam_T);
 int lbm_adjoint_grad_w0(lbm_ctx *ctx, const void *lam0, const double *h0, const double *qx0,
                         const double *qy0, double *grad_h0, double *grad_qx0, double *grad_qy0);
 
+/* Discrete microscopic entropy H(f) = sum_x sum_j h_j(f_j(x)) (Sec. 1), h_j the
+ * Legendre dual of the Perthame-Bouchut potential of population j at a = 0
+ * (Sec. 2 eq. 2-potentiels-st-venant-1d-suite, Sec. 3 eqs. 3-st-venant-
+ * contraintes-2 / 3-st-venant-enplus), taken where the potential is convex.
+ * At equilibrium sum_j h_j(f^eq_j(W)) is the macroscopic entropy
+ * h |u|^2 / 2 + g h^2 / 2, and the domain is the subcharacteristic condition.
+ * state = NULL means the current state.  h_node (device doubles, nx*ny, may be
+ * NULL) receives the per-node sums, +inf at a node with a population outside
+ * the domain.  total_host / invalid_host (may be NULL) receive the total in
+ * double by a deterministic two-stage reduction (+inf if any node is) and the
+ * number of populations outside the domain; asking for either synchronises
+ * the stream.  LBM_EINVAL for the rest-population lattices. */
+int lbm_entropy(lbm_ctx *ctx, const void *state, double *h_node, double *total_host,
+                long *invalid_host);
+
 /* Deterministic sum of n device doubles into *out_host (synchronises). */
 int lbm_sum(lbm_ctx *ctx, const double *partials, long n, double *out_host);
 

@@ -69,7 +69,7 @@ def lib():
         _lib.orc_loss_cs_2d.argtypes = [pp, dp, dp, ctypes.c_double, dp, ctypes.c_long,
                                         ctypes.c_double, dp, dp]
         _lib.orc_entropy.argtypes = [pp, dp, dp, dp, ctypes.POINTER(ctypes.c_long)]
-        _lib.orc_entropy_pop.argtypes = [pp, ctypes.c_int, dp, dp, dp, dp]
+        _lib.orc_entropy_pop.argtypes = [pp, ctypes.c_int, dp, dp, dp]
         for name in ("orc_feq", "orc_collide", "orc_run", "orc_advance", "orc_moments",
                      "orc_adjoint_step", "orc_loss_grad_2d", "orc_loss_cs_2d", "orc_entropy",
                      "orc_entropy_pop"):
@@ -217,15 +217,13 @@ def entropy(P: OrcParams, f):
     return (hn if P.dim == 1 else hn.reshape(P.ny, P.nx)), tot.value, bad.value
 
 
-def entropy_pop(P: OrcParams, j, F, W0):
+def entropy_pop(P: OrcParams, j, F):
     """Entropy of one population j (1D: 0 = +, 1 = -; 2D: 0..3 = e_1..e_4) with
-    components F, Newton started from the entropy variables of W0.  Returns
-    (valid, h, phi)."""
+    components F.  Returns (valid, h, phi)."""
     F = _f64(F)
-    W0 = _f64(np.asarray(list(W0) + [0.0] * (3 - len(W0))))
     h = ctypes.c_double(0.0)
     phi = np.zeros(3)
-    rc = lib().orc_entropy_pop(ctypes.byref(P), int(j), _dp(F), _dp(W0), ctypes.byref(h), _dp(phi))
+    rc = lib().orc_entropy_pop(ctypes.byref(P), int(j), _dp(F), ctypes.byref(h), _dp(phi))
     if rc < 0:
         raise ValueError(f"orc_entropy_pop failed ({rc})")
     return rc == 0, h.value, phi[: (2 if P.dim == 1 else 3)]

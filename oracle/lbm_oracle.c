@@ -654,69 +654,127 @@ static int ent_posdef(int n, double A[3][3])
     return 1;
 }
 
+/* Objective phi . F - h_j^*(phi) of the dual, and whether phi lies in the
+ * convexity domain of h_j^* (Hessian positive definite). */
+static int ent_obj(int dim, int j, double K, double lam, const double *F, const double *phi,
+                   double *obj, double *grad, double hess[3][3])
+{
+    const int n = dim == 1 ? 2 : 3;
+    double hs, g[3], H[3][3];
+    ent_pot(dim, j, K, lam, phi, &hs, g, H);
+    double dot = 0.0;
+    for (int i = 0; i < n; ++i) dot += phi[i] * F[i];
+    *obj = dot - hs;
+    if (grad)
+        for (int i = 0; i < n; ++i) grad[i] = F[i] - g[i];
+    if (hess)
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k) hess[i][k] = H[i][k];
+    return ent_posdef(n, H);
+}
+
 /* Entropy of one population: j = 0 (+) / 1 (-) in 1D, 0..3 (e_1..e_4) in 2D;
- * F = its components (f, g) or (f, gx, gy); phi0 = starting entropy variables.
- * Returns 0 and writes h and phi if the dual is attained in the convexity
- * domain, 1 otherwise. */
+ * F = its components (f, g) or (f, gx, gy).  The objective phi . F - h_j^*(phi)
+ * is concave inside the convexity domain of h_j^*, so its maximiser there is
+ * found by Newton ascent steps, each shortened until the new point stays in
+ * the domain and the objective does not decrease.  The iteration stops when
+ * the full Newton step (the distance to the maximiser to first order) is at
+ * rounding level, or small and no longer shrinking (the rounding floor of a
+ * nearly singular Hessian at the edge of the domain).  The start phi0 must lie
+ * in the domain.  Returns 0 and writes h and phi if the maximum is attained
+ * in the domain, 1 otherwise. */
 static int ent_pop(int dim, int j, double K, double lam, const double *F, const double *phi0,
                    double *h_out, double *phi_out)
 {
     const int n = dim == 1 ? 2 : 3;
     double phi[3] = {phi0[0], phi0[1], dim == 2 ? phi0[2] : 0.0};
-    /* converged when the step is at rounding level, or has become small and
-     * stops shrinking (the rounding floor of a nearly singular Hessian close to
-     * the edge of the domain) */
-    int ok = 0;
+    double obj, grad[3], H[3][3];
+    if (!ent_obj(dim, j, K, lam, F, phi, &obj, grad, H)) return 1;
     double prev = INFINITY;
-    for (int it = 0; it < 100; ++it) {
-        double grad[3], H[3][3], r[3], d[3];
-        ent_pot(dim, j, K, lam, phi, NULL, grad, H);
-        for (int i = 0; i < n; ++i) r[i] = grad[i] - F[i];
-        if (ent_solve(n, H, r, d)) return 1;
-        double big = 0.0;
+    for (int it = 0; it < 2000; ++it) {
+        double d[3];
+        if (ent_solve(n, H, grad, d)) return 1; /* ascent direction H^-1 (F - grad h^*) */
+        double full = 0.0;
         for (int i = 0; i < n; ++i) {
-            phi[i] -= d[i];
-            if (!isfinite(phi[i])) return 1;
             double rel = fabs(d[i]) / (1.0 + fabs(phi[i]));
-            if (rel > big) big = rel;
+            if (rel > full) full = rel;
         }
-        if (big <= 1e-15 || (big < 1e-10 && big >= prev)) {
-            ok = 1;
-            break;
+        if (!(full == full)) return 1;
+        if (full <= 1e-14 || (full < 1e-10 && full >= prev)) {
+            *h_out = obj;
+            if (phi_out)
+                for (int i = 0; i < n; ++i) phi_out[i] = phi[i];
+            return 0;
         }
-        prev = big;
+        prev = full;
+        /* far from the maximiser the objective must not decrease; close to it
+         * (full step below 1e-6, Newton's quadratic region) its change is below
+         * rounding and only the domain is checked */
+        const int test_obj = full >= 1e-6;
+        double t = 1.0, trial[3], tobj, tgrad[3], tH[3][3];
+        int accepted = 0;
+        for (int k = 0; k < 80; ++k, t *= 0.5) {
+            for (int i = 0; i < n; ++i) trial[i] = phi[i] + t * d[i];
+            if (ent_obj(dim, j, K, lam, F, trial, &tobj, tgrad, tH) && (!test_obj || tobj >= obj)) {
+                accepted = 1;
+                break;
+            }
+        }
+        if (!accepted) return 1;
+        if (t < 1.0) prev = INFINITY;
+        for (int i = 0; i < n; ++i) {
+            phi[i] = trial[i];
+            grad[i] = tgrad[i];
+            for (int k = 0; k < n; ++k) H[i][k] = tH[i][k];
+        }
+        obj = tobj;
     }
-    if (!ok) return 1;
-    double hs, H[3][3];
-    ent_pot(dim, j, K, lam, phi, &hs, NULL, H);
-    if (!ent_posdef(n, H)) return 1;
-    double dot = 0.0;
-    for (int i = 0; i < n; ++i) dot += phi[i] * F[i];
-    *h_out = dot - hs;
-    if (phi_out)
-        for (int i = 0; i < n; ++i) phi_out[i] = phi[i];
-    return 0;
+    return 1;
 }
 
-/* Entropy variables (theta, u, v) of a conserved state: theta = g h - |u|^2/2. */
-static void ent_phi_of(const orc_params *P, const double *W, double *phi)
+/* A starting point inside the convexity domain of every population: U = 0 and
+ * theta = 1 / (4 kappa^2) (kappa = 1/lambda in 1D, 2/lambda in 2D), where
+ * h_j^* is convex (D = 1 > kappa sqrt(P) = 1/2). */
+static void ent_start(int dim, double lam, double *phi)
 {
-    const double h = W[0], u = W[1] / h, v = P->dim == 2 ? W[2] / h : 0.0;
-    phi[0] = P->g * h - 0.5 * (u * u + v * v);
-    phi[1] = u;
-    phi[2] = v;
+    const double kappa = dim == 1 ? 1.0 / lam : 2.0 / lam;
+    phi[0] = 0.25 / (kappa * kappa);
+    phi[1] = 0.0;
+    phi[2] = 0.0;
 }
 
-/* Entropy of one population j with components F (exported for the tests);
- * the Newton start is the entropy variables of W0 = (h, qx, qy). */
-int orc_entropy_pop(const orc_params *P, int j, const double *F, const double *W0,
-                    double *h_out, double *phi_out)
+/* Entropy of one population: the ascent is started from the population's own
+ * first-order point (U = (g_x, g_y) / f, P = f / (2 w K), i.e. the potential
+ * read with 1 + e_j . U / (2 alpha lambda) ~ 1) when that point lies in the
+ * domain, and from the generic interior point otherwise or if that fails. */
+static int ent_pop_any(int dim, int j, double K, double lam, const double *F, double *h_out,
+                       double *phi_out)
 {
-    if (!P || !F || !W0 || !h_out || P->a != 0.0 || !(W0[0] > 0.0)) return -1;
-    if (j < 0 || j >= (P->dim == 1 ? 2 : 4)) return -1;
+    const int n = dim == 1 ? 2 : 3;
     double phi0[3];
-    ent_phi_of(P, W0, phi0);
-    return ent_pop(P->dim, j, 0.5 / P->g, P->lambda, F, phi0, h_out, phi_out);
+    if (F[0] > 0.0) {
+        const double w = dim == 1 ? 0.5 : 0.25;
+        double U2 = 0.0;
+        for (int a = 1; a < n; ++a) {
+            phi0[a] = F[a] / F[0];
+            U2 += phi0[a] * phi0[a];
+        }
+        phi0[0] = F[0] / (2.0 * w * K) - 0.5 * U2;
+        double obj, H[3][3];
+        if (ent_obj(dim, j, K, lam, F, phi0, &obj, NULL, H) &&
+            ent_pop(dim, j, K, lam, F, phi0, h_out, phi_out) == 0)
+            return 0;
+    }
+    ent_start(dim, lam, phi0);
+    return ent_pop(dim, j, K, lam, F, phi0, h_out, phi_out);
+}
+
+/* Entropy of one population j with components F (exported for the tests). */
+int orc_entropy_pop(const orc_params *P, int j, const double *F, double *h_out, double *phi_out)
+{
+    if (!P || !F || !h_out || P->a != 0.0 || !(P->lambda > 0.0) || !(P->g > 0.0)) return -1;
+    if (j < 0 || j >= (P->dim == 1 ? 2 : 4)) return -1;
+    return ent_pop_any(P->dim, j, 0.5 / P->g, P->lambda, F, h_out, phi_out);
 }
 
 /* H(f) = sum over nodes and populations of h_j.  h_node (optional) receives
@@ -734,36 +792,29 @@ int orc_entropy(const orc_params *P, const double *f, double *h_node, double *to
     double tot = 0.0;
     long bad = 0;
     for (long i = 0; i < n; ++i) {
-        double fl[ORC_NPMAX], W[3], phi0[3];
+        double fl[ORC_NPMAX];
         for (int q = 0; q < np; ++q) fl[q] = f[(long)q * n + i];
-        moments_node_d(P->dim, fl, W);
         double Hn = 0.0;
         int nodebad = 0;
         if (fl[0] != 0.0) {
             ++bad;
             nodebad = 1;
         }
-        if (!(W[0] > 0.0)) {
-            bad += nj;
-            nodebad = 1;
-        } else {
-            ent_phi_of(P, W, phi0);
-            for (int j = 0; j < nj; ++j) {
-                double F[3], hj;
-                if (P->dim == 1) {
-                    F[0] = fl[1 + j];
-                    F[1] = fl[3 + j];
-                } else {
-                    F[0] = fl[1 + j];
-                    F[1] = fl[5 + j];
-                    F[2] = fl[9 + j];
-                }
-                if (ent_pop(P->dim, j, K, P->lambda, F, phi0, &hj, NULL)) {
-                    ++bad;
-                    nodebad = 1;
-                } else {
-                    Hn += hj;
-                }
+        for (int j = 0; j < nj; ++j) {
+            double F[3], hj;
+            if (P->dim == 1) {
+                F[0] = fl[1 + j];
+                F[1] = fl[3 + j];
+            } else {
+                F[0] = fl[1 + j];
+                F[1] = fl[5 + j];
+                F[2] = fl[9 + j];
+            }
+            if (ent_pop_any(P->dim, j, K, P->lambda, F, &hj, NULL)) {
+                ++bad;
+                nodebad = 1;
+            } else {
+                Hn += hj;
             }
         }
         if (nodebad) Hn = INFINITY;

@@ -442,6 +442,30 @@ extern "C" int lbm_moments(lbm_ctx *c, const void *state, double *h, double *qx,
     return LBM_OK;
 }
 
+extern "C" int lbm_entropy(lbm_ctx *c, const void *state, double *h_node, double *total_host,
+                           long *invalid_host)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (c->rest)
+        return fail(LBM_EINVAL, "the entropy diagnostic is implemented for the a = 0 lattices");
+    const void *s = state ? state : c->buf[c->cur];
+    const bool want = total_host || invalid_host;
+    int nb = 0;
+    HIP_TRY(launch_entropy(c->dim, c->f32, s, c->G, c->p.lambda, c->p.g, h_node,
+                           want ? c->d_partials : nullptr, c->st, &nb));
+    if (want) {
+        double tot[2];
+        HIP_TRY(launch_sum(c->d_partials, nb, 2, 2, c->d_totals, c->st));
+        HIP_TRY(hipMemcpyAsync(tot, c->d_totals, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                               c->st));
+        HIP_TRY(hipStreamSynchronize(c->st));
+        if (total_host) *total_host = tot[0];
+        if (invalid_host) *invalid_host = (long)tot[1];
+    }
+    return LBM_OK;
+}
+
 static int check_adjoint_ctx(lbm_ctx *c)
 {
     int rc = check_ctx(c);

@@ -47,6 +47,10 @@ hipError_t launch_adjoint_grad_w0(bool f32, const void *lam0, const double *h0,
                                   const double *qx0, const double *qy0, double *gh, double *gqx,
                                   double *gqy, const Geo &G, const Phys &P, hipStream_t st);
 
+hipError_t launch_entropy(int dim, bool f32, const void *state, const Geo &G, double lambda,
+                          double g, double *h_node, double *partials, hipStream_t st,
+                          int *nblocks_out);
+
 hipError_t launch_inflow_ghost(int dim, const Geo &G, const Mrt &M, double *ghost,
                                hipStream_t st);
 hipError_t launch_init_rest(int dim, bool f32, void *dst, const double *h0, const double *qx0,

@@ -77,7 +77,7 @@ class LbmBatchTuning(ctypes.Structure):
 
 EXPORTS = [
     "lbm_layout", "lbm_init", "lbm_step", "lbm_step_buffers", "lbm_current", "lbm_export",
-    "lbm_import", "lbm_moments", "lbm_adjoint_step", "lbm_adjoint_partials",
+    "lbm_import", "lbm_moments", "lbm_entropy", "lbm_adjoint_step", "lbm_adjoint_partials",
     "lbm_adjoint_terminal", "lbm_adjoint_grad_w0", "lbm_sum", "lbm_destroy",
     "lbm_batch_layout", "lbm_batch_create", "lbm_batch_init", "lbm_batch_run",
     "lbm_batch_moments", "lbm_batch_current", "lbm_batch_info", "lbm_batch_check",
@@ -109,6 +109,7 @@ def load(path: str = LIB_PATH):
         "lbm_export": (ip, [vp, vp]),
         "lbm_import": (ip, [vp, vp]),
         "lbm_moments": (ip, [vp, vp, vp, vp, vp, dp]),
+        "lbm_entropy": (ip, [vp, vp, vp, dp, ctypes.POINTER(ctypes.c_long)]),
         "lbm_adjoint_step": (ip, [vp, vp, vp, vp, vp]),
         "lbm_adjoint_partials": (lp, [vp]),
         "lbm_adjoint_terminal": (ip, [vp, vp, vp]),
@@ -297,6 +298,23 @@ class Solver:
         if totals:
             return out, (tot[0], tot[1], tot[2])
         return out
+
+    def entropy(self, state=None, per_node=False):
+        """Discrete microscopic entropy of a state (default: the current one):
+        returns (total, number of populations outside the convexity domain) and,
+        with ``per_node``, the per-node entropies as a device float64 tensor."""
+        torch = self.torch
+        hn = None
+        if per_node:
+            shape = (self.nx,) if self.dim == 1 else (self.ny, self.nx)
+            hn = torch.empty(shape, dtype=torch.float64, device=self.device)
+        tot = ctypes.c_double(0.0)
+        bad = ctypes.c_long(0)
+        check(load().lbm_entropy(self.ctx, _ptr(state), _ptr(hn), ctypes.byref(tot),
+                                 ctypes.byref(bad)), "lbm_entropy")
+        if per_node:
+            return tot.value, bad.value, hn
+        return tot.value, bad.value
 
     # -- adjoint -------------------------------------------------------------------------
     def adjoint_partials(self):

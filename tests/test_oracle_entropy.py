@@ -8,9 +8,10 @@ mathematics, not a retyped formula:
   variables (g h - |u|^2 / 2, u, v) (Legendre duality of eta and eta^*);
 * d h_j / d f_j = phi (Legendre duality), checked by central differences;
 * at fixed conserved moments the equilibrium minimises H (Gibbs principle);
-* the convexity domain at equilibrium is exactly the subcharacteristic
-  condition (1D: lambda > |u| + sqrt(g h); 2D: lambda > 2 (|u| + sqrt(g h))
-  along each axis);
+* the entropy variables of W lie in the convexity domain of the potentials
+  exactly under the subcharacteristic condition (1D: lambda > |u| + sqrt(g h);
+  2D: lambda > 2 (max(|u|, |v|) + sqrt(g h))), so only then is the dual of
+  f^eq(W) attained at them;
 * discrete H-theorem: with periodic faces and s <= 1 the relaxation is a
   convex combination and the streaming a permutation, so H never increases.
 """
@@ -53,7 +54,7 @@ def test_entropy_of_equilibrium_is_the_macroscopic_entropy(dim, lam):
         fe = oracle.feq(P, h, h * u, h * v)
         total = 0.0
         for j, F in enumerate(_pops(P, fe, dim)):
-            ok, hj, phi = oracle.entropy_pop(P, j, F, (h, h * u, h * v))
+            ok, hj, phi = oracle.entropy_pop(P, j, F)
             assert ok
             want = [h - 0.5 * (u * u + v * v), u] + ([v] if dim == 2 else [])
             assert np.allclose(phi, want, rtol=0, atol=1e-12)
@@ -72,15 +73,15 @@ def test_entropy_gradient_is_the_dual_variable(dim, lam):
         fe = oracle.feq(P, *W0)
         for j, F0 in enumerate(_pops(P, fe, dim)):
             F = F0 * (1.0 + 0.05 * rng.standard_normal(F0.size))
-            ok, hj, phi = oracle.entropy_pop(P, j, F, W0)
+            ok, hj, phi = oracle.entropy_pop(P, j, F)
             assert ok
             eps = 1e-6
             for k in range(F.size):
                 Fp, Fm = F.copy(), F.copy()
                 Fp[k] += eps
                 Fm[k] -= eps
-                _, hp, _ = oracle.entropy_pop(P, j, Fp, W0)
-                _, hm, _ = oracle.entropy_pop(P, j, Fm, W0)
+                _, hp, _ = oracle.entropy_pop(P, j, Fp)
+                _, hm, _ = oracle.entropy_pop(P, j, Fm)
                 assert abs((hp - hm) / (2 * eps) - phi[k]) <= 1e-6 * (1.0 + abs(phi[k]))
 
 
@@ -116,7 +117,12 @@ def _node_entropy(P, f, dim):
 
 
 @pytest.mark.parametrize("dim", [1, 2])
-def test_convexity_domain_is_the_subcharacteristic_condition(dim):
+def test_equilibrium_duality_holds_exactly_under_the_subcharacteristic_condition(dim):
+    """The entropy variables of W lie in the convexity domain of every h_j^*
+    exactly when lambda satisfies the subcharacteristic condition (1D:
+    lambda > |u| + sqrt(g h); 2D: lambda > 2 (max(|u|, |v|) + sqrt(g h))).
+    Inside, the dual of f^eq(W) is attained at them and H = eta(W); just
+    outside, the maximiser in the domain is another point and H != eta(W)."""
     rng = np.random.default_rng(8)
     for _ in range(20):
         h = rng.uniform(0.3, 3.0)
@@ -126,12 +132,21 @@ def test_convexity_domain_is_the_subcharacteristic_condition(dim):
             crit = abs(u) + math.sqrt(h)
         else:
             crit = 2.0 * (max(abs(u), abs(v)) + math.sqrt(h))
-        for factor, valid in ((1.002, True), (0.998, False)):
+        eta = 0.5 * h * (u * u + v * v) + 0.5 * h * h
+        want = np.array([h - 0.5 * (u * u + v * v), u, v][: (2 if dim == 1 else 3)])
+        for factor, inside in ((1.002, True), (0.998, False)):
             P = oracle.params(dim, 1, 1, lam=factor * crit)
             fe = oracle.feq(P, h, h * u, h * v)
-            _, tot, bad = oracle.entropy(P, fe.reshape(-1, 1))
-            assert (bad == 0) == valid
-            assert math.isfinite(tot) == valid
+            total, far = 0.0, 0.0
+            for j, F in enumerate(_pops(P, fe, dim)):
+                ok, hj, phi = oracle.entropy_pop(P, j, F)
+                assert ok
+                total += hj
+                far = max(far, float(np.abs(phi - want).max()))
+            if inside:
+                assert far <= 1e-10 and abs(total - eta) <= 1e-12 * eta
+            else:
+                assert far > 1e-3 and abs(total - eta) > 1e-9 * eta
 
 
 @pytest.mark.parametrize("s", [0.5, 1.0])
@@ -167,3 +182,36 @@ def test_discrete_h_theorem_periodic_1d():
         Hs.append(H)
     assert (np.diff(Hs) <= 1e-12 * Hs[0]).all()
     assert Hs[-1] < Hs[0] - 1e-6
+
+
+@pytest.mark.parametrize("dim,lam", [(1, 3.0), (2, 6.0)])
+def test_entropy_is_convex_in_the_populations(dim, lam):
+    """h_j is a Legendre dual, hence convex (Sec. 1): Jensen on random pairs of
+    near-equilibrium populations, h((F1 + F2)/2) <= (h(F1) + h(F2))/2."""
+    P = oracle.params(dim, 1, 1, lam=lam)
+    rng = np.random.default_rng(9)
+    states = _random_states(rng, dim, 30, lam)
+    for (h1, u1, v1), (h2, u2, v2) in zip(states[::2], states[1::2]):
+        f1 = oracle.feq(P, h1, h1 * u1, h1 * v1)
+        f2 = oracle.feq(P, h2, h2 * u2, h2 * v2)
+        for j, (F1, F2) in enumerate(zip(_pops(P, f1, dim), _pops(P, f2, dim))):
+            F1 = F1 * (1.0 + 0.05 * rng.standard_normal(F1.size))
+            F2 = F2 * (1.0 + 0.05 * rng.standard_normal(F2.size))
+            ok1, a, _ = oracle.entropy_pop(P, j, F1)
+            ok2, b, _ = oracle.entropy_pop(P, j, F2)
+            okm, m, _ = oracle.entropy_pop(P, j, 0.5 * (F1 + F2))
+            assert ok1 and ok2 and okm
+            assert m <= 0.5 * (a + b) + 1e-13 * (abs(a) + abs(b))
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_nonzero_rest_population_is_outside_the_domain(dim):
+    """At a = 0 the rest potential h_0^* vanishes, so the dual of f_0 is finite
+    only at f_0 = 0 (sup_theta theta f_0 = +inf otherwise)."""
+    P = oracle.params(dim, 1, 1, lam=6.0)
+    fe = oracle.feq(P, 1.3, 0.2, -0.1)
+    _, tot, bad = oracle.entropy(P, fe.reshape(-1, 1))
+    assert bad == 0 and math.isfinite(tot)
+    fe[0] = 1e-3
+    _, tot, bad = oracle.entropy(P, fe.reshape(-1, 1))
+    assert bad == 1 and tot == math.inf
