@@ -36,6 +36,8 @@ def _parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=1000,
+                    help="timed steps of the batched form (the manifest's run is 1000)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--npt", type=int, default=0)
     ap.add_argument("--pad", type=int, default=-1)
@@ -266,7 +268,7 @@ def main():
     f64 = forms.get("fp64") or forms["fp32"]
     if not args.quick and not args.no_batched:
         log("[bench] batched 256 instances x 1000 steps")
-        forms["batched"] = time_batched(torch)
+        forms["batched"] = time_batched(torch, steps=args.batched_steps)
     if not args.quick and not args.no_adjoint:
         log("[bench] adjoint rollout 1024^2 x 500")
         forms["adjoint"] = time_adjoint(torch)
