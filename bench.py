@@ -41,6 +41,8 @@ def _parse():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--npt", type=int, default=0)
     ap.add_argument("--pad", type=int, default=-1)
+    ap.add_argument("--fuse", type=int, default=0, choices=(0, 1, 2),
+                    help="steps per launch of the forward form (0 = tuned / default)")
     ap.add_argument("--probe-copy", action="store_true",
                     help="first run a plain device copy of 2^30 bytes (reference for counters)")
     ap.add_argument("--storage", choices=("both", "f64", "f32"), default="both")
@@ -51,13 +53,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def time_forward(torch, n, storage, steps, warmup, block, npt, pad):
+def time_forward(torch, n, storage, steps, warmup, block, npt, pad, fuse=1):
+    """Forward steps of the headline workload; ``fuse`` = steps per launch (1, or 2
+    for the fused two-step kernel of the all-periodic path)."""
     from paper_1401_0427_amd import workloads as W
     from paper_1401_0427_amd.lbm import Solver
 
     c = W.radial_dam_break_2d(n, lam=6.0)
     S = Solver(2, n, n, lam=c.lam, s=c.s, h0=c.h0, qx0=c.qx0, qy0=c.qy0, storage=storage,
-               block=block, npt=npt, plane_pad=pad)
+               block=block, npt=npt, plane_pad=pad, fuse_steps=fuse)
     S.step(warmup)
     torch.cuda.synchronize()
     st = torch.cuda.current_stream()
@@ -73,9 +77,13 @@ def time_forward(torch, n, storage, steps, warmup, block, npt, pad):
     ok = bool(torch.isfinite(h).all().item()) and tot[0] > 0
     nodes = n * n
     bpl = 12 * 2 * (8 if storage == "f64" else 4)  # algorithmic bytes per lattice update
+    launches = steps / fuse  # steps is even, so every step is in a fused launch when fuse = 2
+    # algorithmic bytes of one launch: the state read once and written once, whatever
+    # the number of steps the launch advances
     return dict(ms_per_step=ms / steps, mlups=nodes * steps / (ms * 1e-3) / 1e6,
-                gbs=nodes * bpl * steps / (ms * 1e-3) / 1e9, bytes_per_lu=bpl, wall_s=wall,
-                finite=ok, mass=tot[0])
+                steps_per_launch=fuse, ms_per_launch=ms / launches,
+                gbs=nodes * bpl * launches / (ms * 1e-3) / 1e9, bytes_per_lu=bpl,
+                bytes_per_launch=nodes * bpl, wall_s=wall, finite=ok, mass=tot[0])
 
 
 def time_batched(torch, steps=1000):
@@ -182,27 +190,35 @@ def time_adjoint(torch, n=1024, T=500, K=23, storage="f32"):
                 grad_s=float(s.grad), grad_h0_norm=float(h0.grad.norm()))
 
 
-def _measured_traffic(n):
+# FP64 step kernels: (source files, committed counter summary)
+KERNELS = {
+    1: (("fwd.hip", "lbm_device.h"), "k_step2d_fwd_4096_traffic.json",
+        "k_step2d<double> (fused pull-stream + BGK collide)"),
+    2: (("tblock.hip", "lbm_device.h"), "k_step2d_x2_fwd_4096_traffic.json",
+        "k_step2d_x2<double> (two pull-stream + BGK collide steps per launch)"),
+}
+
+
+def _measured_traffic(n, fuse):
     """HBM bytes per launch of the FP64 step kernel from the committed rocprofv3
     counter summary (FETCH_SIZE + WRITE_SIZE, each scaled by what the counter
     reads for a plain copy of known size), if it was taken for this grid and
     the current kernel source; else None."""
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                        "k_step2d_fwd_4096_traffic.json")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", KERNELS[fuse][1])
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
-    if d.get("n") != n or d.get("kernel_source_sha") != _kernel_sha():
+    if d.get("n") != n or d.get("kernel_source_sha") != _kernel_sha(fuse):
         return None
     return d.get("traffic_bytes_per_launch_f64")
 
 
-def _kernel_sha():
+def _kernel_sha(fuse=1):
     import hashlib
 
     root = os.path.dirname(os.path.abspath(__file__))
     h = hashlib.sha256()
-    for f in ("fwd.hip", "lbm_device.h"):
+    for f in KERNELS[fuse][0]:
         h.update(open(os.path.join(root, "paper_1401_0427_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -248,7 +264,8 @@ def main():
     def launch(storage):
         t = fwd_tune.get(storage, {})
         return (args.block or t.get("block", 256), args.npt or t.get("npt", 1),
-                args.pad if args.pad >= 0 else t.get("plane_pad", -1))
+                args.pad if args.pad >= 0 else t.get("plane_pad", -1),
+                args.fuse or t.get("fuse_steps", 2))
 
     n = args.n
     if args.probe_copy:
@@ -259,12 +276,17 @@ def main():
         del a, b
         log("[bench] copy probe: 2^30 bytes read, 2^30 bytes written")
     forms = {}
-    if args.storage in ("both", "f64"):
-        log(f"[bench] forward FP64 {n}^2, {args.steps} steps, launch {launch('f64')}")
-        forms["fp64"] = time_forward(torch, n, "f64", args.steps, args.warmup, *launch("f64"))
-    if args.storage in ("both", "f32"):
-        log(f"[bench] forward FP32 {n}^2, {args.steps} steps, launch {launch('f32')}")
-        forms["fp32"] = time_forward(torch, n, "f32", args.steps, args.warmup, *launch("f32"))
+    for storage in ("f64", "f32"):
+        if args.storage not in ("both", storage):
+            continue
+        L = launch(storage)
+        log(f"[bench] forward {storage.upper()} {n}^2, {args.steps} steps, launch {L}")
+        forms["fp" + storage[1:]] = time_forward(torch, n, storage, args.steps, args.warmup, *L)
+        if L[3] != 1 and not args.quick:
+            # the one-step-per-launch kernel on the same workload, for comparison
+            log(f"[bench] forward {storage.upper()} {n}^2, one step per launch")
+            forms["fp" + storage[1:] + "_one_step_per_launch"] = time_forward(
+                torch, n, storage, args.steps, args.warmup, *L[:3], 1)
     f64 = forms.get("fp64") or forms["fp32"]
     if not args.quick and not args.no_batched:
         log("[bench] batched 256 instances x 1000 steps")
@@ -273,11 +295,12 @@ def main():
         log("[bench] adjoint rollout 1024^2 x 500")
         forms["adjoint"] = time_adjoint(torch)
     achieved = f64["gbs"]
+    fuse = f64["steps_per_launch"]
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_step2d<double> (fused pull-stream + BGK collide)",
-            "bytes_per_launch": n * n * f64["bytes_per_lu"]}
-    traffic = _measured_traffic(n)
+            "kernel": KERNELS[fuse][2], "steps_per_launch": fuse,
+            "bytes_per_launch": f64["bytes_per_launch"]}
+    traffic = _measured_traffic(n, fuse)
     if traffic is not None:
         roof["traffic"] = traffic
     cpu = None
@@ -303,7 +326,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "forms": forms,
-        "kernel_source_sha": _kernel_sha(),
+        "kernel_source_sha": _kernel_sha(fuse),
     }
     print(json.dumps(out), flush=True)
 

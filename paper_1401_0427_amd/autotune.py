@@ -1,7 +1,8 @@
 """Project autotuner: picks launch shapes by timing them on the device.
 
 * ``tune_forward``: workgroup size, nodes per thread, plane padding and memory
-  hints of the fused stream + collide kernel for one grid and storage type.
+  hints of the stream + collide kernel, and one or two steps per launch, for
+  one grid and storage type.
 * ``tune_batch``: mode (persistent dataflow or flat per-step launches),
   workgroup size, tile size and nodes per pass of the batched launch for a
   manifest.
@@ -38,7 +39,11 @@ def _timer(torch):
 
 
 def tune_forward(n=4096, storage="f64", steps=60, blocks=(128, 256, 512), npts=(1, 2),
-                 pads=(0, 2048), hints=(2, 6), log=print):
+                 pads=(0, 2048), hints=(2, 6), fuses=(1, 2), log=print):
+    """Sweep the one-step kernel's launch shape, then the fused two-step launch
+    (whose shape is fixed) on each plane padding; the winner is the lowest time
+    per step.  A fused winner keeps the best one-step shape for the steps that
+    are launched singly."""
     import torch
 
     from . import workloads as W
@@ -49,19 +54,30 @@ def tune_forward(n=4096, storage="f64", steps=60, blocks=(128, 256, 512), npts=(
     h0 = torch.as_tensor(c.h0, device="cuda")
     z = torch.zeros_like(h0)
     bpl = 192 if storage == "f64" else 96
+    steps += steps % 2  # whole fused launches
     rows = []
-    for block, npt, pad, hint in itertools.product(blocks, npts, pads, hints):
+
+    def one(block, npt, pad, hint, fuse):
         S = Solver(2, n, n, lam=c.lam, s=c.s, h0=h0, qx0=z, qy0=z, storage=storage, block=block,
-                   npt=npt, plane_pad=pad, mem_hints=hint)
+                   npt=npt, plane_pad=pad, mem_hints=hint, fuse_steps=fuse)
         S.step(4)
         ms = timer(lambda: S.step(steps)) / steps
         del S
         torch.cuda.empty_cache()
-        r = dict(block=block, npt=npt, plane_pad=pad, mem_hints=hint, ms=ms,
-                 gbs=n * n * bpl / ms / 1e6)
+        r = dict(block=block, npt=npt, plane_pad=pad, mem_hints=hint, fuse_steps=fuse, ms=ms,
+                 mlups=n * n / ms / 1e3, gbs=n * n * bpl / fuse / ms / 1e6)
         rows.append(r)
         log(json.dumps(r))
-    best = max(rows, key=lambda r: r["gbs"])
+
+    if 1 in fuses:
+        for block, npt, pad, hint in itertools.product(blocks, npts, pads, hints):
+            one(block, npt, pad, hint, 1)
+    single = [r for r in rows if r["fuse_steps"] == 1]
+    base = min(single, key=lambda r: r["ms"]) if single else dict(block=256, npt=1, mem_hints=6)
+    if 2 in fuses:
+        for pad in pads:
+            one(base["block"], base["npt"], pad, base["mem_hints"], 2)
+    best = min(rows, key=lambda r: r["ms"])
     return best, rows
 
 
@@ -152,8 +168,10 @@ def main():
         sweeps = {}
         for storage in ("f64", "f32"):
             best, rows = tune_forward(storage=storage, steps=args.steps, log=log)
-            fw[storage] = {k: best[k] for k in ("block", "npt", "plane_pad", "mem_hints")}
+            fw[storage] = {k: best[k] for k in ("block", "npt", "plane_pad", "mem_hints",
+                                                "fuse_steps")}
             fw[storage]["gbs"] = round(best["gbs"], 1)
+            fw[storage]["mlups"] = round(best["mlups"], 1)
             sweeps["forward_" + storage] = rows
         out["forward"] = fw
         out["sweeps"] = sweeps

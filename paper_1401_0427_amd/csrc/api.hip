@@ -146,6 +146,7 @@ struct lbm_ctx {
     Geo G;
     Phys P;
     Launch L;
+    int fuse;  // 2: the all-periodic 2D path advances two steps per launch
     void *buf[2];
     int cur;
     long steps;
@@ -161,7 +162,18 @@ struct lbm_ctx {
     int chunk_len;
 };
 
-static const int kChunk = 32;  // steps per captured graph (even: parity preserved)
+static const int kChunk = 32;  // steps per captured graph (a multiple of 4: parity preserved
+                               // with one or two steps per launch)
+// Steps per launch on the all-periodic 2D path when fuse_steps = 0: two when the
+// fused launch has at least kFuseMinBlocks workgroups (about four per compute
+// unit), else one -- on small grids the fused launch has too few workgroups to
+// fill the chip and the one-step kernel is faster (measured at 1024^2 and on the
+// 128^2 .. 1024^2 instances of the batched manifest).
+static const int kFuseMinBlocks = 1024;
+#ifndef LBM_FUSE_SEG
+#define LBM_FUSE_SEG 24
+#endif
+static const int kFuseSeg = LBM_FUSE_SEG;  // rows per workgroup segment of the fused launch
 
 extern "C" void lbm_destroy(lbm_ctx *c)
 {
@@ -219,6 +231,8 @@ extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0
         return fail(LBM_EINVAL, "nodes_per_thread must be 1, 2 or 4 (got %d)", npt);
     if (p->check_every < 0) return fail(LBM_EINVAL, "check_every must be >= 0");
     if (p->mem_hints > 7) return fail(LBM_EINVAL, "mem_hints must be < 8");
+    if (p->fuse_steps < 0 || p->fuse_steps > 2)
+        return fail(LBM_EINVAL, "fuse_steps must be 0, 1 or 2 (got %d)", p->fuse_steps);
 
     lbm_ctx *c = new (std::nothrow) lbm_ctx();
     if (!c) return fail(LBM_EDEVICE, "out of host memory");
@@ -243,6 +257,13 @@ extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0
     c->L.block = block;
     c->L.npt = npt;
     c->L.hints = p->mem_hints < 0 ? kDefaultHints : p->mem_hints;
+    {
+        const bool allper = p->bc[0] == LBM_BC_PERIODIC && p->bc[1] == LBM_BC_PERIODIC &&
+                            p->bc[2] == LBM_BC_PERIODIC && p->bc[3] == LBM_BC_PERIODIC;
+        int want = p->fuse_steps;
+        if (want == 0) want = step2x_blocks(c->G, kFuseSeg) >= kFuseMinBlocks ? 2 : 1;
+        c->fuse = (dim == 2 && !rest && allper) ? want : 1;
+    }
     c->buf[0] = p->f_a;
     c->buf[1] = p->f_b;
     c->cur = 0;
@@ -299,6 +320,12 @@ static hipError_t step_once(lbm_ctx *c, const void *src, void *dst, hipStream_t 
     return launch_step(c->dim, c->f32, src, dst, c->G, c->P, c->L, st);
 }
 
+// Two steps in one launch (fused path): level n in src, level n+2 in dst.
+static hipError_t step_pair(lbm_ctx *c, const void *src, void *dst, hipStream_t st)
+{
+    return launch_step2x(c->f32, src, dst, c->G, c->P, kFuseSeg, st);
+}
+
 static int check_ctx(lbm_ctx *c)
 {
     if (!c) return fail(LBM_ESTATE, "null context");
@@ -330,9 +357,18 @@ static int ensure_chunk(lbm_ctx *c, int from)
     HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
     int cur = from;
     hipError_t le = hipSuccess;
-    for (int k = 0; k < c->chunk_len && le == hipSuccess; ++k) {
-        le = step_once(c, c->buf[cur], c->buf[cur ^ 1], c->cap);
-        cur ^= 1;
+    if (c->fuse == 2) {
+        // chunk_len / 2 fused launches; an even number of them (chunk_len is a
+        // multiple of 4), so the chunk ends on the buffer it started from
+        for (int k = 0; k < c->chunk_len / 2 && le == hipSuccess; ++k) {
+            le = step_pair(c, c->buf[cur], c->buf[cur ^ 1], c->cap);
+            cur ^= 1;
+        }
+    } else {
+        for (int k = 0; k < c->chunk_len && le == hipSuccess; ++k) {
+            le = step_once(c, c->buf[cur], c->buf[cur ^ 1], c->cap);
+            cur ^= 1;
+        }
     }
     hipError_t ee = hipStreamEndCapture(c->cap, &g);
     if (le != hipSuccess || ee != hipSuccess) {
@@ -368,6 +404,12 @@ extern "C" int lbm_step(lbm_ctx *c, long nsteps)
             todo -= c->chunk_len;
             done += c->chunk_len;
             c->steps += c->chunk_len;  // chunk length is even: c->cur unchanged
+        }
+        for (; c->fuse == 2 && todo >= 2; todo -= 2) {
+            HIP_TRY(step_pair(c, c->buf[c->cur], c->buf[c->cur ^ 1], c->st));
+            c->cur ^= 1;
+            done += 2;
+            c->steps += 2;
         }
         for (; todo > 0; --todo) {
             HIP_TRY(step_once(c, c->buf[c->cur], c->buf[c->cur ^ 1], c->st));

@@ -49,6 +49,7 @@ class LbmParams(ctypes.Structure):
         ("nodes_per_thread", ctypes.c_int),
         ("plane_pad", ctypes.c_long),
         ("mem_hints", ctypes.c_int),
+        ("fuse_steps", ctypes.c_int),
         ("f_a", ctypes.c_void_p),
         ("f_b", ctypes.c_void_p),
         ("stream", ctypes.c_void_p),
@@ -180,7 +181,7 @@ def _bc_codes(bc):
 
 def make_params(dim, nx, ny, lam, s, g=1.0, bc=("periodic",) * 4, inflow=None, storage="f64",
                 check_every=0, block=256, npt=1, plane_pad=-1, mem_hints=-1, rest=False, a=0.0,
-                rates=None) -> LbmParams:
+                rates=None, fuse_steps=0) -> LbmParams:
     """Parameter block; ``rest`` selects the rest-population schemes D1Q3Q2 /
     D2Q5Q4Q4 (weight ``a``, MRT ``rates``; 0 / missing rates take ``s``)."""
     p = LbmParams()
@@ -205,6 +206,7 @@ def make_params(dim, nx, ny, lam, s, g=1.0, bc=("periodic",) * 4, inflow=None, s
     p.nodes_per_thread = npt
     p.plane_pad = plane_pad
     p.mem_hints = mem_hints
+    p.fuse_steps = fuse_steps
     return p
 
 
@@ -220,7 +222,8 @@ class Solver:
 
     def __init__(self, dim, nx, ny=1, lam=3.0, s=1.8, g=1.0, bc=("periodic",) * 4, inflow=None,
                  h0=None, qx0=None, qy0=None, storage="f64", check_every=0, block=256, npt=1,
-                 plane_pad=-1, mem_hints=-1, rest=False, a=0.0, rates=None, device="cuda"):
+                 plane_pad=-1, mem_hints=-1, rest=False, a=0.0, rates=None, fuse_steps=0,
+                 device="cuda"):
         import torch
 
         _require_gpu(torch)
@@ -229,7 +232,7 @@ class Solver:
         self.dim = dim
         self.nx, self.ny = nx, (ny if dim == 2 else 1)
         self.params = make_params(dim, nx, ny, lam, s, g, bc, inflow, storage, check_every, block,
-                                  npt, plane_pad, mem_hints, rest, a, rates)
+                                  npt, plane_pad, mem_hints, rest, a, rates, fuse_steps)
         self.ps, self.nplanes, self.nbytes = layout(self.params)
         self.dtype = torch.float32 if self.params.storage == F32 else torch.float64
         self.device = torch.device(device)

@@ -42,7 +42,8 @@ def _launch(storage):
     if os.path.exists(TUNING):
         t = json.load(open(TUNING)).get("forward", {}).get(storage, {})
         return dict(block=t.get("block", 256), npt=t.get("npt", 1),
-                    plane_pad=t.get("plane_pad", -1), mem_hints=t.get("mem_hints", -1))
+                    plane_pad=t.get("plane_pad", -1), mem_hints=t.get("mem_hints", -1),
+                    fuse_steps=t.get("fuse_steps", 0))
     return {}
 
 
@@ -112,6 +113,26 @@ def test_radial_4096_full_steps_invariants(storage):
     assert rel <= (1e-12 if storage == "f64" else 1e-5)
     assert abs(tot[1]) <= 1e-9 * mass0 and abs(tot[2]) <= 1e-9 * mass0
     del S
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_radial_4096_fused_launch_equals_single_steps(storage):
+    """The headline grid: 40 steps as 20 fused two-step launches give bit for bit
+    the state of 40 single-step launches."""
+    import torch
+
+    case = W.radial_dam_break_2d(4096, lam=6.0)
+    A = gpu_solver(case, storage=storage, fuse_steps=1)
+    A.step(40)
+    a = A.planes().clone()
+    del A
+    B = gpu_solver(case, storage=storage, fuse_steps=2)
+    B.step(40)
+    same = bool(torch.equal(a, B.planes()))
+    say(f"[full] 4096^2 {storage}: fused == single steps bitwise: {same}")
+    assert same
+    del B, a
     torch.cuda.empty_cache()
 
 

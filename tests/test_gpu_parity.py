@@ -194,3 +194,35 @@ def test_oblique_shock_reflection_fp64_matches_oracle(ny):
     err = per_plane_rel(got, ref)
     say(f"  {case.name} {case.steps} steps: max plane rel err {err:.3e}")
     assert err <= TOL64
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("shape,steps", [((300, 70), 6), ((600, 130), 7), ((17, 5), 9),
+                                         ((96, 80), 37), ((254, 64), 2), ((1100, 50), 4)])
+def test_fused_two_step_launch_equals_single_steps(storage, shape, steps):
+    """fuse_steps = 2 (two steps per launch, all-periodic 2D) gives bit for bit the
+    state of single steps: one strip, two and three strips with a ragged last one
+    (600, 1100 columns over 510-column strips), ragged row segments, a grid
+    smaller than one strip, an odd step count (the last step single) and a run
+    long enough for the captured graph chunks."""
+    nx, ny = shape
+    case = smooth_random_2d(nx, ny, seed=5)
+    say(f"[fused] {nx}x{ny} steps={steps} storage={storage}")
+    A = gpu_solver(case, storage=storage, fuse_steps=1)
+    B = gpu_solver(case, storage=storage, fuse_steps=2)
+    A.step(steps)
+    B.step(steps)
+    a, b = to_np(A.planes()), to_np(B.planes())
+    assert np.array_equal(a, b)
+    if storage == "f64":
+        ref, _ = orc_state(case, steps)
+        assert per_plane_rel(b, ref) <= TOL64
+
+
+def test_fused_request_on_walls_takes_single_steps():
+    """Non-periodic faces: fuse_steps = 2 is accepted and the single-step path runs."""
+    case = W.oblique_shock_2d(20, steps=60)
+    S = gpu_solver(case, fuse_steps=2)
+    S.step(case.steps)
+    ref, _ = orc_state(case, case.steps)
+    assert per_plane_rel(to_np(S.planes()), ref) <= TOL64
