@@ -35,6 +35,7 @@ def _parse():
     ap.add_argument("--quick", action="store_true", help="headline only (no batched/adjoint/cpu)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-1d", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=1000,
                     help="timed steps of the batched form (the manifest's run is 1000)")
@@ -84,6 +85,34 @@ def time_forward(torch, n, storage, steps, warmup, block, npt, pad, fuse=1):
                 steps_per_launch=fuse, ms_per_launch=ms / launches,
                 gbs=nodes * bpl * launches / (ms * 1e-3) / 1e9, bytes_per_lu=bpl,
                 bytes_per_launch=nodes * bpl, wall_s=wall, finite=ok, mass=tot[0])
+
+
+def time_1d(torch, storage, steps=2000, warmup=64, fuse=0):
+    """1D wall reflection, 2^20 nodes (inflow ghost left, wall right, lambda = 3,
+    s = 1.9): the state (32 MiB FP64 per buffer) stays in the 256 MB MALL, so the
+    rate is reported as effective bandwidth, not as an HBM claim.  ``fuse`` =
+    steps per launch (0 = library default)."""
+    from paper_1401_0427_amd import workloads as W
+    from paper_1401_0427_amd.lbm import Solver
+
+    c = W.wall_reflection_1d()
+    S = Solver(1, c.nx, 1, lam=c.lam, s=c.s, bc=c.bc, inflow=c.inflow, h0=c.h0, qx0=c.qx0,
+               storage=storage, fuse_steps=fuse)
+    S.step(warmup)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    S.step(steps)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    h = S.moments()[0]
+    ok = bool(torch.isfinite(h).all().item())
+    bpl = 4 * 2 * (8 if storage == "f64" else 4)
+    return dict(nodes=c.nx, steps=steps, ms_per_step=ms / steps,
+                mlups=c.nx * steps / (ms * 1e-3) / 1e6, effective_gbs=c.nx * bpl * steps / (ms * 1e-3) / 1e9,
+                bytes_per_lu=bpl, finite=ok)
 
 
 def time_batched(torch, steps=1000):
@@ -288,6 +317,10 @@ def main():
             forms["fp" + storage[1:] + "_one_step_per_launch"] = time_forward(
                 torch, n, storage, args.steps, args.warmup, *L[:3], 1)
     f64 = forms.get("fp64") or forms["fp32"]
+    if not args.quick and not args.no_1d:
+        for storage in ("f64", "f32"):
+            log(f"[bench] 1D wall reflection 2^20 {storage.upper()}")
+            forms["wall_1d_" + storage] = time_1d(torch, storage)
     if not args.quick and not args.no_batched:
         log("[bench] batched 256 instances x 1000 steps")
         forms["batched"] = time_batched(torch, steps=args.batched_steps)

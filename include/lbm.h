@@ -101,10 +101,12 @@ typedef struct {
     int mem_hints;        /* bit 0: non-temporal loads, bit 1: non-temporal stores,
                              bit 2: plain workgroup order (no XCD-aware tile remap);
                              < 0 = library default */
-    int fuse_steps;       /* steps per launch of the all-periodic 2D path: 1, or 2
-                             (two steps fused, bitwise identical to two single
-                             steps, about half the HBM traffic per step);
-                             0 = library default (2).  Other grids always take 1. */
+    int fuse_steps;       /* steps per launch (temporal blocking; bitwise identical
+                             to single steps): 0 = library default, else a power
+                             of two <= 16.  2D all-periodic grids fuse at most 2
+                             (default 2 when the fused launch has >= 1024
+                             workgroups, e.g. 4096^2, else 1); 1D grids any
+                             (default 16); 2D grids with other faces take 1. */
     void *f_a, *f_b;      /* caller-owned device state buffers (ping-pong) */
     void *stream;         /* hipStream_t; NULL = default stream */
 } lbm_params;

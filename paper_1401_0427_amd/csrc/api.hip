@@ -162,14 +162,18 @@ struct lbm_ctx {
     int chunk_len;
 };
 
-static const int kChunk = 32;  // steps per captured graph (a multiple of 4: parity preserved
-                               // with one or two steps per launch)
+static const int kChunk = 32;  // steps per captured graph: with up to 16 steps per launch it
+                               // holds an even number of launches (parity preserved)
 // Steps per launch on the all-periodic 2D path when fuse_steps = 0: two when the
 // fused launch has at least kFuseMinBlocks workgroups (about four per compute
 // unit), else one -- on small grids the fused launch has too few workgroups to
 // fill the chip and the one-step kernel is faster (measured at 1024^2 and on the
 // 128^2 .. 1024^2 instances of the batched manifest).
 static const int kFuseMinBlocks = 1024;
+// 1D: steps per launch by default and at most (tiles of 1024 nodes hold the K
+// levels in LDS; K divides the graph chunk with an even number of launches).
+static const int kDefaultFuse1d = 16;
+static const int kMaxFuse1d = 16;
 #ifndef LBM_FUSE_SEG
 #define LBM_FUSE_SEG 24
 #endif
@@ -231,8 +235,10 @@ extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0
         return fail(LBM_EINVAL, "nodes_per_thread must be 1, 2 or 4 (got %d)", npt);
     if (p->check_every < 0) return fail(LBM_EINVAL, "check_every must be >= 0");
     if (p->mem_hints > 7) return fail(LBM_EINVAL, "mem_hints must be < 8");
-    if (p->fuse_steps < 0 || p->fuse_steps > 2)
-        return fail(LBM_EINVAL, "fuse_steps must be 0, 1 or 2 (got %d)", p->fuse_steps);
+    if (p->fuse_steps < 0 || p->fuse_steps > kMaxFuse1d ||
+        (p->fuse_steps & (p->fuse_steps - 1)) != 0)
+        return fail(LBM_EINVAL, "fuse_steps must be 0 or a power of two up to %d (got %d)",
+                    kMaxFuse1d, p->fuse_steps);
 
     lbm_ctx *c = new (std::nothrow) lbm_ctx();
     if (!c) return fail(LBM_EDEVICE, "out of host memory");
@@ -261,8 +267,15 @@ extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0
         const bool allper = p->bc[0] == LBM_BC_PERIODIC && p->bc[1] == LBM_BC_PERIODIC &&
                             p->bc[2] == LBM_BC_PERIODIC && p->bc[3] == LBM_BC_PERIODIC;
         int want = p->fuse_steps;
-        if (want == 0) want = step2x_blocks(c->G, kFuseSeg) >= kFuseMinBlocks ? 2 : 1;
-        c->fuse = (dim == 2 && !rest && allper) ? want : 1;
+        if (rest)
+            c->fuse = 1;
+        else if (dim == 1)
+            c->fuse = want ? want : kDefaultFuse1d;
+        else if (allper)
+            c->fuse = want ? (want > 2 ? 2 : want)
+                           : (step2x_blocks(c->G, kFuseSeg) >= kFuseMinBlocks ? 2 : 1);
+        else
+            c->fuse = 1;
     }
     c->buf[0] = p->f_a;
     c->buf[1] = p->f_b;
@@ -320,10 +333,12 @@ static hipError_t step_once(lbm_ctx *c, const void *src, void *dst, hipStream_t 
     return launch_step(c->dim, c->f32, src, dst, c->G, c->P, c->L, st);
 }
 
-// Two steps in one launch (fused path): level n in src, level n+2 in dst.
-static hipError_t step_pair(lbm_ctx *c, const void *src, void *dst, hipStream_t st)
+// k steps (1 <= k <= c->fuse) in one launch: level n in src, level n+k in dst.
+static hipError_t step_k(lbm_ctx *c, int k, const void *src, void *dst, hipStream_t st)
 {
-    return launch_step2x(c->f32, src, dst, c->G, c->P, kFuseSeg, st);
+    if (k == 1) return step_once(c, src, dst, st);
+    if (c->dim == 2) return launch_step2x(c->f32, src, dst, c->G, c->P, kFuseSeg, st);
+    return launch_step1k(c->f32, src, dst, c->G, c->P, k, st);
 }
 
 static int check_ctx(lbm_ctx *c)
@@ -357,18 +372,11 @@ static int ensure_chunk(lbm_ctx *c, int from)
     HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
     int cur = from;
     hipError_t le = hipSuccess;
-    if (c->fuse == 2) {
-        // chunk_len / 2 fused launches; an even number of them (chunk_len is a
-        // multiple of 4), so the chunk ends on the buffer it started from
-        for (int k = 0; k < c->chunk_len / 2 && le == hipSuccess; ++k) {
-            le = step_pair(c, c->buf[cur], c->buf[cur ^ 1], c->cap);
-            cur ^= 1;
-        }
-    } else {
-        for (int k = 0; k < c->chunk_len && le == hipSuccess; ++k) {
-            le = step_once(c, c->buf[cur], c->buf[cur ^ 1], c->cap);
-            cur ^= 1;
-        }
+    // chunk_len / fuse launches of fuse steps each; an even number of them, so
+    // the chunk ends on the buffer it started from
+    for (int k = 0; k < c->chunk_len / c->fuse && le == hipSuccess; ++k) {
+        le = step_k(c, c->fuse, c->buf[cur], c->buf[cur ^ 1], c->cap);
+        cur ^= 1;
     }
     hipError_t ee = hipStreamEndCapture(c->cap, &g);
     if (le != hipSuccess || ee != hipSuccess) {
@@ -405,17 +413,15 @@ extern "C" int lbm_step(lbm_ctx *c, long nsteps)
             done += c->chunk_len;
             c->steps += c->chunk_len;  // chunk length is even: c->cur unchanged
         }
-        for (; c->fuse == 2 && todo >= 2; todo -= 2) {
-            HIP_TRY(step_pair(c, c->buf[c->cur], c->buf[c->cur ^ 1], c->st));
+        while (todo > 0) {
+            // the 2D fused kernel takes exactly two steps; the 1D one any k <= fuse
+            int k = (int)(todo < c->fuse ? todo : c->fuse);
+            if (c->dim == 2 && k != 2) k = 1;
+            HIP_TRY(step_k(c, k, c->buf[c->cur], c->buf[c->cur ^ 1], c->st));
             c->cur ^= 1;
-            done += 2;
-            c->steps += 2;
-        }
-        for (; todo > 0; --todo) {
-            HIP_TRY(step_once(c, c->buf[c->cur], c->buf[c->cur ^ 1], c->st));
-            c->cur ^= 1;
-            ++done;
-            ++c->steps;
+            todo -= k;
+            done += k;
+            c->steps += k;
         }
         if (c->p.check_every > 0 && c->steps % c->p.check_every == 0)
             if ((rc = check_state(c, c->steps))) return rc;

@@ -48,6 +48,8 @@ hipError_t launch_adjoint_grad_w0(bool f32, const void *lam0, const double *h0,
                                   double *gqy, const Geo &G, const Phys &P, hipStream_t st);
 
 int step2x_blocks(const Geo &G, int seg);
+hipError_t launch_step1k(bool f32, const void *src, void *dst, const Geo &G, const Phys &P,
+                         int K, hipStream_t st);
 hipError_t launch_step2x(bool f32, const void *src, void *dst, const Geo &G, const Phys &P,
                          int seg, hipStream_t st);
 hipError_t launch_entropy(int dim, bool f32, const void *state, const Geo &G, double lambda,

@@ -1,4 +1,5 @@
-// Two steps of the all-periodic 2D path in one launch (temporal blocking).
+// Several steps per launch (temporal blocking): two steps of the all-periodic
+// 2D path, and K steps of the 1D path.
 //
 // A step of the scheme reads every population once and writes it once, so one
 // launch per step is bound by 192 B (FP64) / 96 B (FP32) of HBM traffic per
@@ -132,6 +133,310 @@ __global__ void __launch_bounds__(kX2Threads)
         }
         __syncthreads();
     }
+}
+
+// ---- 2D: K steps per launch, one wavefront per column strip ------------------------
+// Each wavefront works alone (no LDS, no barrier): lane l holds column
+// x0 - (K - 1) + l and the wavefront marches up a segment of rows with the K
+// time levels skewed by one row: in iteration i it computes level 1 at row i,
+// level 2 at row i - 1, ..., level K at row i - K + 1.  Level k + 1 at row r
+// pulls from level k: e2 planes of row r - 1 and e4 planes of row r + 1 from
+// the lane's own registers, e1 planes of row r from lane l - 1 and e3 planes
+// from lane l + 1 (cross-lane permutes).  Level 1 pulls straight from the
+// level-n state in memory.  Each level loses one lane at each end of the
+// wavefront, so a strip yields 64 - 2 (K - 1) output columns; the segment is
+// extended by K - 1 rows at each end for the same reason.  Intermediate levels
+// are rounded to the storage type (as a store and reload would round them), and
+// the per-node arithmetic is the one-step kernel's, so K steps in one launch
+// equal K single steps bit for bit.  The next row's level-n pulls are issued
+// before the current row is computed, so loads overlap the arithmetic.
+#ifndef LBM_XK_WAVES
+#define LBM_XK_WAVES 4
+#endif
+#ifndef LBM_XK_PREFETCH
+#define LBM_XK_PREFETCH 1
+#endif
+#ifndef LBM_XK_REMAP
+#define LBM_XK_REMAP 0
+#endif
+constexpr int kXkWaves = LBM_XK_WAVES;  // strips (wavefronts) per workgroup
+
+// Value of lane l - 1 (shift 1) or lane l + 1 (shift -1); the end lanes get an
+// arbitrary lane's value (they are outside the valid range of the next level).
+__device__ __forceinline__ float xk_from(float v, int lane, int shift)
+{
+    const int src = (lane - shift) & 63;
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+__device__ __forceinline__ double xk_from(double v, int lane, int shift)
+{
+    const int src = ((lane - shift) & 63) << 2;
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(src, (int)(b & 0xffffffffLL));
+    const int hi = __builtin_amdgcn_ds_bpermute(src, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Level-n pulls of the level-1 node in column (xm, xw, xp) and rows (rm, row, rp)
+// (element offsets of the three rows).
+template <typename T>
+__device__ __forceinline__ void xk_load(const T *__restrict__ src, long ps, long rm, long row,
+                                        long rp, int xm, int xw, int xp, T *f)
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const T *b = src + (4 * c) * ps;
+        f[4 * c + 0] = b[row + xm];
+        f[4 * c + 1] = b[ps + rm + xw];
+        f[4 * c + 2] = b[2 * ps + row + xp];
+        f[4 * c + 3] = b[3 * ps + rp + xw];
+    }
+}
+
+template <typename T, int K>
+__global__ void __launch_bounds__(64 * kXkWaves)
+    k_step2d_xk(const T *__restrict__ src, T *__restrict__ dst, Geo G, Phys P, int nstrips,
+                int seg)
+{
+    constexpr int WO = 64 - 2 * (K - 1);  // output columns per strip
+    const int nx = G.nx, ny = G.ny;
+    const long ps = G.ps;
+    const int lane = threadIdx.x & 63;
+    const int ngroups = (nstrips + kXkWaves - 1) / kXkWaves;
+    const int nseg = (ny + seg - 1) / seg;
+    const int tile = xcd_tile(blockIdx.x, ngroups * nseg, LBM_XK_REMAP != 0);
+    const int strip = (tile % ngroups) * kXkWaves + (threadIdx.x >> 6);
+    if (strip >= nstrips) return;  // whole wavefront; nothing here waits on others
+    const int y0 = (tile / ngroups) * seg;
+    const int y1 = min(y0 + seg, ny);
+    const int x0 = strip * WO;                    // first output column
+    const int xc = x0 - (K - 1) + lane;           // this lane's column, unwrapped
+    const int xw = ((xc % nx) + nx) % nx;
+    const int xm = xw == 0 ? nx - 1 : xw - 1;
+    const int xp = xw == nx - 1 ? 0 : xw + 1;
+    const bool olane = lane >= K - 1 && lane < 64 - (K - 1) && xc < nx;
+    const int niter = (y1 - y0) + 2 * (K - 1);
+    int r = (((y0 - (K - 1)) % ny) + ny) % ny;  // level-1 row of the iteration, wrapped
+
+    // state of the intermediate levels 1 .. K-1 (index k-1), storage precision:
+    // e2 planes of the last two rows, e1 planes of the last row from lane l-1 and
+    // e3 planes from lane l+1
+    T e2m[K - 1][3], e2c[K - 1][3], s1[K - 1][3], s3[K - 1][3];
+#pragma unroll
+    for (int k = 0; k < K - 1; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) e2m[k][c] = e2c[k][c] = s1[k][c] = s3[k][c] = (T)0;
+
+    T cur[12];
+    {
+        const long row = (long)r * nx;
+        const long rm = r == 0 ? (long)(ny - 1) * nx : row - nx;
+        const long rp = r == ny - 1 ? 0 : row + nx;
+        xk_load(src, ps, rm, row, rp, xm, xw, xp, cur);
+    }
+    for (int j = 0; j < niter; ++j) {
+        r = r == ny - 1 ? 0 : r + 1;
+        T nxt[12];
+#if LBM_XK_PREFETCH
+        if (j + 1 < niter) {
+            const long row = (long)r * nx;
+            const long rm = r == 0 ? (long)(ny - 1) * nx : row - nx;
+            const long rp = r == ny - 1 ? 0 : row + nx;
+            xk_load(src, ps, rm, row, rp, xm, xw, xp, nxt);
+        }
+#endif
+        double v[12];
+#pragma unroll
+        for (int pl = 0; pl < 12; ++pl) v[pl] = (double)cur[pl];
+        collide2d(v, P);  // level 1
+        bool live = true;
+#pragma unroll
+        for (int k = 1; k < K; ++k) {
+            // v: level k (rounded next), one row above the level-k+1 row computed here
+#pragma unroll
+            for (int pl = 0; pl < 12; ++pl) v[pl] = (double)(T)v[pl];
+            const bool act = j >= 2 * k;  // level k+1 has a row this iteration
+            double o[12];
+            if (act) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    o[4 * c + 0] = (double)s1[k - 1][c];
+                    o[4 * c + 1] = (double)e2m[k - 1][c];
+                    o[4 * c + 2] = (double)s3[k - 1][c];
+                    o[4 * c + 3] = v[4 * c + 3];
+                }
+                collide2d(o, P);
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                e2m[k - 1][c] = e2c[k - 1][c];
+                e2c[k - 1][c] = (T)v[4 * c + 1];
+                s1[k - 1][c] = xk_from((T)v[4 * c + 0], lane, 1);
+                s3[k - 1][c] = xk_from((T)v[4 * c + 2], lane, -1);
+            }
+            if (!act) {
+                live = false;
+                break;
+            }
+#pragma unroll
+            for (int pl = 0; pl < 12; ++pl) v[pl] = o[pl];
+        }
+        if (live && olane) {
+            T *out = dst + (long)(y0 - 2 * (K - 1) + j) * nx + xc;
+#pragma unroll
+            for (int pl = 0; pl < 12; ++pl) sth<2>(out + pl * ps, v[pl]);
+        }
+#if LBM_XK_PREFETCH
+#pragma unroll
+        for (int pl = 0; pl < 12; ++pl) cur[pl] = nxt[pl];
+#else
+        if (j + 1 < niter) {
+            const long row = (long)r * nx;
+            const long rm = r == 0 ? (long)(ny - 1) * nx : row - nx;
+            const long rp = r == ny - 1 ? 0 : row + nx;
+            xk_load(src, ps, rm, row, rp, xm, xw, xp, cur);
+        }
+        (void)nxt;
+#endif
+    }
+}
+
+int step2k_strips(const Geo &G, int K) { return (G.nx + (64 - 2 * (K - 1)) - 1) / (64 - 2 * (K - 1)); }
+
+int step2k_blocks(const Geo &G, int K, int seg)
+{
+    const int ngroups = (step2k_strips(G, K) + kXkWaves - 1) / kXkWaves;
+    return ngroups * ((G.ny + seg - 1) / seg);
+}
+
+hipError_t launch_step2k(bool f32, const void *src, void *dst, const Geo &G, const Phys &P,
+                         int K, int seg, hipStream_t st)
+{
+    const int ns = step2k_strips(G, K);
+    const int nb = step2k_blocks(G, K, seg);
+    const dim3 grid(nb), block(64 * kXkWaves);
+#define LBM_XK_CASE(KK)                                                                       \
+    case KK:                                                                                  \
+        if (f32)                                                                              \
+            hipLaunchKernelGGL((k_step2d_xk<float, KK>), grid, block, 0, st,                  \
+                               (const float *)src, (float *)dst, G, P, ns, seg);              \
+        else                                                                                  \
+            hipLaunchKernelGGL((k_step2d_xk<double, KK>), grid, block, 0, st,                 \
+                               (const double *)src, (double *)dst, G, P, ns, seg);            \
+        break;
+    switch (K) {
+        LBM_XK_CASE(2)
+        LBM_XK_CASE(4)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef LBM_XK_CASE
+    return hipGetLastError();
+}
+
+// ---- 1D: K steps per launch -------------------------------------------------------
+// A workgroup of 1024 threads holds a tile of 1024 consecutive nodes in LDS
+// (four planes, double-buffered) and advances it K steps, one node per thread,
+// one barrier per step.  The tile starts K nodes before its 1024 - 2K output
+// nodes: each step invalidates one more node at each tile edge inside the
+// domain, so the outputs are exact after K steps.  At a non-periodic domain end
+// the face rule (Neumann / wall / inflow, as in the one-step kernel) is applied
+// to the node's own previous-level values, so nothing is lost there; with
+// periodic faces the tile simply wraps.  Each level is rounded to the storage
+// type, as a store and a reload would round it: K steps in one launch equal K
+// single steps bit for bit.
+constexpr int kK1Threads = 1024;
+
+// Ghost value of plane pl beyond face (0: x-, 1: x+) of a non-periodic end, from
+// the end node's own post-collision values (the one-step kernel's face rules).
+__device__ __forceinline__ double k1_face(const Geo &G, int pl, int face, const double *own,
+                                          const double *weq)
+{
+    switch (G.bc[face]) {
+    case BC_NEUMANN:
+        return own[pl];
+    case BC_WALL: {
+        const double v = own[pl ^ 1];
+        return pl >= 2 ? -v : v;
+    }
+    default:  // BC_INFLOW
+        return weq[face * 4 + pl];
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kK1Threads)
+    k_step1d_k(const T *__restrict__ src, T *__restrict__ dst, Geo G, Phys P, int K, int nout)
+{
+    __shared__ T sh[2][4][kK1Threads];
+    const int t = threadIdx.x;
+    const int nx = G.nx;
+    const long ps = G.ps;
+    const bool per = G.bc[0] == BC_PERIODIC;  // the two 1D faces are periodic together
+    const int ob = blockIdx.x * nout;          // output nodes [ob, oe)
+    const int oe = min(ob + nout, nx);
+    const int x = ob - K + t;                  // this thread's node, unwrapped
+    const bool in = per || (x >= 0 && x < nx);
+    const int xw = per ? ((x % nx) + nx) % nx : x;
+    const int tl = t > 0 ? t - 1 : t;          // clamped neighbours (edge values are
+    const int tr = t < kK1Threads - 1 ? t + 1 : t;  // invalid anyway)
+    double weq[8];
+#pragma unroll
+    for (int face = 0; face < 2; ++face)
+        if (G.bc[face] == BC_INFLOW) feq1d(G.win[face][0], G.win[face][1], P, weq + 4 * face);
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (in) {
+#pragma unroll
+        for (int pl = 0; pl < 4; ++pl) v[pl] = ld(src + pl * ps + xw);
+    }
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl) sh[0][pl][t] = (T)v[pl];
+    __syncthreads();
+    int b = 0;
+    for (int k = 0; k < K; ++k) {
+        double f[4];
+        // f+ and g+ from x - 1, f- and g- from x + 1
+        if (!per && x == 0) {
+            f[0] = k1_face(G, 0, 0, v, weq);
+            f[2] = k1_face(G, 2, 0, v, weq);
+        } else {
+            f[0] = (double)sh[b][0][tl];
+            f[2] = (double)sh[b][2][tl];
+        }
+        if (!per && x == nx - 1) {
+            f[1] = k1_face(G, 1, 1, v, weq);
+            f[3] = k1_face(G, 3, 1, v, weq);
+        } else {
+            f[1] = (double)sh[b][1][tr];
+            f[3] = (double)sh[b][3][tr];
+        }
+        collide1d(f, P);
+        b ^= 1;
+#pragma unroll
+        for (int pl = 0; pl < 4; ++pl) {
+            v[pl] = (double)(T)f[pl];
+            sh[b][pl][t] = (T)v[pl];
+        }
+        __syncthreads();
+    }
+    if (in && x >= ob && x < oe) {
+#pragma unroll
+        for (int pl = 0; pl < 4; ++pl) sth<2>(dst + pl * ps + xw, v[pl]);
+    }
+}
+
+hipError_t launch_step1k(bool f32, const void *src, void *dst, const Geo &G, const Phys &P,
+                         int K, hipStream_t st)
+{
+    const int nout = kK1Threads - 2 * K;
+    const int nb = (G.nx + nout - 1) / nout;
+    if (f32)
+        hipLaunchKernelGGL(k_step1d_k<float>, dim3(nb), dim3(kK1Threads), 0, st,
+                           (const float *)src, (float *)dst, G, P, K, nout);
+    else
+        hipLaunchKernelGGL(k_step1d_k<double>, dim3(nb), dim3(kK1Threads), 0, st,
+                           (const double *)src, (double *)dst, G, P, K, nout);
+    return hipGetLastError();
 }
 
 int step2x_blocks(const Geo &G, int seg)

@@ -226,3 +226,40 @@ def test_fused_request_on_walls_takes_single_steps():
     S.step(case.steps)
     ref, _ = orc_state(case, case.steps)
     assert per_plane_rel(to_np(S.planes()), ref) <= TOL64
+
+
+def _case_1d(n, bc, inflow, seed):
+    rng = np.random.default_rng(seed)
+    x = W.cell_centres(n)
+    h = 1.0 + 0.5 * (x < 0.5) + 0.05 * rng.random(n)
+    q = 0.1 * np.sin(2 * np.pi * x) + 0.02 * rng.standard_normal(n)
+    return W.Case(1, n, 1, 3.0, 1.9, 0, bc=bc + ("periodic", "periodic"), h0=h, qx0=q,
+                  inflow=inflow, name=f"fused1d_{n}")
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("fuse", [2, 4, 16])
+@pytest.mark.parametrize("n,bc,inflow,steps", [
+    (777, ("periodic", "periodic"), {}, 37),        # one tile, wraps onto itself
+    (5000, ("periodic", "periodic"), {}, 70),       # several tiles, ragged last one
+    (2000, ("neumann", "neumann"), {}, 45),
+    (3000, ("inflow", "wall"), {0: (1.5, 0.75, 0.0)}, 101),
+    (1500, ("wall", "inflow"), {1: (1.2, -0.3, 0.0)}, 33),
+    (40, ("wall", "wall"), {}, 19),                 # grid smaller than the halo
+])
+def test_fused_1d_launch_equals_single_steps(storage, fuse, n, bc, inflow, steps):
+    """fuse_steps = K on the 1D path (K steps per launch through LDS) gives bit for
+    bit the state of single steps, for every face rule, one or several tiles,
+    ragged tails, grids smaller than one tile, step counts that are not multiples
+    of K (a shorter last launch) and runs long enough for the captured graphs."""
+    case = _case_1d(n, bc, inflow, seed=n + fuse)
+    say(f"[fused1d] n={n} bc={bc} fuse={fuse} steps={steps} storage={storage}")
+    A = gpu_solver(case, storage=storage, fuse_steps=1)
+    B = gpu_solver(case, storage=storage, fuse_steps=fuse)
+    A.step(steps)
+    B.step(steps)
+    a, b = to_np(A.planes()), to_np(B.planes())
+    assert np.array_equal(a, b)
+    if storage == "f64":
+        ref, _ = orc_state(case, steps)
+        assert per_plane_rel(b, ref) <= TOL64
