@@ -3,16 +3,21 @@
 
 Headline workload: 2D shallow-water radial dam break, D2Q4 per component
 (12 distributions per node), 4096 x 4096 periodic grid, lambda = 6, s = 1.8,
-FP64 storage (the paper's arithmetic precision).  One "step" = one fused
-pull-stream + collide pass over the whole grid (one kernel launch).  `value` is
-MLUPS (million lattice-node updates per second) with the state resident in HBM.
+FP64 storage (the paper's arithmetic precision).  One "step" = one pull-stream +
+collide pass over the whole grid; the library advances several steps per kernel
+launch (temporal blocking, bitwise identical to single steps), so the launch
+reads the state once and writes it once for all of them.  `value` is MLUPS
+(million lattice-node updates per second) with the state resident in HBM.
 
 Beside it on the same JSON line:
   forms.fp32     the same workload with FP32 storage (FP64 arithmetic)
   forms.batched  256 mixed 1D / 2D Riemann problems in one persistent launch
                  (FP32 storage, 1000 steps) vs the plain path launched per instance
   forms.adjoint  2D 1024^2 gradient rollout (T = 500, checkpoints every 23 steps)
-  roofline       dominant kernel (FP64 step) against MI355X HBM peak
+  forms.*_one_step_per_launch  the same with one step per launch
+  forms.wall_1d_*  1D wall reflection, 2^20 nodes (MALL-resident)
+  roofline       dominant kernel (FP64 step launch) against MI355X HBM peak:
+                 algorithmic bytes per launch / average launch time
   cpu_baseline   the CPU FP64 oracle on a bounded sample of the headline workload
 
 Usage: python bench.py [--gpus 1] [--steps 2000] [--warmup 20] [--quick]
@@ -42,8 +47,8 @@ def _parse():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--npt", type=int, default=0)
     ap.add_argument("--pad", type=int, default=-1)
-    ap.add_argument("--fuse", type=int, default=0, choices=(0, 1, 2),
-                    help="steps per launch of the forward form (0 = tuned / default)")
+    ap.add_argument("--fuse", type=int, default=0, choices=tuple(range(0, 9)),
+                    help="steps per launch of the forward form (0 = tuned / library default)")
     ap.add_argument("--probe-copy", action="store_true",
                     help="first run a plain device copy of 2^30 bytes (reference for counters)")
     ap.add_argument("--storage", choices=("both", "f64", "f32"), default="both")
@@ -55,14 +60,16 @@ def log(*a):
 
 
 def time_forward(torch, n, storage, steps, warmup, block, npt, pad, fuse=1):
-    """Forward steps of the headline workload; ``fuse`` = steps per launch (1, or 2
-    for the fused two-step kernel of the all-periodic path)."""
+    """Forward steps of the headline workload; ``fuse`` = steps per launch asked
+    for (0 = the library's choice; lbm_launch_info reports what runs)."""
     from paper_1401_0427_amd import workloads as W
     from paper_1401_0427_amd.lbm import Solver
 
     c = W.radial_dam_break_2d(n, lam=6.0)
     S = Solver(2, n, n, lam=c.lam, s=c.s, h0=c.h0, qx0=c.qx0, qy0=c.qy0, storage=storage,
                block=block, npt=npt, plane_pad=pad, fuse_steps=fuse)
+    info = S.launch_info()
+    fuse = info["steps_per_launch"]
     S.step(warmup)
     torch.cuda.synchronize()
     st = torch.cuda.current_stream()
@@ -78,11 +85,14 @@ def time_forward(torch, n, storage, steps, warmup, block, npt, pad, fuse=1):
     ok = bool(torch.isfinite(h).all().item()) and tot[0] > 0
     nodes = n * n
     bpl = 12 * 2 * (8 if storage == "f64" else 4)  # algorithmic bytes per lattice update
-    launches = steps / fuse  # steps is even, so every step is in a fused launch when fuse = 2
+    # average launch: steps / fuse launches (when fuse does not divide steps the
+    # last launch is shorter; the average is then over equivalent full launches)
+    launches = steps / fuse
     # algorithmic bytes of one launch: the state read once and written once, whatever
     # the number of steps the launch advances
     return dict(ms_per_step=ms / steps, mlups=nodes * steps / (ms * 1e-3) / 1e6,
-                steps_per_launch=fuse, ms_per_launch=ms / launches,
+                steps_per_launch=fuse, segment_rows=info["segment_rows"],
+                resident_blocks=info["resident_blocks"], ms_per_launch=ms / launches,
                 gbs=nodes * bpl * launches / (ms * 1e-3) / 1e9, bytes_per_lu=bpl,
                 bytes_per_launch=nodes * bpl, wall_s=wall, finite=ok, mass=tot[0])
 
@@ -219,35 +229,48 @@ def time_adjoint(torch, n=1024, T=500, K=23, storage="f32"):
                 grad_s=float(s.grad), grad_h0_norm=float(h0.grad.norm()))
 
 
-# FP64 step kernels: (source files, committed counter summary)
+# FP64 step kernels: (source files, committed counter summary, name)
 KERNELS = {
-    1: (("fwd.hip", "lbm_device.h"), "k_step2d_fwd_4096_traffic.json",
-        "k_step2d<double> (fused pull-stream + BGK collide)"),
-    2: (("tblock.hip", "lbm_device.h"), "k_step2d_x2_fwd_4096_traffic.json",
-        "k_step2d_x2<double> (two pull-stream + BGK collide steps per launch)"),
+    "one_step": (("fwd.hip", "lbm_device.h"), "k_step2d_fwd_4096_traffic.json",
+                 "k_step2d<double> (fused pull-stream + BGK collide)"),
+    "lds_two_step": (("tblock.hip", "lbm_device.h"), "k_step2d_x2_fwd_4096_traffic.json",
+                     "k_step2d_x2<double> (two pull-stream + BGK collide steps per launch)"),
+    "wave_strip": (("tblock.hip", "lbm_device.h"), "k_step2d_xk_fwd_4096_traffic.json",
+                   "k_step2d_xk<double, {K}> ({K} pull-stream + BGK collide steps per launch, "
+                   "one wavefront per column strip)"),
 }
 
 
-def _measured_traffic(n, fuse):
+def kernel_kind(form):
+    """Which FP64 step kernel a timed forward form ran (from its launch plan)."""
+    if form["steps_per_launch"] == 1:
+        return "one_step"
+    if form["steps_per_launch"] == 2 and form["resident_blocks"] == 0:
+        return "lds_two_step"
+    return "wave_strip"
+
+
+def _measured_traffic(n, kind, K):
     """HBM bytes per launch of the FP64 step kernel from the committed rocprofv3
     counter summary (FETCH_SIZE + WRITE_SIZE, each scaled by what the counter
-    reads for a plain copy of known size), if it was taken for this grid and
-    the current kernel source; else None."""
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", KERNELS[fuse][1])
+    reads for a plain copy of known size), if it was taken for this grid, launch
+    depth and the current kernel source; else None."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", KERNELS[kind][1])
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
-    if d.get("n") != n or d.get("kernel_source_sha") != _kernel_sha(fuse):
+    if (d.get("n") != n or d.get("kernel_source_sha") != _kernel_sha(kind)
+            or d.get("steps_per_launch", K) != K):
         return None
     return d.get("traffic_bytes_per_launch_f64")
 
 
-def _kernel_sha(fuse=1):
+def _kernel_sha(kind="one_step"):
     import hashlib
 
     root = os.path.dirname(os.path.abspath(__file__))
     h = hashlib.sha256()
-    for f in KERNELS[fuse][0]:
+    for f in KERNELS[kind][0]:
         h.update(open(os.path.join(root, "paper_1401_0427_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -294,7 +317,7 @@ def main():
         t = fwd_tune.get(storage, {})
         return (args.block or t.get("block", 256), args.npt or t.get("npt", 1),
                 args.pad if args.pad >= 0 else t.get("plane_pad", -1),
-                args.fuse or t.get("fuse_steps", 2))
+                args.fuse or t.get("fuse_steps", 0))
 
     n = args.n
     if args.probe_copy:
@@ -311,7 +334,7 @@ def main():
         L = launch(storage)
         log(f"[bench] forward {storage.upper()} {n}^2, {args.steps} steps, launch {L}")
         forms["fp" + storage[1:]] = time_forward(torch, n, storage, args.steps, args.warmup, *L)
-        if L[3] != 1 and not args.quick:
+        if forms["fp" + storage[1:]]["steps_per_launch"] != 1 and not args.quick:
             # the one-step-per-launch kernel on the same workload, for comparison
             log(f"[bench] forward {storage.upper()} {n}^2, one step per launch")
             forms["fp" + storage[1:] + "_one_step_per_launch"] = time_forward(
@@ -329,11 +352,13 @@ def main():
         forms["adjoint"] = time_adjoint(torch)
     achieved = f64["gbs"]
     fuse = f64["steps_per_launch"]
+    kind = kernel_kind(f64)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": KERNELS[fuse][2], "steps_per_launch": fuse,
-            "bytes_per_launch": f64["bytes_per_launch"]}
-    traffic = _measured_traffic(n, fuse)
+            "kernel": KERNELS[kind][2].format(K=fuse), "steps_per_launch": fuse,
+            "bytes_per_launch": f64["bytes_per_launch"],
+            "per_step_equivalent_gbs": round(achieved * fuse, 1)}
+    traffic = _measured_traffic(n, kind, fuse)
     if traffic is not None:
         roof["traffic"] = traffic
     cpu = None
@@ -359,7 +384,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "forms": forms,
-        "kernel_source_sha": _kernel_sha(fuse),
+        "kernel_source_sha": _kernel_sha(kind),
     }
     print(json.dumps(out), flush=True)
 

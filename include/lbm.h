@@ -102,11 +102,15 @@ typedef struct {
                              bit 2: plain workgroup order (no XCD-aware tile remap);
                              < 0 = library default */
     int fuse_steps;       /* steps per launch (temporal blocking; bitwise identical
-                             to single steps): 0 = library default, else a power
-                             of two <= 16.  2D all-periodic grids fuse at most 2
-                             (default 2 when the fused launch has >= 1024
-                             workgroups, e.g. 4096^2, else 1); 1D grids any
-                             (default 16); 2D grids with other faces take 1. */
+                             to single steps): 0 = library default, else 1 .. 16.
+                             2D all-periodic grids fuse at most 8 (larger values
+                             take 8; default 8 for FP64 and 6 for FP32 storage
+                             when that launch fills at least a third of the
+                             device, e.g. 1024^2 and larger, else 2 when the LDS
+                             two-step launch has >= 1024 workgroups, else 1;
+                             planes of 2 GiB or more take 1); 1D grids any
+                             (default 16); 2D grids with other faces take 1.
+                             lbm_launch_info reports the choice. */
     void *f_a, *f_b;      /* caller-owned device state buffers (ping-pong) */
     void *stream;         /* hipStream_t; NULL = default stream */
 } lbm_params;
@@ -133,6 +137,14 @@ int lbm_step_buffers(lbm_ctx *ctx, const void *src, void *dst);
 
 /* Pointer to the buffer holding the current level and the number of steps done. */
 int lbm_current(lbm_ctx *ctx, void **state, long *steps_done);
+
+/* Launch plan chosen at init (any output may be NULL): steps per launch
+ * (temporal blocking depth, see fuse_steps); rows per workgroup (LDS two-step
+ * kernel) or per wavefront (wave-strip K-step kernel) segment, 0 for one-step
+ * and 1D launches; and, for the wave-strip kernel, the workgroups resident on
+ * the device at once, which the segment length was chosen against (0 otherwise). */
+int lbm_launch_info(lbm_ctx *ctx, int *steps_per_launch, int *segment_rows,
+                    long *resident_blocks);
 
 /* Copy the current state to dst / overwrite it from src (device, same layout). */
 int lbm_export(lbm_ctx *ctx, void *dst);

@@ -1,7 +1,7 @@
 """Project autotuner: picks launch shapes by timing them on the device.
 
 * ``tune_forward``: workgroup size, nodes per thread, plane padding and memory
-  hints of the stream + collide kernel, and one or two steps per launch, for
+  hints of the stream + collide kernel, and the steps per launch (1 .. 8), for
   one grid and storage type.
 * ``tune_batch``: mode (persistent dataflow or flat per-step launches),
   workgroup size, tile size and nodes per pass of the batched launch for a
@@ -38,11 +38,12 @@ def _timer(torch):
     return run
 
 
-def tune_forward(n=4096, storage="f64", steps=60, blocks=(128, 256, 512), npts=(1, 2),
-                 pads=(0, 2048), hints=(2, 6), fuses=(1, 2), log=print):
-    """Sweep the one-step kernel's launch shape, then the fused two-step launch
-    (whose shape is fixed) on each plane padding; the winner is the lowest time
-    per step.  A fused winner keeps the best one-step shape for the steps that
+def tune_forward(n=4096, storage="f64", steps=120, blocks=(128, 256, 512), npts=(1, 2),
+                 pads=(0, 2048), hints=(2, 6), fuses=(1, 2, 3, 4, 5, 6, 8), log=print):
+    """Sweep the one-step kernel's launch shape, then the multi-step launches
+    (steps per launch in ``fuses``; their shapes are fixed or chosen by the
+    library per grid) on each plane padding; the winner is the lowest time per
+    step.  A multi-step winner keeps the best one-step shape for the steps that
     are launched singly."""
     import torch
 
@@ -54,7 +55,7 @@ def tune_forward(n=4096, storage="f64", steps=60, blocks=(128, 256, 512), npts=(
     h0 = torch.as_tensor(c.h0, device="cuda")
     z = torch.zeros_like(h0)
     bpl = 192 if storage == "f64" else 96
-    steps += steps % 2  # whole fused launches
+    steps = max(120, steps // 120 * 120)  # whole launches for 1 .. 6 and 8 steps per launch
     rows = []
 
     def one(block, npt, pad, hint, fuse):
@@ -74,9 +75,10 @@ def tune_forward(n=4096, storage="f64", steps=60, blocks=(128, 256, 512), npts=(
             one(block, npt, pad, hint, 1)
     single = [r for r in rows if r["fuse_steps"] == 1]
     base = min(single, key=lambda r: r["ms"]) if single else dict(block=256, npt=1, mem_hints=6)
-    if 2 in fuses:
-        for pad in pads:
-            one(base["block"], base["npt"], pad, base["mem_hints"], 2)
+    for fuse in fuses:
+        if fuse > 1:
+            for pad in pads:
+                one(base["block"], base["npt"], pad, base["mem_hints"], fuse)
     best = min(rows, key=lambda r: r["ms"])
     return best, rows
 

@@ -160,10 +160,13 @@ struct lbm_ctx {
     hipStream_t cap;
     hipGraphExec_t chunk[2];
     int chunk_len;
+    int xk_seg;     // rows per segment of the wave-strip K-step launch
+    long xk_slots;  // its resident workgroups on the device
 };
 
-static const int kChunk = 32;  // steps per captured graph: with up to 16 steps per launch it
-                               // holds an even number of launches (parity preserved)
+// Steps per captured graph: the smallest multiple of twice the steps per launch that is
+// at least kChunk, so a chunk holds an even number of launches (parity preserved).
+static const int kChunk = 32;
 // Steps per launch on the all-periodic 2D path when fuse_steps = 0: two when the
 // fused launch has at least kFuseMinBlocks workgroups (about four per compute
 // unit), else one -- on small grids the fused launch has too few workgroups to
@@ -171,13 +174,35 @@ static const int kChunk = 32;  // steps per captured graph: with up to 16 steps 
 // 128^2 .. 1024^2 instances of the batched manifest).
 static const int kFuseMinBlocks = 1024;
 // 1D: steps per launch by default and at most (tiles of 1024 nodes hold the K
-// levels in LDS; K divides the graph chunk with an even number of launches).
+// levels in LDS).
 static const int kDefaultFuse1d = 16;
 static const int kMaxFuse1d = 16;
 #ifndef LBM_FUSE_SEG
 #define LBM_FUSE_SEG 24
 #endif
-static const int kFuseSeg = LBM_FUSE_SEG;  // rows per workgroup segment of the fused launch
+static const int kFuseSeg = LBM_FUSE_SEG;  // rows per workgroup segment of the LDS two-step launch
+#ifndef LBM_XK_SEG
+#define LBM_XK_SEG 160
+#endif
+// Rows per wavefront segment of the wave-strip launch when the device cannot be
+// queried (else chosen per grid at init, step2k_seg).
+static const int kXkSeg = LBM_XK_SEG;
+// Default steps per launch on all-periodic 2D grids (wave-strip kernel),
+// measured at 4096^2: FP64 8 (155 GLUPS; 4: 93, one step: 29), FP32 6 (204
+// GLUPS; 8: 190, the FP32 K = 8 kernel holds two wavefronts per SIMD, K = 6
+// three; one step: 61); at 1024^2 FP64 8 gives 86 GLUPS (one step: 25).
+static const int kDefaultFuse2dF64 = 8;
+static const int kDefaultFuse2dF32 = 6;
+// Shortest segment of a wave-strip launch (the halo rows cost 2 (K - 1) per
+// segment; the segment length itself is chosen per grid, step2k_seg).  Grids
+// whose launch cannot fill a third of the device keep the one- or two-step
+// launches by default.
+static const int kXkMinSeg = 16;
+#ifndef LBM_FUSE2_LDS
+#define LBM_FUSE2_LDS 1  // two steps per launch: the LDS strip kernel (faster at K = 2)
+#endif
+// 2D all-periodic: steps per launch at most (wave-strip kernel: K = 2 .. 8)
+static const int kMaxFuse2d = 8;
 
 extern "C" void lbm_destroy(lbm_ctx *c)
 {
@@ -235,10 +260,9 @@ extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0
         return fail(LBM_EINVAL, "nodes_per_thread must be 1, 2 or 4 (got %d)", npt);
     if (p->check_every < 0) return fail(LBM_EINVAL, "check_every must be >= 0");
     if (p->mem_hints > 7) return fail(LBM_EINVAL, "mem_hints must be < 8");
-    if (p->fuse_steps < 0 || p->fuse_steps > kMaxFuse1d ||
-        (p->fuse_steps & (p->fuse_steps - 1)) != 0)
-        return fail(LBM_EINVAL, "fuse_steps must be 0 or a power of two up to %d (got %d)",
-                    kMaxFuse1d, p->fuse_steps);
+    if (p->fuse_steps < 0 || p->fuse_steps > kMaxFuse1d)
+        return fail(LBM_EINVAL, "fuse_steps must be in 0 .. %d (got %d)", kMaxFuse1d,
+                    p->fuse_steps);
 
     lbm_ctx *c = new (std::nothrow) lbm_ctx();
     if (!c) return fail(LBM_EDEVICE, "out of host memory");
@@ -271,18 +295,37 @@ extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0
             c->fuse = 1;
         else if (dim == 1)
             c->fuse = want ? want : kDefaultFuse1d;
-        else if (allper)
-            c->fuse = want ? (want > 2 ? 2 : want)
-                           : (step2x_blocks(c->G, kFuseSeg) >= kFuseMinBlocks ? 2 : 1);
-        else
+        else if (allper && (size_t)ps * (c->f32 ? 4 : 8) < ((size_t)1 << 31)) {
+            if (want) {
+                c->fuse = want > kMaxFuse2d ? kMaxFuse2d : want;
+                if (c->fuse > 2 || !LBM_FUSE2_LDS) {
+                    c->xk_seg = step2k_seg(c->G, c->f32, c->fuse, kXkMinSeg, nullptr,
+                                           &c->xk_slots);
+                    if (c->xk_seg <= 0) c->xk_seg = kXkSeg;
+                }
+            } else {
+                const int kd = c->f32 ? kDefaultFuse2dF32 : kDefaultFuse2dF64;
+                bool full = false;
+                long slots = 0;
+                const int seg = step2k_seg(c->G, c->f32, kd, kXkMinSeg, &full, &slots);
+                if (seg > 0 && full) {
+                    c->fuse = kd;
+                    c->xk_seg = seg;
+                    c->xk_slots = slots;
+                } else {
+                    c->fuse = step2x_blocks(c->G, kFuseSeg) >= kFuseMinBlocks ? 2 : 1;
+                }
+            }
+        } else {
             c->fuse = 1;
+        }
     }
     c->buf[0] = p->f_a;
     c->buf[1] = p->f_b;
     c->cur = 0;
     c->steps = 0;
     c->st = (hipStream_t)p->stream;
-    c->chunk_len = kChunk;
+    c->chunk_len = 2 * c->fuse * ((kChunk + 2 * c->fuse - 1) / (2 * c->fuse));
 
     hipError_t e;
     const int nmb = moments_blocks(c->G);
@@ -337,7 +380,12 @@ static hipError_t step_once(lbm_ctx *c, const void *src, void *dst, hipStream_t 
 static hipError_t step_k(lbm_ctx *c, int k, const void *src, void *dst, hipStream_t st)
 {
     if (k == 1) return step_once(c, src, dst, st);
-    if (c->dim == 2) return launch_step2x(c->f32, src, dst, c->G, c->P, kFuseSeg, st);
+    if (c->dim == 2) {
+        if (LBM_FUSE2_LDS && k == 2)
+            return launch_step2x(c->f32, src, dst, c->G, c->P, kFuseSeg, st);
+        return launch_step2k(c->f32, src, dst, c->G, c->P, k, c->xk_seg > 0 ? c->xk_seg : kXkSeg,
+                             st);
+    }
     return launch_step1k(c->f32, src, dst, c->G, c->P, k, st);
 }
 
@@ -414,9 +462,7 @@ extern "C" int lbm_step(lbm_ctx *c, long nsteps)
             c->steps += c->chunk_len;  // chunk length is even: c->cur unchanged
         }
         while (todo > 0) {
-            // the 2D fused kernel takes exactly two steps; the 1D one any k <= fuse
-            int k = (int)(todo < c->fuse ? todo : c->fuse);
-            if (c->dim == 2 && k != 2) k = 1;
+            const int k = (int)(todo < c->fuse ? todo : c->fuse);
             HIP_TRY(step_k(c, k, c->buf[c->cur], c->buf[c->cur ^ 1], c->st));
             c->cur ^= 1;
             todo -= k;
@@ -445,6 +491,18 @@ extern "C" int lbm_current(lbm_ctx *c, void **state, long *steps_done)
     if (rc) return rc;
     if (state) *state = c->buf[c->cur];
     if (steps_done) *steps_done = c->steps;
+    return LBM_OK;
+}
+
+extern "C" int lbm_launch_info(lbm_ctx *c, int *steps_per_launch, int *segment_rows,
+                               long *resident_blocks)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    const bool xk = c->dim == 2 && c->fuse >= 2 && !(LBM_FUSE2_LDS && c->fuse == 2);
+    if (steps_per_launch) *steps_per_launch = c->fuse;
+    if (segment_rows) *segment_rows = xk ? c->xk_seg : (c->fuse == 2 ? kFuseSeg : 0);
+    if (resident_blocks) *resident_blocks = xk ? c->xk_slots : 0;
     return LBM_OK;
 }
 

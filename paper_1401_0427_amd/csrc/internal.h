@@ -52,6 +52,10 @@ hipError_t launch_step1k(bool f32, const void *src, void *dst, const Geo &G, con
                          int K, hipStream_t st);
 hipError_t launch_step2x(bool f32, const void *src, void *dst, const Geo &G, const Phys &P,
                          int seg, hipStream_t st);
+int step2k_blocks(const Geo &G, bool f32, int K, int seg);
+int step2k_seg(const Geo &G, bool f32, int K, int min_seg, bool *full, long *slots_out);
+hipError_t launch_step2k(bool f32, const void *src, void *dst, const Geo &G, const Phys &P,
+                         int K, int seg, hipStream_t st);
 hipError_t launch_entropy(int dim, bool f32, const void *state, const Geo &G, double lambda,
                           double g, double *h_node, double *partials, hipStream_t st,
                           int *nblocks_out);

@@ -149,17 +149,50 @@ __global__ void __launch_bounds__(kX2Threads)
 // are rounded to the storage type (as a store and reload would round them), and
 // the per-node arithmetic is the one-step kernel's, so K steps in one launch
 // equal K single steps bit for bit.  The next row's level-n pulls are issued
-// before the current row is computed, so loads overlap the arithmetic.
+// before the current row is computed, so loads overlap the arithmetic.  The row
+// loop is unrolled by two with the roles of the row registers swapped, so no
+// register is copied from one row to the next; plane addresses are a uniform
+// base plus a 32-bit byte offset (planes below 2 GiB).
 #ifndef LBM_XK_WAVES
 #define LBM_XK_WAVES 4
 #endif
-#ifndef LBM_XK_PREFETCH
-#define LBM_XK_PREFETCH 1
-#endif
 #ifndef LBM_XK_REMAP
-#define LBM_XK_REMAP 0
+#define LBM_XK_REMAP 1
+#endif
+#ifndef LBM_XK_DEPTH
+#define LBM_XK_DEPTH 2
+#endif
+// Output strips start and end on this many bytes (0: no alignment), and the
+// stores are non-temporal (1) or not (0), per storage type.  Measured at 4096^2:
+// FP64 -- 64-byte strips with non-temporal stores (94 vs 77 GLUPS unaligned);
+// FP32 -- unaligned strips with ordinary stores, whose partly written segments
+// at strip edges merge in L2 (140 vs 122 GLUPS for 64-byte strips).
+#ifndef LBM_XK_ALIGN_F64
+#define LBM_XK_ALIGN_F64 64
+#endif
+#ifndef LBM_XK_NT_F64
+#define LBM_XK_NT_F64 1
+#endif
+#ifndef LBM_XK_ALIGN_F32
+#define LBM_XK_ALIGN_F32 0
+#endif
+#ifndef LBM_XK_NT_F32
+#define LBM_XK_NT_F32 0
 #endif
 constexpr int kXkWaves = LBM_XK_WAVES;  // strips (wavefronts) per workgroup
+constexpr int kXkDepth = LBM_XK_DEPTH;  // rows of level-n pulls in flight
+
+// Workgroup b runs on XCD b % 8 (round-robin dispatch).  Give XCD x the
+// contiguous tile range [x q + min(x, r), ...) of q + (x < r) tiles (q, r =
+// ntiles / 8, ntiles % 8): neighbouring strips then share one XCD's L2, so the
+// halo columns two strips both read are fetched from memory once.  A bijection
+// of [0, ntiles) for any ntiles.
+__device__ __forceinline__ int xk_tile(int b, int ntiles, bool remap)
+{
+    if (!remap) return b;
+    const int x = b & 7, k = b >> 3, q = ntiles >> 3, r = ntiles & 7;
+    return x * q + (x < r ? x : r) + k;
+}
 
 // Value of lane l - 1 (shift 1) or lane l + 1 (shift -1); the end lanes get an
 // arbitrary lane's value (they are outside the valid range of the next level).
@@ -177,156 +210,311 @@ __device__ __forceinline__ double xk_from(double v, int lane, int shift)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Level-n pulls of the level-1 node in column (xm, xw, xp) and rows (rm, row, rp)
-// (element offsets of the three rows).
 template <typename T>
-__device__ __forceinline__ void xk_load(const T *__restrict__ src, long ps, long rm, long row,
-                                        long rp, int xm, int xw, int xp, T *f)
+__device__ __forceinline__ T xk_at(const T *base, unsigned off)
+{
+    return *(const T *)((const char *)base + off);
+}
+
+// Byte offsets (within a plane) of the level-n pulls of one level-1 node.
+struct XkOff {
+    unsigned e1, e2, e3, e4;
+};
+
+template <typename T>
+__device__ __forceinline__ XkOff xk_offsets(int r, int nx, int ny, int xm, int xw, int xp)
+{
+    const unsigned row = (unsigned)r * (unsigned)nx;
+    const unsigned rm = r == 0 ? (unsigned)(ny - 1) * (unsigned)nx : row - nx;
+    const unsigned rp = r == ny - 1 ? 0u : row + nx;
+    return XkOff{(row + xm) * (unsigned)sizeof(T), (rm + xw) * (unsigned)sizeof(T),
+                 (row + xp) * (unsigned)sizeof(T), (rp + xw) * (unsigned)sizeof(T)};
+}
+
+template <typename T>
+__device__ __forceinline__ void xk_load(const T *__restrict__ src, long ps, const XkOff &o, T *f)
 {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const T *b = src + (4 * c) * ps;
-        f[4 * c + 0] = b[row + xm];
-        f[4 * c + 1] = b[ps + rm + xw];
-        f[4 * c + 2] = b[2 * ps + row + xp];
-        f[4 * c + 3] = b[3 * ps + rp + xw];
+        f[4 * c + 0] = xk_at(src + (4 * c + 0) * ps, o.e1);
+        f[4 * c + 1] = xk_at(src + (4 * c + 1) * ps, o.e2);
+        f[4 * c + 2] = xk_at(src + (4 * c + 2) * ps, o.e3);
+        f[4 * c + 3] = xk_at(src + (4 * c + 3) * ps, o.e4);
     }
 }
 
+// Vector buffer store of one value; the hardware drops it when the byte offset
+// is at or beyond the resource's size (non-output lanes add kXkDrop), so stores
+// need no branch.  aux 2: non-temporal.
+constexpr unsigned kXkDrop = 0x80000000u;
+__device__ __forceinline__ void xk_store(__amdgpu_buffer_rsrc_t r, unsigned off, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(
+        __builtin_bit_cast(__attribute__((ext_vector_type(2))) int, v), r, off, 0,
+        LBM_XK_NT_F64 ? 2 : 0);
+}
+__device__ __forceinline__ void xk_store(__amdgpu_buffer_rsrc_t r, unsigned off, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(v), r, off, 0, LBM_XK_NT_F32 ? 2 : 0);
+}
+
+// Output columns per strip: 64 lanes minus K - 1 halo lanes per side, rounded
+// down to a whole number of aligned chunks, so (on rows that start aligned)
+// each strip writes whole memory segments and never shares one with another
+// strip: a partially written segment would cost the DRAM a read-modify-write.
 template <typename T, int K>
+constexpr int xk_wo()
+{
+    constexpr int A = (sizeof(T) == 8 ? LBM_XK_ALIGN_F64 : LBM_XK_ALIGN_F32) / (int)sizeof(T);
+    return A > 1 ? (64 - 2 * (K - 1)) / A * A : 64 - 2 * (K - 1);
+}
+// Halo lanes before the first output column (>= K - 1 on both sides).
+template <typename T, int K>
+constexpr int xk_halo()
+{
+    return (64 - xk_wo<T, K>()) / 2;
+}
+
+// One iteration j of the row loop.  cur: level-n pulls of this iteration's
+// level-1 row; nxt (the buffer consumed in the previous iteration): receives
+// those of iteration j + D, whose rows' byte offsets are onext (always a row of
+// the grid, also past the segment's end).  em: e2 planes of each intermediate
+// level one row below the row this iteration consumes (it is overwritten with
+// the newest row, the other array then holding the older one).  There is no
+// branch: levels without a valid row yet (the first 2 (K - 1) iterations) and
+// iterations past the end compute values that are never stored nor reach a
+// stored value, and their stores, like those of non-output lanes, carry an
+// offset the hardware drops -- so the compiler's memory waits see one straight
+// sequence and keep the D rows of loads in flight.
+template <typename T, int K>
+__device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const Phys &P,
+                                       int lane, const __amdgpu_buffer_rsrc_t *orsrc,
+                                       unsigned ooff, const XkOff &onext, const T (&cur)[12],
+                                       T (&nxt)[12], T (&em)[K - 1][3], T (&s1)[K - 1][3],
+                                       T (&s3)[K - 1][3])
+{
+    xk_load(src, ps, onext, nxt);
+    double v[12];
+#pragma unroll
+    for (int pl = 0; pl < 12; ++pl) v[pl] = (double)cur[pl];
+    collide2d(v, P);  // level 1
+#pragma unroll
+    for (int k = 1; k < K; ++k) {
+        // v: level k, one row above the level-k+1 row computed here
+#pragma unroll
+        for (int pl = 0; pl < 12; ++pl) v[pl] = (double)(T)v[pl];
+        double o[12];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            o[4 * c + 0] = (double)s1[k - 1][c];
+            o[4 * c + 1] = (double)em[k - 1][c];
+            o[4 * c + 2] = (double)s3[k - 1][c];
+            o[4 * c + 3] = v[4 * c + 3];
+            em[k - 1][c] = (T)v[4 * c + 1];
+            s1[k - 1][c] = xk_from((T)v[4 * c + 0], lane, 1);
+            s3[k - 1][c] = xk_from((T)v[4 * c + 2], lane, -1);
+        }
+        collide2d(o, P);
+#pragma unroll
+        for (int pl = 0; pl < 12; ++pl) v[pl] = o[pl];
+    }
+#pragma unroll
+    for (int pl = 0; pl < 12; ++pl) xk_store(orsrc[pl], ooff, (T)v[pl]);
+}
+
+constexpr int xk_gcd(int a, int b) { return b == 0 ? a : xk_gcd(b, a % b); }
+
+// D = rows of level-n pulls in flight ahead of the row being computed (a ring of
+// D + 1 register buffers); the loop is unrolled by lcm(2, D + 1) so every ring
+// slot and e2 array is addressed statically, and runs a whole number of
+// unrolled blocks (the extra iterations store nothing).
+template <typename T, int K, int D>
 __global__ void __launch_bounds__(64 * kXkWaves)
     k_step2d_xk(const T *__restrict__ src, T *__restrict__ dst, Geo G, Phys P, int nstrips,
                 int seg)
 {
-    constexpr int WO = 64 - 2 * (K - 1);  // output columns per strip
+    constexpr int WO = xk_wo<T, K>();  // output columns per strip
+    constexpr int H = xk_halo<T, K>();
+    static_assert(H >= K - 1 && 64 - H - WO >= K - 1, "halo lanes");
+    constexpr int U = 2 * (D + 1) / xk_gcd(2, D + 1);
     const int nx = G.nx, ny = G.ny;
     const long ps = G.ps;
     const int lane = threadIdx.x & 63;
     const int ngroups = (nstrips + kXkWaves - 1) / kXkWaves;
     const int nseg = (ny + seg - 1) / seg;
-    const int tile = xcd_tile(blockIdx.x, ngroups * nseg, LBM_XK_REMAP != 0);
+    const int tile = xk_tile(blockIdx.x, ngroups * nseg, LBM_XK_REMAP != 0);
     const int strip = (tile % ngroups) * kXkWaves + (threadIdx.x >> 6);
     if (strip >= nstrips) return;  // whole wavefront; nothing here waits on others
     const int y0 = (tile / ngroups) * seg;
     const int y1 = min(y0 + seg, ny);
-    const int x0 = strip * WO;                    // first output column
-    const int xc = x0 - (K - 1) + lane;           // this lane's column, unwrapped
+    const int x0 = strip * WO;     // first output column
+    const int xc = x0 - H + lane;  // this lane's column, unwrapped
     const int xw = ((xc % nx) + nx) % nx;
     const int xm = xw == 0 ? nx - 1 : xw - 1;
     const int xp = xw == nx - 1 ? 0 : xw + 1;
-    const bool olane = lane >= K - 1 && lane < 64 - (K - 1) && xc < nx;
+    const bool olane = lane >= H && lane < H + WO && xc < nx;
     const int niter = (y1 - y0) + 2 * (K - 1);
-    int r = (((y0 - (K - 1)) % ny) + ny) % ny;  // level-1 row of the iteration, wrapped
+    // Output row of iteration j is y0 - 2 (K - 1) + j, stored when it lies in
+    // [y0, y1); byte offset of (row, xc) within a plane, or a dropped offset.
+    const unsigned plane_bytes = (unsigned)nx * (unsigned)ny * (unsigned)sizeof(T);
+    const unsigned ostep = (unsigned)nx * (unsigned)sizeof(T);
+    const unsigned lane_off = olane ? (unsigned)xc * (unsigned)sizeof(T) : kXkDrop;
+    __amdgpu_buffer_rsrc_t orsrc[12];
+#pragma unroll
+    for (int pl = 0; pl < 12; ++pl)
+        orsrc[pl] = __builtin_amdgcn_make_buffer_rsrc(dst + pl * ps, 0, (int)plane_bytes,
+                                                      0x00020000);
+    int rl = (((y0 - (K - 1)) % ny) + ny) % ny;  // level-1 row of the last load, wrapped
 
     // state of the intermediate levels 1 .. K-1 (index k-1), storage precision:
-    // e2 planes of the last two rows, e1 planes of the last row from lane l-1 and
-    // e3 planes from lane l+1
-    T e2m[K - 1][3], e2c[K - 1][3], s1[K - 1][3], s3[K - 1][3];
+    // e2 planes of the last two rows (e2[0] / e2[1] alternate), e1 planes of the
+    // last row from lane l-1 and e3 planes from lane l+1
+    T e2[2][K - 1][3], s1[K - 1][3], s3[K - 1][3];
 #pragma unroll
     for (int k = 0; k < K - 1; ++k)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) e2m[k][c] = e2c[k][c] = s1[k][c] = s3[k][c] = (T)0;
+        for (int c = 0; c < 3; ++c) e2[0][k][c] = e2[1][k][c] = s1[k][c] = s3[k][c] = (T)0;
 
-    T cur[12];
-    {
-        const long row = (long)r * nx;
-        const long rm = r == 0 ? (long)(ny - 1) * nx : row - nx;
-        const long rp = r == ny - 1 ? 0 : row + nx;
-        xk_load(src, ps, rm, row, rp, xm, xw, xp, cur);
+    T buf[D + 1][12];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        xk_load(src, ps, xk_offsets<T>(rl, nx, ny, xm, xw, xp), buf[d]);
+        if (d + 1 < D) rl = rl == ny - 1 ? 0 : rl + 1;
     }
-    for (int j = 0; j < niter; ++j) {
-        r = r == ny - 1 ? 0 : r + 1;
-        T nxt[12];
-#if LBM_XK_PREFETCH
-        if (j + 1 < niter) {
-            const long row = (long)r * nx;
-            const long rm = r == 0 ? (long)(ny - 1) * nx : row - nx;
-            const long rp = r == ny - 1 ? 0 : row + nx;
-            xk_load(src, ps, rm, row, rp, xm, xw, xp, nxt);
+    for (int j = 0; j < niter; j += U) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int jj = j + u;
+            const int orow = y0 - 2 * (K - 1) + jj;
+            const unsigned ooff = (orow >= y0 && orow < y1)
+                                      ? (unsigned)orow * ostep + lane_off
+                                      : kXkDrop;
+            rl = rl == ny - 1 ? 0 : rl + 1;
+            xk_row<T, K>(src, ps, P, lane, orsrc, ooff, xk_offsets<T>(rl, nx, ny, xm, xw, xp),
+                         buf[u % (D + 1)], buf[(u + D) % (D + 1)], e2[u % 2], s1, s3);
         }
-#endif
-        double v[12];
-#pragma unroll
-        for (int pl = 0; pl < 12; ++pl) v[pl] = (double)cur[pl];
-        collide2d(v, P);  // level 1
-        bool live = true;
-#pragma unroll
-        for (int k = 1; k < K; ++k) {
-            // v: level k (rounded next), one row above the level-k+1 row computed here
-#pragma unroll
-            for (int pl = 0; pl < 12; ++pl) v[pl] = (double)(T)v[pl];
-            const bool act = j >= 2 * k;  // level k+1 has a row this iteration
-            double o[12];
-            if (act) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    o[4 * c + 0] = (double)s1[k - 1][c];
-                    o[4 * c + 1] = (double)e2m[k - 1][c];
-                    o[4 * c + 2] = (double)s3[k - 1][c];
-                    o[4 * c + 3] = v[4 * c + 3];
-                }
-                collide2d(o, P);
-            }
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                e2m[k - 1][c] = e2c[k - 1][c];
-                e2c[k - 1][c] = (T)v[4 * c + 1];
-                s1[k - 1][c] = xk_from((T)v[4 * c + 0], lane, 1);
-                s3[k - 1][c] = xk_from((T)v[4 * c + 2], lane, -1);
-            }
-            if (!act) {
-                live = false;
-                break;
-            }
-#pragma unroll
-            for (int pl = 0; pl < 12; ++pl) v[pl] = o[pl];
-        }
-        if (live && olane) {
-            T *out = dst + (long)(y0 - 2 * (K - 1) + j) * nx + xc;
-#pragma unroll
-            for (int pl = 0; pl < 12; ++pl) sth<2>(out + pl * ps, v[pl]);
-        }
-#if LBM_XK_PREFETCH
-#pragma unroll
-        for (int pl = 0; pl < 12; ++pl) cur[pl] = nxt[pl];
-#else
-        if (j + 1 < niter) {
-            const long row = (long)r * nx;
-            const long rm = r == 0 ? (long)(ny - 1) * nx : row - nx;
-            const long rp = r == ny - 1 ? 0 : row + nx;
-            xk_load(src, ps, rm, row, rp, xm, xw, xp, cur);
-        }
-        (void)nxt;
-#endif
     }
 }
 
-int step2k_strips(const Geo &G, int K) { return (G.nx + (64 - 2 * (K - 1)) - 1) / (64 - 2 * (K - 1)); }
-
-int step2k_blocks(const Geo &G, int K, int seg)
+static int xk_wo_of(bool f32, int K)
 {
-    const int ngroups = (step2k_strips(G, K) + kXkWaves - 1) / kXkWaves;
+    switch (K) {
+    case 2: return f32 ? xk_wo<float, 2>() : xk_wo<double, 2>();
+    case 3: return f32 ? xk_wo<float, 3>() : xk_wo<double, 3>();
+    case 4: return f32 ? xk_wo<float, 4>() : xk_wo<double, 4>();
+    case 5: return f32 ? xk_wo<float, 5>() : xk_wo<double, 5>();
+    case 6: return f32 ? xk_wo<float, 6>() : xk_wo<double, 6>();
+    case 7: return f32 ? xk_wo<float, 7>() : xk_wo<double, 7>();
+    default: return f32 ? xk_wo<float, 8>() : xk_wo<double, 8>();
+    }
+}
+
+static int step2k_strips(const Geo &G, bool f32, int K)
+{
+    const int wo = xk_wo_of(f32, K);
+    return (G.nx + wo - 1) / wo;
+}
+
+int step2k_blocks(const Geo &G, bool f32, int K, int seg)
+{
+    const int ngroups = (step2k_strips(G, f32, K) + kXkWaves - 1) / kXkWaves;
     return ngroups * ((G.ny + seg - 1) / seg);
+}
+
+// Workgroups of the K-step launch resident per compute unit (occupancy API).
+static int xk_per_cu(bool f32, int K)
+{
+    int n = 0;
+    const int bs = 64 * kXkWaves;
+    hipError_t e = hipErrorInvalidValue;
+#define LBM_XK_OCC(KK)                                                                        \
+    case KK:                                                                                  \
+        e = f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                               \
+                      &n, k_step2d_xk<float, KK, kXkDepth>, bs, 0)                            \
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(                               \
+                      &n, k_step2d_xk<double, KK, kXkDepth>, bs, 0);                          \
+        break;
+    switch (K) {
+        LBM_XK_OCC(2)
+        LBM_XK_OCC(3)
+        LBM_XK_OCC(4)
+        LBM_XK_OCC(5)
+        LBM_XK_OCC(6)
+        LBM_XK_OCC(7)
+        LBM_XK_OCC(8)
+    default:
+        break;
+    }
+#undef LBM_XK_OCC
+    return e == hipSuccess ? n : 0;
+}
+
+// Rows per segment of the K-step launch.  Every wavefront of the launch runs
+// seg + 2 (K - 1) row iterations and the workgroups run in rounds of `slots`
+// (resident workgroups on the whole device), so the launch takes about
+//     ceil(blocks / slots) * (seg + 2 (K - 1))
+// iteration times (a partly filled single round proportionally longer: fewer
+// wavefronts share the memory system).  Return the seg >= min_seg that minimises
+// this, in *full whether that choice fills at least a third of the device (below
+// that the few wavefronts cannot keep the memory system busy: a 512^2 FP32 grid
+// at 12 % ran slower than one step per launch, FP64 at 37 % faster) and in
+// *slots_out the resident workgroups; 0 when the device cannot be queried.
+int step2k_seg(const Geo &G, bool f32, int K, int min_seg, bool *full, long *slots_out)
+{
+    int dev = 0, ncu = 0;
+    if (full) *full = false;
+    if (slots_out) *slots_out = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    const long slots = (long)ncu * xk_per_cu(f32, K);
+    if (slots_out) *slots_out = slots;
+    if (slots <= 0) return 0;
+    const long ngroups = (step2k_strips(G, f32, K) + kXkWaves - 1) / kXkWaves;
+    int best = 0;
+    double best_cost = 0.0;
+    bool best_full = false;
+    for (int nseg = 1; nseg <= G.ny; ++nseg) {
+        const int seg = (G.ny + nseg - 1) / nseg;
+        if (seg < min_seg) break;
+        if ((G.ny + seg - 1) / seg != nseg) continue;  // same seg as a smaller nseg
+        const long blocks = ngroups * nseg;
+        const long rounds = (blocks + slots - 1) / slots;
+        double cost = (double)rounds * (seg + 2 * (K - 1));
+        if (blocks < slots) cost *= (double)slots / (double)blocks;
+        if (best == 0 || cost < best_cost) {
+            best = seg;
+            best_cost = cost;
+            best_full = 3 * blocks >= slots;
+        }
+    }
+    if (full) *full = best_full;
+    return best;
 }
 
 hipError_t launch_step2k(bool f32, const void *src, void *dst, const Geo &G, const Phys &P,
                          int K, int seg, hipStream_t st)
 {
-    const int ns = step2k_strips(G, K);
-    const int nb = step2k_blocks(G, K, seg);
+    const int ns = step2k_strips(G, f32, K);
+    const int nb = step2k_blocks(G, f32, K, seg);
     const dim3 grid(nb), block(64 * kXkWaves);
 #define LBM_XK_CASE(KK)                                                                       \
     case KK:                                                                                  \
         if (f32)                                                                              \
-            hipLaunchKernelGGL((k_step2d_xk<float, KK>), grid, block, 0, st,                  \
+            hipLaunchKernelGGL((k_step2d_xk<float, KK, kXkDepth>), grid, block, 0, st,                  \
                                (const float *)src, (float *)dst, G, P, ns, seg);              \
         else                                                                                  \
-            hipLaunchKernelGGL((k_step2d_xk<double, KK>), grid, block, 0, st,                 \
+            hipLaunchKernelGGL((k_step2d_xk<double, KK, kXkDepth>), grid, block, 0, st,                 \
                                (const double *)src, (double *)dst, G, P, ns, seg);            \
         break;
     switch (K) {
         LBM_XK_CASE(2)
+        LBM_XK_CASE(3)
         LBM_XK_CASE(4)
+        LBM_XK_CASE(5)
+        LBM_XK_CASE(6)
+        LBM_XK_CASE(7)
+        LBM_XK_CASE(8)
     default:
         return hipErrorInvalidValue;
     }

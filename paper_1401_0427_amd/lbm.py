@@ -77,7 +77,8 @@ class LbmBatchTuning(ctypes.Structure):
 
 
 EXPORTS = [
-    "lbm_layout", "lbm_init", "lbm_step", "lbm_step_buffers", "lbm_current", "lbm_export",
+    "lbm_layout", "lbm_init", "lbm_step", "lbm_step_buffers", "lbm_current",
+    "lbm_launch_info", "lbm_export",
     "lbm_import", "lbm_moments", "lbm_entropy", "lbm_adjoint_step", "lbm_adjoint_partials",
     "lbm_adjoint_terminal", "lbm_adjoint_grad_w0", "lbm_sum", "lbm_destroy",
     "lbm_batch_layout", "lbm_batch_create", "lbm_batch_init", "lbm_batch_run",
@@ -107,6 +108,8 @@ def load(path: str = LIB_PATH):
         "lbm_step": (ip, [vp, lp]),
         "lbm_step_buffers": (ip, [vp, vp, vp]),
         "lbm_current": (ip, [vp, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_long)]),
+        "lbm_launch_info": (ip, [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                 ctypes.POINTER(ctypes.c_long)]),
         "lbm_export": (ip, [vp, vp]),
         "lbm_import": (ip, [vp, vp]),
         "lbm_moments": (ip, [vp, vp, vp, vp, vp, dp]),
@@ -268,6 +271,14 @@ class Solver:
         check(load().lbm_current(self.ctx, ctypes.byref(ptr), ctypes.byref(steps)))
         buf = self.fa if ptr.value == self.fa.data_ptr() else self.fb
         return buf, steps.value
+
+    def launch_info(self):
+        """dict(steps_per_launch, segment_rows, resident_blocks) chosen at init."""
+        k, seg, res = ctypes.c_int(), ctypes.c_int(), ctypes.c_long()
+        check(load().lbm_launch_info(self.ctx, ctypes.byref(k), ctypes.byref(seg),
+                                     ctypes.byref(res)), "lbm_launch_info")
+        return dict(steps_per_launch=k.value, segment_rows=seg.value,
+                    resident_blocks=res.value)
 
     def planes(self, buf=None):
         """(nplanes, ny, nx) view (1D: (nplanes, nx)) of a state buffer."""

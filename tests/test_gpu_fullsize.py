@@ -118,8 +118,8 @@ def test_radial_4096_full_steps_invariants(storage):
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_radial_4096_fused_launch_equals_single_steps(storage):
-    """The headline grid: 40 steps as 20 fused two-step launches give bit for bit
-    the state of 40 single-step launches."""
+    """The headline grid: 40 steps as two-, three- (the last one shorter), four-
+    or eight-step launches give bit for bit the state of 40 single-step launches."""
     import torch
 
     case = W.radial_dam_break_2d(4096, lam=6.0)
@@ -127,12 +127,14 @@ def test_radial_4096_fused_launch_equals_single_steps(storage):
     A.step(40)
     a = A.planes().clone()
     del A
-    B = gpu_solver(case, storage=storage, fuse_steps=2)
-    B.step(40)
-    same = bool(torch.equal(a, B.planes()))
-    say(f"[full] 4096^2 {storage}: fused == single steps bitwise: {same}")
-    assert same
-    del B, a
+    for fuse in (2, 3, 4, 8):
+        B = gpu_solver(case, storage=storage, fuse_steps=fuse)
+        B.step(40)
+        same = bool(torch.equal(a, B.planes()))
+        say(f"[full] 4096^2 {storage}: {fuse} steps per launch == single steps bitwise: {same}")
+        assert same
+        del B
+    del a
     torch.cuda.empty_cache()
 
 

@@ -197,19 +197,22 @@ def test_oblique_shock_reflection_fp64_matches_oracle(ny):
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("fuse", [2, 3, 4, 5, 8])
 @pytest.mark.parametrize("shape,steps", [((300, 70), 6), ((600, 130), 7), ((17, 5), 9),
-                                         ((96, 80), 37), ((254, 64), 2), ((1100, 50), 4)])
-def test_fused_two_step_launch_equals_single_steps(storage, shape, steps):
-    """fuse_steps = 2 (two steps per launch, all-periodic 2D) gives bit for bit the
-    state of single steps: one strip, two and three strips with a ragged last one
-    (600, 1100 columns over 510-column strips), ragged row segments, a grid
-    smaller than one strip, an odd step count (the last step single) and a run
-    long enough for the captured graph chunks."""
+                                         ((96, 80), 37), ((254, 64), 2), ((1100, 50), 4),
+                                         ((3, 2), 11), ((58, 97), 8), ((2, 300), 13),
+                                         ((233, 211), 70)])
+def test_fused_launch_equals_single_steps(storage, fuse, shape, steps):
+    """fuse_steps = 2 .. 8 (steps per launch, all-periodic 2D) gives bit for bit
+    the state of single steps: one strip, several strips with a ragged last one,
+    ragged row segments, grids smaller than one strip or than the halo, step
+    counts that are not multiples of the launch depth (shorter last launches) and
+    runs long enough for the captured graph chunks."""
     nx, ny = shape
     case = smooth_random_2d(nx, ny, seed=5)
-    say(f"[fused] {nx}x{ny} steps={steps} storage={storage}")
+    say(f"[fused] {nx}x{ny} steps={steps} fuse={fuse} storage={storage}")
     A = gpu_solver(case, storage=storage, fuse_steps=1)
-    B = gpu_solver(case, storage=storage, fuse_steps=2)
+    B = gpu_solver(case, storage=storage, fuse_steps=fuse)
     A.step(steps)
     B.step(steps)
     a, b = to_np(A.planes()), to_np(B.planes())
@@ -263,3 +266,25 @@ def test_fused_1d_launch_equals_single_steps(storage, fuse, n, bc, inflow, steps
     if storage == "f64":
         ref, _ = orc_state(case, steps)
         assert per_plane_rel(b, ref) <= TOL64
+
+
+def test_default_launch_plans():
+    """lbm_launch_info reports the plan chosen at init: the wave-strip multi-step
+    launch on grids it can fill (FP64 8 steps, FP32 6), with a segment length and
+    the resident workgroups it was chosen against; one step per launch on a
+    small FP32 grid; 16 steps per launch in 1D; one step with non-periodic 2D
+    faces; an explicit request is honoured up to 8 steps."""
+    big64 = gpu_solver(smooth_random_2d(1024, 1024, seed=8), storage="f64").launch_info()
+    assert big64["steps_per_launch"] == 8 and big64["segment_rows"] >= 16
+    assert big64["resident_blocks"] > 0
+    big32 = gpu_solver(smooth_random_2d(1024, 1024, seed=8), storage="f32").launch_info()
+    assert big32["steps_per_launch"] == 6 and big32["segment_rows"] >= 16
+    small32 = gpu_solver(smooth_random_2d(256, 256, seed=8), storage="f32").launch_info()
+    assert small32["steps_per_launch"] == 1
+    one_d = gpu_solver(W.dam_break_1d(1000)).launch_info()
+    assert one_d["steps_per_launch"] == 16 and one_d["segment_rows"] == 0
+    walls = gpu_solver(W.oblique_shock_2d(20, steps=10), fuse_steps=4).launch_info()
+    assert walls["steps_per_launch"] == 1
+    asked = gpu_solver(smooth_random_2d(300, 70, seed=8), fuse_steps=16).launch_info()
+    assert asked["steps_per_launch"] == 8
+    say(f"[plans] 1024^2 f64 {big64}, f32 {big32}, 256^2 f32 {small32}")
