@@ -158,9 +158,13 @@ def time_batched(torch, steps=1000):
     ok = bool(torch.isfinite(h).all().item())
     byt = sum((4 if i["dim"] == 1 else 12) * 2 * 4 * i["nx"] * (i["ny"] if i["dim"] == 2 else 1)
               for i in insts)
+    # algorithmic bytes per launch: each launch reads and writes every instance's
+    # state once, whatever the number of steps it advances
+    k = (tune.get("fuse_steps") or 6) if tune.get("mode") == 3 else 1
     out = dict(instances=len(insts), nodes=nodes, steps=steps, ms=ms, ms_per_step=ms / steps,
-               mlups=nodes * steps / (ms * 1e-3) / 1e6, gbs=byt * steps / (ms * 1e-3) / 1e9,
-               tiles=nt, grid=grid, tuning=tune, finite=ok)
+               mlups=nodes * steps / (ms * 1e-3) / 1e6, steps_per_launch=k,
+               gbs=byt * steps / k / (ms * 1e-3) / 1e9, tiles=nt, grid=grid, tuning=tune,
+               finite=ok)
     del B
     # the plain path, one instance after another (graph-chunked lbm_step), same steps
     psteps = 100

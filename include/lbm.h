@@ -234,7 +234,18 @@ typedef struct {
                                 one workgroup per unit of `block` nodes; the launch
                                 boundary is the step barrier; chunks of 32 steps replay
                                 a captured HIP graph.  tile_nodes, grid and pass_nodes
-                                are ignored. */
+                                are ignored;
+                             3: fused -- fuse_steps steps per launch over all
+                                instances (temporal blocking, bitwise identical to
+                                single steps): the 2D instances (periodic faces
+                                only; others: LBM_EINVAL) as tiles of the
+                                wave-strip multi-step kernel, the 1D instances as
+                                1024-node tiles of the 1D multi-step kernel; graph
+                                chunks as in mode 2; steps that do not fill a launch
+                                run as flat single steps.  block, tile_nodes, grid
+                                and pass_nodes are ignored. */
+    int fuse_steps;       /* mode 3: steps per launch, 2 .. 8 (0 = 6 for FP32, 8 for
+                             FP64 storage) */
 } lbm_batch_tuning;
 
 /* Assign state_offset / node_offset to n instances (in place) for the given
@@ -252,7 +263,8 @@ int lbm_batch_init(lbm_batch *b, const double *h0, const double *qx0, const doub
 
 /* Advance every instance by nsteps in the mode chosen at creation (tuning.mode):
  * dataflow -- ONE persistent kernel launch (replayed from a captured HIP graph);
- * flat -- one launch per step (graph chunks of 32 steps).  Stream-ordered;
+ * flat -- one launch per step (graph chunks of 32 steps); fused -- one launch
+ * pair (2D, 1D) per fuse_steps steps (graph chunks).  Stream-ordered;
  * lbm_batch_check reports whether a dataflow launch completed. */
 int lbm_batch_run(lbm_batch *b, long nsteps);
 
@@ -267,8 +279,9 @@ int lbm_batch_moments(lbm_batch *b, double *h, double *qx, double *qy);
 /* Current state buffer of the batch. */
 int lbm_batch_current(lbm_batch *b, void **state, long *steps_done);
 
-/* Number of work tiles (dataflow) or units (step-synchronous) and of persistent
- * workgroups the batch launches. */
+/* Number of work tiles (dataflow, fused) or units (step-synchronous, flat), and
+ * the workgroups of the persistent launch (dataflow, step-synchronous) or of one
+ * launch (flat; fused: both launches of a step group). */
 int lbm_batch_info(lbm_batch *b, int *ntiles, int *grid);
 
 void lbm_batch_destroy(lbm_batch *b);

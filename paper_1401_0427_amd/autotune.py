@@ -3,9 +3,9 @@
 * ``tune_forward``: workgroup size, nodes per thread, plane padding and memory
   hints of the stream + collide kernel, and the steps per launch (1 .. 8), for
   one grid and storage type.
-* ``tune_batch``: mode (persistent dataflow or flat per-step launches),
-  workgroup size, tile size and nodes per pass of the batched launch for a
-  manifest.
+* ``tune_batch``: mode (persistent dataflow, flat per-step launches or fused
+  multi-step launches), workgroup size, tile size, nodes per pass and steps per
+  launch of the batched launch for a manifest.
 
 Results are cached in ``paper_1401_0427_amd/tuning.json`` (read by bench.py):
     {"forward": {"f64": {...}, "f32": {...}}, "batch": {...}, "sweeps": {...}}
@@ -95,14 +95,14 @@ def _manifest_dicts(man):
     return out
 
 
-def tune_batch(seed=0, steps=100, blocks=(256, 512), tiles=(4096, 8192, 16384, 32768),
-               grids=(0,), passes=(1, 2), storage="f32", modes=(0, 2),
-               unit_blocks=(128, 256, 512), log=print):
+def tune_batch(seed=0, steps=96, blocks=(256, 512), tiles=(4096, 8192, 16384, 32768),
+               grids=(0,), passes=(1, 2), storage="f32", modes=(0, 2, 3),
+               unit_blocks=(128, 256, 512), fuses=(4, 5, 6, 8), log=print):
     """Sweep the batch modes in ``modes``: the dataflow mode (0) over workgroup
     size, tile size, grid and nodes per pass; the step-synchronous (1, which the
     library currently rejects) and flat (2) modes over workgroup size (= nodes
-    per unit).  A configuration whose run is aborted by the bounded waits is
-    reported and skipped."""
+    per unit); the fused mode (3) over steps per launch.  A configuration whose
+    run is aborted by the bounded waits is reported and skipped."""
     import torch
 
     from . import workloads as W
@@ -121,6 +121,10 @@ def tune_batch(seed=0, steps=100, blocks=(256, 512), tiles=(4096, 8192, 16384, 3
     if 2 in modes:
         for block in unit_blocks:
             configs.append(dict(mode=2, block=block, tile_nodes=block, grid=0, pass_nodes=1))
+    if 3 in modes:
+        for fuse in fuses:
+            configs.append(dict(mode=3, fuse_steps=fuse, block=256, tile_nodes=256, grid=0,
+                                pass_nodes=1))
     rows = []
     for cfg in configs:
         B = Batch(insts, storage=storage, **cfg)
@@ -180,6 +184,8 @@ def main():
     if not args.skip_batch:
         best, rows = tune_batch(steps=args.steps, log=log)
         out["batch"] = {k: best[k] for k in ("mode", "block", "tile_nodes", "grid", "pass_nodes")}
+        if best.get("fuse_steps"):
+            out["batch"]["fuse_steps"] = best["fuse_steps"]
         out.setdefault("sweeps", {})["batch"] = rows
     save(out)
     log(json.dumps({"saved": CACHE, "forward": out.get("forward"), "batch": out.get("batch")}))

@@ -32,14 +32,6 @@
 
 namespace lbm {
 
-struct InstDev {
-    int dim;
-    int allper;  // all faces periodic
-    long off;    // element offset of the instance's planes in the batch buffer
-    Geo G;
-    Phys P;
-};
-
 struct TileDev {
     int inst;
     int begin, end;  // 1D: node range; 2D: row range
@@ -496,7 +488,14 @@ struct lbm_batch {
     double *d_ghost;
     unsigned *d_bar;
     int grid;
-    // flat mode: one captured graph of kFlatChunk steps per starting buffer
+    // fused mode: K steps per launch pair (2D wave-strip tiles + 1D tiles)
+    XkTileDev *d_xtiles;
+    K1TileDev *d_ktiles;
+    int nxtiles, nktiles;
+    int fuse;      // steps per launch
+    int xk_seg;    // rows per 2D segment
+    long chunk;    // steps per captured graph (flat and fused modes)
+    // flat / fused modes: one captured graph of `chunk` steps per starting buffer
     hipGraphExec_t fexec[2];
     // one captured graph per (nsteps, starting buffer); the last one is kept
     hipGraphExec_t gexec;
@@ -550,7 +549,47 @@ extern "C" void lbm_batch_destroy(lbm_batch *b)
     (void)hipFree(b->d_units);
     (void)hipFree(b->d_ghost);
     (void)hipFree(b->d_bar);
+    (void)hipFree(b->d_xtiles);
+    (void)hipFree(b->d_ktiles);
     delete b;
+}
+
+// Rows per 2D segment of the fused mode: one value for every 2D instance, chosen
+// like the single-grid launch (tblock.hip, step2k_seg) -- workgroups run in
+// rounds of the resident slots and each wavefront runs seg + 2 (K - 1) row
+// iterations, so minimise ceil(blocks / slots) * (seg + 2 (K - 1)), a partly
+// filled single round counting proportionally longer.
+static int fused_seg(bool f32, int K, const std::vector<lbm_instance> &inst)
+{
+    int dev = 0, ncu = 0;
+    long slots = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+        slots = (long)ncu * batch_xk_per_cu(f32, K);
+    int maxny = 0;
+    for (const lbm_instance &I : inst)
+        if (I.lattice == LBM_D2Q4x3) maxny = std::max(maxny, I.ny);
+    if (maxny == 0) return 16;
+    if (slots <= 0) return std::min(maxny, 160);
+    const int wo = batch_xk_out(f32, K), w = batch_xk_waves();
+    int best = 0;
+    double best_cost = 0.0;
+    for (int seg = 16; seg <= maxny; ++seg) {
+        long blocks = 0;
+        for (const lbm_instance &I : inst) {
+            if (I.lattice != LBM_D2Q4x3) continue;
+            const long groups = ((I.nx + wo - 1) / wo + w - 1) / w;
+            blocks += groups * ((I.ny + seg - 1) / seg);
+        }
+        const long rounds = (blocks + slots - 1) / slots;
+        double cost = (double)rounds * (seg + 2 * (K - 1));
+        if (blocks < slots) cost *= (double)slots / (double)blocks;
+        if (best == 0 || cost < best_cost) {
+            best = seg;
+            best_cost = cost;
+        }
+    }
+    return best;
 }
 
 extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage, void *f_a,
@@ -580,11 +619,26 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
                 return bfail(LBM_EINVAL, "instance %d: inflow h must be > 0", i);
         }
     }
-    lbm_batch_tuning tune = {256, 16384, 0, 1, 0};
+    lbm_batch_tuning tune = {256, 16384, 0, 1, 0, 0};
     if (tuning) tune = *tuning;
-    if (tune.mode < 0 || tune.mode > 2)
-        return bfail(LBM_EINVAL,
-                     "tuning.mode must be 0 (dataflow), 1 (step-synchronous) or 2 (flat)");
+    if (tune.mode < 0 || tune.mode > 3)
+        return bfail(LBM_EINVAL, "tuning.mode must be 0 (dataflow), 1 (step-synchronous), 2 "
+                                 "(flat) or 3 (fused)");
+    if (tune.mode == 3) {
+        if (tune.fuse_steps < 0 || tune.fuse_steps > 8)
+            return bfail(LBM_EINVAL, "tuning.fuse_steps must be in 0 .. 8 (got %d)",
+                         tune.fuse_steps);
+        for (int i = 0; i < n; ++i) {
+            const lbm_instance &I = inst[i];
+            if (I.lattice == LBM_D2Q4x3 &&
+                !(I.bc[0] == 0 && I.bc[1] == 0 && I.bc[2] == 0 && I.bc[3] == 0))
+                return bfail(LBM_EINVAL,
+                             "instance %d: the fused mode (3) runs 2D instances with periodic "
+                             "faces only (use mode 2 or 0)", i);
+            if ((long)I.nx * I.ny * (storage == LBM_F32 ? 4 : 8) >= (1L << 31))
+                return bfail(LBM_EINVAL, "instance %d: planes of 2 GiB or more (mode 3)", i);
+        }
+    }
     if (tune.mode == 1)
         return bfail(LBM_EINVAL,
                      "tuning.mode 1 (step-synchronous) is disabled: its first GPU run with wall / "
@@ -684,6 +738,34 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
         return bfail(LBM_EINVAL, "too many units for one launch: raise tuning.block");
     }
     b->nunits = (int)hu.size();
+    // fused mode: tile tables of the 2D wave-strip and 1D multi-step launches
+    std::vector<XkTileDev> hx;
+    std::vector<K1TileDev> hk;
+    b->chunk = 32;
+    if (tune.mode == 3) {
+        const int K = tune.fuse_steps ? tune.fuse_steps : (b->f32 ? 6 : 8);
+        b->fuse = K;
+        b->chunk = 2L * K * ((32 + 2 * K - 1) / (2 * K));
+        b->xk_seg = fused_seg(b->f32, K, inst);
+        const int wo = batch_xk_out(b->f32, K), w = batch_xk_waves(), n1 = batch_1k_out(K);
+        for (int i = 0; i < n; ++i) {
+            const lbm_instance &I = inst[i];
+            if (I.lattice == LBM_D1Q2x2) {
+                for (int ob = 0; ob < I.nx; ob += n1) hk.push_back(K1TileDev{i, ob});
+                continue;
+            }
+            const int ns = (I.nx + wo - 1) / wo;
+            for (int y0 = 0; y0 < I.ny; y0 += b->xk_seg)
+                for (int s0 = 0; s0 < ns; s0 += w)
+                    hx.push_back(XkTileDev{i, s0, ns, y0, std::min(I.ny, y0 + b->xk_seg)});
+        }
+        if (hx.size() > (size_t)INT32_MAX || hk.size() > (size_t)INT32_MAX) {
+            lbm_batch_destroy(b);
+            return bfail(LBM_EINVAL, "too many tiles for one launch");
+        }
+    }
+    b->nxtiles = (int)hx.size();
+    b->nktiles = (int)hk.size();
 
     hipError_t e;
     if ((e = hipMalloc(&b->d_inst, sizeof(InstDev) * n)) != hipSuccess ||
@@ -694,6 +776,14 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
         (e = hipMalloc(&b->d_units, sizeof(UnitDev) * hu.size())) != hipSuccess ||
         (e = hipMalloc(&b->d_ghost, sizeof(double) * 48 * (size_t)n)) != hipSuccess ||
         (e = hipMalloc(&b->d_bar, sizeof(unsigned))) != hipSuccess ||
+        (e = hipMalloc(&b->d_xtiles, sizeof(XkTileDev) * std::max<size_t>(1, hx.size()))) !=
+            hipSuccess ||
+        (e = hipMalloc(&b->d_ktiles, sizeof(K1TileDev) * std::max<size_t>(1, hk.size()))) !=
+            hipSuccess ||
+        (!hx.empty() && (e = hipMemcpy(b->d_xtiles, hx.data(), sizeof(XkTileDev) * hx.size(),
+                                       hipMemcpyHostToDevice)) != hipSuccess) ||
+        (!hk.empty() && (e = hipMemcpy(b->d_ktiles, hk.data(), sizeof(K1TileDev) * hk.size(),
+                                       hipMemcpyHostToDevice)) != hipSuccess) ||
         (e = hipMemcpy(b->d_units, hu.data(), sizeof(UnitDev) * hu.size(),
                        hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemset(b->d_abort, 0, sizeof(int))) != hipSuccess ||
@@ -715,8 +805,8 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
     int dev = 0, ncu = 0, per_cu = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (tune.mode == 2)
-        per_cu = 1;  // ordinary launches: one workgroup per unit
+    if (tune.mode >= 2)
+        per_cu = 1;  // ordinary launches: one workgroup per unit / tile
     else if (tune.mode == 1 && b->f32)
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_sync<float>, tune.block, 0);
     else if (tune.mode == 1)
@@ -731,7 +821,9 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<double, 1>, tune.block, 0);
     if (ncu <= 0) ncu = 256;
     if (per_cu <= 0) per_cu = 1;
-    b->grid = tune.mode == 2 ? b->nunits : (tune.grid > 0 ? tune.grid : ncu * per_cu);
+    b->grid = tune.mode == 2 ? b->nunits
+              : tune.mode == 3 ? b->nxtiles + b->nktiles
+                               : (tune.grid > 0 ? tune.grid : ncu * per_cu);
     *out = b;
     return LBM_OK;
 }
@@ -822,20 +914,41 @@ static void launch_flat(lbm_batch *b, int cur, hipStream_t st)
                            b->d_inst, b->d_units, (const double *)src, (double *)dst);
 }
 
-// Flat mode: whole chunks of kFlatChunk steps (an even number, so the chunk
-// starts and ends on the same buffer) replay one captured graph per starting
-// buffer; the remaining steps are launched one by one.
-static constexpr long kFlatChunk = 32;
+// K steps of every instance from buffer cur into the other: the 2D wave-strip
+// tiles, then the 1D tiles (independent instances; one ordered pair of launches).
+static hipError_t launch_fused(lbm_batch *b, int cur, hipStream_t st)
+{
+    const void *src = b->buf[cur];
+    void *dst = b->buf[cur ^ 1];
+    hipError_t e = launch_batch_xk(b->f32, b->fuse, b->d_inst, b->d_xtiles, b->nxtiles, src, dst,
+                                   st);
+    if (e == hipSuccess)
+        e = launch_batch_1k(b->f32, b->fuse, b->d_inst, b->d_ktiles, b->nktiles, src, dst, st);
+    return e;
+}
 
+// Flat and fused modes: whole chunks of b->chunk steps (an even number of
+// launches, so the chunk starts and ends on the same buffer) replay one captured
+// graph per starting buffer; the remaining steps are launched directly (whole
+// fused launches, then single flat steps, which give the same state bit for bit).
 static int run_flat(lbm_batch *b, long nsteps)
 {
+    const bool fused = b->tune.mode == 3;
+    const long per = fused ? b->fuse : 1;
     long left = nsteps;
-    if (left >= kFlatChunk && !b->fexec[b->cur]) {
+    if (left >= b->chunk && !b->fexec[b->cur]) {
         if (!b->cap) BHIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
         hipGraph_t g = nullptr;
         BHIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-        for (long k = 0; k < kFlatChunk; ++k) launch_flat(b, (int)((b->cur + k) & 1), b->cap);
-        hipError_t le = hipGetLastError();
+        hipError_t le = hipSuccess;
+        for (long k = 0; k < b->chunk / per && le == hipSuccess; ++k) {
+            const int c = (int)((b->cur + k) & 1);
+            if (fused)
+                le = launch_fused(b, c, b->cap);
+            else
+                launch_flat(b, c, b->cap);
+        }
+        if (le == hipSuccess) le = hipGetLastError();
         hipError_t ee = hipStreamEndCapture(b->cap, &g);
         if (le != hipSuccess || ee != hipSuccess) {
             if (g) (void)hipGraphDestroy(g);
@@ -849,9 +962,14 @@ static int run_flat(lbm_batch *b, long nsteps)
             return bfail(LBM_EDEVICE, "batch graph instantiate failed: %s", hipGetErrorString(ie));
         }
     }
-    for (; left >= kFlatChunk; left -= kFlatChunk) {
+    for (; left >= b->chunk; left -= b->chunk) {
         BHIP(hipGraphLaunch(b->fexec[b->cur], b->st));
-        b->steps += kFlatChunk;
+        b->steps += b->chunk;
+    }
+    for (; fused && left >= per; left -= per) {
+        BHIP(launch_fused(b, b->cur, b->st));
+        b->cur ^= 1;
+        b->steps += per;
     }
     for (; left > 0; --left) {
         launch_flat(b, b->cur, b->st);
@@ -866,7 +984,7 @@ extern "C" int lbm_batch_run(lbm_batch *b, long nsteps)
 {
     if (!b) return bfail(LBM_ESTATE, "null batch");
     if (nsteps < 0 || nsteps > (1L << 30)) return bfail(LBM_EINVAL, "bad nsteps");
-    if (b->tune.mode == 2) return run_flat(b, nsteps);
+    if (b->tune.mode >= 2) return run_flat(b, nsteps);
     if (b->tune.mode == 1 && (double)nsteps * b->grid >= 2147483648.0)
         return bfail(LBM_EINVAL, "nsteps x grid too large for the step-synchronous mode");
     if (nsteps == 0) return LBM_OK;
@@ -936,11 +1054,14 @@ extern "C" int lbm_batch_current(lbm_batch *b, void **state, long *steps_done)
     return LBM_OK;
 }
 
-// Number of work tiles and persistent workgroups (for tuning reports).
+// Number of work tiles and workgroups per launch (for tuning reports).
 extern "C" int lbm_batch_info(lbm_batch *b, int *ntiles, int *grid)
 {
     if (!b) return bfail(LBM_ESTATE, "null batch");
-    if (ntiles) *ntiles = b->tune.mode != 0 ? b->nunits : b->ntiles;
+    if (ntiles)
+        *ntiles = b->tune.mode == 0 ? b->ntiles
+                  : b->tune.mode == 3 ? b->nxtiles + b->nktiles
+                                      : b->nunits;
     if (grid) *grid = b->grid;
     return LBM_OK;
 }

@@ -16,6 +16,31 @@ struct Mrt {
     double rate[10];  // relaxation rates of the non-conserved moments
 };
 
+// One instance of the batched form: geometry, physics and the element offset of
+// its planes in the batch buffers.
+struct InstDev {
+    int dim;
+    int allper;  // all faces periodic
+    long off;    // element offset of the instance's planes in the batch buffer
+    Geo G;
+    Phys P;
+};
+
+// Tile of the batched multi-step launch of 2D instances: strips [strip0,
+// strip0 + waves) (of nstrips) of instance inst, output rows [y0, y1).
+struct XkTileDev {
+    int inst;
+    int strip0, nstrips;
+    int y0, y1;
+};
+
+// Tile of the batched multi-step launch of 1D instances: output nodes [ob, ob +
+// 1024 - 2K) of instance inst.
+struct K1TileDev {
+    int inst;
+    int ob;
+};
+
 // Launch shape of the plain forward / adjoint kernels.
 struct Launch {
     int block;  // threads per workgroup
@@ -54,6 +79,16 @@ hipError_t launch_step2x(bool f32, const void *src, void *dst, const Geo &G, con
                          int seg, hipStream_t st);
 int step2k_blocks(const Geo &G, bool f32, int K, int seg);
 int step2k_seg(const Geo &G, bool f32, int K, int min_seg, bool *full, long *slots_out);
+
+// Batched multi-step launches (tblock.hip).
+int batch_xk_out(bool f32, int K);  // output columns per strip
+int batch_1k_out(int K);            // output nodes per 1D tile
+int batch_xk_waves();               // strips per workgroup
+int batch_xk_per_cu(bool f32, int K);
+hipError_t launch_batch_xk(bool f32, int K, const InstDev *inst, const XkTileDev *tiles,
+                           int ntiles, const void *src, void *dst, hipStream_t st);
+hipError_t launch_batch_1k(bool f32, int K, const InstDev *inst, const K1TileDev *tiles,
+                           int ntiles, const void *src, void *dst, hipStream_t st);
 hipError_t launch_step2k(bool f32, const void *src, void *dst, const Geo &G, const Phys &P,
                          int K, int seg, hipStream_t st);
 hipError_t launch_entropy(int dim, bool f32, const void *state, const Geo &G, double lambda,

@@ -328,10 +328,11 @@ constexpr int xk_gcd(int a, int b) { return b == 0 ? a : xk_gcd(b, a % b); }
 // D + 1 register buffers); the loop is unrolled by lcm(2, D + 1) so every ring
 // slot and e2 array is addressed statically, and runs a whole number of
 // unrolled blocks (the extra iterations store nothing).
+// One wavefront: column strip `strip` of the grid (G, P) in src / dst, output
+// rows [y0, y1).
 template <typename T, int K, int D>
-__global__ void __launch_bounds__(64 * kXkWaves)
-    k_step2d_xk(const T *__restrict__ src, T *__restrict__ dst, Geo G, Phys P, int nstrips,
-                int seg)
+__device__ __forceinline__ void xk_wave(const T *__restrict__ src, T *__restrict__ dst,
+                                        const Geo &G, const Phys &P, int strip, int y0, int y1)
 {
     constexpr int WO = xk_wo<T, K>();  // output columns per strip
     constexpr int H = xk_halo<T, K>();
@@ -340,13 +341,6 @@ __global__ void __launch_bounds__(64 * kXkWaves)
     const int nx = G.nx, ny = G.ny;
     const long ps = G.ps;
     const int lane = threadIdx.x & 63;
-    const int ngroups = (nstrips + kXkWaves - 1) / kXkWaves;
-    const int nseg = (ny + seg - 1) / seg;
-    const int tile = xk_tile(blockIdx.x, ngroups * nseg, LBM_XK_REMAP != 0);
-    const int strip = (tile % ngroups) * kXkWaves + (threadIdx.x >> 6);
-    if (strip >= nstrips) return;  // whole wavefront; nothing here waits on others
-    const int y0 = (tile / ngroups) * seg;
-    const int y1 = min(y0 + seg, ny);
     const int x0 = strip * WO;     // first output column
     const int xc = x0 - H + lane;  // this lane's column, unwrapped
     const int xw = ((xc % nx) + nx) % nx;
@@ -394,6 +388,34 @@ __global__ void __launch_bounds__(64 * kXkWaves)
                          buf[u % (D + 1)], buf[(u + D) % (D + 1)], e2[u % 2], s1, s3);
         }
     }
+}
+
+template <typename T, int K, int D>
+__global__ void __launch_bounds__(64 * kXkWaves)
+    k_step2d_xk(const T *__restrict__ src, T *__restrict__ dst, Geo G, Phys P, int nstrips,
+                int seg)
+{
+    const int ngroups = (nstrips + kXkWaves - 1) / kXkWaves;
+    const int nseg = (G.ny + seg - 1) / seg;
+    const int tile = xk_tile(blockIdx.x, ngroups * nseg, LBM_XK_REMAP != 0);
+    const int strip = (tile % ngroups) * kXkWaves + (threadIdx.x >> 6);
+    if (strip >= nstrips) return;  // whole wavefront; nothing here waits on others
+    const int y0 = (tile / ngroups) * seg;
+    xk_wave<T, K, D>(src, dst, G, P, strip, y0, min(y0 + seg, G.ny));
+}
+
+// Batched form: workgroup b takes tile b' (the XCD-contiguous order of b) of a
+// tile table spanning many all-periodic 2D instances packed in one buffer.
+template <typename T, int K, int D>
+__global__ void __launch_bounds__(64 * kXkWaves)
+    k_batch_xk(const InstDev *__restrict__ inst, const XkTileDev *__restrict__ tiles, int ntiles,
+               const T *__restrict__ src, T *__restrict__ dst)
+{
+    const XkTileDev td = tiles[xk_tile(blockIdx.x, ntiles, LBM_XK_REMAP != 0)];
+    const InstDev &I = inst[td.inst];
+    const int strip = td.strip0 + (int)(threadIdx.x >> 6);
+    if (strip >= td.nstrips) return;
+    xk_wave<T, K, D>(src + I.off, dst + I.off, I.G, I.P, strip, td.y0, td.y1);
 }
 
 static int xk_wo_of(bool f32, int K)
@@ -552,17 +574,18 @@ __device__ __forceinline__ double k1_face(const Geo &G, int pl, int face, const 
     }
 }
 
+// One tile: output nodes [ob, ob + nout) of the grid (G, P) in src / dst, with
+// the workgroup's LDS array sh.
 template <typename T>
-__global__ void __launch_bounds__(kK1Threads)
-    k_step1d_k(const T *__restrict__ src, T *__restrict__ dst, Geo G, Phys P, int K, int nout)
+__device__ __forceinline__ void k1_tile(const T *__restrict__ src, T *__restrict__ dst,
+                                        const Geo &G, const Phys &P, int K, int ob, int nout,
+                                        T (*sh)[4][kK1Threads])
 {
-    __shared__ T sh[2][4][kK1Threads];
     const int t = threadIdx.x;
     const int nx = G.nx;
     const long ps = G.ps;
     const bool per = G.bc[0] == BC_PERIODIC;  // the two 1D faces are periodic together
-    const int ob = blockIdx.x * nout;          // output nodes [ob, oe)
-    const int oe = min(ob + nout, nx);
+    const int oe = min(ob + nout, nx);         // output nodes [ob, oe)
     const int x = ob - K + t;                  // this thread's node, unwrapped
     const bool in = per || (x >= 0 && x < nx);
     const int xw = per ? ((x % nx) + nx) % nx : x;
@@ -613,6 +636,26 @@ __global__ void __launch_bounds__(kK1Threads)
     }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(kK1Threads)
+    k_step1d_k(const T *__restrict__ src, T *__restrict__ dst, Geo G, Phys P, int K, int nout)
+{
+    __shared__ T sh[2][4][kK1Threads];
+    k1_tile(src, dst, G, P, K, (int)blockIdx.x * nout, nout, sh);
+}
+
+// Batched form: workgroup b takes 1D tile b of a table spanning many 1D instances.
+template <typename T>
+__global__ void __launch_bounds__(kK1Threads)
+    k_batch_1k(const InstDev *__restrict__ inst, const K1TileDev *__restrict__ tiles,
+               const T *__restrict__ src, T *__restrict__ dst, int K)
+{
+    __shared__ T sh[2][4][kK1Threads];
+    const K1TileDev td = tiles[blockIdx.x];
+    const InstDev &I = inst[td.inst];
+    k1_tile(src + I.off, dst + I.off, I.G, I.P, K, td.ob, kK1Threads - 2 * K, sh);
+}
+
 hipError_t launch_step1k(bool f32, const void *src, void *dst, const Geo &G, const Phys &P,
                          int K, hipStream_t st)
 {
@@ -644,6 +687,80 @@ hipError_t launch_step2x(bool f32, const void *src, void *dst, const Geo &G, con
     else
         hipLaunchKernelGGL(k_step2d_x2<double>, dim3(nb), dim3(kX2Threads), 0, st,
                            (const double *)src, (double *)dst, G, P, nstrips, seg);
+    return hipGetLastError();
+}
+
+// ---- batched launchers -----------------------------------------------------------------
+int batch_xk_out(bool f32, int K) { return xk_wo_of(f32, K); }
+int batch_1k_out(int K) { return kK1Threads - 2 * K; }
+int batch_xk_waves() { return kXkWaves; }
+
+int batch_xk_per_cu(bool f32, int K)
+{
+    int n = 0;
+    const int bs = 64 * kXkWaves;
+    hipError_t e = hipErrorInvalidValue;
+#define LBM_BXK_OCC(KK)                                                                       \
+    case KK:                                                                                  \
+        e = f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                               \
+                      &n, k_batch_xk<float, KK, kXkDepth>, bs, 0)                             \
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(                               \
+                      &n, k_batch_xk<double, KK, kXkDepth>, bs, 0);                           \
+        break;
+    switch (K) {
+        LBM_BXK_OCC(2)
+        LBM_BXK_OCC(3)
+        LBM_BXK_OCC(4)
+        LBM_BXK_OCC(5)
+        LBM_BXK_OCC(6)
+        LBM_BXK_OCC(7)
+        LBM_BXK_OCC(8)
+    default:
+        break;
+    }
+#undef LBM_BXK_OCC
+    return e == hipSuccess ? n : 0;
+}
+
+hipError_t launch_batch_xk(bool f32, int K, const InstDev *inst, const XkTileDev *tiles,
+                           int ntiles, const void *src, void *dst, hipStream_t st)
+{
+    if (ntiles <= 0) return hipSuccess;
+    const dim3 grid(ntiles), block(64 * kXkWaves);
+#define LBM_BXK_CASE(KK)                                                                      \
+    case KK:                                                                                  \
+        if (f32)                                                                              \
+            hipLaunchKernelGGL((k_batch_xk<float, KK, kXkDepth>), grid, block, 0, st, inst,   \
+                               tiles, ntiles, (const float *)src, (float *)dst);              \
+        else                                                                                  \
+            hipLaunchKernelGGL((k_batch_xk<double, KK, kXkDepth>), grid, block, 0, st, inst,  \
+                               tiles, ntiles, (const double *)src, (double *)dst);            \
+        break;
+    switch (K) {
+        LBM_BXK_CASE(2)
+        LBM_BXK_CASE(3)
+        LBM_BXK_CASE(4)
+        LBM_BXK_CASE(5)
+        LBM_BXK_CASE(6)
+        LBM_BXK_CASE(7)
+        LBM_BXK_CASE(8)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef LBM_BXK_CASE
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_1k(bool f32, int K, const InstDev *inst, const K1TileDev *tiles,
+                           int ntiles, const void *src, void *dst, hipStream_t st)
+{
+    if (ntiles <= 0) return hipSuccess;
+    if (f32)
+        hipLaunchKernelGGL(k_batch_1k<float>, dim3(ntiles), dim3(kK1Threads), 0, st, inst, tiles,
+                           (const float *)src, (float *)dst, K);
+    else
+        hipLaunchKernelGGL(k_batch_1k<double>, dim3(ntiles), dim3(kK1Threads), 0, st, inst, tiles,
+                           (const double *)src, (double *)dst, K);
     return hipGetLastError();
 }
 

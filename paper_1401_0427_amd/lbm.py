@@ -73,7 +73,7 @@ class LbmInstance(ctypes.Structure):
 
 class LbmBatchTuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int), ("tile_nodes", ctypes.c_int), ("grid", ctypes.c_int),
-                ("pass_nodes", ctypes.c_int), ("mode", ctypes.c_int)]
+                ("pass_nodes", ctypes.c_int), ("mode", ctypes.c_int), ("fuse_steps", ctypes.c_int)]
 
 
 EXPORTS = [
@@ -377,11 +377,12 @@ class Batch:
     """Many independent problems advanced in one persistent launch."""
 
     def __init__(self, instances, storage="f32", block=256, tile_nodes=16384, grid=0, pass_nodes=1,
-                 mode=0, device="cuda"):
+                 mode=0, fuse_steps=0, device="cuda"):
         """``instances``: iterable of dicts with keys dim, nx, ny, lam, s, g, bc,
         inflow, h0, qx0, qy0 (numpy arrays of the instance's nodes).  ``mode`` 0 is
-        the dataflow persistent launch; mode 1 (step-synchronous) is rejected by
-        the library while it is switched off."""
+        the dataflow persistent launch, 2 one flat launch per step, 3 ``fuse_steps``
+        steps per launch (0 = library default); mode 1 (step-synchronous) is
+        rejected by the library while it is switched off."""
         import torch
 
         _require_gpu(torch)
@@ -425,7 +426,7 @@ class Batch:
                 qy0[o:o + m] = np.asarray(d["qy0"]).reshape(-1)
         f64 = dict(dtype=torch.float64, device=self.device)
         self.h0, self.qx0, self.qy0 = (torch.as_tensor(a, **f64) for a in (h0, qx0, qy0))
-        tune = LbmBatchTuning(block, tile_nodes, grid, pass_nodes, mode)
+        tune = LbmBatchTuning(block, tile_nodes, grid, pass_nodes, mode, fuse_steps)
         b = ctypes.c_void_p()
         check(L.lbm_batch_create(arr, n, self.storage, _ptr(self.fa), _ptr(self.fb),
                                  _stream_handle(torch), ctypes.byref(tune), ctypes.byref(b)),
@@ -455,6 +456,20 @@ class Batch:
         check(load().lbm_batch_moments(self.b, _ptr(h), _ptr(qx), _ptr(qy)), "lbm_batch_moments")
         self.check()
         return h, qx, qy
+
+    def instance_planes(self, i):
+        """(nplanes, ny, nx) view (1D: (nplanes, nx)) of instance i's planes in the
+        current state buffer."""
+        ptr, steps = ctypes.c_void_p(), ctypes.c_long()
+        check(load().lbm_batch_current(self.b, ctypes.byref(ptr), ctypes.byref(steps)),
+              "lbm_batch_current")
+        buf = self.fa if ptr.value == self.fa.data_ptr() else self.fb
+        I = self.inst[i]
+        m = I.nx * I.ny
+        ps = (m + 63) // 64 * 64
+        npl = 4 if I.lattice == D1Q2x2 else 12
+        v = buf[I.state_offset:I.state_offset + npl * ps].view(npl, ps)[:, :m]
+        return v if I.lattice == D1Q2x2 else v.reshape(npl, I.ny, I.nx)
 
     def instance_view(self, i, packed):
         I = self.inst[i]

@@ -114,3 +114,68 @@ def test_batch_fp32_l1(mode):
         worst = max(worst, l1_rel(to_np(B.instance_view(i, hs)), ref))
     say(f"  worst L1 rel of h {worst:.3e}")
     assert worst <= 1e-5
+
+
+def _fused_instances(seed):
+    """Mixed 1D faces (inflow / wall / Neumann / periodic), 2D periodic (the fused
+    mode's domain), sizes below and above one strip / one 1D tile."""
+    insts = instance_dicts(W.small_manifest(seed=seed), mixed_bc=True)
+    out = []
+    for d in insts:
+        if d["dim"] == 2:
+            d = dict(d, bc=("periodic",) * 4, inflow={})
+        out.append(d)
+    rng = np.random.default_rng(seed)
+    for nx, ny in ((130, 75), (2, 40)):  # two and three strips; a grid narrower than the halo
+        out.append(dict(dim=2, nx=nx, ny=ny, lam=6.0, s=1.7, g=W.G, bc=("periodic",) * 4,
+                        inflow={}, h0=1.0 + 0.2 * rng.random((ny, nx)),
+                        qx0=0.05 * rng.standard_normal((ny, nx)),
+                        qy0=0.05 * rng.standard_normal((ny, nx))))
+    out.append(dict(dim=1, nx=2500, ny=1, lam=3.0, s=1.9, g=W.G, bc=("inflow", "wall",
+               "periodic", "periodic"), inflow={0: (1.5, 0.75, 0.0)}, h0=1.0 + 0.1 * rng.random(2500),
+               qx0=0.01 * rng.standard_normal(2500), qy0=None))
+    return out
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("fuse", [0, 2, 3, 5, 8])
+def test_batch_fused_mode_equals_flat_mode(storage, fuse):
+    """Mode 3 (fuse_steps steps per launch over every instance) gives bit for bit
+    the state of mode 2 (one step per launch), after a step count that needs graph
+    chunks, whole fused launches and single leftover steps; FP64 also matches the
+    oracle per instance."""
+    from paper_1401_0427_amd.lbm import Batch
+
+    insts = _fused_instances(seed=4)
+    steps = 157
+    say(f"[batch fused] {len(insts)} instances, {steps} steps, fuse {fuse}, {storage}")
+    A = Batch(insts, storage=storage, mode=2)
+    B = Batch(insts, storage=storage, mode=3, fuse_steps=fuse)
+    A.run(steps)
+    B.run(steps)
+    for i in range(len(insts)):
+        assert np.array_equal(to_np(A.instance_planes(i)), to_np(B.instance_planes(i))), i
+    for a, b in zip(A.moments(), B.moments()):
+        assert np.array_equal(to_np(a), to_np(b))
+    if storage == "f64":
+        mom = [to_np(t) for t in B.moments()]
+        worst = 0.0
+        for i, d in enumerate(insts):
+            ref = oracle_moments(d, steps)
+            got = [B.instance_view(i, t) for t in mom[: 2 if d["dim"] == 1 else 3]]
+            worst = max(worst, max(normwise_rel(a, b) for a, b in zip(got, ref)))
+        say(f"  worst instance rel err {worst:.3e}")
+        assert worst <= 1e-12
+
+
+def test_batch_fused_mode_run_twice_equals_one_long_run():
+    from paper_1401_0427_amd.lbm import Batch
+
+    insts = _fused_instances(seed=5)
+    A = Batch(insts, storage="f64", mode=3)
+    B = Batch(insts, storage="f64", mode=3)
+    A.run(51)
+    A.run(50)
+    B.run(101)
+    for a, b in zip(A.moments(), B.moments()):
+        assert np.array_equal(to_np(a), to_np(b))
