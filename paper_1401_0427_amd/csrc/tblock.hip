@@ -162,6 +162,9 @@ __global__ void __launch_bounds__(kX2Threads)
 #ifndef LBM_XK_DEPTH
 #define LBM_XK_DEPTH 2
 #endif
+#ifndef LBM_XK_DELAY
+#define LBM_XK_DELAY 1
+#endif
 // Output strips start and end on this many bytes (0: no alignment), and the
 // stores are non-temporal (1) or not (0), per storage type.  Measured at 4096^2:
 // FP64 -- 64-byte strips with non-temporal stores (94 vs 77 GLUPS unaligned);
@@ -291,12 +294,22 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
                                        int lane, const __amdgpu_buffer_rsrc_t *orsrc,
                                        unsigned ooff, const XkOff &onext, const T (&cur)[12],
                                        T (&nxt)[12], T (&em)[K - 1][3], T (&s1)[K - 1][3],
-                                       T (&s3)[K - 1][3])
+                                       T (&s3)[K - 1][3], T (&pend)[12], unsigned &pend_off)
 {
-    xk_load(src, ps, onext, nxt);
     double v[12];
 #pragma unroll
     for (int pl = 0; pl < 12; ++pl) v[pl] = (double)cur[pl];
+#if LBM_XK_DELAY
+    // The previous row's outputs are stored only now, after this row's loaded
+    // values have been consumed: the wait for those loads (issued D rows ago)
+    // then finds no fresh stores issued after them, and the memory counter,
+    // which counts stores and loads together, does not stall on this row's
+    // stores.  The scheduling barrier keeps that order.
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int pl = 0; pl < 12; ++pl) xk_store(orsrc[pl], pend_off, pend[pl]);
+#endif
+    xk_load(src, ps, onext, nxt);
     collide2d(v, P);  // level 1
 #pragma unroll
     for (int k = 1; k < K; ++k) {
@@ -318,8 +331,16 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
 #pragma unroll
         for (int pl = 0; pl < 12; ++pl) v[pl] = o[pl];
     }
+#if LBM_XK_DELAY
+#pragma unroll
+    for (int pl = 0; pl < 12; ++pl) pend[pl] = (T)v[pl];
+    pend_off = ooff;
+#else
 #pragma unroll
     for (int pl = 0; pl < 12; ++pl) xk_store(orsrc[pl], ooff, (T)v[pl]);
+    (void)pend;
+    (void)pend_off;
+#endif
 }
 
 constexpr int xk_gcd(int a, int b) { return b == 0 ? a : xk_gcd(b, a % b); }
@@ -375,6 +396,10 @@ __device__ __forceinline__ void xk_wave(const T *__restrict__ src, T *__restrict
         xk_load(src, ps, xk_offsets<T>(rl, nx, ny, xm, xw, xp), buf[d]);
         if (d + 1 < D) rl = rl == ny - 1 ? 0 : rl + 1;
     }
+    T pend[12];  // outputs of the last row, stored one iteration later
+    unsigned pend_off = kXkDrop;
+#pragma unroll
+    for (int pl = 0; pl < 12; ++pl) pend[pl] = (T)0;
     for (int j = 0; j < niter; j += U) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -385,9 +410,14 @@ __device__ __forceinline__ void xk_wave(const T *__restrict__ src, T *__restrict
                                       : kXkDrop;
             rl = rl == ny - 1 ? 0 : rl + 1;
             xk_row<T, K>(src, ps, P, lane, orsrc, ooff, xk_offsets<T>(rl, nx, ny, xm, xw, xp),
-                         buf[u % (D + 1)], buf[(u + D) % (D + 1)], e2[u % 2], s1, s3);
+                         buf[u % (D + 1)], buf[(u + D) % (D + 1)], e2[u % 2], s1, s3, pend,
+                         pend_off);
         }
     }
+#if LBM_XK_DELAY
+#pragma unroll
+    for (int pl = 0; pl < 12; ++pl) xk_store(orsrc[pl], pend_off, pend[pl]);
+#endif
 }
 
 template <typename T, int K, int D>
