@@ -165,6 +165,18 @@ __global__ void __launch_bounds__(kX2Threads)
 #ifndef LBM_XK_DELAY
 #define LBM_XK_DELAY 1
 #endif
+// FP64 launches of at least LBM_XK_LDS_MIN_K steps exchange the e1 / e3 planes of
+// their first LBM_XK_LDS_LEVELS intermediate levels through a per-wavefront LDS row
+// instead of cross-lane permutes into registers; 0 levels = off.  At K = 8 this
+// takes the kernel from 332 registers (one wavefront per SIMD) to 231 (two):
+// 171 vs 157 GLUPS at 4096^2 (4, 5 or 6 levels alike; 6 uses 72 KiB of LDS per
+// workgroup, two workgroups per compute unit).
+#ifndef LBM_XK_LDS_LEVELS
+#define LBM_XK_LDS_LEVELS 6
+#endif
+#ifndef LBM_XK_LDS_MIN_K
+#define LBM_XK_LDS_MIN_K 7
+#endif
 // Output strips start and end on this many bytes (0: no alignment), and the
 // stores are non-temporal (1) or not (0), per storage type.  Measured at 4096^2:
 // FP64 -- 64-byte strips with non-temporal stores (94 vs 77 GLUPS unaligned);
@@ -261,6 +273,21 @@ __device__ __forceinline__ void xk_store(__amdgpu_buffer_rsrc_t r, unsigned off,
     __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(v), r, off, 0, LBM_XK_NT_F32 ? 2 : 0);
 }
 
+// Intermediate levels whose e1 / e3 exchange goes through LDS.
+template <typename T, int K>
+constexpr int xk_lds_levels()
+{
+    return (sizeof(T) == 8 && K >= LBM_XK_LDS_MIN_K)
+               ? (LBM_XK_LDS_LEVELS < K - 1 ? LBM_XK_LDS_LEVELS : K - 1)
+               : 0;
+}
+// LDS elements per wavefront (at least one, so the array is never empty).
+template <typename T, int K>
+constexpr int xk_lds_elems()
+{
+    return xk_lds_levels<T, K>() > 0 ? xk_lds_levels<T, K>() * 6 * 64 : 1;
+}
+
 // Output columns per strip: 64 lanes minus K - 1 halo lanes per side, rounded
 // down to a whole number of aligned chunks, so (on rows that start aligned)
 // each strip writes whole memory segments and never shares one with another
@@ -294,8 +321,10 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
                                        int lane, const __amdgpu_buffer_rsrc_t *orsrc,
                                        unsigned ooff, const XkOff &onext, const T (&cur)[12],
                                        T (&nxt)[12], T (&em)[K - 1][3], T (&s1)[K - 1][3],
-                                       T (&s3)[K - 1][3], T (&pend)[12], unsigned &pend_off)
+                                       T (&s3)[K - 1][3], T (&pend)[12], unsigned &pend_off,
+                                       T *__restrict__ xsw)
 {
+    constexpr int L = xk_lds_levels<T, K>();
     double v[12];
 #pragma unroll
     for (int pl = 0; pl < 12; ++pl) v[pl] = (double)cur[pl];
@@ -317,15 +346,40 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
 #pragma unroll
         for (int pl = 0; pl < 12; ++pl) v[pl] = (double)(T)v[pl];
         double o[12];
+        if (k - 1 < L) {
+            // this wavefront's LDS row of level k: planes e1 (c) and e3 (3 + c);
+            // read the previous row's neighbours, then overwrite with this row
+            // (the wavefront executes in lockstep and its LDS operations in
+            // order; the compiler barriers keep the reads before the writes and
+            // the writes before the next row's reads)
+            T *row = xsw + (k - 1) * 6 * 64;
+            const int lm = (lane - 1) & 63, lp = (lane + 1) & 63;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            o[4 * c + 0] = (double)s1[k - 1][c];
-            o[4 * c + 1] = (double)em[k - 1][c];
-            o[4 * c + 2] = (double)s3[k - 1][c];
-            o[4 * c + 3] = v[4 * c + 3];
-            em[k - 1][c] = (T)v[4 * c + 1];
-            s1[k - 1][c] = xk_from((T)v[4 * c + 0], lane, 1);
-            s3[k - 1][c] = xk_from((T)v[4 * c + 2], lane, -1);
+            for (int c = 0; c < 3; ++c) {
+                o[4 * c + 0] = (double)row[c * 64 + lm];
+                o[4 * c + 1] = (double)em[k - 1][c];
+                o[4 * c + 2] = (double)row[(3 + c) * 64 + lp];
+                o[4 * c + 3] = v[4 * c + 3];
+                em[k - 1][c] = (T)v[4 * c + 1];
+            }
+            __asm__ __volatile__("" ::: "memory");
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                row[c * 64 + lane] = (T)v[4 * c + 0];
+                row[(3 + c) * 64 + lane] = (T)v[4 * c + 2];
+            }
+            __asm__ __volatile__("" ::: "memory");
+        } else {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                o[4 * c + 0] = (double)s1[k - 1][c];
+                o[4 * c + 1] = (double)em[k - 1][c];
+                o[4 * c + 2] = (double)s3[k - 1][c];
+                o[4 * c + 3] = v[4 * c + 3];
+                em[k - 1][c] = (T)v[4 * c + 1];
+                s1[k - 1][c] = xk_from((T)v[4 * c + 0], lane, 1);
+                s3[k - 1][c] = xk_from((T)v[4 * c + 2], lane, -1);
+            }
         }
         collide2d(o, P);
 #pragma unroll
@@ -353,7 +407,8 @@ constexpr int xk_gcd(int a, int b) { return b == 0 ? a : xk_gcd(b, a % b); }
 // rows [y0, y1).
 template <typename T, int K, int D>
 __device__ __forceinline__ void xk_wave(const T *__restrict__ src, T *__restrict__ dst,
-                                        const Geo &G, const Phys &P, int strip, int y0, int y1)
+                                        const Geo &G, const Phys &P, int strip, int y0, int y1,
+                                        T *__restrict__ xsw)
 {
     constexpr int WO = xk_wo<T, K>();  // output columns per strip
     constexpr int H = xk_halo<T, K>();
@@ -411,7 +466,7 @@ __device__ __forceinline__ void xk_wave(const T *__restrict__ src, T *__restrict
             rl = rl == ny - 1 ? 0 : rl + 1;
             xk_row<T, K>(src, ps, P, lane, orsrc, ooff, xk_offsets<T>(rl, nx, ny, xm, xw, xp),
                          buf[u % (D + 1)], buf[(u + D) % (D + 1)], e2[u % 2], s1, s3, pend,
-                         pend_off);
+                         pend_off, xsw);
         }
     }
 #if LBM_XK_DELAY
@@ -425,13 +480,14 @@ __global__ void __launch_bounds__(64 * kXkWaves)
     k_step2d_xk(const T *__restrict__ src, T *__restrict__ dst, Geo G, Phys P, int nstrips,
                 int seg)
 {
+    __shared__ T xs[kXkWaves][xk_lds_elems<T, K>()];
     const int ngroups = (nstrips + kXkWaves - 1) / kXkWaves;
     const int nseg = (G.ny + seg - 1) / seg;
     const int tile = xk_tile(blockIdx.x, ngroups * nseg, LBM_XK_REMAP != 0);
     const int strip = (tile % ngroups) * kXkWaves + (threadIdx.x >> 6);
     if (strip >= nstrips) return;  // whole wavefront; nothing here waits on others
     const int y0 = (tile / ngroups) * seg;
-    xk_wave<T, K, D>(src, dst, G, P, strip, y0, min(y0 + seg, G.ny));
+    xk_wave<T, K, D>(src, dst, G, P, strip, y0, min(y0 + seg, G.ny), xs[threadIdx.x >> 6]);
 }
 
 // Batched form: workgroup b takes tile b' (the XCD-contiguous order of b) of a
@@ -441,11 +497,13 @@ __global__ void __launch_bounds__(64 * kXkWaves)
     k_batch_xk(const InstDev *__restrict__ inst, const XkTileDev *__restrict__ tiles, int ntiles,
                const T *__restrict__ src, T *__restrict__ dst)
 {
+    __shared__ T xs[kXkWaves][xk_lds_elems<T, K>()];
     const XkTileDev td = tiles[xk_tile(blockIdx.x, ntiles, LBM_XK_REMAP != 0)];
     const InstDev &I = inst[td.inst];
     const int strip = td.strip0 + (int)(threadIdx.x >> 6);
     if (strip >= td.nstrips) return;
-    xk_wave<T, K, D>(src + I.off, dst + I.off, I.G, I.P, strip, td.y0, td.y1);
+    xk_wave<T, K, D>(src + I.off, dst + I.off, I.G, I.P, strip, td.y0, td.y1,
+                     xs[threadIdx.x >> 6]);
 }
 
 static int xk_wo_of(bool f32, int K)
