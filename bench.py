@@ -59,9 +59,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def time_forward(torch, n, storage, steps, warmup, block, npt, pad, fuse=1):
+def time_forward(torch, n, storage, steps, warmup, block, npt, pad, fuse=1, keep_h=False):
     """Forward steps of the headline workload; ``fuse`` = steps per launch asked
-    for (0 = the library's choice; lbm_launch_info reports what runs)."""
+    for (0 = the library's choice; lbm_launch_info reports what runs).  With
+    ``keep_h`` the final height field is returned under "h" (device tensor)."""
     from paper_1401_0427_amd import workloads as W
     from paper_1401_0427_amd.lbm import Solver
 
@@ -90,8 +91,9 @@ def time_forward(torch, n, storage, steps, warmup, block, npt, pad, fuse=1):
     launches = steps / fuse
     # algorithmic bytes of one launch: the state read once and written once, whatever
     # the number of steps the launch advances
+    out_h = {"h": h.clone()} if keep_h else {}
     return dict(ms_per_step=ms / steps, mlups=nodes * steps / (ms * 1e-3) / 1e6,
-                steps_per_launch=fuse, segment_rows=info["segment_rows"],
+                **out_h, steps_per_launch=fuse, segment_rows=info["segment_rows"],
                 resident_blocks=info["resident_blocks"], ms_per_launch=ms / launches,
                 gbs=nodes * bpl * launches / (ms * 1e-3) / 1e9, bytes_per_lu=bpl,
                 bytes_per_launch=nodes * bpl, wall_s=wall, finite=ok, mass=tot[0])
@@ -226,11 +228,38 @@ def time_adjoint(torch, n=1024, T=500, K=23, storage="f32"):
     torch.cuda.synchronize()
     fwd_ms = e0.elapsed_time(e1) / T
     es = 4 if storage == "f32" else 8
-    return dict(n=n, T=T, K=K, storage=storage, forward_s=t1 - t0, backward_s=t2 - t1,
-                grad_mlups=n * n * T / (t2 - t0) / 1e6, adjoint_step_ms=adj_ms,
-                forward_step_ms=fwd_ms, adjoint_over_forward=adj_ms / fwd_ms,
-                adjoint_gbs=n * n * 36 * es / (adj_ms * 1e-3) / 1e9,
-                grad_s=float(s.grad), grad_h0_norm=float(h0.grad.norm()))
+    out = dict(n=n, T=T, K=K, storage=storage, forward_s=t1 - t0, backward_s=t2 - t1,
+               grad_mlups=n * n * T / (t2 - t0) / 1e6, adjoint_step_ms=adj_ms,
+               forward_step_ms=fwd_ms, adjoint_over_forward=adj_ms / fwd_ms,
+               adjoint_gbs=n * n * 36 * es / (adj_ms * 1e-3) / 1e9,
+               grad_s=float(s.grad), grad_h0_norm=float(h0.grad.norm()))
+    del S, a, b, u, part
+    # the adjoint kernel against the one-step forward kernel on a grid far beyond the
+    # 256 MB MALL (4096^2): both HBM-bound
+    nb, tb = 4096, 50
+    cb, _ = W.adjoint_case(n=nb, steps=tb)
+    S = Solver(2, nb, nb, lam=cb.lam, s=cb.s, h0=cb.h0, storage=storage, fuse_steps=1)
+    a, b, u = S.new_state(), S.new_state(), S.current()[0]
+    part = S.adjoint_partials()
+    S.adjoint_step(u, a, b, part)
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(tb):
+        S.adjoint_step(u, a, b, part)
+        a, b = b, a
+    e1.record(st)
+    torch.cuda.synchronize()
+    adj_b = e0.elapsed_time(e1) / tb
+    e0.record(st)
+    S.step(tb)
+    e1.record(st)
+    torch.cuda.synchronize()
+    fwd_b = e0.elapsed_time(e1) / tb
+    out.update(adjoint_step_ms_4096=adj_b, forward_one_step_ms_4096=fwd_b,
+               adjoint_over_forward_4096=adj_b / fwd_b,
+               adjoint_gbs_4096=nb * nb * 36 * es / (adj_b * 1e-3) / 1e9,
+               forward_gbs_4096=nb * nb * 24 * es / (fwd_b * 1e-3) / 1e9)
+    return out
 
 
 # FP64 step kernels: (source files, committed counter summary, name)
@@ -337,12 +366,20 @@ def main():
             continue
         L = launch(storage)
         log(f"[bench] forward {storage.upper()} {n}^2, {args.steps} steps, launch {L}")
-        forms["fp" + storage[1:]] = time_forward(torch, n, storage, args.steps, args.warmup, *L)
+        forms["fp" + storage[1:]] = time_forward(torch, n, storage, args.steps, args.warmup, *L,
+                                                 keep_h=True)
         if forms["fp" + storage[1:]]["steps_per_launch"] != 1 and not args.quick:
             # the one-step-per-launch kernel on the same workload, for comparison
             log(f"[bench] forward {storage.upper()} {n}^2, one step per launch")
             forms["fp" + storage[1:] + "_one_step_per_launch"] = time_forward(
                 torch, n, storage, args.steps, args.warmup, *L[:3], 1)
+    if "fp64" in forms and "fp32" in forms:
+        # FP32 storage against FP64 after the same steps (the FP64 path equals the
+        # CPU FP64 oracle bit for bit in the parity tests): L1 relative error of h
+        h64, h32 = forms["fp64"]["h"], forms["fp32"]["h"]
+        forms["fp32"]["l1_rel_h_vs_fp64"] = float((h32 - h64).abs().sum() / h64.abs().sum())
+    for f in forms.values():
+        f.pop("h", None)
     f64 = forms.get("fp64") or forms["fp32"]
     if not args.quick and not args.no_1d:
         for storage in ("f64", "f32"):

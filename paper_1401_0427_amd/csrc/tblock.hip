@@ -177,6 +177,9 @@ __global__ void __launch_bounds__(kX2Threads)
 #ifndef LBM_XK_LDS_MIN_K
 #define LBM_XK_LDS_MIN_K 7
 #endif
+#ifndef LBM_XK_LDS_LEVELS_F32
+#define LBM_XK_LDS_LEVELS_F32 0  // the same for FP32 launches (0 = off)
+#endif
 // Output strips start and end on this many bytes (0: no alignment), and the
 // stores are non-temporal (1) or not (0), per storage type.  Measured at 4096^2:
 // FP64 -- 64-byte strips with non-temporal stores (94 vs 77 GLUPS unaligned);
@@ -277,9 +280,8 @@ __device__ __forceinline__ void xk_store(__amdgpu_buffer_rsrc_t r, unsigned off,
 template <typename T, int K>
 constexpr int xk_lds_levels()
 {
-    return (sizeof(T) == 8 && K >= LBM_XK_LDS_MIN_K)
-               ? (LBM_XK_LDS_LEVELS < K - 1 ? LBM_XK_LDS_LEVELS : K - 1)
-               : 0;
+    constexpr int L = sizeof(T) == 8 ? LBM_XK_LDS_LEVELS : LBM_XK_LDS_LEVELS_F32;
+    return K >= LBM_XK_LDS_MIN_K ? (L < K - 1 ? L : K - 1) : 0;
 }
 // LDS elements per wavefront (at least one, so the array is never empty).
 template <typename T, int K>
