@@ -254,3 +254,72 @@ def test_adjoint_full_1024_fp64_matches_oracle_and_fd():
     say(f"  FP32 forward: grad_h0 rel {normwise_rel(gh32, gh_ref):.3e}; grad_s rel "
         f"{abs(gs32 - gs_ref) / abs(gs_ref):.3e} (reported)")
     assert normwise_rel(gh32, gh_ref) < 1e-2
+
+
+def _smooth_2d(n, seed):
+    rng = np.random.default_rng(seed)
+    x = W.cell_centres(n)
+    gx = np.exp(-((x - 0.4) ** 2) / 0.03)
+    gy = np.exp(-((x - 0.55) ** 2) / 0.03)
+    h = 1.0 + 0.3 * np.outer(gy, gx)
+    h += 0.02 * rng.random((n, n))
+    qx = np.broadcast_to((0.2 * np.sin(2 * np.pi * x))[:, None], (n, n)).copy()
+    qy = np.broadcast_to((0.15 * np.cos(2 * np.pi * x))[None, :], (n, n)).copy()
+    return W.Case(2, n, n, 6.0, 1.8, 0, h0=h, qx0=qx, qy0=qy, name=f"smooth2d_{n}")
+
+
+def test_largest_2d_grid_sampled_nodes_match_oracle():
+    """The largest square grid the ABI accepts (11585^2 = 1.34e8 nodes, FP64:
+    12.9 GB per state buffer, 1.07 GB per plane -- byte offsets within a plane
+    reach 2^30): 16 steps as two 8-step launches of the default plan, sampled
+    nodes at the grid's ends, strip and segment edges against the oracle."""
+    import torch
+
+    n, steps = 11585, 16
+    case = _smooth_2d(n, seed=3)
+    S = gpu_solver(case, storage="f64")
+    plan = S.launch_info()
+    say(f"[max 2D] {n}^2 FP64, plan {plan}")
+    assert plan["steps_per_launch"] == 8
+    S.step(steps)
+    planes = S.planes()
+    seg = plan["segment_rows"]
+    samples = [(0, 0), (n - 1, n - 1), (n - 1, 0), (0, n - 1), (47, seg - 1), (48, seg),
+               (n // 2, n // 2), (n - 2, n - 3), (5791, n - 1), (n - 1, 7000)]
+    worst = 0.0
+    for (x, y) in samples:
+        got = planes[:, y, x].cpu().numpy()
+        ref = _oracle_centre_2d(case, x, y, steps)
+        worst = max(worst, np.abs(got - ref).max() / np.abs(ref).max())
+    say(f"  worst sampled relative error {worst:.3e}")
+    assert worst <= 1e-12
+    del S, planes
+    torch.cuda.empty_cache()
+
+
+def test_largest_1d_grid_sampled_nodes_match_oracle():
+    """The largest 1D grid the ABI accepts (2^27 nodes, FP64): inflow on the left,
+    wall on the right, 40 steps (16-step launches and a shorter last one),
+    sampled nodes at both ends, tile edges and the middle against the oracle."""
+    import torch
+
+    n, steps = 1 << 27, 40
+    rng = np.random.default_rng(4)
+    h0 = 1.0 + 0.1 * rng.random(n)
+    q0 = 0.05 * rng.standard_normal(n)
+    case = W.Case(1, n, 1, 3.0, 1.9, steps, bc=("inflow", "wall", "periodic", "periodic"),
+                  inflow={0: (1.5, 0.75, 0.0)}, h0=h0, qx0=q0, name="max1d")
+    S = gpu_solver(case, storage="f64")
+    plan = S.launch_info()
+    say(f"[max 1D] 2^27 FP64, plan {plan}")
+    S.step(steps)
+    planes = S.planes()
+    worst = 0.0
+    for x in (0, 1, 991, 992, 993, n // 2, n - 993, n - 2, n - 1):
+        got = planes[:, x].cpu().numpy()
+        ref = _oracle_centre_1d(case, x, steps)
+        worst = max(worst, np.abs(got - ref).max() / np.abs(ref).max())
+    say(f"  worst sampled relative error {worst:.3e}")
+    assert worst <= 1e-12
+    del S, planes
+    torch.cuda.empty_cache()
