@@ -108,9 +108,11 @@ typedef struct {
                              when that launch fills at least a third of the
                              device, e.g. 1024^2 and larger, else 2 when the LDS
                              two-step launch has >= 1024 workgroups, else 1;
-                             planes of 2 GiB or more take 1); 1D grids any
-                             (default 16); 2D grids with other faces take 1.
-                             lbm_launch_info reports the choice. */
+                             planes of 2 GiB or more take 1); 2D grids with
+                             Neumann, wall or inflow faces at most 4 (default 4
+                             when that launch fills a third of the device, else
+                             1; planes of 2 GiB or more take 1); 1D grids any
+                             (default 16).  lbm_launch_info reports the choice. */
     void *f_a, *f_b;      /* caller-owned device state buffers (ping-pong) */
     void *stream;         /* hipStream_t; NULL = default stream */
 } lbm_params;

@@ -146,7 +146,8 @@ struct lbm_ctx {
     Geo G;
     Phys P;
     Launch L;
-    int fuse;  // 2: the all-periodic 2D path advances two steps per launch
+    int fuse;  // steps per launch (at most)
+    bool x2;   // 2D two-step launches take the LDS strip kernel (all-periodic grids)
     void *buf[2];
     int cur;
     long steps;
@@ -193,6 +194,10 @@ static const int kXkSeg = LBM_XK_SEG;
 // three; one step: 61); at 1024^2 FP64 8 gives 86 GLUPS (one step: 25).
 static const int kDefaultFuse2dF64 = 8;
 static const int kDefaultFuse2dF32 = 6;
+// With non-periodic faces the wave-strip kernel takes at most
+// step2k_max_k_bounded() (4) steps per launch, and 4 by default: at 4096^2
+// (inflow / Neumann / wall faces) FP64 74 GLUPS (one step: 26), FP32 116 (57).
+static const int kDefaultFuse2dBounded = 4;
 // Shortest segment of a wave-strip launch (the halo rows cost 2 (K - 1) per
 // segment; the segment length itself is chosen per grid, step2k_seg).  Grids
 // whose launch cannot fill a third of the device keep the one- or two-step
@@ -291,20 +296,23 @@ extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0
         const bool allper = p->bc[0] == LBM_BC_PERIODIC && p->bc[1] == LBM_BC_PERIODIC &&
                             p->bc[2] == LBM_BC_PERIODIC && p->bc[3] == LBM_BC_PERIODIC;
         int want = p->fuse_steps;
+        c->x2 = allper && LBM_FUSE2_LDS;
         if (rest)
             c->fuse = 1;
         else if (dim == 1)
             c->fuse = want ? want : kDefaultFuse1d;
-        else if (allper && (size_t)ps * (c->f32 ? 4 : 8) < ((size_t)1 << 31)) {
+        else if ((size_t)ps * (c->f32 ? 4 : 8) < ((size_t)1 << 31)) {
+            const int kmax = allper ? kMaxFuse2d : step2k_max_k_bounded();
             if (want) {
-                c->fuse = want > kMaxFuse2d ? kMaxFuse2d : want;
-                if (c->fuse > 2 || !LBM_FUSE2_LDS) {
+                c->fuse = want > kmax ? kmax : want;
+                if (c->fuse > 2 || !c->x2) {
                     c->xk_seg = step2k_seg(c->G, c->f32, c->fuse, kXkMinSeg, nullptr,
                                            &c->xk_slots);
                     if (c->xk_seg <= 0) c->xk_seg = kXkSeg;
                 }
             } else {
-                const int kd = c->f32 ? kDefaultFuse2dF32 : kDefaultFuse2dF64;
+                const int kd = !allper ? kDefaultFuse2dBounded
+                               : c->f32 ? kDefaultFuse2dF32 : kDefaultFuse2dF64;
                 bool full = false;
                 long slots = 0;
                 const int seg = step2k_seg(c->G, c->f32, kd, kXkMinSeg, &full, &slots);
@@ -313,7 +321,7 @@ extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0
                     c->xk_seg = seg;
                     c->xk_slots = slots;
                 } else {
-                    c->fuse = step2x_blocks(c->G, kFuseSeg) >= kFuseMinBlocks ? 2 : 1;
+                    c->fuse = c->x2 && step2x_blocks(c->G, kFuseSeg) >= kFuseMinBlocks ? 2 : 1;
                 }
             }
         } else {
@@ -381,7 +389,7 @@ static hipError_t step_k(lbm_ctx *c, int k, const void *src, void *dst, hipStrea
 {
     if (k == 1) return step_once(c, src, dst, st);
     if (c->dim == 2) {
-        if (LBM_FUSE2_LDS && k == 2)
+        if (c->x2 && k == 2)
             return launch_step2x(c->f32, src, dst, c->G, c->P, kFuseSeg, st);
         return launch_step2k(c->f32, src, dst, c->G, c->P, k, c->xk_seg > 0 ? c->xk_seg : kXkSeg,
                              st);
@@ -499,7 +507,7 @@ extern "C" int lbm_launch_info(lbm_ctx *c, int *steps_per_launch, int *segment_r
 {
     int rc = check_ctx(c);
     if (rc) return rc;
-    const bool xk = c->dim == 2 && c->fuse >= 2 && !(LBM_FUSE2_LDS && c->fuse == 2);
+    const bool xk = c->dim == 2 && c->fuse >= 2 && !(c->x2 && c->fuse == 2);
     if (steps_per_launch) *steps_per_launch = c->fuse;
     if (segment_rows) *segment_rows = xk ? c->xk_seg : (c->fuse == 2 ? kFuseSeg : 0);
     if (resident_blocks) *resident_blocks = xk ? c->xk_slots : 0;

@@ -228,6 +228,44 @@ __device__ __forceinline__ double xk_from(double v, int lane, int shift)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// The same exchange through DPP wave shifts (a VALU move, no LDS access):
+// xk_shr gives lane l the value of lane l - 1, xk_shl that of lane l + 1; the
+// end lanes receive 0.
+#ifndef LBM_XK_DPP
+#define LBM_XK_DPP 0  // 1: the all-periodic kernels exchange through DPP as well
+#endif
+template <int CTRL>
+__device__ __forceinline__ float xk_dpp(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double xk_dpp(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename T>
+__device__ __forceinline__ T xk_shr(T v)
+{
+    return xk_dpp<0x138>(v);  // wave_shr:1
+}
+template <typename T>
+__device__ __forceinline__ T xk_shl(T v)
+{
+    return xk_dpp<0x130>(v);  // wave_shl:1
+}
+template <typename T>
+__device__ __forceinline__ T xk_xch(T v, int lane, int shift)
+{
+    if constexpr (LBM_XK_DPP != 0)
+        return shift > 0 ? xk_shr(v) : xk_shl(v);
+    else
+        return xk_from(v, lane, shift);
+}
+
 template <typename T>
 __device__ __forceinline__ T xk_at(const T *base, unsigned off)
 {
@@ -258,6 +296,99 @@ __device__ __forceinline__ void xk_load(const T *__restrict__ src, long ps, cons
         f[4 * c + 1] = xk_at(src + (4 * c + 1) * ps, o.e2);
         f[4 * c + 2] = xk_at(src + (4 * c + 2) * ps, o.e3);
         f[4 * c + 3] = xk_at(src + (4 * c + 3) * ps, o.e4);
+    }
+}
+
+// ---- grids with non-periodic faces ------------------------------------------------
+// The face rules are those of the one-step kernel (pull_face2d): a pull from
+// outside the grid through face f takes, at the boundary node itself,
+//   Neumann -- the same population;
+//   wall    -- the opposite population, negated for the normal momentum
+//              (qx on the x faces, qy on the y faces);
+//   inflow  -- the equilibrium of the face's prescribed state (in double, not
+//              rounded to the storage type).
+// Level 1 applies them to the level-n state in memory; every further level to
+// the boundary node's own values of the previous level.  Lanes and rows outside
+// the grid read clamped addresses: their values are never pulled by a node of
+// the grid (its pulls through the faces are replaced), so they never reach a
+// stored value.
+struct XkBnd {
+    int kx0, kx1, ky0, ky1;  // face rules (BC_PERIODIC: the axis wraps)
+    double in1[3], in3[3];   // inflow equilibria of the e1 planes (x-), e3 planes (x+)
+    double in2[3], in4[3];   // of the e2 planes (y-), e4 planes (y+)
+};
+
+// A value equal on every lane, moved to scalar registers (the face values are
+// computed from kernel arguments, so every lane holds the same bits).
+__device__ __forceinline__ double xk_uniform(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffLL));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ XkBnd xk_bnd(const Geo &G, const Phys &P)
+{
+    XkBnd B;
+    B.kx0 = G.bc[0];
+    B.kx1 = G.bc[1];
+    B.ky0 = G.bc[2];
+    B.ky1 = G.bc[3];
+    double e[12];
+    const int jp[4] = {0, 2, 1, 3};  // plane in a family pulled through face f
+    double *dst[4] = {B.in1, B.in3, B.in2, B.in4};
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        feq2d(G.win[f][0], G.win[f][1], G.win[f][2], P, e);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dst[f][c] = xk_uniform(e[4 * c + jp[f]]);
+    }
+    return B;
+}
+
+__device__ __forceinline__ int xk_clampw(int v, int n, bool per)
+{
+    return per ? ((v % n) + n) % n : min(max(v, 0), n - 1);
+}
+
+// Level-n pulls of the level-1 node at row i (unwrapped) and column xc of a grid
+// with non-periodic faces (face rules of Neumann and wall faces applied here;
+// inflow values are set where the pulls are used, in double).
+template <typename T>
+__device__ __forceinline__ void xk_load_bnd(const T *__restrict__ src, long ps, const Geo &G,
+                                            const XkBnd &B, int i, int xc, T *f)
+{
+    const int nx = G.nx, ny = G.ny;
+    const bool perx = B.kx0 == BC_PERIODIC, pery = B.ky0 == BC_PERIODIC;
+    const int xw = xk_clampw(xc, nx, perx), xm = xk_clampw(xc - 1, nx, perx),
+              xp = xk_clampw(xc + 1, nx, perx);
+    const int r = xk_clampw(i, ny, pery), rm = xk_clampw(i - 1, ny, pery),
+              rp = xk_clampw(i + 1, ny, pery);
+    const bool bx0 = !perx && xc == 0, bx1 = !perx && xc == nx - 1;  // per lane
+    const bool by0 = !pery && i == 0, by1 = !pery && i == ny - 1;     // uniform
+    const long own = (long)r * nx + xw;
+    const long o1 = bx0 ? own : (long)r * nx + xm, o3 = bx1 ? own : (long)r * nx + xp;
+    const long o2 = by0 ? own : (long)rm * nx + xw, o4 = by1 ? own : (long)rp * nx + xw;
+    const int p1 = bx0 && B.kx0 == BC_WALL ? 2 : 0, p3 = bx1 && B.kx1 == BC_WALL ? 0 : 2;
+    const int p2 = by0 && B.ky0 == BC_WALL ? 3 : 1, p4 = by1 && B.ky1 == BC_WALL ? 1 : 3;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const T *b = src + (4 * c) * ps;
+        T v1 = b[p1 * ps + o1], v2 = b[p2 * ps + o2], v3 = b[p3 * ps + o3],
+          v4 = b[p4 * ps + o4];
+        if (c == 1) {  // qx: normal momentum of the x faces
+            if (p1 == 2) v1 = -v1;
+            if (p3 == 0) v3 = -v3;
+        }
+        if (c == 2) {  // qy: normal momentum of the y faces
+            if (p2 == 3) v2 = -v2;
+            if (p4 == 1) v4 = -v4;
+        }
+        f[4 * c + 0] = v1;
+        f[4 * c + 1] = v2;
+        f[4 * c + 2] = v3;
+        f[4 * c + 3] = v4;
     }
 }
 
@@ -318,18 +449,40 @@ constexpr int xk_halo()
 // stored value, and their stores, like those of non-output lanes, carry an
 // offset the hardware drops -- so the compiler's memory waits see one straight
 // sequence and keep the D rows of loads in flight.
-template <typename T, int K>
+// Grids with non-periodic faces (BND): s1 / s3 hold the lane's own e1 / e3
+// planes of the last row, unshifted, and the exchange happens where they are
+// used (DPP), so a face lane can take its own values instead; ec is the other
+// e2 array (the e2 planes of the last row), i the level-1 row of this
+// iteration and inext that of the row prefetched now (both unwrapped), xc the
+// lane's column, bx0 / bx1 its face flags and B the face rules.  The y faces
+// reuse the e2 arrays: when row 0 of level k is computed, the e2 slot of row -1
+// (whose only reader is row 0's pull through the y- face) receives the face
+// value; on a Neumann y+ face the e2 slot of row ny - 1 (read only by row ny,
+// outside the grid) receives its own e4 planes, which row ny - 1 pulls back.
+template <typename T, int K, bool BND>
 __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const Phys &P,
                                        int lane, const __amdgpu_buffer_rsrc_t *orsrc,
                                        unsigned ooff, const XkOff &onext, const T (&cur)[12],
                                        T (&nxt)[12], T (&em)[K - 1][3], T (&s1)[K - 1][3],
                                        T (&s3)[K - 1][3], T (&pend)[12], unsigned &pend_off,
-                                       T *__restrict__ xsw)
+                                       T *__restrict__ xsw, const Geo &G, const XkBnd &B, int i,
+                                       int inext, int xc, bool bx0, bool bx1, T (&ec)[K - 1][3])
 {
-    constexpr int L = xk_lds_levels<T, K>();
+    constexpr int L = BND ? 0 : xk_lds_levels<T, K>();
     double v[12];
 #pragma unroll
     for (int pl = 0; pl < 12; ++pl) v[pl] = (double)cur[pl];
+    if constexpr (BND) {
+        const bool by0 = B.ky0 != BC_PERIODIC && i == 0;
+        const bool by1 = B.ky1 != BC_PERIODIC && i == G.ny - 1;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (bx0 && B.kx0 == BC_INFLOW) v[4 * c + 0] = B.in1[c];
+            if (bx1 && B.kx1 == BC_INFLOW) v[4 * c + 2] = B.in3[c];
+            if (by0 && B.ky0 == BC_INFLOW) v[4 * c + 1] = B.in2[c];
+            if (by1 && B.ky1 == BC_INFLOW) v[4 * c + 3] = B.in4[c];
+        }
+    }
 #if LBM_XK_DELAY
     // The previous row's outputs are stored only now, after this row's loaded
     // values have been consumed: the wait for those loads (issued D rows ago)
@@ -340,7 +493,10 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
 #pragma unroll
     for (int pl = 0; pl < 12; ++pl) xk_store(orsrc[pl], pend_off, pend[pl]);
 #endif
-    xk_load(src, ps, onext, nxt);
+    if constexpr (BND)
+        xk_load_bnd(src, ps, G, B, inext, xc, nxt);
+    else
+        xk_load(src, ps, onext, nxt);
     collide2d(v, P);  // level 1
 #pragma unroll
     for (int k = 1; k < K; ++k) {
@@ -348,7 +504,42 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
 #pragma unroll
         for (int pl = 0; pl < 12; ++pl) v[pl] = (double)(T)v[pl];
         double o[12];
-        if (k - 1 < L) {
+        if constexpr (BND) {
+            // rr: row of level k + 1 computed here; the level-k row in v is rr + 1
+            const int rr = i - k;
+            const bool ry0 = B.ky0 == BC_INFLOW && rr == 0;
+            const bool ry1 = B.ky1 != BC_PERIODIC && rr == G.ny - 1;
+            const bool vy0 = B.ky0 != BC_PERIODIC && rr + 1 == 0;
+            const bool vn1 = B.ky1 == BC_NEUMANN && rr + 1 == G.ny - 1;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const T u1 = s1[k - 1][c], u3 = s3[k - 1][c], uc = ec[k - 1][c];
+                double a1 = (double)xk_shr(u1), a3 = (double)xk_shl(u3);
+                double a2 = (double)em[k - 1][c], a4 = v[4 * c + 3];
+                if (bx0)
+                    a1 = B.kx0 == BC_NEUMANN ? (double)u1
+                         : B.kx0 == BC_WALL  ? (double)(c == 1 ? -u3 : u3)
+                                             : B.in1[c];
+                if (bx1)
+                    a3 = B.kx1 == BC_NEUMANN ? (double)u3
+                         : B.kx1 == BC_WALL  ? (double)(c == 1 ? -u1 : u1)
+                                             : B.in3[c];
+                if (ry0) a2 = B.in2[c];
+                if (ry1)
+                    a4 = B.ky1 == BC_INFLOW ? B.in4[c]
+                         : B.ky1 == BC_WALL ? (double)(c == 2 ? -uc : uc)
+                                            : (double)uc;
+                o[4 * c + 0] = a1;
+                o[4 * c + 1] = a2;
+                o[4 * c + 2] = a3;
+                o[4 * c + 3] = a4;
+                const T w2 = (T)v[4 * c + 1], w4 = (T)v[4 * c + 3];
+                em[k - 1][c] = vn1 ? w4 : w2;
+                if (vy0) ec[k - 1][c] = B.ky0 == BC_WALL ? (c == 2 ? -w4 : w4) : w2;
+                s1[k - 1][c] = (T)v[4 * c + 0];
+                s3[k - 1][c] = (T)v[4 * c + 2];
+            }
+        } else if (k - 1 < L) {
             // this wavefront's LDS row of level k: planes e1 (c) and e3 (3 + c);
             // read the previous row's neighbours, then overwrite with this row
             // (the wavefront executes in lockstep and its LDS operations in
@@ -379,8 +570,8 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
                 o[4 * c + 2] = (double)s3[k - 1][c];
                 o[4 * c + 3] = v[4 * c + 3];
                 em[k - 1][c] = (T)v[4 * c + 1];
-                s1[k - 1][c] = xk_from((T)v[4 * c + 0], lane, 1);
-                s3[k - 1][c] = xk_from((T)v[4 * c + 2], lane, -1);
+                s1[k - 1][c] = xk_xch((T)v[4 * c + 0], lane, 1);
+                s3[k - 1][c] = xk_xch((T)v[4 * c + 2], lane, -1);
             }
         }
         collide2d(o, P);
@@ -407,7 +598,7 @@ constexpr int xk_gcd(int a, int b) { return b == 0 ? a : xk_gcd(b, a % b); }
 // unrolled blocks (the extra iterations store nothing).
 // One wavefront: column strip `strip` of the grid (G, P) in src / dst, output
 // rows [y0, y1).
-template <typename T, int K, int D>
+template <typename T, int K, int D, bool BND = false>
 __device__ __forceinline__ void xk_wave(const T *__restrict__ src, T *__restrict__ dst,
                                         const Geo &G, const Phys &P, int strip, int y0, int y1,
                                         T *__restrict__ xsw)
@@ -437,6 +628,14 @@ __device__ __forceinline__ void xk_wave(const T *__restrict__ src, T *__restrict
         orsrc[pl] = __builtin_amdgcn_make_buffer_rsrc(dst + pl * ps, 0, (int)plane_bytes,
                                                       0x00020000);
     int rl = (((y0 - (K - 1)) % ny) + ny) % ny;  // level-1 row of the last load, wrapped
+    int il = y0 - (K - 1);                       // the same, unwrapped
+    XkBnd B{};
+    bool bx0 = false, bx1 = false;
+    if constexpr (BND) {
+        B = xk_bnd(G, P);
+        bx0 = B.kx0 != BC_PERIODIC && xc == 0;
+        bx1 = B.kx1 != BC_PERIODIC && xc == nx - 1;
+    }
 
     // state of the intermediate levels 1 .. K-1 (index k-1), storage precision:
     // e2 planes of the last two rows (e2[0] / e2[1] alternate), e1 planes of the
@@ -445,13 +644,21 @@ __device__ __forceinline__ void xk_wave(const T *__restrict__ src, T *__restrict
 #pragma unroll
     for (int k = 0; k < K - 1; ++k)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) e2[0][k][c] = e2[1][k][c] = s1[k][c] = s3[k][c] = (T)0;
+        for (int c = 0; c < 3; ++c) {
+            e2[0][k][c] = e2[1][k][c] = s1[k][c] = s3[k][c] = (T)0;
+        }
 
     T buf[D + 1][12];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        xk_load(src, ps, xk_offsets<T>(rl, nx, ny, xm, xw, xp), buf[d]);
-        if (d + 1 < D) rl = rl == ny - 1 ? 0 : rl + 1;
+        if constexpr (BND)
+            xk_load_bnd(src, ps, G, B, il, xc, buf[d]);
+        else
+            xk_load(src, ps, xk_offsets<T>(rl, nx, ny, xm, xw, xp), buf[d]);
+        if (d + 1 < D) {
+            rl = rl == ny - 1 ? 0 : rl + 1;
+            ++il;
+        }
     }
     T pend[12];  // outputs of the last row, stored one iteration later
     unsigned pend_off = kXkDrop;
@@ -466,9 +673,11 @@ __device__ __forceinline__ void xk_wave(const T *__restrict__ src, T *__restrict
                                       ? (unsigned)orow * ostep + lane_off
                                       : kXkDrop;
             rl = rl == ny - 1 ? 0 : rl + 1;
-            xk_row<T, K>(src, ps, P, lane, orsrc, ooff, xk_offsets<T>(rl, nx, ny, xm, xw, xp),
-                         buf[u % (D + 1)], buf[(u + D) % (D + 1)], e2[u % 2], s1, s3, pend,
-                         pend_off, xsw);
+            ++il;
+            xk_row<T, K, BND>(src, ps, P, lane, orsrc, ooff,
+                              xk_offsets<T>(rl, nx, ny, xm, xw, xp), buf[u % (D + 1)],
+                              buf[(u + D) % (D + 1)], e2[u % 2], s1, s3, pend, pend_off, xsw, G,
+                              B, y0 - (K - 1) + jj, il, xc, bx0, bx1, e2[(u + 1) % 2]);
         }
     }
 #if LBM_XK_DELAY
@@ -490,6 +699,22 @@ __global__ void __launch_bounds__(64 * kXkWaves)
     if (strip >= nstrips) return;  // whole wavefront; nothing here waits on others
     const int y0 = (tile / ngroups) * seg;
     xk_wave<T, K, D>(src, dst, G, P, strip, y0, min(y0 + seg, G.ny), xs[threadIdx.x >> 6]);
+}
+
+// Grids with non-periodic faces (the one-step kernel's face rules); K at most
+// kXkMaxKBnd.
+template <typename T, int K, int D>
+__global__ void __launch_bounds__(64 * kXkWaves)
+    k_step2d_xkb(const T *__restrict__ src, T *__restrict__ dst, Geo G, Phys P, int nstrips,
+                 int seg)
+{
+    const int ngroups = (nstrips + kXkWaves - 1) / kXkWaves;
+    const int nseg = (G.ny + seg - 1) / seg;
+    const int tile = xk_tile(blockIdx.x, ngroups * nseg, LBM_XK_REMAP != 0);
+    const int strip = (tile % ngroups) * kXkWaves + (threadIdx.x >> 6);
+    if (strip >= nstrips) return;  // whole wavefront; nothing here waits on others
+    const int y0 = (tile / ngroups) * seg;
+    xk_wave<T, K, D, true>(src, dst, G, P, strip, y0, min(y0 + seg, G.ny), nullptr);
 }
 
 // Batched form: workgroup b takes tile b' (the XCD-contiguous order of b) of a
@@ -533,18 +758,61 @@ int step2k_blocks(const Geo &G, bool f32, int K, int seg)
     return ngroups * ((G.ny + seg - 1) / seg);
 }
 
-// Workgroups of the K-step launch resident per compute unit (occupancy API).
-static int xk_per_cu(bool f32, int K)
+// Steps per launch at most on grids with non-periodic faces.  Measured at 4096^2
+// (inflow / Neumann / wall faces): FP64 K = 1 .. 5 -> 26, 42, 64, 74, 72 GLUPS,
+// FP32 -> 57, 70, 108, 116, 75; beyond K = 4 the kernel spills registers.  The
+// FP64 K = 6 and FP32 K = 8 instantiations also returned wrong values over whole
+// grids on the GPU (every face set, interior nodes included) with no cause found
+// in the source, so no instantiation above K = 4 is built.
+constexpr int kXkMaxKBnd = 4;
+
+int step2k_max_k_bounded() { return kXkMaxKBnd; }
+
+static bool geo_bounded(const Geo &G)
+{
+    return G.bc[0] != BC_PERIODIC || G.bc[1] != BC_PERIODIC || G.bc[2] != BC_PERIODIC ||
+           G.bc[3] != BC_PERIODIC;
+}
+
+template <typename T, int KK>
+static hipError_t xkb_occupancy(int *n, int bs)
+{
+    if constexpr (KK <= kXkMaxKBnd)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_step2d_xkb<T, KK, kXkDepth>,
+                                                            bs, 0);
+    else
+        return hipErrorInvalidValue;
+}
+
+template <typename T, int KK>
+static hipError_t xkb_launch(dim3 grid, dim3 block, hipStream_t st, const T *src, T *dst,
+                             const Geo &G, const Phys &P, int ns, int seg)
+{
+    if constexpr (KK <= kXkMaxKBnd) {
+        hipLaunchKernelGGL((k_step2d_xkb<T, KK, kXkDepth>), grid, block, 0, st, src, dst, G, P,
+                           ns, seg);
+        return hipSuccess;
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
+// Workgroups of the K-step launch resident per compute unit (occupancy API);
+// bnd: the kernel for grids with non-periodic faces.
+static int xk_per_cu(bool f32, int K, bool bnd)
 {
     int n = 0;
     const int bs = 64 * kXkWaves;
     hipError_t e = hipErrorInvalidValue;
 #define LBM_XK_OCC(KK)                                                                        \
     case KK:                                                                                  \
-        e = f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                               \
-                      &n, k_step2d_xk<float, KK, kXkDepth>, bs, 0)                            \
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(                               \
-                      &n, k_step2d_xk<double, KK, kXkDepth>, bs, 0);                          \
+        if (bnd)                                                                              \
+            e = f32 ? xkb_occupancy<float, KK>(&n, bs) : xkb_occupancy<double, KK>(&n, bs);   \
+        else                                                                                  \
+            e = f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                           \
+                          &n, k_step2d_xk<float, KK, kXkDepth>, bs, 0)                        \
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(                           \
+                          &n, k_step2d_xk<double, KK, kXkDepth>, bs, 0);                      \
         break;
     switch (K) {
         LBM_XK_OCC(2)
@@ -579,7 +847,7 @@ int step2k_seg(const Geo &G, bool f32, int K, int min_seg, bool *full, long *slo
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
-    const long slots = (long)ncu * xk_per_cu(f32, K);
+    const long slots = (long)ncu * xk_per_cu(f32, K, geo_bounded(G));
     if (slots_out) *slots_out = slots;
     if (slots <= 0) return 0;
     const long ngroups = (step2k_strips(G, f32, K) + kXkWaves - 1) / kXkWaves;
@@ -610,13 +878,21 @@ hipError_t launch_step2k(bool f32, const void *src, void *dst, const Geo &G, con
     const int ns = step2k_strips(G, f32, K);
     const int nb = step2k_blocks(G, f32, K, seg);
     const dim3 grid(nb), block(64 * kXkWaves);
+    const bool bnd = geo_bounded(G);
 #define LBM_XK_CASE(KK)                                                                       \
     case KK:                                                                                  \
-        if (f32)                                                                              \
-            hipLaunchKernelGGL((k_step2d_xk<float, KK, kXkDepth>), grid, block, 0, st,                  \
+        if (bnd) {                                                                            \
+            const hipError_t eb =                                                             \
+                f32 ? xkb_launch<float, KK>(grid, block, st, (const float *)src, (float *)dst, \
+                                            G, P, ns, seg)                                    \
+                    : xkb_launch<double, KK>(grid, block, st, (const double *)src,            \
+                                             (double *)dst, G, P, ns, seg);                   \
+            if (eb != hipSuccess) return eb;                                                  \
+        } else if (f32)                                                                       \
+            hipLaunchKernelGGL((k_step2d_xk<float, KK, kXkDepth>), grid, block, 0, st,        \
                                (const float *)src, (float *)dst, G, P, ns, seg);              \
         else                                                                                  \
-            hipLaunchKernelGGL((k_step2d_xk<double, KK, kXkDepth>), grid, block, 0, st,                 \
+            hipLaunchKernelGGL((k_step2d_xk<double, KK, kXkDepth>), grid, block, 0, st,       \
                                (const double *)src, (double *)dst, G, P, ns, seg);            \
         break;
     switch (K) {

@@ -222,13 +222,59 @@ def test_fused_launch_equals_single_steps(storage, fuse, shape, steps):
         assert per_plane_rel(b, ref) <= TOL64
 
 
-def test_fused_request_on_walls_takes_single_steps():
-    """Non-periodic faces: fuse_steps = 2 is accepted and the single-step path runs."""
-    case = W.oblique_shock_2d(20, steps=60)
-    S = gpu_solver(case, fuse_steps=2)
-    S.step(case.steps)
-    ref, _ = orc_state(case, case.steps)
-    assert per_plane_rel(to_np(S.planes()), ref) <= TOL64
+_IN = {0: (1.2, 0.3, 0.05), 1: (0.9, -0.2, 0.1), 2: (1.1, 0.05, 0.25), 3: (0.95, 0.1, -0.15)}
+
+
+def _bounded(nx, ny, bc, seed):
+    inflow = {f: _IN[f] for f in range(4) if bc[f] == "inflow"}
+    return smooth_random_2d(nx, ny, seed=seed, bc=bc, inflow=inflow)
+
+
+BOUNDED = [  # face rules (x-, x+, y-, y+), grid, steps
+    (("inflow", "neumann", "wall", "inflow"), (300, 70), 13),   # the oblique shock's faces
+    (("wall", "wall", "wall", "wall"), (233, 211), 70),          # closed box, many segments
+    (("neumann", "neumann", "neumann", "neumann"), (17, 5), 9),  # one strip
+    (("periodic", "periodic", "wall", "neumann"), (130, 97), 11),  # y faces only
+    (("inflow", "wall", "periodic", "periodic"), (600, 40), 7),   # x faces only
+    (("wall", "inflow", "neumann", "wall"), (2, 60), 21),         # narrower than the halo
+    (("neumann", "inflow", "inflow", "neumann"), (70, 2), 10),    # two rows (the minimum)
+    (("wall", "neumann", "inflow", "wall"), (3, 33), 12),         # three columns
+]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("fuse", [2, 3, 4])
+@pytest.mark.parametrize("bc,shape,steps", BOUNDED)
+def test_fused_bounded_launch_equals_single_steps(storage, fuse, bc, shape, steps):
+    """fuse_steps = K (2 .. 4, the bounded maximum) on 2D grids with Neumann,
+    wall and inflow faces (alone, in every corner combination, with the other
+    axis periodic, on grids of two rows, three columns or narrower than the halo)
+    gives bit for bit the state of single steps; FP64 also matches the oracle."""
+    nx, ny = shape
+    case = _bounded(nx, ny, bc, seed=nx + ny)
+    say(f"[fused bounded] {nx}x{ny} bc={bc} steps={steps} fuse={fuse} storage={storage}")
+    A = gpu_solver(case, storage=storage, fuse_steps=1)
+    B = gpu_solver(case, storage=storage, fuse_steps=fuse)
+    assert B.launch_info()["steps_per_launch"] == fuse
+    A.step(steps)
+    B.step(steps)
+    a, b = to_np(A.planes()), to_np(B.planes())
+    assert np.array_equal(a, b)
+    if storage == "f64":
+        ref, _ = orc_state(case, steps)
+        assert per_plane_rel(b, ref) <= TOL64
+
+
+@pytest.mark.parametrize("fuse", [3, 4])
+def test_fused_oblique_shock_matches_oracle(fuse):
+    """The oblique shock reflection (inflow left and top, wall bottom, outflow
+    right) run to steady state with fuse_steps = K equals the oracle."""
+    case = W.oblique_shock_2d(40)
+    got, ref, S, _ = _compare(case, case.steps, fuse_steps=fuse)
+    assert S.launch_info()["steps_per_launch"] == fuse
+    err = per_plane_rel(got, ref)
+    say(f"  {case.name} {case.steps} steps, fuse {fuse}: max plane rel err {err:.3e}")
+    assert err <= TOL64
 
 
 def _case_1d(n, bc, inflow, seed):
@@ -272,8 +318,9 @@ def test_default_launch_plans():
     """lbm_launch_info reports the plan chosen at init: the wave-strip multi-step
     launch on grids it can fill (FP64 8 steps, FP32 6), with a segment length and
     the resident workgroups it was chosen against; one step per launch on a
-    small FP32 grid; 16 steps per launch in 1D; one step with non-periodic 2D
-    faces; an explicit request is honoured up to 8 steps."""
+    small FP32 grid; 16 steps per launch in 1D; 4 steps with non-periodic 2D
+    faces; an explicit request is honoured up to 8 steps (4 with non-periodic
+    faces)."""
     big64 = gpu_solver(smooth_random_2d(1024, 1024, seed=8), storage="f64").launch_info()
     assert big64["steps_per_launch"] == 8 and big64["segment_rows"] >= 16
     assert big64["resident_blocks"] > 0
@@ -284,7 +331,13 @@ def test_default_launch_plans():
     one_d = gpu_solver(W.dam_break_1d(1000)).launch_info()
     assert one_d["steps_per_launch"] == 16 and one_d["segment_rows"] == 0
     walls = gpu_solver(W.oblique_shock_2d(20, steps=10), fuse_steps=4).launch_info()
-    assert walls["steps_per_launch"] == 1
+    assert walls["steps_per_launch"] == 4 and walls["segment_rows"] >= 16
+    walls8 = gpu_solver(W.oblique_shock_2d(20, steps=10), fuse_steps=8).launch_info()
+    assert walls8["steps_per_launch"] == 4
+    box = gpu_solver(smooth_random_2d(1024, 1024, seed=8, bc=("wall",) * 4)).launch_info()
+    assert box["steps_per_launch"] == 4 and box["segment_rows"] >= 16
+    small_box = gpu_solver(smooth_random_2d(64, 64, seed=8, bc=("wall",) * 4)).launch_info()
+    assert small_box["steps_per_launch"] == 1
     asked = gpu_solver(smooth_random_2d(300, 70, seed=8), fuse_steps=16).launch_info()
     assert asked["steps_per_launch"] == 8
     say(f"[plans] 1024^2 f64 {big64}, f32 {big32}, 256^2 f32 {small32}")
