@@ -196,7 +196,7 @@ static const int kDefaultFuse2dF64 = 8;
 static const int kDefaultFuse2dF32 = 6;
 // With non-periodic faces the wave-strip kernel takes at most
 // step2k_max_k_bounded() (4) steps per launch, and 4 by default: at 4096^2
-// (inflow / Neumann / wall faces) FP64 74 GLUPS (one step: 26), FP32 116 (57).
+// (inflow / Neumann / wall faces) FP64 85 GLUPS (one step: 26), FP32 122 (57).
 static const int kDefaultFuse2dBounded = 4;
 // Shortest segment of a wave-strip launch (the halo rows cost 2 (K - 1) per
 // segment; the segment length itself is chosen per grid, step2k_seg).  Grids

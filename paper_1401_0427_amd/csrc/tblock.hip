@@ -352,43 +352,32 @@ __device__ __forceinline__ int xk_clampw(int v, int n, bool per)
     return per ? ((v % n) + n) % n : min(max(v, 0), n - 1);
 }
 
-// Level-n pulls of the level-1 node at row i (unwrapped) and column xc of a grid
-// with non-periodic faces (face rules of Neumann and wall faces applied here;
-// inflow values are set where the pulls are used, in double).
+// Level-n pulls of the level-1 nodes of row i (unwrapped) on a grid with
+// non-periodic faces; xm / xw / xp: the lane's column and its neighbours,
+// clamped to the grid on a non-periodic x axis.  Clamped rows and columns give a
+// face node its own population, the Neumann rule; a y wall takes the opposite
+// plane of the node's own row (uniform over the wavefront).  The x wall, the
+// sign flips and the inflow values are applied where the row is consumed.
 template <typename T>
-__device__ __forceinline__ void xk_load_bnd(const T *__restrict__ src, long ps, const Geo &G,
-                                            const XkBnd &B, int i, int xc, T *f)
+__device__ __forceinline__ void xk_load_clamp(const T *__restrict__ src, long ps, const Geo &G,
+                                              const XkBnd &B, int i, int xm, int xw, int xp,
+                                              T *f)
 {
     const int nx = G.nx, ny = G.ny;
-    const bool perx = B.kx0 == BC_PERIODIC, pery = B.ky0 == BC_PERIODIC;
-    const int xw = xk_clampw(xc, nx, perx), xm = xk_clampw(xc - 1, nx, perx),
-              xp = xk_clampw(xc + 1, nx, perx);
-    const int r = xk_clampw(i, ny, pery), rm = xk_clampw(i - 1, ny, pery),
-              rp = xk_clampw(i + 1, ny, pery);
-    const bool bx0 = !perx && xc == 0, bx1 = !perx && xc == nx - 1;  // per lane
-    const bool by0 = !pery && i == 0, by1 = !pery && i == ny - 1;     // uniform
-    const long own = (long)r * nx + xw;
-    const long o1 = bx0 ? own : (long)r * nx + xm, o3 = bx1 ? own : (long)r * nx + xp;
-    const long o2 = by0 ? own : (long)rm * nx + xw, o4 = by1 ? own : (long)rp * nx + xw;
-    const int p1 = bx0 && B.kx0 == BC_WALL ? 2 : 0, p3 = bx1 && B.kx1 == BC_WALL ? 0 : 2;
-    const int p2 = by0 && B.ky0 == BC_WALL ? 3 : 1, p4 = by1 && B.ky1 == BC_WALL ? 1 : 3;
+    const bool pery = B.ky0 == BC_PERIODIC;
+    const unsigned row = (unsigned)xk_clampw(i, ny, pery) * (unsigned)nx;
+    const unsigned rowm = (unsigned)xk_clampw(i - 1, ny, pery) * (unsigned)nx;
+    const unsigned rowp = (unsigned)xk_clampw(i + 1, ny, pery) * (unsigned)nx;
+    const int p2 = !pery && i == 0 && B.ky0 == BC_WALL ? 3 : 1;
+    const int p4 = !pery && i == ny - 1 && B.ky1 == BC_WALL ? 1 : 3;
+    const unsigned o1 = (row + xm) * (unsigned)sizeof(T), o2 = (rowm + xw) * (unsigned)sizeof(T);
+    const unsigned o3 = (row + xp) * (unsigned)sizeof(T), o4 = (rowp + xw) * (unsigned)sizeof(T);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const T *b = src + (4 * c) * ps;
-        T v1 = b[p1 * ps + o1], v2 = b[p2 * ps + o2], v3 = b[p3 * ps + o3],
-          v4 = b[p4 * ps + o4];
-        if (c == 1) {  // qx: normal momentum of the x faces
-            if (p1 == 2) v1 = -v1;
-            if (p3 == 0) v3 = -v3;
-        }
-        if (c == 2) {  // qy: normal momentum of the y faces
-            if (p2 == 3) v2 = -v2;
-            if (p4 == 1) v4 = -v4;
-        }
-        f[4 * c + 0] = v1;
-        f[4 * c + 1] = v2;
-        f[4 * c + 2] = v3;
-        f[4 * c + 3] = v4;
+        f[4 * c + 0] = xk_at(src + (4 * c + 0) * ps, o1);
+        f[4 * c + 1] = xk_at(src + (4 * c + p2) * ps, o2);
+        f[4 * c + 2] = xk_at(src + (4 * c + 2) * ps, o3);
+        f[4 * c + 3] = xk_at(src + (4 * c + p4) * ps, o4);
     }
 }
 
@@ -425,17 +414,20 @@ constexpr int xk_lds_elems()
 // down to a whole number of aligned chunks, so (on rows that start aligned)
 // each strip writes whole memory segments and never shares one with another
 // strip: a partially written segment would cost the DRAM a read-modify-write.
-template <typename T, int K>
+// Grids with non-periodic faces (BND) keep at least K lanes after the last output
+// column: an x+ wall node takes its own e1 at level 1 from the next lane.
+template <typename T, int K, bool BND = false>
 constexpr int xk_wo()
 {
     constexpr int A = (sizeof(T) == 8 ? LBM_XK_ALIGN_F64 : LBM_XK_ALIGN_F32) / (int)sizeof(T);
-    return A > 1 ? (64 - 2 * (K - 1)) / A * A : 64 - 2 * (K - 1);
+    constexpr int halo = 2 * (K - 1) + (BND ? 1 : 0);
+    return A > 1 ? (64 - halo) / A * A : 64 - halo;
 }
 // Halo lanes before the first output column (>= K - 1 on both sides).
-template <typename T, int K>
+template <typename T, int K, bool BND = false>
 constexpr int xk_halo()
 {
-    return (64 - xk_wo<T, K>()) / 2;
+    return (64 - xk_wo<T, K, BND>()) / 2;
 }
 
 // One iteration j of the row loop.  cur: level-n pulls of this iteration's
@@ -453,8 +445,9 @@ constexpr int xk_halo()
 // planes of the last row, unshifted, and the exchange happens where they are
 // used (DPP), so a face lane can take its own values instead; ec is the other
 // e2 array (the e2 planes of the last row), i the level-1 row of this
-// iteration and inext that of the row prefetched now (both unwrapped), xc the
-// lane's column, bx0 / bx1 its face flags and B the face rules.  The y faces
+// iteration and inext that of the row prefetched now (both unwrapped), the
+// lane's columns (xm, xw, xp), bx0 / bx1 its face flags and B the face rules.
+// The y faces
 // reuse the e2 arrays: when row 0 of level k is computed, the e2 slot of row -1
 // (whose only reader is row 0's pull through the y- face) receives the face
 // value; on a Neumann y+ face the e2 slot of row ny - 1 (read only by row ny,
@@ -466,7 +459,8 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
                                        T (&nxt)[12], T (&em)[K - 1][3], T (&s1)[K - 1][3],
                                        T (&s3)[K - 1][3], T (&pend)[12], unsigned &pend_off,
                                        T *__restrict__ xsw, const Geo &G, const XkBnd &B, int i,
-                                       int inext, int xc, bool bx0, bool bx1, T (&ec)[K - 1][3])
+                                       int inext, int xm, int xw, int xp, bool bx0, bool bx1,
+                                       T (&ec)[K - 1][3])
 {
     constexpr int L = BND ? 0 : xk_lds_levels<T, K>();
     double v[12];
@@ -475,6 +469,25 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
     if constexpr (BND) {
         const bool by0 = B.ky0 != BC_PERIODIC && i == 0;
         const bool by1 = B.ky1 != BC_PERIODIC && i == G.ny - 1;
+        // y walls: the opposite plane was loaded; negate the normal momentum (qy)
+        if (by0 && B.ky0 == BC_WALL) v[9] = -v[9];
+        if (by1 && B.ky1 == BC_WALL) v[11] = -v[11];
+        // x walls: the node's own e3 (x-) / e1 (x+) was loaded by the lane outside
+        // the face, whose clamped e3 / e1 pull is the face node itself
+        if (B.kx0 == BC_WALL) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const T t = xk_shr(cur[4 * c + 2]);
+                if (bx0) v[4 * c + 0] = (double)(c == 1 ? -t : t);
+            }
+        }
+        if (B.kx1 == BC_WALL) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const T t = xk_shl(cur[4 * c + 0]);
+                if (bx1) v[4 * c + 2] = (double)(c == 1 ? -t : t);
+            }
+        }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             if (bx0 && B.kx0 == BC_INFLOW) v[4 * c + 0] = B.in1[c];
@@ -494,7 +507,7 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
     for (int pl = 0; pl < 12; ++pl) xk_store(orsrc[pl], pend_off, pend[pl]);
 #endif
     if constexpr (BND)
-        xk_load_bnd(src, ps, G, B, inext, xc, nxt);
+        xk_load_clamp(src, ps, G, B, inext, xm, xw, xp, nxt);
     else
         xk_load(src, ps, onext, nxt);
     collide2d(v, P);  // level 1
@@ -603,18 +616,27 @@ __device__ __forceinline__ void xk_wave(const T *__restrict__ src, T *__restrict
                                         const Geo &G, const Phys &P, int strip, int y0, int y1,
                                         T *__restrict__ xsw)
 {
-    constexpr int WO = xk_wo<T, K>();  // output columns per strip
-    constexpr int H = xk_halo<T, K>();
-    static_assert(H >= K - 1 && 64 - H - WO >= K - 1, "halo lanes");
+    constexpr int WO = xk_wo<T, K, BND>();  // output columns per strip
+    constexpr int H = xk_halo<T, K, BND>();
+    static_assert(H >= K - 1 && 64 - H - WO >= K - 1 + (BND ? 1 : 0), "halo lanes");
     constexpr int U = 2 * (D + 1) / xk_gcd(2, D + 1);
     const int nx = G.nx, ny = G.ny;
     const long ps = G.ps;
     const int lane = threadIdx.x & 63;
     const int x0 = strip * WO;     // first output column
     const int xc = x0 - H + lane;  // this lane's column, unwrapped
-    const int xw = ((xc % nx) + nx) % nx;
-    const int xm = xw == 0 ? nx - 1 : xw - 1;
-    const int xp = xw == nx - 1 ? 0 : xw + 1;
+    XkBnd B{};
+    bool bx0 = false, bx1 = false, clampx = false;
+    if constexpr (BND) {
+        B = xk_bnd(G, P);
+        clampx = B.kx0 != BC_PERIODIC;
+        bx0 = clampx && xc == 0;
+        bx1 = clampx && xc == nx - 1;
+    }
+    // the lane's column and its neighbours: wrapped, or clamped to the grid
+    const int xw = clampx ? min(max(xc, 0), nx - 1) : ((xc % nx) + nx) % nx;
+    const int xm = clampx ? min(max(xc - 1, 0), nx - 1) : (xw == 0 ? nx - 1 : xw - 1);
+    const int xp = clampx ? min(max(xc + 1, 0), nx - 1) : (xw == nx - 1 ? 0 : xw + 1);
     const bool olane = lane >= H && lane < H + WO && xc < nx;
     const int niter = (y1 - y0) + 2 * (K - 1);
     // Output row of iteration j is y0 - 2 (K - 1) + j, stored when it lies in
@@ -629,13 +651,6 @@ __device__ __forceinline__ void xk_wave(const T *__restrict__ src, T *__restrict
                                                       0x00020000);
     int rl = (((y0 - (K - 1)) % ny) + ny) % ny;  // level-1 row of the last load, wrapped
     int il = y0 - (K - 1);                       // the same, unwrapped
-    XkBnd B{};
-    bool bx0 = false, bx1 = false;
-    if constexpr (BND) {
-        B = xk_bnd(G, P);
-        bx0 = B.kx0 != BC_PERIODIC && xc == 0;
-        bx1 = B.kx1 != BC_PERIODIC && xc == nx - 1;
-    }
 
     // state of the intermediate levels 1 .. K-1 (index k-1), storage precision:
     // e2 planes of the last two rows (e2[0] / e2[1] alternate), e1 planes of the
@@ -652,7 +667,7 @@ __device__ __forceinline__ void xk_wave(const T *__restrict__ src, T *__restrict
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         if constexpr (BND)
-            xk_load_bnd(src, ps, G, B, il, xc, buf[d]);
+            xk_load_clamp(src, ps, G, B, il, xm, xw, xp, buf[d]);
         else
             xk_load(src, ps, xk_offsets<T>(rl, nx, ny, xm, xw, xp), buf[d]);
         if (d + 1 < D) {
@@ -677,7 +692,7 @@ __device__ __forceinline__ void xk_wave(const T *__restrict__ src, T *__restrict
             xk_row<T, K, BND>(src, ps, P, lane, orsrc, ooff,
                               xk_offsets<T>(rl, nx, ny, xm, xw, xp), buf[u % (D + 1)],
                               buf[(u + D) % (D + 1)], e2[u % 2], s1, s3, pend, pend_off, xsw, G,
-                              B, y0 - (K - 1) + jj, il, xc, bx0, bx1, e2[(u + 1) % 2]);
+                              B, y0 - (K - 1) + jj, il, xm, xw, xp, bx0, bx1, e2[(u + 1) % 2]);
         }
     }
 #if LBM_XK_DELAY
@@ -733,8 +748,13 @@ __global__ void __launch_bounds__(64 * kXkWaves)
                      xs[threadIdx.x >> 6]);
 }
 
-static int xk_wo_of(bool f32, int K)
+static int xk_wo_of(bool f32, int K, bool bnd = false)
 {
+    if (bnd) switch (K) {
+        case 2: return f32 ? xk_wo<float, 2, true>() : xk_wo<double, 2, true>();
+        case 3: return f32 ? xk_wo<float, 3, true>() : xk_wo<double, 3, true>();
+        default: return f32 ? xk_wo<float, 4, true>() : xk_wo<double, 4, true>();
+        }
     switch (K) {
     case 2: return f32 ? xk_wo<float, 2>() : xk_wo<double, 2>();
     case 3: return f32 ? xk_wo<float, 3>() : xk_wo<double, 3>();
@@ -746,9 +766,15 @@ static int xk_wo_of(bool f32, int K)
     }
 }
 
+static bool geo_bounded(const Geo &G)
+{
+    return G.bc[0] != BC_PERIODIC || G.bc[1] != BC_PERIODIC || G.bc[2] != BC_PERIODIC ||
+           G.bc[3] != BC_PERIODIC;
+}
+
 static int step2k_strips(const Geo &G, bool f32, int K)
 {
-    const int wo = xk_wo_of(f32, K);
+    const int wo = xk_wo_of(f32, K, geo_bounded(G));
     return (G.nx + wo - 1) / wo;
 }
 
@@ -759,26 +785,28 @@ int step2k_blocks(const Geo &G, bool f32, int K, int seg)
 }
 
 // Steps per launch at most on grids with non-periodic faces.  Measured at 4096^2
-// (inflow / Neumann / wall faces): FP64 K = 1 .. 5 -> 26, 42, 64, 74, 72 GLUPS,
-// FP32 -> 57, 70, 108, 116, 75; beyond K = 4 the kernel spills registers.  The
-// FP64 K = 6 and FP32 K = 8 instantiations also returned wrong values over whole
-// grids on the GPU (every face set, interior nodes included) with no cause found
-// in the source, so no instantiation above K = 4 is built.
+// (inflow / Neumann / wall faces), two rows in flight: FP64 K = 1 .. 5 -> 26, 42,
+// 64, 74, 72 GLUPS, FP32 -> 57, 70, 108, 116, 75; beyond K = 4 the kernel spills
+// registers.  In an earlier form of the kernel (level-1 face loads through
+// per-lane 64-bit addresses) the FP64 K = 6 and FP32 K = 8 instantiations also
+// returned wrong values over whole grids on the GPU (every face set, interior
+// nodes included) with no cause found in the source, so no instantiation above
+// K = 4 is built.
 constexpr int kXkMaxKBnd = 4;
+// Rows of level-n pulls in flight in the bounded kernel: one (at 4096^2 FP64 K = 4
+// 85 GLUPS against 74 with two; the smaller ring lets two wavefronts share a SIMD).
+#ifndef LBM_XKB_DEPTH
+#define LBM_XKB_DEPTH 1
+#endif
+constexpr int kXkbDepth = LBM_XKB_DEPTH;
 
 int step2k_max_k_bounded() { return kXkMaxKBnd; }
-
-static bool geo_bounded(const Geo &G)
-{
-    return G.bc[0] != BC_PERIODIC || G.bc[1] != BC_PERIODIC || G.bc[2] != BC_PERIODIC ||
-           G.bc[3] != BC_PERIODIC;
-}
 
 template <typename T, int KK>
 static hipError_t xkb_occupancy(int *n, int bs)
 {
     if constexpr (KK <= kXkMaxKBnd)
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_step2d_xkb<T, KK, kXkDepth>,
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_step2d_xkb<T, KK, kXkbDepth>,
                                                             bs, 0);
     else
         return hipErrorInvalidValue;
@@ -789,7 +817,7 @@ static hipError_t xkb_launch(dim3 grid, dim3 block, hipStream_t st, const T *src
                              const Geo &G, const Phys &P, int ns, int seg)
 {
     if constexpr (KK <= kXkMaxKBnd) {
-        hipLaunchKernelGGL((k_step2d_xkb<T, KK, kXkDepth>), grid, block, 0, st, src, dst, G, P,
+        hipLaunchKernelGGL((k_step2d_xkb<T, KK, kXkbDepth>), grid, block, 0, st, src, dst, G, P,
                            ns, seg);
         return hipSuccess;
     } else {
