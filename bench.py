@@ -42,6 +42,8 @@ def _parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-1d", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-faces", action="store_true",
+                    help="skip the forward run with inflow / Neumann / wall faces")
     ap.add_argument("--batched-steps", type=int, default=1000,
                     help="timed steps of the batched form (the manifest's run is 1000)")
     ap.add_argument("--block", type=int, default=0)
@@ -59,7 +61,14 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def time_forward(torch, n, storage, steps, warmup, block, npt, pad, fuse=1, keep_h=False):
+# Faces of the bounded forward run: the oblique shock's set (inflow left and top,
+# outflow right, wall bottom) around the radial dam break.
+FACES = ("inflow", "neumann", "wall", "inflow")
+FACES_INFLOW = {0: (1.0, 0.2, 0.0), 3: (1.0, 0.0, -0.2)}
+
+
+def time_forward(torch, n, storage, steps, warmup, block, npt, pad, fuse=1, keep_h=False,
+                 bc=("periodic",) * 4, inflow=None):
     """Forward steps of the headline workload; ``fuse`` = steps per launch asked
     for (0 = the library's choice; lbm_launch_info reports what runs).  With
     ``keep_h`` the final height field is returned under "h" (device tensor)."""
@@ -68,7 +77,7 @@ def time_forward(torch, n, storage, steps, warmup, block, npt, pad, fuse=1, keep
 
     c = W.radial_dam_break_2d(n, lam=6.0)
     S = Solver(2, n, n, lam=c.lam, s=c.s, h0=c.h0, qx0=c.qx0, qy0=c.qy0, storage=storage,
-               block=block, npt=npt, plane_pad=pad, fuse_steps=fuse)
+               block=block, npt=npt, plane_pad=pad, fuse_steps=fuse, bc=bc, inflow=inflow)
     info = S.launch_info()
     fuse = info["steps_per_launch"]
     S.step(warmup)
@@ -378,6 +387,12 @@ def main():
             log(f"[bench] forward {storage.upper()} {n}^2, one step per launch")
             forms["fp" + storage[1:] + "_one_step_per_launch"] = time_forward(
                 torch, n, storage, args.steps, args.warmup, *L[:3], 1)
+        if not args.quick and not args.no_faces:
+            # the same grid with inflow / Neumann / wall faces (library default launch)
+            log(f"[bench] forward {storage.upper()} {n}^2, faces {FACES}")
+            forms["fp" + storage[1:] + "_faces"] = time_forward(
+                torch, n, storage, args.steps, args.warmup, *L[:3], 0, bc=FACES,
+                inflow=FACES_INFLOW)
     if "fp64" in forms and "fp32" in forms:
         # FP32 storage against FP64 after the same steps (the FP64 path equals the
         # CPU FP64 oracle bit for bit in the parity tests): L1 relative error of h

@@ -138,6 +138,34 @@ def test_radial_4096_fused_launch_equals_single_steps(storage):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_faces_4096_fused_launch_equals_single_steps(storage):
+    """The headline grid with the bench's inflow / Neumann / wall / inflow faces:
+    40 steps as two-, three- and four-step launches (the library default there)
+    give bit for bit the state of 40 single-step launches."""
+    import torch
+
+    import bench
+
+    case = W.radial_dam_break_2d(4096, lam=6.0)
+    case.bc, case.inflow = bench.FACES, bench.FACES_INFLOW
+    A = gpu_solver(case, storage=storage, fuse_steps=1)
+    A.step(40)
+    a = A.planes().clone()
+    del A
+    for fuse in (2, 3, 0):
+        B = gpu_solver(case, storage=storage, fuse_steps=fuse)
+        k = B.launch_info()["steps_per_launch"]
+        assert k == (fuse or 4)
+        B.step(40)
+        same = bool(torch.equal(a, B.planes()))
+        say(f"[full] 4096^2 faces {storage}: {k} steps per launch == single steps bitwise: {same}")
+        assert same
+        del B
+    del a
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("s,storage", [(1.9, "f64"), (1.5, "f64"), (1.9, "f32")])
 def test_wall_reflection_2pow20_sampled_after_20000_steps(s, storage):
     """1D inflow toward a wall, 2^20 nodes, 20000 steps (the full run): nodes at
