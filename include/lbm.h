@@ -104,7 +104,7 @@ typedef struct {
     int fuse_steps;       /* steps per launch (temporal blocking; bitwise identical
                              to single steps): 0 = library default, else 1 .. 16.
                              2D all-periodic grids fuse at most 8 (larger values
-                             take 8; default 8 for FP64 and 6 for FP32 storage
+                             take 8; default 8 for both storages
                              when that launch fills at least a third of the
                              device, e.g. 1024^2 and larger, else 2 when the LDS
                              two-step launch has >= 1024 workgroups, else 1;

@@ -189,11 +189,11 @@ static const int kFuseSeg = LBM_FUSE_SEG;  // rows per workgroup segment of the 
 // queried (else chosen per grid at init, step2k_seg).
 static const int kXkSeg = LBM_XK_SEG;
 // Default steps per launch on all-periodic 2D grids (wave-strip kernel),
-// measured at 4096^2: FP64 8 (155 GLUPS; 4: 93, one step: 29), FP32 6 (204
-// GLUPS; 8: 190, the FP32 K = 8 kernel holds two wavefronts per SIMD, K = 6
-// three; one step: 61); at 1024^2 FP64 8 gives 86 GLUPS (one step: 25).
+// measured at 4096^2: FP64 8 (155-176 GLUPS; 4: 93, one step: 29); FP32 8 with
+// 256-lane strips (222-224 GLUPS; 6: 219-221; 64-lane strips K = 6: 208, K =
+// 8: 197; one step: 61); at 1024^2 FP64 8 gives 86 GLUPS (one step: 25).
 static const int kDefaultFuse2dF64 = 8;
-static const int kDefaultFuse2dF32 = 6;
+static const int kDefaultFuse2dF32 = 8;
 // With non-periodic faces the wave-strip kernel takes at most
 // step2k_max_k_bounded() (4) steps per launch, and 4 by default: at 4096^2
 // (inflow / Neumann / wall faces) FP64 85 GLUPS (one step: 26), FP32 122 (57).

@@ -197,7 +197,26 @@ __global__ void __launch_bounds__(kX2Threads)
 #ifndef LBM_XK_NT_F32
 #define LBM_XK_NT_F32 0
 #endif
-constexpr int kXkWaves = LBM_XK_WAVES;  // strips (wavefronts) per workgroup
+constexpr int kXkWaves = LBM_XK_WAVES;  // wavefronts per workgroup
+// Wide strips, per storage type: the all-periodic single-grid launch gives each
+// workgroup one strip of 64 x kXkWaves lanes (0: one 64-lane strip per
+// wavefront).  Wavefronts then meet inside a strip and exchange their edge
+// lanes' e1 / e3 planes through LDS, with one workgroup barrier per row; the
+// halo lanes recomputed per strip drop from 2 (K - 1) per 64 to 2 (K - 1) per
+// 64 x kXkWaves.  Measured at 4096^2, alternating runs on one device: FP32 K = 6
+// 208 GLUPS with 64-lane strips, 219-221 wide, K = 8 wide 222-224; FP64 no gain
+// (K = 8: 158-164 wide against 163-166, K = 7: 134-149 against 143).
+#ifndef LBM_XK_WIDE_F64
+#define LBM_XK_WIDE_F64 0
+#endif
+#ifndef LBM_XK_WIDE_F32
+#define LBM_XK_WIDE_F32 1
+#endif
+template <typename T>
+constexpr int xk_sw()
+{
+    return (sizeof(T) == 8 ? LBM_XK_WIDE_F64 : LBM_XK_WIDE_F32) ? kXkWaves : 1;
+}
 constexpr int kXkDepth = LBM_XK_DEPTH;  // rows of level-n pulls in flight
 
 // Workgroup b runs on XCD b % 8 (round-robin dispatch).  Give XCD x the
@@ -403,6 +422,35 @@ constexpr int xk_lds_levels()
     constexpr int L = sizeof(T) == 8 ? LBM_XK_LDS_LEVELS : LBM_XK_LDS_LEVELS_F32;
     return K >= LBM_XK_LDS_MIN_K ? (L < K - 1 ? L : K - 1) : 0;
 }
+// Elements per LDS row of an exchange level (wide strips: two edge slots).
+constexpr int xk_lds_width(int sw) { return sw > 1 ? 66 : 64; }
+// Intermediate levels exchanged through LDS rows on wide strips, at most:
+// FP64 6 (with 66-element rows, 4 wavefronts take 76 KiB and two workgroups
+// share a compute unit), FP32 7.
+#ifndef LBM_XK_WIDE_LDS_F64
+#define LBM_XK_WIDE_LDS_F64 6
+#endif
+#ifndef LBM_XK_WIDE_LDS_F32
+#define LBM_XK_WIDE_LDS_F32 7
+#endif
+template <typename T, int K, int SW>
+constexpr int xk_lds_levels_sw()
+{
+    constexpr int cap = sizeof(T) == 8 ? LBM_XK_WIDE_LDS_F64 : LBM_XK_WIDE_LDS_F32;
+    return SW > 1 ? (K - 1 < cap ? K - 1 : cap) : xk_lds_levels<T, K>();
+}
+// Wide strips: edge slots per wavefront of the register levels, and its junk area.
+template <typename T, int K, int SW>
+constexpr int xk_edge_slots()
+{
+    return (K - 1 - xk_lds_levels_sw<T, K, SW>()) * 6 * 2;
+}
+template <typename T, int K, int SW>
+constexpr int xk_wide_rows()
+{
+    return xk_lds_levels_sw<T, K, SW>() * 6 * xk_lds_width(SW) + 2 * xk_edge_slots<T, K, SW>() +
+           66;
+}
 // LDS elements per wavefront (at least one, so the array is never empty).
 template <typename T, int K>
 constexpr int xk_lds_elems()
@@ -416,19 +464,46 @@ constexpr int xk_lds_elems()
 // strip: a partially written segment would cost the DRAM a read-modify-write.
 // Grids with non-periodic faces (BND) keep at least K lanes after the last output
 // column: an x+ wall node takes its own e1 at level 1 from the next lane.
-template <typename T, int K, bool BND = false>
+// SW: wavefronts per strip (64 SW lanes).
+template <typename T, int K, bool BND = false, int SW = 1>
 constexpr int xk_wo()
 {
     constexpr int A = (sizeof(T) == 8 ? LBM_XK_ALIGN_F64 : LBM_XK_ALIGN_F32) / (int)sizeof(T);
-    constexpr int halo = 2 * (K - 1) + (BND ? 1 : 0);
-    return A > 1 ? (64 - halo) / A * A : 64 - halo;
+    constexpr int halo = 2 * (K - 1) + (BND ? 1 : 0), a = A > 1 ? A : 1;
+    return (64 * SW - halo) / a * a;
 }
 // Halo lanes before the first output column (>= K - 1 on both sides).
-template <typename T, int K, bool BND = false>
+template <typename T, int K, bool BND = false, int SW = 1>
 constexpr int xk_halo()
 {
-    return (64 - xk_wo<T, K, BND>()) / 2;
+    return (64 * SW - xk_wo<T, K, BND, SW>()) / 2;
 }
+
+// LDS exchange levels of a wavefront.  Each level has six rows (e1 planes c,
+// e3 planes 3 + c) of xk_lds_width(SW) elements; `row` is the element index of
+// the wavefront's first row in the workgroup's LDS array, and the other fields
+// are per-lane element offsets within a row: where the lane reads its e1 / e3
+// pull (from lane l - 1 / l + 1) and writes its own e1 / e3.
+//   One wavefront per strip: 64 columns, column l = lane l.
+//   Wide strips: an e1 row holds two edge slots (columns 0, 1: one per row
+//   parity) and lane l at column l + 2; an e3 row holds lane l at column l and
+//   two edge slots (64, 65).  Lane 63 writes its e1 into the next wavefront's
+//   edge slot and lane 0 its e3 into the previous one's (no lane of its own
+//   wavefront reads them); lane 0 / 63 read those slots.  The slots alternate
+//   with the row parity, and the workgroup meets one barrier per row, so a slot
+//   is never written while its previous value may still be read.
+//   Wide strips, levels exchanged in registers (cross-lane permutes): only the
+//   edge values go through LDS, in slots [level][e1 (c), e3 (3 + c)][parity] of
+//   each wavefront (er: read base); w1 / w3 point the edge lanes' stores at the
+//   neighbour's slots and every other lane's at a junk area of its own, so the
+//   stores need no branch.
+struct XkLds {
+    int row;
+    int r1, r3, w1, w3;
+    int er, ew1, ew3;
+    int w;  // wavefront within the strip
+};
+
 
 // One iteration j of the row loop.  cur: level-n pulls of this iteration's
 // level-1 row; nxt (the buffer consumed in the previous iteration): receives
@@ -452,17 +527,17 @@ constexpr int xk_halo()
 // (whose only reader is row 0's pull through the y- face) receives the face
 // value; on a Neumann y+ face the e2 slot of row ny - 1 (read only by row ny,
 // outside the grid) receives its own e4 planes, which row ny - 1 pulls back.
-template <typename T, int K, bool BND>
+template <typename T, int K, bool BND, int SW = 1>
 __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const Phys &P,
                                        int lane, const __amdgpu_buffer_rsrc_t *orsrc,
                                        unsigned ooff, const XkOff &onext, const T (&cur)[12],
                                        T (&nxt)[12], T (&em)[K - 1][3], T (&s1)[K - 1][3],
                                        T (&s3)[K - 1][3], T (&pend)[12], unsigned &pend_off,
-                                       T *__restrict__ xsw, const Geo &G, const XkBnd &B, int i,
+                                       T *__restrict__ lds, const Geo &G, const XkBnd &B, int i,
                                        int inext, int xm, int xw, int xp, bool bx0, bool bx1,
-                                       T (&ec)[K - 1][3])
+                                       T (&ec)[K - 1][3], const XkLds &X)
 {
-    constexpr int L = BND ? 0 : xk_lds_levels<T, K>();
+    constexpr int L = BND ? 0 : xk_lds_levels_sw<T, K, SW>();
     double v[12];
 #pragma unroll
     for (int pl = 0; pl < 12; ++pl) v[pl] = (double)cur[pl];
@@ -558,34 +633,52 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
             // (the wavefront executes in lockstep and its LDS operations in
             // order; the compiler barriers keep the reads before the writes and
             // the writes before the next row's reads)
-            T *row = xsw + (k - 1) * 6 * 64;
-            const int lm = (lane - 1) & 63, lp = (lane + 1) & 63;
+            // (the per-lane offsets are loop invariant and the row index a
+            // constant, so each access is one address register plus an
+            // immediate offset)
+            constexpr int RW = xk_lds_width(SW);
+            T *row = lds + X.row + (k - 1) * 6 * RW;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                o[4 * c + 0] = (double)row[c * 64 + lm];
+                o[4 * c + 0] = (double)row[c * RW + X.r1];
                 o[4 * c + 1] = (double)em[k - 1][c];
-                o[4 * c + 2] = (double)row[(3 + c) * 64 + lp];
+                o[4 * c + 2] = (double)row[(3 + c) * RW + X.r3];
                 o[4 * c + 3] = v[4 * c + 3];
                 em[k - 1][c] = (T)v[4 * c + 1];
             }
             __asm__ __volatile__("" ::: "memory");
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                row[c * 64 + lane] = (T)v[4 * c + 0];
-                row[(3 + c) * 64 + lane] = (T)v[4 * c + 2];
+                row[c * RW + X.w1] = (T)v[4 * c + 0];
+                row[(3 + c) * RW + X.w3] = (T)v[4 * c + 2];
             }
             __asm__ __volatile__("" ::: "memory");
         } else {
+            const bool el = SW > 1 && lane == 0 && X.w > 0;
+            const bool er = SW > 1 && lane == 63 && X.w < SW - 1;
+            const int kk = (k - 1 - L) * 12;  // this level's edge slots
+            if constexpr (SW > 1) __asm__ __volatile__("" ::: "memory");
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                o[4 * c + 0] = (double)s1[k - 1][c];
+                T a1 = s1[k - 1][c], a3 = s3[k - 1][c];
+                if constexpr (SW > 1) {
+                    const T t1 = lds[X.er + kk + 2 * c], t3 = lds[X.er + kk + 2 * (3 + c)];
+                    a1 = el ? t1 : a1;
+                    a3 = er ? t3 : a3;
+                }
+                o[4 * c + 0] = (double)a1;
                 o[4 * c + 1] = (double)em[k - 1][c];
-                o[4 * c + 2] = (double)s3[k - 1][c];
+                o[4 * c + 2] = (double)a3;
                 o[4 * c + 3] = v[4 * c + 3];
                 em[k - 1][c] = (T)v[4 * c + 1];
                 s1[k - 1][c] = xk_xch((T)v[4 * c + 0], lane, 1);
                 s3[k - 1][c] = xk_xch((T)v[4 * c + 2], lane, -1);
+                if constexpr (SW > 1) {
+                    lds[X.ew1 + kk + 2 * c] = (T)v[4 * c + 0];
+                    lds[X.ew3 + kk + 2 * (3 + c)] = (T)v[4 * c + 2];
+                }
             }
+            if constexpr (SW > 1) __asm__ __volatile__("" ::: "memory");
         }
         collide2d(o, P);
 #pragma unroll
@@ -611,20 +704,54 @@ constexpr int xk_gcd(int a, int b) { return b == 0 ? a : xk_gcd(b, a % b); }
 // unrolled blocks (the extra iterations store nothing).
 // One wavefront: column strip `strip` of the grid (G, P) in src / dst, output
 // rows [y0, y1).
-template <typename T, int K, int D, bool BND = false>
+// lds: the workgroup's LDS array; rows: its elements per wavefront (the
+// wavefront's rows start at w rows).  Wide strips (SW > 1): wavefront w of the
+// workgroup takes lanes [64 w, 64 w + 64) of the strip; every wavefront of the
+// workgroup runs the same rows and meets one barrier per row.
+template <typename T, int K, int D, bool BND = false, int SW = 1>
 __device__ __forceinline__ void xk_wave(const T *__restrict__ src, T *__restrict__ dst,
                                         const Geo &G, const Phys &P, int strip, int y0, int y1,
-                                        T *__restrict__ xsw)
+                                        T *__restrict__ lds, int rows = 0)
 {
-    constexpr int WO = xk_wo<T, K, BND>();  // output columns per strip
-    constexpr int H = xk_halo<T, K, BND>();
-    static_assert(H >= K - 1 && 64 - H - WO >= K - 1 + (BND ? 1 : 0), "halo lanes");
+    constexpr int WO = xk_wo<T, K, BND, SW>();  // output columns per strip
+    constexpr int H = xk_halo<T, K, BND, SW>();
+    static_assert(H >= K - 1 && 64 * SW - H - WO >= K - 1 + (BND ? 1 : 0), "halo lanes");
+    static_assert(SW == 1 || !BND, "wide strips: all-periodic grids only");
     constexpr int U = 2 * (D + 1) / xk_gcd(2, D + 1);
     const int nx = G.nx, ny = G.ny;
     const long ps = G.ps;
     const int lane = threadIdx.x & 63;
-    const int x0 = strip * WO;     // first output column
-    const int xc = x0 - H + lane;  // this lane's column, unwrapped
+    const int wv = SW > 1 ? (int)(threadIdx.x >> 6) : 0;  // wavefront within the strip
+    const int gl = 64 * wv + lane;                        // lane within the strip
+    const int x0 = strip * WO;                            // first output column
+    const int xc = x0 - H + gl;                           // this lane's column, unwrapped
+    // LDS offsets per row parity p (XkLds)
+    XkLds Lp[2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        Lp[p].row = wv * rows;
+        Lp[p].w = wv;
+        Lp[p].er = Lp[p].ew1 = Lp[p].ew3 = 0;
+        if constexpr (SW > 1) {
+            const bool el = lane == 0 && wv > 0, er = lane == 63 && wv < SW - 1;
+            Lp[p].r1 = el ? p : lane + 1;
+            Lp[p].w1 = er ? rows + p : lane + 2;
+            Lp[p].r3 = er ? 64 + p : lane + 1;
+            Lp[p].w3 = el ? 64 + p - rows : lane;
+            // edge slots of the register levels and the junk area (xk_wide_rows)
+            constexpr int lr = xk_lds_levels_sw<T, K, SW>() * 6 * xk_lds_width(SW);
+            constexpr int ne = xk_edge_slots<T, K, SW>();
+            const int junk = wv * rows + lr + ne + lane + p;
+            Lp[p].er = wv * rows + lr + p;
+            Lp[p].ew1 = er ? (wv + 1) * rows + lr + p : junk;
+            Lp[p].ew3 = el ? (wv - 1) * rows + lr + p : junk;
+        } else {
+            Lp[p].r1 = (lane - 1) & 63;
+            Lp[p].w1 = lane;
+            Lp[p].r3 = (lane + 1) & 63;
+            Lp[p].w3 = lane;
+        }
+    }
     XkBnd B{};
     bool bx0 = false, bx1 = false, clampx = false;
     if constexpr (BND) {
@@ -637,7 +764,7 @@ __device__ __forceinline__ void xk_wave(const T *__restrict__ src, T *__restrict
     const int xw = clampx ? min(max(xc, 0), nx - 1) : ((xc % nx) + nx) % nx;
     const int xm = clampx ? min(max(xc - 1, 0), nx - 1) : (xw == 0 ? nx - 1 : xw - 1);
     const int xp = clampx ? min(max(xc + 1, 0), nx - 1) : (xw == nx - 1 ? 0 : xw + 1);
-    const bool olane = lane >= H && lane < H + WO && xc < nx;
+    const bool olane = gl >= H && gl < H + WO && xc < nx;
     const int niter = (y1 - y0) + 2 * (K - 1);
     // Output row of iteration j is y0 - 2 (K - 1) + j, stored when it lies in
     // [y0, y1); byte offset of (row, xc) within a plane, or a dropped offset.
@@ -684,15 +811,27 @@ __device__ __forceinline__ void xk_wave(const T *__restrict__ src, T *__restrict
         for (int u = 0; u < U; ++u) {
             const int jj = j + u;
             const int orow = y0 - 2 * (K - 1) + jj;
+            // reads from the previous row's parity, writes to this row's
+            const XkLds X{Lp[0].row,        Lp[(u + 1) % 2].r1, Lp[(u + 1) % 2].r3,
+                          Lp[u % 2].w1,     Lp[u % 2].w3,       Lp[(u + 1) % 2].er,
+                          Lp[u % 2].ew1,    Lp[u % 2].ew3,      wv};
+            if constexpr (SW > 1) {
+                // every wavefront has written the previous row's edge values;
+                // this row's slots were last read one row ago
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+                __builtin_amdgcn_s_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+            }
             const unsigned ooff = (orow >= y0 && orow < y1)
                                       ? (unsigned)orow * ostep + lane_off
                                       : kXkDrop;
             rl = rl == ny - 1 ? 0 : rl + 1;
             ++il;
-            xk_row<T, K, BND>(src, ps, P, lane, orsrc, ooff,
+            xk_row<T, K, BND, SW>(src, ps, P, lane, orsrc, ooff,
                               xk_offsets<T>(rl, nx, ny, xm, xw, xp), buf[u % (D + 1)],
-                              buf[(u + D) % (D + 1)], e2[u % 2], s1, s3, pend, pend_off, xsw, G,
-                              B, y0 - (K - 1) + jj, il, xm, xw, xp, bx0, bx1, e2[(u + 1) % 2]);
+                              buf[(u + D) % (D + 1)], e2[u % 2], s1, s3, pend, pend_off, lds, G,
+                              B, y0 - (K - 1) + jj, il, xm, xw, xp, bx0, bx1, e2[(u + 1) % 2],
+                              X);
         }
     }
 #if LBM_XK_DELAY
@@ -706,14 +845,26 @@ __global__ void __launch_bounds__(64 * kXkWaves)
     k_step2d_xk(const T *__restrict__ src, T *__restrict__ dst, Geo G, Phys P, int nstrips,
                 int seg)
 {
-    __shared__ T xs[kXkWaves][xk_lds_elems<T, K>()];
-    const int ngroups = (nstrips + kXkWaves - 1) / kXkWaves;
     const int nseg = (G.ny + seg - 1) / seg;
-    const int tile = xk_tile(blockIdx.x, ngroups * nseg, LBM_XK_REMAP != 0);
-    const int strip = (tile % ngroups) * kXkWaves + (threadIdx.x >> 6);
-    if (strip >= nstrips) return;  // whole wavefront; nothing here waits on others
-    const int y0 = (tile / ngroups) * seg;
-    xk_wave<T, K, D>(src, dst, G, P, strip, y0, min(y0 + seg, G.ny), xs[threadIdx.x >> 6]);
+    if constexpr (xk_sw<T>() > 1) {
+        // one strip per workgroup; every wavefront runs to the end (barriers)
+        constexpr int SW = xk_sw<T>();
+        constexpr int rows = xk_wide_rows<T, K, SW>();
+        __shared__ T lds[kXkWaves * rows];
+        const int tile = xk_tile(blockIdx.x, nstrips * nseg, LBM_XK_REMAP != 0);
+        const int strip = tile % nstrips;
+        const int y0 = (tile / nstrips) * seg;
+        xk_wave<T, K, D, false, SW>(src, dst, G, P, strip, y0, min(y0 + seg, G.ny), lds,
+                                       rows);
+    } else {
+        __shared__ T xs[kXkWaves][xk_lds_elems<T, K>()];
+        const int ngroups = (nstrips + kXkWaves - 1) / kXkWaves;
+        const int tile = xk_tile(blockIdx.x, ngroups * nseg, LBM_XK_REMAP != 0);
+        const int strip = (tile % ngroups) * kXkWaves + (threadIdx.x >> 6);
+        if (strip >= nstrips) return;  // whole wavefront; nothing here waits on others
+        const int y0 = (tile / ngroups) * seg;
+        xk_wave<T, K, D>(src, dst, G, P, strip, y0, min(y0 + seg, G.ny), xs[threadIdx.x >> 6]);
+    }
 }
 
 // Grids with non-periodic faces (the one-step kernel's face rules); K at most
@@ -748,8 +899,26 @@ __global__ void __launch_bounds__(64 * kXkWaves)
                      xs[threadIdx.x >> 6]);
 }
 
-static int xk_wo_of(bool f32, int K, bool bnd = false)
+// Output columns per strip: bnd -- the bounded kernel; else the all-periodic
+// kernel with sw wavefronts per strip (1, or xk_sw of the storage type).
+static int xk_wo_of(bool f32, int K, bool bnd = false, int sw = 1)
 {
+    if (sw > 1 && !bnd) switch (K) {
+        case 2: return f32 ? xk_wo<float, 2, false, xk_sw<float>()>()
+                       : xk_wo<double, 2, false, xk_sw<double>()>();
+        case 3: return f32 ? xk_wo<float, 3, false, xk_sw<float>()>()
+                       : xk_wo<double, 3, false, xk_sw<double>()>();
+        case 4: return f32 ? xk_wo<float, 4, false, xk_sw<float>()>()
+                       : xk_wo<double, 4, false, xk_sw<double>()>();
+        case 5: return f32 ? xk_wo<float, 5, false, xk_sw<float>()>()
+                       : xk_wo<double, 5, false, xk_sw<double>()>();
+        case 6: return f32 ? xk_wo<float, 6, false, xk_sw<float>()>()
+                       : xk_wo<double, 6, false, xk_sw<double>()>();
+        case 7: return f32 ? xk_wo<float, 7, false, xk_sw<float>()>()
+                       : xk_wo<double, 7, false, xk_sw<double>()>();
+        default: return f32 ? xk_wo<float, 8, false, xk_sw<float>()>()
+                       : xk_wo<double, 8, false, xk_sw<double>()>();
+        }
     if (bnd) switch (K) {
         case 2: return f32 ? xk_wo<float, 2, true>() : xk_wo<double, 2, true>();
         case 3: return f32 ? xk_wo<float, 3, true>() : xk_wo<double, 3, true>();
@@ -774,13 +943,23 @@ static bool geo_bounded(const Geo &G)
 
 static int step2k_strips(const Geo &G, bool f32, int K)
 {
-    const int wo = xk_wo_of(f32, K, geo_bounded(G));
+    const bool bnd = geo_bounded(G);
+    const int sw = f32 ? xk_sw<float>() : xk_sw<double>();
+    const int wo = xk_wo_of(f32, K, bnd, bnd ? 1 : sw);
     return (G.nx + wo - 1) / wo;
+}
+
+// Workgroups across the grid: one per wide strip, else one per kXkWaves strips.
+static int step2k_groups(const Geo &G, bool f32, int K)
+{
+    const int ns = step2k_strips(G, f32, K);
+    const int sw = f32 ? xk_sw<float>() : xk_sw<double>();
+    return sw > 1 && !geo_bounded(G) ? ns : (ns + kXkWaves - 1) / kXkWaves;
 }
 
 int step2k_blocks(const Geo &G, bool f32, int K, int seg)
 {
-    const int ngroups = (step2k_strips(G, f32, K) + kXkWaves - 1) / kXkWaves;
+    const int ngroups = step2k_groups(G, f32, K);
     return ngroups * ((G.ny + seg - 1) / seg);
 }
 
@@ -878,7 +1057,7 @@ int step2k_seg(const Geo &G, bool f32, int K, int min_seg, bool *full, long *slo
     const long slots = (long)ncu * xk_per_cu(f32, K, geo_bounded(G));
     if (slots_out) *slots_out = slots;
     if (slots <= 0) return 0;
-    const long ngroups = (step2k_strips(G, f32, K) + kXkWaves - 1) / kXkWaves;
+    const long ngroups = step2k_groups(G, f32, K);
     int best = 0;
     double best_cost = 0.0;
     bool best_full = false;
