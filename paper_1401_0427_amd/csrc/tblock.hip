@@ -445,6 +445,9 @@ constexpr int xk_edge_slots()
 {
     return (K - 1 - xk_lds_levels_sw<T, K, SW>()) * 6 * 2;
 }
+// LDS elements per wavefront on wide strips: the exchange-level rows, the edge
+// slots of the register levels, and the junk area (as large as the slots plus
+// one element per lane and parity).
 template <typename T, int K, int SW>
 constexpr int xk_wide_rows()
 {

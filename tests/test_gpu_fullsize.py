@@ -296,31 +296,33 @@ def _smooth_2d(n, seed):
     return W.Case(2, n, n, 6.0, 1.8, 0, h0=h, qx0=qx, qy0=qy, name=f"smooth2d_{n}")
 
 
-def test_largest_2d_grid_sampled_nodes_match_oracle():
-    """The largest square grid the ABI accepts (11585^2 = 1.34e8 nodes, FP64:
+@pytest.mark.parametrize("storage,strip", [("f64", 48), ("f32", 242)])
+def test_largest_2d_grid_sampled_nodes_match_oracle(storage, strip):
+    """The largest square grid the ABI accepts (11585^2 = 1.34e8 nodes; FP64:
     12.9 GB per state buffer, 1.07 GB per plane -- byte offsets within a plane
     reach 2^30): 16 steps as two 8-step launches of the default plan, sampled
-    nodes at the grid's ends, strip and segment edges against the oracle."""
+    nodes at the grid's ends, strip (48 FP64 output columns, 242 FP32) and
+    segment edges against the oracle (FP32 storage: relative error <= 1e-5)."""
     import torch
 
     n, steps = 11585, 16
     case = _smooth_2d(n, seed=3)
-    S = gpu_solver(case, storage="f64")
+    S = gpu_solver(case, storage=storage)
     plan = S.launch_info()
-    say(f"[max 2D] {n}^2 FP64, plan {plan}")
+    say(f"[max 2D] {n}^2 {storage}, plan {plan}")
     assert plan["steps_per_launch"] == 8
     S.step(steps)
     planes = S.planes()
     seg = plan["segment_rows"]
-    samples = [(0, 0), (n - 1, n - 1), (n - 1, 0), (0, n - 1), (47, seg - 1), (48, seg),
-               (n // 2, n // 2), (n - 2, n - 3), (5791, n - 1), (n - 1, 7000)]
+    samples = [(0, 0), (n - 1, n - 1), (n - 1, 0), (0, n - 1), (strip - 1, seg - 1),
+               (strip, seg), (n // 2, n // 2), (n - 2, n - 3), (5791, n - 1), (n - 1, 7000)]
     worst = 0.0
     for (x, y) in samples:
-        got = planes[:, y, x].cpu().numpy()
+        got = planes[:, y, x].double().cpu().numpy()
         ref = _oracle_centre_2d(case, x, y, steps)
         worst = max(worst, np.abs(got - ref).max() / np.abs(ref).max())
     say(f"  worst sampled relative error {worst:.3e}")
-    assert worst <= 1e-12
+    assert worst <= (1e-12 if storage == "f64" else 1e-5)
     del S, planes
     torch.cuda.empty_cache()
 
