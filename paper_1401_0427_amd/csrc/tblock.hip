@@ -159,8 +159,12 @@ __global__ void __launch_bounds__(kX2Threads)
 #ifndef LBM_XK_REMAP
 #define LBM_XK_REMAP 1
 #endif
+// Rows of level-n pulls in flight ahead of the row being computed.  Measured at
+// 4096^2, alternating runs on one device: FP64 K = 8 174-176 GLUPS with one row,
+// 171-173 with two; FP32 (256-lane strips, K = 8) 223 either way, with 154
+// instead of 178 registers.
 #ifndef LBM_XK_DEPTH
-#define LBM_XK_DEPTH 2
+#define LBM_XK_DEPTH 1
 #endif
 #ifndef LBM_XK_DELAY
 #define LBM_XK_DELAY 1
@@ -218,6 +222,12 @@ constexpr int xk_sw()
     return (sizeof(T) == 8 ? LBM_XK_WIDE_F64 : LBM_XK_WIDE_F32) ? kXkWaves : 1;
 }
 constexpr int kXkDepth = LBM_XK_DEPTH;  // rows of level-n pulls in flight
+// The same for the batched launch: two rows (the 256-instance manifest, FP32,
+// K = 8: 164-172 GLUPS, with one row 155).
+#ifndef LBM_XK_BATCH_DEPTH
+#define LBM_XK_BATCH_DEPTH 2
+#endif
+constexpr int kXkBatchDepth = LBM_XK_BATCH_DEPTH;
 
 // Workgroup b runs on XCD b % 8 (round-robin dispatch).  Give XCD x the
 // contiguous tile range [x q + min(x, r), ...) of q + (x < r) tiles (q, r =
@@ -1279,9 +1289,9 @@ int batch_xk_per_cu(bool f32, int K)
 #define LBM_BXK_OCC(KK)                                                                       \
     case KK:                                                                                  \
         e = f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                               \
-                      &n, k_batch_xk<float, KK, kXkDepth>, bs, 0)                             \
+                      &n, k_batch_xk<float, KK, kXkBatchDepth>, bs, 0)                        \
                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(                               \
-                      &n, k_batch_xk<double, KK, kXkDepth>, bs, 0);                           \
+                      &n, k_batch_xk<double, KK, kXkBatchDepth>, bs, 0);                      \
         break;
     switch (K) {
         LBM_BXK_OCC(2)
@@ -1306,10 +1316,10 @@ hipError_t launch_batch_xk(bool f32, int K, const InstDev *inst, const XkTileDev
 #define LBM_BXK_CASE(KK)                                                                      \
     case KK:                                                                                  \
         if (f32)                                                                              \
-            hipLaunchKernelGGL((k_batch_xk<float, KK, kXkDepth>), grid, block, 0, st, inst,   \
+            hipLaunchKernelGGL((k_batch_xk<float, KK, kXkBatchDepth>), grid, block, 0, st, inst, \
                                tiles, ntiles, (const float *)src, (float *)dst);              \
         else                                                                                  \
-            hipLaunchKernelGGL((k_batch_xk<double, KK, kXkDepth>), grid, block, 0, st, inst,  \
+            hipLaunchKernelGGL((k_batch_xk<double, KK, kXkBatchDepth>), grid, block, 0, st, inst, \
                                tiles, ntiles, (const double *)src, (double *)dst);            \
         break;
     switch (K) {
