@@ -104,9 +104,11 @@ typedef struct {
     int fuse_steps;       /* steps per launch (temporal blocking; bitwise identical
                              to single steps): 0 = library default, else 1 .. 16.
                              2D all-periodic grids fuse at most 8 (larger values
-                             take 8; default 8 for both storages
-                             when that launch fills at least a third of the
-                             device, e.g. 1024^2 and larger, else 2 when the LDS
+                             take 8; default 8 -- FP32: 6 unless the 8-step
+                             launch has three workgroups per resident slot,
+                             e.g. below 3072^2 -- when that launch fills at least
+                             a third of the device, e.g. 1024^2 and larger, else
+                             2 when the LDS
                              two-step launch has >= 1024 workgroups, else 1;
                              planes of 2 GiB or more take 1); 2D grids with
                              Neumann, wall or inflow faces at most 4 (default 4

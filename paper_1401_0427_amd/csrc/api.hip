@@ -188,12 +188,15 @@ static const int kFuseSeg = LBM_FUSE_SEG;  // rows per workgroup segment of the 
 // Rows per wavefront segment of the wave-strip launch when the device cannot be
 // queried (else chosen per grid at init, step2k_seg).
 static const int kXkSeg = LBM_XK_SEG;
-// Default steps per launch on all-periodic 2D grids (wave-strip kernel),
-// measured at 4096^2: FP64 8 (155-176 GLUPS; 4: 93, one step: 29); FP32 8 with
-// 256-lane strips (222-224 GLUPS; 6: 219-221; 64-lane strips K = 6: 208, K =
-// 8: 197; one step: 61); at 1024^2 FP64 8 gives 86 GLUPS (one step: 25).
+// Default steps per launch on all-periodic 2D grids (wave-strip kernel).
+// FP64: 8 (GLUPS at 1024^2 / 2048^2 / 3072^2 / 4096^2 for K = 6, 7, 8: 75, 81,
+// 79 / 119, 134, 136 / 136, 155, 167 / 139, 160, 176; one step at 4096^2: 29).
+// FP32 (256-lane strips): 8 on grids whose 8-step launch has at least three
+// workgroups per resident slot, else 6 (K = 6, 8: 77, 70 / 151, 144 / 192, 193 /
+// 217, 224; one step at 4096^2: 61).
 static const int kDefaultFuse2dF64 = 8;
 static const int kDefaultFuse2dF32 = 8;
+static const int kDefaultFuse2dF32Small = 6;
 // With non-periodic faces the wave-strip kernel takes at most
 // step2k_max_k_bounded() (4) steps per launch, and 4 by default: at 4096^2
 // (inflow / Neumann / wall faces) FP64 85 GLUPS (one step: 26), FP32 122 (57).
@@ -311,8 +314,14 @@ extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0
                     if (c->xk_seg <= 0) c->xk_seg = kXkSeg;
                 }
             } else {
-                const int kd = !allper ? kDefaultFuse2dBounded
-                               : c->f32 ? kDefaultFuse2dF32 : kDefaultFuse2dF64;
+                int kd = !allper ? kDefaultFuse2dBounded
+                         : c->f32 ? kDefaultFuse2dF32 : kDefaultFuse2dF64;
+                if (allper && c->f32) {
+                    long s8 = 0;
+                    (void)step2k_seg(c->G, true, kDefaultFuse2dF32, kXkMinSeg, nullptr, &s8);
+                    if (s8 > 0 && step2k_blocks(c->G, true, kDefaultFuse2dF32, kXkMinSeg) < 3 * s8)
+                        kd = kDefaultFuse2dF32Small;
+                }
                 bool full = false;
                 long slots = 0;
                 const int seg = step2k_seg(c->G, c->f32, kd, kXkMinSeg, &full, &slots);

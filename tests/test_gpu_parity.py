@@ -316,7 +316,8 @@ def test_fused_1d_launch_equals_single_steps(storage, fuse, n, bc, inflow, steps
 
 def test_default_launch_plans():
     """lbm_launch_info reports the plan chosen at init: the wave-strip multi-step
-    launch on grids it can fill (8 steps per launch), with a segment length and
+    launch on grids it can fill (8 steps per launch; FP32 6 on grids below about
+    three workgroups per resident slot, such as 1024^2), with a segment length and
     the resident workgroups it was chosen against; one step per launch on a
     small FP32 grid; 16 steps per launch in 1D; 4 steps with non-periodic 2D
     faces; an explicit request is honoured up to 8 steps (4 with non-periodic
@@ -325,7 +326,9 @@ def test_default_launch_plans():
     assert big64["steps_per_launch"] == 8 and big64["segment_rows"] >= 16
     assert big64["resident_blocks"] > 0
     big32 = gpu_solver(smooth_random_2d(1024, 1024, seed=8), storage="f32").launch_info()
-    assert big32["steps_per_launch"] == 8 and big32["segment_rows"] >= 16
+    assert big32["steps_per_launch"] == 6 and big32["segment_rows"] >= 16
+    huge32 = gpu_solver(smooth_random_2d(4096, 4096, seed=8), storage="f32").launch_info()
+    assert huge32["steps_per_launch"] == 8
     small32 = gpu_solver(smooth_random_2d(256, 256, seed=8), storage="f32").launch_info()
     assert small32["steps_per_launch"] == 1
     one_d = gpu_solver(W.dam_break_1d(1000)).launch_info()
