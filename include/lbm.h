@@ -241,15 +241,17 @@ typedef struct {
                                 are ignored;
                              3: fused -- fuse_steps steps per launch over all
                                 instances (temporal blocking, bitwise identical to
-                                single steps): the 2D instances (periodic faces
-                                only; others: LBM_EINVAL) as tiles of the
-                                wave-strip multi-step kernel, the 1D instances as
+                                single steps): the 2D instances as tiles of the
+                                wave-strip multi-step kernels (with any 2D
+                                instance that has Neumann, wall or inflow faces,
+                                at most 4 steps per launch for the whole batch),
+                                the 1D instances as
                                 1024-node tiles of the 1D multi-step kernel; graph
                                 chunks as in mode 2; steps that do not fill a launch
                                 run as flat single steps.  block, tile_nodes, grid
                                 and pass_nodes are ignored. */
     int fuse_steps;       /* mode 3: steps per launch, 2 .. 8 (0 = 6 for FP32, 8 for
-                             FP64 storage) */
+                             FP64 storage; 1 is rejected) */
 } lbm_batch_tuning;
 
 /* Assign state_offset / node_offset to n instances (in place) for the given

@@ -490,8 +490,9 @@ struct lbm_batch {
     int grid;
     // fused mode: K steps per launch pair (2D wave-strip tiles + 1D tiles)
     XkTileDev *d_xtiles;
+    XkTileDev *d_xbtiles;  // tiles of 2D instances with non-periodic faces
     K1TileDev *d_ktiles;
-    int nxtiles, nktiles;
+    int nxtiles, nxbtiles, nktiles;
     int fuse;      // steps per launch
     int xk_seg;    // rows per 2D segment
     long chunk;    // steps per captured graph (flat and fused modes)
@@ -550,6 +551,7 @@ extern "C" void lbm_batch_destroy(lbm_batch *b)
     (void)hipFree(b->d_ghost);
     (void)hipFree(b->d_bar);
     (void)hipFree(b->d_xtiles);
+    (void)hipFree(b->d_xbtiles);
     (void)hipFree(b->d_ktiles);
     delete b;
 }
@@ -559,6 +561,12 @@ extern "C" void lbm_batch_destroy(lbm_batch *b)
 // rounds of the resident slots and each wavefront runs seg + 2 (K - 1) row
 // iterations, so minimise ceil(blocks / slots) * (seg + 2 (K - 1)), a partly
 // filled single round counting proportionally longer.
+static bool inst_bounded(const lbm_instance &I)
+{
+    return I.lattice == LBM_D2Q4x3 &&
+           !(I.bc[0] == 0 && I.bc[1] == 0 && I.bc[2] == 0 && I.bc[3] == 0);
+}
+
 static int fused_seg(bool f32, int K, const std::vector<lbm_instance> &inst)
 {
     int dev = 0, ncu = 0;
@@ -572,13 +580,15 @@ static int fused_seg(bool f32, int K, const std::vector<lbm_instance> &inst)
     if (maxny == 0) return 16;
     if (slots <= 0) return std::min(maxny, 160);
     const int wo = batch_xk_out(f32, K), w = batch_xk_waves();
+    const int wob = inst.size() && K <= step2k_max_k_bounded() ? batch_xkb_out(f32, K) : wo;
     int best = 0;
     double best_cost = 0.0;
     for (int seg = 16; seg <= maxny; ++seg) {
         long blocks = 0;
         for (const lbm_instance &I : inst) {
             if (I.lattice != LBM_D2Q4x3) continue;
-            const long groups = ((I.nx + wo - 1) / wo + w - 1) / w;
+            const int o = inst_bounded(I) ? wob : wo;
+            const long groups = ((I.nx + o - 1) / o + w - 1) / w;
             blocks += groups * ((I.ny + seg - 1) / seg);
         }
         const long rounds = (blocks + slots - 1) / slots;
@@ -625,16 +635,11 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
         return bfail(LBM_EINVAL, "tuning.mode must be 0 (dataflow), 1 (step-synchronous), 2 "
                                  "(flat) or 3 (fused)");
     if (tune.mode == 3) {
-        if (tune.fuse_steps < 0 || tune.fuse_steps > 8)
-            return bfail(LBM_EINVAL, "tuning.fuse_steps must be in 0 .. 8 (got %d)",
+        if (tune.fuse_steps < 0 || tune.fuse_steps == 1 || tune.fuse_steps > 8)
+            return bfail(LBM_EINVAL, "tuning.fuse_steps must be 0 or in 2 .. 8 (got %d)",
                          tune.fuse_steps);
         for (int i = 0; i < n; ++i) {
             const lbm_instance &I = inst[i];
-            if (I.lattice == LBM_D2Q4x3 &&
-                !(I.bc[0] == 0 && I.bc[1] == 0 && I.bc[2] == 0 && I.bc[3] == 0))
-                return bfail(LBM_EINVAL,
-                             "instance %d: the fused mode (3) runs 2D instances with periodic "
-                             "faces only (use mode 2 or 0)", i);
             if ((long)I.nx * I.ny * (storage == LBM_F32 ? 4 : 8) >= (1L << 31))
                 return bfail(LBM_EINVAL, "instance %d: planes of 2 GiB or more (mode 3)", i);
         }
@@ -738,33 +743,45 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
         return bfail(LBM_EINVAL, "too many units for one launch: raise tuning.block");
     }
     b->nunits = (int)hu.size();
-    // fused mode: tile tables of the 2D wave-strip and 1D multi-step launches
-    std::vector<XkTileDev> hx;
+    // fused mode: tile tables of the 2D wave-strip launches (all-periodic instances,
+    // and instances with other faces) and of the 1D multi-step launch.  With any
+    // 2D instance of the second kind the whole batch takes at most
+    // step2k_max_k_bounded() steps per launch.
+    std::vector<XkTileDev> hx, hxb;
     std::vector<K1TileDev> hk;
     b->chunk = 32;
     if (tune.mode == 3) {
-        const int K = tune.fuse_steps ? tune.fuse_steps : (b->f32 ? 6 : 8);
+        int K = tune.fuse_steps ? tune.fuse_steps : (b->f32 ? 6 : 8);
+        bool anyb = false;
+        for (int i = 0; i < n; ++i) anyb = anyb || inst_bounded(inst[i]);
+        if (anyb && K > step2k_max_k_bounded()) K = step2k_max_k_bounded();
         b->fuse = K;
         b->chunk = 2L * K * ((32 + 2 * K - 1) / (2 * K));
         b->xk_seg = fused_seg(b->f32, K, inst);
         const int wo = batch_xk_out(b->f32, K), w = batch_xk_waves(), n1 = batch_1k_out(K);
+        const int wob = anyb ? batch_xkb_out(b->f32, K) : wo;
         for (int i = 0; i < n; ++i) {
             const lbm_instance &I = inst[i];
             if (I.lattice == LBM_D1Q2x2) {
                 for (int ob = 0; ob < I.nx; ob += n1) hk.push_back(K1TileDev{i, ob});
                 continue;
             }
-            const int ns = (I.nx + wo - 1) / wo;
+            const bool bnd = inst_bounded(I);
+            const int o = bnd ? wob : wo;
+            const int ns = (I.nx + o - 1) / o;
             for (int y0 = 0; y0 < I.ny; y0 += b->xk_seg)
                 for (int s0 = 0; s0 < ns; s0 += w)
-                    hx.push_back(XkTileDev{i, s0, ns, y0, std::min(I.ny, y0 + b->xk_seg)});
+                    (bnd ? hxb : hx)
+                        .push_back(XkTileDev{i, s0, ns, y0, std::min(I.ny, y0 + b->xk_seg)});
         }
-        if (hx.size() > (size_t)INT32_MAX || hk.size() > (size_t)INT32_MAX) {
+        if (hx.size() > (size_t)INT32_MAX || hxb.size() > (size_t)INT32_MAX ||
+            hk.size() > (size_t)INT32_MAX) {
             lbm_batch_destroy(b);
             return bfail(LBM_EINVAL, "too many tiles for one launch");
         }
     }
     b->nxtiles = (int)hx.size();
+    b->nxbtiles = (int)hxb.size();
     b->nktiles = (int)hk.size();
 
     hipError_t e;
@@ -778,10 +795,14 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
         (e = hipMalloc(&b->d_bar, sizeof(unsigned))) != hipSuccess ||
         (e = hipMalloc(&b->d_xtiles, sizeof(XkTileDev) * std::max<size_t>(1, hx.size()))) !=
             hipSuccess ||
+        (e = hipMalloc(&b->d_xbtiles, sizeof(XkTileDev) * std::max<size_t>(1, hxb.size()))) !=
+            hipSuccess ||
         (e = hipMalloc(&b->d_ktiles, sizeof(K1TileDev) * std::max<size_t>(1, hk.size()))) !=
             hipSuccess ||
         (!hx.empty() && (e = hipMemcpy(b->d_xtiles, hx.data(), sizeof(XkTileDev) * hx.size(),
                                        hipMemcpyHostToDevice)) != hipSuccess) ||
+        (!hxb.empty() && (e = hipMemcpy(b->d_xbtiles, hxb.data(), sizeof(XkTileDev) * hxb.size(),
+                                        hipMemcpyHostToDevice)) != hipSuccess) ||
         (!hk.empty() && (e = hipMemcpy(b->d_ktiles, hk.data(), sizeof(K1TileDev) * hk.size(),
                                        hipMemcpyHostToDevice)) != hipSuccess) ||
         (e = hipMemcpy(b->d_units, hu.data(), sizeof(UnitDev) * hu.size(),
@@ -822,7 +843,7 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
     if (ncu <= 0) ncu = 256;
     if (per_cu <= 0) per_cu = 1;
     b->grid = tune.mode == 2 ? b->nunits
-              : tune.mode == 3 ? b->nxtiles + b->nktiles
+              : tune.mode == 3 ? b->nxtiles + b->nxbtiles + b->nktiles
                                : (tune.grid > 0 ? tune.grid : ncu * per_cu);
     *out = b;
     return LBM_OK;
@@ -915,13 +936,17 @@ static void launch_flat(lbm_batch *b, int cur, hipStream_t st)
 }
 
 // K steps of every instance from buffer cur into the other: the 2D wave-strip
-// tiles, then the 1D tiles (independent instances; one ordered pair of launches).
+// tiles (all-periodic instances, then those with other faces), then the 1D tiles
+// (independent instances; one ordered sequence of launches).
 static hipError_t launch_fused(lbm_batch *b, int cur, hipStream_t st)
 {
     const void *src = b->buf[cur];
     void *dst = b->buf[cur ^ 1];
     hipError_t e = launch_batch_xk(b->f32, b->fuse, b->d_inst, b->d_xtiles, b->nxtiles, src, dst,
                                    st);
+    if (e == hipSuccess)
+        e = launch_batch_xkb(b->f32, b->fuse, b->d_inst, b->d_xbtiles, b->nxbtiles, src, dst,
+                             st);
     if (e == hipSuccess)
         e = launch_batch_1k(b->f32, b->fuse, b->d_inst, b->d_ktiles, b->nktiles, src, dst, st);
     return e;
@@ -1060,7 +1085,7 @@ extern "C" int lbm_batch_info(lbm_batch *b, int *ntiles, int *grid)
     if (!b) return bfail(LBM_ESTATE, "null batch");
     if (ntiles)
         *ntiles = b->tune.mode == 0 ? b->ntiles
-                  : b->tune.mode == 3 ? b->nxtiles + b->nktiles
+                  : b->tune.mode == 3 ? b->nxtiles + b->nxbtiles + b->nktiles
                                       : b->nunits;
     if (grid) *grid = b->grid;
     return LBM_OK;

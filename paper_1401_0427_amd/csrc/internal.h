@@ -82,12 +82,15 @@ int step2k_seg(const Geo &G, bool f32, int K, int min_seg, bool *full, long *slo
 int step2k_max_k_bounded();  // steps per launch at most with non-periodic faces
 
 // Batched multi-step launches (tblock.hip).
-int batch_xk_out(bool f32, int K);  // output columns per strip
+int batch_xk_out(bool f32, int K);   // output columns per strip
+int batch_xkb_out(bool f32, int K);  // the same, instances with non-periodic faces
 int batch_1k_out(int K);            // output nodes per 1D tile
 int batch_xk_waves();               // strips per workgroup
 int batch_xk_per_cu(bool f32, int K);
 hipError_t launch_batch_xk(bool f32, int K, const InstDev *inst, const XkTileDev *tiles,
                            int ntiles, const void *src, void *dst, hipStream_t st);
+hipError_t launch_batch_xkb(bool f32, int K, const InstDev *inst, const XkTileDev *tiles,
+                            int ntiles, const void *src, void *dst, hipStream_t st);
 hipError_t launch_batch_1k(bool f32, int K, const InstDev *inst, const K1TileDev *tiles,
                            int ntiles, const void *src, void *dst, hipStream_t st);
 hipError_t launch_step2k(bool f32, const void *src, void *dst, const Geo &G, const Phys &P,

@@ -914,6 +914,20 @@ __global__ void __launch_bounds__(64 * kXkWaves)
 
 // Output columns per strip: bnd -- the bounded kernel; else the all-periodic
 // kernel with sw wavefronts per strip (1, or xk_sw of the storage type).
+// Batched form, 2D instances with non-periodic faces (the bounded kernel; tiles
+// of its strip geometry, K at most kXkMaxKBnd).
+template <typename T, int K, int D>
+__global__ void __launch_bounds__(64 * kXkWaves)
+    k_batch_xkb(const InstDev *__restrict__ inst, const XkTileDev *__restrict__ tiles,
+                int ntiles, const T *__restrict__ src, T *__restrict__ dst)
+{
+    const XkTileDev td = tiles[xk_tile(blockIdx.x, ntiles, LBM_XK_REMAP != 0)];
+    const InstDev &I = inst[td.inst];
+    const int strip = td.strip0 + (int)(threadIdx.x >> 6);
+    if (strip >= td.nstrips) return;
+    xk_wave<T, K, D, true>(src + I.off, dst + I.off, I.G, I.P, strip, td.y0, td.y1, nullptr);
+}
+
 static int xk_wo_of(bool f32, int K, bool bnd = false, int sw = 1)
 {
     if (sw > 1 && !bnd) switch (K) {
@@ -1278,6 +1292,7 @@ hipError_t launch_step2x(bool f32, const void *src, void *dst, const Geo &G, con
 
 // ---- batched launchers -----------------------------------------------------------------
 int batch_xk_out(bool f32, int K) { return xk_wo_of(f32, K); }
+int batch_xkb_out(bool f32, int K) { return xk_wo_of(f32, K, true); }
 int batch_1k_out(int K) { return kK1Threads - 2 * K; }
 int batch_xk_waves() { return kXkWaves; }
 
@@ -1334,6 +1349,41 @@ hipError_t launch_batch_xk(bool f32, int K, const InstDev *inst, const XkTileDev
         return hipErrorInvalidValue;
     }
 #undef LBM_BXK_CASE
+    return hipGetLastError();
+}
+
+template <typename T, int KK>
+static void bxkb_launch(dim3 grid, dim3 block, hipStream_t st, const InstDev *inst,
+                        const XkTileDev *tiles, int ntiles, const T *src, T *dst)
+{
+    if constexpr (KK <= kXkMaxKBnd)
+        hipLaunchKernelGGL((k_batch_xkb<T, KK, kXkbDepth>), grid, block, 0, st, inst, tiles,
+                           ntiles, src, dst);
+}
+
+hipError_t launch_batch_xkb(bool f32, int K, const InstDev *inst, const XkTileDev *tiles,
+                            int ntiles, const void *src, void *dst, hipStream_t st)
+{
+    if (ntiles <= 0) return hipSuccess;
+    if (K < 2 || K > kXkMaxKBnd) return hipErrorInvalidValue;
+    const dim3 grid(ntiles), block(64 * kXkWaves);
+#define LBM_BXKB_CASE(KK)                                                                     \
+    case KK:                                                                                  \
+        if (f32)                                                                              \
+            bxkb_launch<float, KK>(grid, block, st, inst, tiles, ntiles, (const float *)src,  \
+                                   (float *)dst);                                             \
+        else                                                                                  \
+            bxkb_launch<double, KK>(grid, block, st, inst, tiles, ntiles,                     \
+                                    (const double *)src, (double *)dst);                      \
+        break;
+    switch (K) {
+        LBM_BXKB_CASE(2)
+        LBM_BXKB_CASE(3)
+        LBM_BXKB_CASE(4)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef LBM_BXKB_CASE
     return hipGetLastError();
 }
 

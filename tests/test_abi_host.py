@@ -107,15 +107,13 @@ def test_batch_create_rejects_disabled_step_synchronous_mode(L):
     assert "disabled" in L.last_error()
 
 
-@pytest.mark.parametrize("bad", [dict(mode=3, bc=1), dict(mode=3, fuse=9), dict(mode=4)])
+@pytest.mark.parametrize("bad", [dict(mode=3, fuse=1), dict(mode=3, fuse=9), dict(mode=4)])
 def test_batch_create_rejects_bad_fused_mode(L, bad):
-    """Mode 3 runs 2D instances with periodic faces only and 2 .. 8 steps per
-    launch; unknown modes are rejected."""
+    """Mode 3 takes 2 .. 8 steps per launch (0: its default); unknown modes are
+    rejected."""
     arr = (L.LbmInstance * 1)()
     arr[0].lattice, arr[0].nx, arr[0].ny = L.D2Q4x3, 64, 64
     arr[0].lam, arr[0].s, arr[0].g = 6.0, 1.8, 1.0
-    if bad.get("bc"):
-        arr[0].bc[0] = arr[0].bc[1] = 2  # walls
     nb, nodes = ctypes.c_size_t(), ctypes.c_long()
     lib = L.load()
     assert lib.lbm_batch_layout(arr, 1, L.F32, ctypes.byref(nb), ctypes.byref(nodes)) == 0

@@ -179,3 +179,64 @@ def test_batch_fused_mode_run_twice_equals_one_long_run():
     B.run(101)
     for a, b in zip(A.moments(), B.moments()):
         assert np.array_equal(to_np(a), to_np(b))
+
+
+def _faces_instances(seed):
+    """The small manifest with every instance on a cycle of face sets (2D: inflow /
+    Neumann / wall / periodic in corner combinations; 1D likewise), plus 2D grids
+    of several strips, narrower than the halo, and with the oblique shock's faces."""
+    out = instance_dicts(W.small_manifest(seed=seed), mixed_bc=True)
+    rng = np.random.default_rng(seed)
+    extra = [((300, 70), ("inflow", "neumann", "wall", "inflow")),
+             ((130, 75), ("wall", "wall", "wall", "wall")),
+             ((2, 40), ("neumann", "inflow", "periodic", "periodic")),
+             ((97, 33), ("periodic", "periodic", "wall", "neumann"))]
+    for (nx, ny), bc in extra:
+        inflow = {f: (1.1, 0.1 * (f - 1.5), 0.05) for f in range(4) if bc[f] == "inflow"}
+        out.append(dict(dim=2, nx=nx, ny=ny, lam=6.0, s=1.7, g=W.G, bc=bc, inflow=inflow,
+                        h0=1.0 + 0.2 * rng.random((ny, nx)),
+                        qx0=0.05 * rng.standard_normal((ny, nx)),
+                        qy0=0.05 * rng.standard_normal((ny, nx))))
+    return out
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("fuse", [0, 2, 3, 4, 8])
+def test_batch_fused_mode_with_faces_equals_flat_mode(storage, fuse):
+    """Mode 3 with 2D instances that have Neumann, wall or inflow faces (the whole
+    batch then takes at most 4 steps per launch) gives bit for bit the state of
+    mode 2 after a step count that needs graph chunks, whole fused launches and
+    leftover single steps; FP64 also matches the oracle per instance."""
+    from paper_1401_0427_amd.lbm import Batch
+
+    insts = _faces_instances(seed=6)
+    steps = 157
+    say(f"[batch fused faces] {len(insts)} instances, {steps} steps, fuse {fuse}, {storage}")
+    A = Batch(insts, storage=storage, mode=2)
+    B = Batch(insts, storage=storage, mode=3, fuse_steps=fuse)
+    A.run(steps)
+    B.run(steps)
+    for i in range(len(insts)):
+        assert np.array_equal(to_np(A.instance_planes(i)), to_np(B.instance_planes(i))), i
+    if storage == "f64":
+        mom = [to_np(t) for t in B.moments()]
+        worst = 0.0
+        for i, d in enumerate(insts):
+            ref = oracle_moments(d, steps)
+            got = [B.instance_view(i, t) for t in mom[: 2 if d["dim"] == 1 else 3]]
+            worst = max(worst, max(normwise_rel(a, b) for a, b in zip(got, ref)))
+        say(f"  worst instance rel err {worst:.3e}")
+        assert worst <= 1e-12
+
+
+def test_batch_fused_mode_with_faces_run_twice_equals_one_long_run():
+    from paper_1401_0427_amd.lbm import Batch
+
+    insts = _faces_instances(seed=7)
+    A = Batch(insts, storage="f64", mode=3)
+    B = Batch(insts, storage="f64", mode=3)
+    A.run(51)
+    A.run(50)
+    B.run(101)
+    for a, b in zip(A.moments(), B.moments()):
+        assert np.array_equal(to_np(a), to_np(b))
