@@ -117,6 +117,31 @@ def test_radial_4096_full_steps_invariants(storage):
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_radial_4096_default_launches_are_deterministic(storage):
+    """Two runs of 2000 steps in the default plan (FP32: 256-lane strips whose
+    wavefronts exchange edge values through LDS with one barrier per row) end in
+    bit-identical states, and 40 steps of that plan equal 40 single steps."""
+    import torch
+
+    case = W.radial_dam_break_2d(4096, lam=6.0)
+    A = gpu_solver(case, storage=storage, **_launch(storage))
+    B = gpu_solver(case, storage=storage, **_launch(storage))
+    A.step(2000)
+    B.step(2000)
+    same = bool(torch.equal(A.planes(), B.planes()))
+    say(f"[full] 4096^2 {storage} default plan {A.launch_info()}: two runs equal: {same}")
+    assert same
+    del A, B
+    C = gpu_solver(case, storage=storage, **_launch(storage))
+    D = gpu_solver(case, storage=storage, fuse_steps=1)
+    C.step(40)
+    D.step(40)
+    assert torch.equal(C.planes(), D.planes())
+    del C, D
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_radial_4096_fused_launch_equals_single_steps(storage):
     """The headline grid: 40 steps as two-, three- (the last one shorter), four-
     or eight-step launches give bit for bit the state of 40 single-step launches."""
