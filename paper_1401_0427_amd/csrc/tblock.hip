@@ -507,16 +507,15 @@ constexpr int xk_halo()
 //   is never written while its previous value may still be read.
 //   Wide strips, levels exchanged in registers (cross-lane permutes): only the
 //   edge values go through LDS, in slots [level][e1 (c), e3 (3 + c)][parity] of
-//   each wavefront (er: read base); w1 / w3 point the edge lanes' stores at the
-//   neighbour's slots and every other lane's at a junk area of its own, so the
-//   stores need no branch.
+//   each wavefront (er: read base); ew1 / ew3 point the edge lanes' stores at
+//   the neighbour's slots and every other lane's at a junk area of its own, so
+//   the stores need no branch.
 struct XkLds {
     int row;
     int r1, r3, w1, w3;
     int er, ew1, ew3;
     int w;  // wavefront within the strip
 };
-
 
 // One iteration j of the row loop.  cur: level-n pulls of this iteration's
 // level-1 row; nxt (the buffer consumed in the previous iteration): receives
@@ -535,11 +534,12 @@ struct XkLds {
 // e2 array (the e2 planes of the last row), i the level-1 row of this
 // iteration and inext that of the row prefetched now (both unwrapped), the
 // lane's columns (xm, xw, xp), bx0 / bx1 its face flags and B the face rules.
-// The y faces
-// reuse the e2 arrays: when row 0 of level k is computed, the e2 slot of row -1
-// (whose only reader is row 0's pull through the y- face) receives the face
-// value; on a Neumann y+ face the e2 slot of row ny - 1 (read only by row ny,
-// outside the grid) receives its own e4 planes, which row ny - 1 pulls back.
+// The y faces reuse the e2 arrays: when row 0 of level k is computed, the e2
+// slot of row -1 (whose only reader is row 0's pull through the y- face)
+// receives the face value; on a Neumann y+ face the e2 slot of row ny - 1 (read
+// only by row ny, outside the grid) receives its own e4 planes, which row
+// ny - 1 pulls back.
+// X: the wavefront's LDS offsets for this row (XkLds).
 template <typename T, int K, bool BND, int SW = 1>
 __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const Phys &P,
                                        int lane, const __amdgpu_buffer_rsrc_t *orsrc,
@@ -717,10 +717,11 @@ constexpr int xk_gcd(int a, int b) { return b == 0 ? a : xk_gcd(b, a % b); }
 // unrolled blocks (the extra iterations store nothing).
 // One wavefront: column strip `strip` of the grid (G, P) in src / dst, output
 // rows [y0, y1).
-// lds: the workgroup's LDS array; rows: its elements per wavefront (the
-// wavefront's rows start at w rows).  Wide strips (SW > 1): wavefront w of the
-// workgroup takes lanes [64 w, 64 w + 64) of the strip; every wavefront of the
-// workgroup runs the same rows and meets one barrier per row.
+// lds: the workgroup's LDS array, rows: its elements per wavefront (the
+// wavefront's part starts at w rows); with 64-lane strips, the wavefront's own
+// array and rows = 0.  Wide strips (SW > 1): wavefront w of the workgroup takes
+// lanes [64 w, 64 w + 64) of the strip; every wavefront of the workgroup runs
+// the same rows and meets one barrier per row.
 template <typename T, int K, int D, bool BND = false, int SW = 1>
 __device__ __forceinline__ void xk_wave(const T *__restrict__ src, T *__restrict__ dst,
                                         const Geo &G, const Phys &P, int strip, int y0, int y1,
