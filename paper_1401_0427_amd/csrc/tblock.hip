@@ -178,6 +178,12 @@ __global__ void __launch_bounds__(kX2Threads)
 #ifndef LBM_XK_LDS_LEVELS
 #define LBM_XK_LDS_LEVELS 6
 #endif
+// LDS exchange levels read one level ahead, for FP32 launches of at most this
+// many steps (0: never).  Measured at 2048^2, FP32 K = 6: 159-160 GLUPS against
+// 151; FP32 K = 8 at 4096^2: 221 against 224; FP64 K = 8 unchanged (177).
+#ifndef LBM_XK_LDS_PREFETCH_F32_MAXK
+#define LBM_XK_LDS_PREFETCH_F32_MAXK 6
+#endif
 #ifndef LBM_XK_LDS_MIN_K
 #define LBM_XK_LDS_MIN_K 7
 #endif
@@ -598,6 +604,18 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
         xk_load_clamp(src, ps, G, B, inext, xm, xw, xp, nxt);
     else
         xk_load(src, ps, onext, nxt);
+    // LDS exchange levels: each level's e1 / e3 pulls are read one level ahead
+    // (before the previous level's arithmetic), so the LDS latency overlaps it
+    constexpr int RW = xk_lds_width(SW);
+    constexpr bool PF = sizeof(T) == 4 && K <= LBM_XK_LDS_PREFETCH_F32_MAXK;
+    T pf1[3], pf3[3];
+    if constexpr (L > 0 && PF) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            pf1[c] = lds[X.row + c * RW + X.r1];
+            pf3[c] = lds[X.row + (3 + c) * RW + X.r3];
+        }
+    }
     collide2d(v, P);  // level 1
 #pragma unroll
     for (int k = 1; k < K; ++k) {
@@ -649,13 +667,16 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
             // (the per-lane offsets are loop invariant and the row index a
             // constant, so each access is one address register plus an
             // immediate offset)
-            constexpr int RW = xk_lds_width(SW);
             T *row = lds + X.row + (k - 1) * 6 * RW;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                o[4 * c + 0] = (double)row[c * RW + X.r1];
+                if constexpr (!PF) {
+                    pf1[c] = row[c * RW + X.r1];
+                    pf3[c] = row[(3 + c) * RW + X.r3];
+                }
+                o[4 * c + 0] = (double)pf1[c];
                 o[4 * c + 1] = (double)em[k - 1][c];
-                o[4 * c + 2] = (double)row[(3 + c) * RW + X.r3];
+                o[4 * c + 2] = (double)pf3[c];
                 o[4 * c + 3] = v[4 * c + 3];
                 em[k - 1][c] = (T)v[4 * c + 1];
             }
@@ -666,6 +687,15 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
                 row[(3 + c) * RW + X.w3] = (T)v[4 * c + 2];
             }
             __asm__ __volatile__("" ::: "memory");
+            if (PF && k < L) {
+                // the next level's pulls, written one row ago
+                T *nrow = row + 6 * RW;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    pf1[c] = nrow[c * RW + X.r1];
+                    pf3[c] = nrow[(3 + c) * RW + X.r3];
+                }
+            }
         } else {
             const bool el = SW > 1 && lane == 0 && X.w > 0;
             const bool er = SW > 1 && lane == 63 && X.w < SW - 1;
