@@ -579,16 +579,18 @@ static int fused_seg(bool f32, int K, const std::vector<lbm_instance> &inst)
         if (I.lattice == LBM_D2Q4x3) maxny = std::max(maxny, I.ny);
     if (maxny == 0) return 16;
     if (slots <= 0) return std::min(maxny, 160);
-    const int wo = batch_xk_out(f32, K), w = batch_xk_waves();
+    const int wo = batch_xk_out(f32, K), w = batch_xk_waves(f32, false);
     const int wob = inst.size() && K <= step2k_max_k_bounded() ? batch_xkb_out(f32, K) : wo;
+    const int wb = batch_xk_waves(f32, true);
     int best = 0;
     double best_cost = 0.0;
     for (int seg = 16; seg <= maxny; ++seg) {
         long blocks = 0;
         for (const lbm_instance &I : inst) {
             if (I.lattice != LBM_D2Q4x3) continue;
-            const int o = inst_bounded(I) ? wob : wo;
-            const long groups = ((I.nx + o - 1) / o + w - 1) / w;
+            const bool bnd = inst_bounded(I);
+            const int o = bnd ? wob : wo, ww = bnd ? wb : w;
+            const long groups = ((I.nx + o - 1) / o + ww - 1) / ww;
             blocks += groups * ((I.ny + seg - 1) / seg);
         }
         const long rounds = (blocks + slots - 1) / slots;
@@ -758,7 +760,7 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
         b->fuse = K;
         b->chunk = 2L * K * ((32 + 2 * K - 1) / (2 * K));
         b->xk_seg = fused_seg(b->f32, K, inst);
-        const int wo = batch_xk_out(b->f32, K), w = batch_xk_waves(), n1 = batch_1k_out(K);
+        const int wo = batch_xk_out(b->f32, K), n1 = batch_1k_out(K);
         const int wob = anyb ? batch_xkb_out(b->f32, K) : wo;
         for (int i = 0; i < n; ++i) {
             const lbm_instance &I = inst[i];
@@ -767,7 +769,7 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
                 continue;
             }
             const bool bnd = inst_bounded(I);
-            const int o = bnd ? wob : wo;
+            const int o = bnd ? wob : wo, w = batch_xk_waves(b->f32, bnd);
             const int ns = (I.nx + o - 1) / o;
             for (int y0 = 0; y0 < I.ny; y0 += b->xk_seg)
                 for (int s0 = 0; s0 < ns; s0 += w)

@@ -85,7 +85,7 @@ int step2k_max_k_bounded();  // steps per launch at most with non-periodic faces
 int batch_xk_out(bool f32, int K);   // output columns per strip
 int batch_xkb_out(bool f32, int K);  // the same, instances with non-periodic faces
 int batch_1k_out(int K);            // output nodes per 1D tile
-int batch_xk_waves();               // strips per workgroup
+int batch_xk_waves(bool f32, bool bnd);  // strips per workgroup (bnd: non-periodic faces)
 int batch_xk_per_cu(bool f32, int K);
 hipError_t launch_batch_xk(bool f32, int K, const InstDev *inst, const XkTileDev *tiles,
                            int ntiles, const void *src, void *dst, hipStream_t st);

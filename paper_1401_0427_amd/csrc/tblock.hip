@@ -228,12 +228,33 @@ constexpr int xk_sw()
     return (sizeof(T) == 8 ? LBM_XK_WIDE_F64 : LBM_XK_WIDE_F32) ? kXkWaves : 1;
 }
 constexpr int kXkDepth = LBM_XK_DEPTH;  // rows of level-n pulls in flight
-// The same for the batched launch: two rows (the 256-instance manifest, FP32,
-// K = 8: 164-172 GLUPS, with one row 155).
+// Wide strips in the batched launch (all-periodic instances), per storage type as
+// for single grids: 1 = the storage type's xk_sw, 0 = 64-lane strips.  The
+// 256-instance manifest (FP32, K = 8, fused against flat mode bit for bit): 184
+// GLUPS with 256-lane strips, 170 with 64-lane strips.
+#ifndef LBM_XK_BATCH_WIDE
+#define LBM_XK_BATCH_WIDE 1
+#endif
+template <typename T>
+constexpr int xk_batch_sw()
+{
+    return LBM_XK_BATCH_WIDE ? xk_sw<T>() : 1;
+}
+// Rows of level-n pulls in flight in the batched launch, per storage type.  The
+// same manifest, FP32: 64-lane strips 164-172 GLUPS with two rows, 155 with one;
+// 256-lane strips 184 with one row (154 registers, three wavefronts per SIMD),
+// 179 with two (183 registers).
 #ifndef LBM_XK_BATCH_DEPTH
 #define LBM_XK_BATCH_DEPTH 2
 #endif
-constexpr int kXkBatchDepth = LBM_XK_BATCH_DEPTH;
+#ifndef LBM_XK_BATCH_DEPTH_F32
+#define LBM_XK_BATCH_DEPTH_F32 (LBM_XK_BATCH_WIDE && LBM_XK_WIDE_F32 ? 1 : 2)
+#endif
+template <typename T>
+constexpr int xk_batch_depth()
+{
+    return sizeof(T) == 4 ? LBM_XK_BATCH_DEPTH_F32 : LBM_XK_BATCH_DEPTH;
+}
 
 // Workgroup b runs on XCD b % 8 (round-robin dispatch).  Give XCD x the
 // contiguous tile range [x q + min(x, r), ...) of q + (x < r) tiles (q, r =
@@ -928,19 +949,29 @@ __global__ void __launch_bounds__(64 * kXkWaves)
 }
 
 // Batched form: workgroup b takes tile b' (the XCD-contiguous order of b) of a
-// tile table spanning many all-periodic 2D instances packed in one buffer.
+// tile table spanning many all-periodic 2D instances packed in one buffer.  A
+// tile is one wide strip (xk_batch_sw > 1) or kXkWaves 64-lane strips.
 template <typename T, int K, int D>
 __global__ void __launch_bounds__(64 * kXkWaves)
     k_batch_xk(const InstDev *__restrict__ inst, const XkTileDev *__restrict__ tiles, int ntiles,
                const T *__restrict__ src, T *__restrict__ dst)
 {
-    __shared__ T xs[kXkWaves][xk_lds_elems<T, K>()];
     const XkTileDev td = tiles[xk_tile(blockIdx.x, ntiles, LBM_XK_REMAP != 0)];
     const InstDev &I = inst[td.inst];
-    const int strip = td.strip0 + (int)(threadIdx.x >> 6);
-    if (strip >= td.nstrips) return;
-    xk_wave<T, K, D>(src + I.off, dst + I.off, I.G, I.P, strip, td.y0, td.y1,
-                     xs[threadIdx.x >> 6]);
+    if constexpr (xk_batch_sw<T>() > 1) {
+        // every wavefront runs to the end (barriers)
+        constexpr int SW = xk_batch_sw<T>();
+        constexpr int rows = xk_wide_rows<T, K, SW>();
+        __shared__ T lds[kXkWaves * rows];
+        xk_wave<T, K, D, false, SW>(src + I.off, dst + I.off, I.G, I.P, td.strip0, td.y0, td.y1,
+                                    lds, rows);
+    } else {
+        __shared__ T xs[kXkWaves][xk_lds_elems<T, K>()];
+        const int strip = td.strip0 + (int)(threadIdx.x >> 6);
+        if (strip >= td.nstrips) return;
+        xk_wave<T, K, D>(src + I.off, dst + I.off, I.G, I.P, strip, td.y0, td.y1,
+                         xs[threadIdx.x >> 6]);
+    }
 }
 
 // Output columns per strip: bnd -- the bounded kernel; else the all-periodic
@@ -1322,10 +1353,17 @@ hipError_t launch_step2x(bool f32, const void *src, void *dst, const Geo &G, con
 }
 
 // ---- batched launchers -----------------------------------------------------------------
-int batch_xk_out(bool f32, int K) { return xk_wo_of(f32, K); }
+int batch_xk_out(bool f32, int K)
+{
+    return xk_wo_of(f32, K, false, f32 ? xk_batch_sw<float>() : xk_batch_sw<double>());
+}
 int batch_xkb_out(bool f32, int K) { return xk_wo_of(f32, K, true); }
 int batch_1k_out(int K) { return kK1Threads - 2 * K; }
-int batch_xk_waves() { return kXkWaves; }
+int batch_xk_waves(bool f32, bool bnd)
+{
+    const int sw = f32 ? xk_batch_sw<float>() : xk_batch_sw<double>();
+    return sw > 1 && !bnd ? 1 : kXkWaves;
+}
 
 int batch_xk_per_cu(bool f32, int K)
 {
@@ -1335,9 +1373,9 @@ int batch_xk_per_cu(bool f32, int K)
 #define LBM_BXK_OCC(KK)                                                                       \
     case KK:                                                                                  \
         e = f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                               \
-                      &n, k_batch_xk<float, KK, kXkBatchDepth>, bs, 0)                        \
+                      &n, k_batch_xk<float, KK, xk_batch_depth<float>()>, bs, 0)              \
                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(                               \
-                      &n, k_batch_xk<double, KK, kXkBatchDepth>, bs, 0);                      \
+                      &n, k_batch_xk<double, KK, xk_batch_depth<double>()>, bs, 0);           \
         break;
     switch (K) {
         LBM_BXK_OCC(2)
@@ -1362,11 +1400,12 @@ hipError_t launch_batch_xk(bool f32, int K, const InstDev *inst, const XkTileDev
 #define LBM_BXK_CASE(KK)                                                                      \
     case KK:                                                                                  \
         if (f32)                                                                              \
-            hipLaunchKernelGGL((k_batch_xk<float, KK, kXkBatchDepth>), grid, block, 0, st, inst, \
-                               tiles, ntiles, (const float *)src, (float *)dst);              \
+            hipLaunchKernelGGL((k_batch_xk<float, KK, xk_batch_depth<float>()>), grid, block, \
+                               0, st, inst, tiles, ntiles, (const float *)src, (float *)dst); \
         else                                                                                  \
-            hipLaunchKernelGGL((k_batch_xk<double, KK, kXkBatchDepth>), grid, block, 0, st, inst, \
-                               tiles, ntiles, (const double *)src, (double *)dst);            \
+            hipLaunchKernelGGL((k_batch_xk<double, KK, xk_batch_depth<double>()>), grid, block, \
+                               0, st, inst, tiles, ntiles, (const double *)src,               \
+                               (double *)dst);                                                \
         break;
     switch (K) {
         LBM_BXK_CASE(2)
