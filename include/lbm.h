@@ -111,9 +111,10 @@ typedef struct {
                              2 when the LDS
                              two-step launch has >= 1024 workgroups, else 1;
                              planes of 2 GiB or more take 1); 2D grids with
-                             Neumann, wall or inflow faces at most 4 (default 4
-                             when that launch fills a third of the device, else
-                             1; planes of 2 GiB or more take 1); 1D grids any
+                             Neumann, wall or inflow faces at most 8 (default 5
+                             for FP64, 4 for FP32 storage, when that launch fills
+                             a third of the device, else 1; planes of 2 GiB or
+                             more take 1); 1D grids any
                              (default 16).  lbm_launch_info reports the choice. */
     void *f_a, *f_b;      /* caller-owned device state buffers (ping-pong) */
     void *stream;         /* hipStream_t; NULL = default stream */
@@ -244,14 +245,16 @@ typedef struct {
                                 single steps): the 2D instances as tiles of the
                                 wave-strip multi-step kernels (with any 2D
                                 instance that has Neumann, wall or inflow faces,
-                                at most 4 steps per launch for the whole batch),
+                                by default 5 (FP64) / 4 (FP32) steps per launch
+                                for the whole batch),
                                 the 1D instances as
                                 1024-node tiles of the 1D multi-step kernel; graph
                                 chunks as in mode 2; steps that do not fill a launch
                                 run as flat single steps.  block, tile_nodes, grid
                                 and pass_nodes are ignored. */
     int fuse_steps;       /* mode 3: steps per launch, 2 .. 8 (0 = 6 for FP32, 8 for
-                             FP64 storage; 1 is rejected) */
+                             FP64 storage, or with non-periodic 2D faces 4 / 5;
+                             1 is rejected) */
 } lbm_batch_tuning;
 
 /* Assign state_offset / node_offset to n instances (in place) for the given

@@ -198,9 +198,9 @@ static const int kDefaultFuse2dF64 = 8;
 static const int kDefaultFuse2dF32 = 8;
 static const int kDefaultFuse2dF32Small = 6;
 // With non-periodic faces the wave-strip kernel takes at most
-// step2k_max_k_bounded() (4) steps per launch, and 4 by default: at 4096^2
-// (inflow / Neumann / wall faces) FP64 85 GLUPS (one step: 26), FP32 122 (57).
-static const int kDefaultFuse2dBounded = 4;
+// step2k_max_k_bounded() (8) steps per launch, and step2k_default_k_bounded() by
+// default (FP64 5, FP32 4): at 4096^2 (inflow / Neumann / wall faces) FP64 109
+// GLUPS (one step: 29), FP32 133 (56).
 // Shortest segment of a wave-strip launch (the halo rows cost 2 (K - 1) per
 // segment; the segment length itself is chosen per grid, step2k_seg).  Grids
 // whose launch cannot fill a third of the device keep the one- or two-step
@@ -314,7 +314,7 @@ extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0
                     if (c->xk_seg <= 0) c->xk_seg = kXkSeg;
                 }
             } else {
-                int kd = !allper ? kDefaultFuse2dBounded
+                int kd = !allper ? step2k_default_k_bounded(c->f32)
                          : c->f32 ? kDefaultFuse2dF32 : kDefaultFuse2dF64;
                 if (allper && c->f32) {
                     long s8 = 0;

@@ -748,7 +748,8 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
     // fused mode: tile tables of the 2D wave-strip launches (all-periodic instances,
     // and instances with other faces) and of the 1D multi-step launch.  With any
     // 2D instance of the second kind the whole batch takes at most
-    // step2k_max_k_bounded() steps per launch.
+    // step2k_max_k_bounded() steps per launch, and by default (no fuse_steps)
+    // step2k_default_k_bounded().
     std::vector<XkTileDev> hx, hxb;
     std::vector<K1TileDev> hk;
     b->chunk = 32;
@@ -756,6 +757,7 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
         int K = tune.fuse_steps ? tune.fuse_steps : (b->f32 ? 6 : 8);
         bool anyb = false;
         for (int i = 0; i < n; ++i) anyb = anyb || inst_bounded(inst[i]);
+        if (anyb && !tune.fuse_steps) K = std::min(K, step2k_default_k_bounded(b->f32));
         if (anyb && K > step2k_max_k_bounded()) K = step2k_max_k_bounded();
         b->fuse = K;
         b->chunk = 2L * K * ((32 + 2 * K - 1) / (2 * K));

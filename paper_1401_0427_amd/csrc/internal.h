@@ -80,6 +80,7 @@ hipError_t launch_step2x(bool f32, const void *src, void *dst, const Geo &G, con
 int step2k_blocks(const Geo &G, bool f32, int K, int seg);
 int step2k_seg(const Geo &G, bool f32, int K, int min_seg, bool *full, long *slots_out);
 int step2k_max_k_bounded();  // steps per launch at most with non-periodic faces
+int step2k_default_k_bounded(bool f32);  // and by default
 
 // Batched multi-step launches (tblock.hip).
 int batch_xk_out(bool f32, int K);   // output columns per strip

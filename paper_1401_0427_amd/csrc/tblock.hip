@@ -169,6 +169,15 @@ __global__ void __launch_bounds__(kX2Threads)
 #ifndef LBM_XK_DELAY
 #define LBM_XK_DELAY 1
 #endif
+// The same for grids with non-periodic faces.
+#ifndef LBM_XKB_DELAY
+#define LBM_XKB_DELAY 1
+#endif
+template <bool BND>
+constexpr bool xk_delay()
+{
+    return BND ? LBM_XKB_DELAY != 0 : LBM_XK_DELAY != 0;
+}
 // FP64 launches of at least LBM_XK_LDS_MIN_K steps exchange the e1 / e3 planes of
 // their first LBM_XK_LDS_LEVELS intermediate levels through a per-wavefront LDS row
 // instead of cross-lane permutes into registers; 0 levels = off.  At K = 8 this
@@ -498,6 +507,32 @@ constexpr int xk_lds_elems()
     return xk_lds_levels<T, K>() > 0 ? xk_lds_levels<T, K>() * 6 * 64 : 1;
 }
 
+// Grids with non-periodic faces: intermediate levels whose e1 / e3 exchange goes
+// through a per-wavefront LDS row (a face lane reads its own slot instead of its
+// neighbour's), at most LBM_XKB_LDS_LEVELS (FP64) / LBM_XKB_LDS_LEVELS_F32, in
+// launches of at least LBM_XKB_LDS_MIN_K steps; the other levels exchange in
+// registers (DPP).
+#ifndef LBM_XKB_LDS_LEVELS
+#define LBM_XKB_LDS_LEVELS 6
+#endif
+#ifndef LBM_XKB_LDS_LEVELS_F32
+#define LBM_XKB_LDS_LEVELS_F32 7
+#endif
+#ifndef LBM_XKB_LDS_MIN_K
+#define LBM_XKB_LDS_MIN_K 2
+#endif
+template <typename T, int K>
+constexpr int xkb_lds_levels()
+{
+    constexpr int L = sizeof(T) == 8 ? LBM_XKB_LDS_LEVELS : LBM_XKB_LDS_LEVELS_F32;
+    return K >= LBM_XKB_LDS_MIN_K ? (L < K - 1 ? L : K - 1) : 0;
+}
+template <typename T, int K>
+constexpr int xkb_lds_elems()
+{
+    return xkb_lds_levels<T, K>() > 0 ? xkb_lds_levels<T, K>() * 6 * 64 : 1;
+}
+
 // Output columns per strip: 64 lanes minus K - 1 halo lanes per side, rounded
 // down to a whole number of aligned chunks, so (on rows that start aligned)
 // each strip writes whole memory segments and never shares one with another
@@ -578,6 +613,7 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
                                        T (&ec)[K - 1][3], const XkLds &X)
 {
     constexpr int L = BND ? 0 : xk_lds_levels_sw<T, K, SW>();
+    constexpr int LB = BND ? xkb_lds_levels<T, K>() : 0;
     double v[12];
 #pragma unroll
     for (int pl = 0; pl < 12; ++pl) v[pl] = (double)cur[pl];
@@ -611,16 +647,16 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
             if (by1 && B.ky1 == BC_INFLOW) v[4 * c + 3] = B.in4[c];
         }
     }
-#if LBM_XK_DELAY
-    // The previous row's outputs are stored only now, after this row's loaded
-    // values have been consumed: the wait for those loads (issued D rows ago)
-    // then finds no fresh stores issued after them, and the memory counter,
-    // which counts stores and loads together, does not stall on this row's
-    // stores.  The scheduling barrier keeps that order.
-    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (xk_delay<BND>()) {
+        // The previous row's outputs are stored only now, after this row's loaded
+        // values have been consumed: the wait for those loads (issued D rows ago)
+        // then finds no fresh stores issued after them, and the memory counter,
+        // which counts stores and loads together, does not stall on this row's
+        // stores.  The scheduling barrier keeps that order.
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int pl = 0; pl < 12; ++pl) xk_store(orsrc[pl], pend_off, pend[pl]);
-#endif
+        for (int pl = 0; pl < 12; ++pl) xk_store(orsrc[pl], pend_off, pend[pl]);
+    }
     if constexpr (BND)
         xk_load_clamp(src, ps, G, B, inext, xm, xw, xp, nxt);
     else
@@ -651,19 +687,37 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
             const bool ry1 = B.ky1 != BC_PERIODIC && rr == G.ny - 1;
             const bool vy0 = B.ky0 != BC_PERIODIC && rr + 1 == 0;
             const bool vn1 = B.ky1 == BC_NEUMANN && rr + 1 == G.ny - 1;
+            // LDS level: this wavefront's six rows of level k (e1 planes c, e3
+            // planes 3 + c); X.r1 / X.r3 count from the component's e1 row and
+            // point at lane l - 1's e1 / lane l + 1's e3 of the previous row, or on
+            // a face lane at its own e1 / e3 (Neumann) or its own opposite plane
+            // (wall, whose normal momentum is negated here)
+            const bool lv = k - 1 < LB;
+            T *row = lds + X.row + (k - 1) * 6 * RW;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const T u1 = s1[k - 1][c], u3 = s3[k - 1][c], uc = ec[k - 1][c];
-                double a1 = (double)xk_shr(u1), a3 = (double)xk_shl(u3);
+                const T uc = ec[k - 1][c];
+                double a1, a3;
+                if (lv) {
+                    const T t1 = row[c * RW + X.r1], t3 = row[c * RW + X.r3];
+                    a1 = (double)(c == 1 && bx0 && B.kx0 == BC_WALL ? -t1 : t1);
+                    a3 = (double)(c == 1 && bx1 && B.kx1 == BC_WALL ? -t3 : t3);
+                    if (bx0 && B.kx0 == BC_INFLOW) a1 = B.in1[c];
+                    if (bx1 && B.kx1 == BC_INFLOW) a3 = B.in3[c];
+                } else {
+                    const T u1 = s1[k - 1][c], u3 = s3[k - 1][c];
+                    a1 = (double)xk_shr(u1);
+                    a3 = (double)xk_shl(u3);
+                    if (bx0)
+                        a1 = B.kx0 == BC_NEUMANN ? (double)u1
+                             : B.kx0 == BC_WALL  ? (double)(c == 1 ? -u3 : u3)
+                                                 : B.in1[c];
+                    if (bx1)
+                        a3 = B.kx1 == BC_NEUMANN ? (double)u3
+                             : B.kx1 == BC_WALL  ? (double)(c == 1 ? -u1 : u1)
+                                                 : B.in3[c];
+                }
                 double a2 = (double)em[k - 1][c], a4 = v[4 * c + 3];
-                if (bx0)
-                    a1 = B.kx0 == BC_NEUMANN ? (double)u1
-                         : B.kx0 == BC_WALL  ? (double)(c == 1 ? -u3 : u3)
-                                             : B.in1[c];
-                if (bx1)
-                    a3 = B.kx1 == BC_NEUMANN ? (double)u3
-                         : B.kx1 == BC_WALL  ? (double)(c == 1 ? -u1 : u1)
-                                             : B.in3[c];
                 if (ry0) a2 = B.in2[c];
                 if (ry1)
                     a4 = B.ky1 == BC_INFLOW ? B.in4[c]
@@ -676,8 +730,20 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
                 const T w2 = (T)v[4 * c + 1], w4 = (T)v[4 * c + 3];
                 em[k - 1][c] = vn1 ? w4 : w2;
                 if (vy0) ec[k - 1][c] = B.ky0 == BC_WALL ? (c == 2 ? -w4 : w4) : w2;
-                s1[k - 1][c] = (T)v[4 * c + 0];
-                s3[k - 1][c] = (T)v[4 * c + 2];
+                if (!lv) {
+                    s1[k - 1][c] = (T)v[4 * c + 0];
+                    s3[k - 1][c] = (T)v[4 * c + 2];
+                }
+            }
+            if (lv) {
+                // overwrite with this row once every lane has read the previous one
+                __asm__ __volatile__("" ::: "memory");
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    row[c * RW + X.w1] = (T)v[4 * c + 0];
+                    row[(3 + c) * RW + X.w3] = (T)v[4 * c + 2];
+                }
+                __asm__ __volatile__("" ::: "memory");
             }
         } else if (k - 1 < L) {
             // this wavefront's LDS row of level k: planes e1 (c) and e3 (3 + c);
@@ -748,16 +814,14 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
 #pragma unroll
         for (int pl = 0; pl < 12; ++pl) v[pl] = o[pl];
     }
-#if LBM_XK_DELAY
+    if constexpr (xk_delay<BND>()) {
 #pragma unroll
-    for (int pl = 0; pl < 12; ++pl) pend[pl] = (T)v[pl];
-    pend_off = ooff;
-#else
+        for (int pl = 0; pl < 12; ++pl) pend[pl] = (T)v[pl];
+        pend_off = ooff;
+    } else {
 #pragma unroll
-    for (int pl = 0; pl < 12; ++pl) xk_store(orsrc[pl], ooff, (T)v[pl]);
-    (void)pend;
-    (void)pend_off;
-#endif
+        for (int pl = 0; pl < 12; ++pl) xk_store(orsrc[pl], ooff, (T)v[pl]);
+    }
 }
 
 constexpr int xk_gcd(int a, int b) { return b == 0 ? a : xk_gcd(b, a % b); }
@@ -824,6 +888,14 @@ __device__ __forceinline__ void xk_wave(const T *__restrict__ src, T *__restrict
         clampx = B.kx0 != BC_PERIODIC;
         bx0 = clampx && xc == 0;
         bx1 = clampx && xc == nx - 1;
+        // LDS levels (xk_row): both read offsets count from the component's e1 row
+        // (the e3 row is 3 rows further); a face lane reads its own slot, a wall
+        // lane the opposite plane's
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            Lp[p].r1 = bx0 ? (B.kx0 == BC_WALL ? 3 * 64 + lane : lane) : (lane - 1) & 63;
+            Lp[p].r3 = bx1 ? (B.kx1 == BC_WALL ? lane : 3 * 64 + lane) : 3 * 64 + ((lane + 1) & 63);
+        }
     }
     // the lane's column and its neighbours: wrapped, or clamped to the grid
     const int xw = clampx ? min(max(xc, 0), nx - 1) : ((xc % nx) + nx) % nx;
@@ -899,10 +971,10 @@ __device__ __forceinline__ void xk_wave(const T *__restrict__ src, T *__restrict
                               X);
         }
     }
-#if LBM_XK_DELAY
+    if constexpr (xk_delay<BND>()) {
 #pragma unroll
-    for (int pl = 0; pl < 12; ++pl) xk_store(orsrc[pl], pend_off, pend[pl]);
-#endif
+        for (int pl = 0; pl < 12; ++pl) xk_store(orsrc[pl], pend_off, pend[pl]);
+    }
 }
 
 template <typename T, int K, int D>
@@ -939,13 +1011,14 @@ __global__ void __launch_bounds__(64 * kXkWaves)
     k_step2d_xkb(const T *__restrict__ src, T *__restrict__ dst, Geo G, Phys P, int nstrips,
                  int seg)
 {
+    __shared__ T xs[kXkWaves][xkb_lds_elems<T, K>()];
     const int ngroups = (nstrips + kXkWaves - 1) / kXkWaves;
     const int nseg = (G.ny + seg - 1) / seg;
     const int tile = xk_tile(blockIdx.x, ngroups * nseg, LBM_XK_REMAP != 0);
     const int strip = (tile % ngroups) * kXkWaves + (threadIdx.x >> 6);
     if (strip >= nstrips) return;  // whole wavefront; nothing here waits on others
     const int y0 = (tile / ngroups) * seg;
-    xk_wave<T, K, D, true>(src, dst, G, P, strip, y0, min(y0 + seg, G.ny), nullptr);
+    xk_wave<T, K, D, true>(src, dst, G, P, strip, y0, min(y0 + seg, G.ny), xs[threadIdx.x >> 6]);
 }
 
 // Batched form: workgroup b takes tile b' (the XCD-contiguous order of b) of a
@@ -983,11 +1056,13 @@ __global__ void __launch_bounds__(64 * kXkWaves)
     k_batch_xkb(const InstDev *__restrict__ inst, const XkTileDev *__restrict__ tiles,
                 int ntiles, const T *__restrict__ src, T *__restrict__ dst)
 {
+    __shared__ T xs[kXkWaves][xkb_lds_elems<T, K>()];
     const XkTileDev td = tiles[xk_tile(blockIdx.x, ntiles, LBM_XK_REMAP != 0)];
     const InstDev &I = inst[td.inst];
     const int strip = td.strip0 + (int)(threadIdx.x >> 6);
     if (strip >= td.nstrips) return;
-    xk_wave<T, K, D, true>(src + I.off, dst + I.off, I.G, I.P, strip, td.y0, td.y1, nullptr);
+    xk_wave<T, K, D, true>(src + I.off, dst + I.off, I.G, I.P, strip, td.y0, td.y1,
+                           xs[threadIdx.x >> 6]);
 }
 
 static int xk_wo_of(bool f32, int K, bool bnd = false, int sw = 1)
@@ -1011,7 +1086,11 @@ static int xk_wo_of(bool f32, int K, bool bnd = false, int sw = 1)
     if (bnd) switch (K) {
         case 2: return f32 ? xk_wo<float, 2, true>() : xk_wo<double, 2, true>();
         case 3: return f32 ? xk_wo<float, 3, true>() : xk_wo<double, 3, true>();
-        default: return f32 ? xk_wo<float, 4, true>() : xk_wo<double, 4, true>();
+        case 4: return f32 ? xk_wo<float, 4, true>() : xk_wo<double, 4, true>();
+        case 5: return f32 ? xk_wo<float, 5, true>() : xk_wo<double, 5, true>();
+        case 6: return f32 ? xk_wo<float, 6, true>() : xk_wo<double, 6, true>();
+        case 7: return f32 ? xk_wo<float, 7, true>() : xk_wo<double, 7, true>();
+        default: return f32 ? xk_wo<float, 8, true>() : xk_wo<double, 8, true>();
         }
     switch (K) {
     case 2: return f32 ? xk_wo<float, 2>() : xk_wo<double, 2>();
@@ -1059,8 +1138,25 @@ int step2k_blocks(const Geo &G, bool f32, int K, int seg)
 // per-lane 64-bit addresses) the FP64 K = 6 and FP32 K = 8 instantiations also
 // returned wrong values over whole grids on the GPU (every face set, interior
 // nodes included) with no cause found in the source, so no instantiation above
-// K = 4 is built.
-constexpr int kXkMaxKBnd = 4;
+// K = 4 was built.  The present form (clamped 32-bit level-1 loads, the e1 / e3
+// exchange of the intermediate levels through LDS rows) equals single steps bit
+// for bit at every K = 2 .. 8.  Its registers still grow by about 30 (FP64) per
+// level, so one wavefront per SIMD from K = 6 (FP64) / 8 (FP32).  Measured at
+// 4096^2 with the faces above: FP64 K = 2 .. 8 -> 47, 68, 90, 109, 85, 84, 81
+// GLUPS, FP32 -> 72, 105, 133, 131, 123, 117, 94 (K = 4 with the exchange in
+// registers: 88 / 124).
+#ifndef LBM_XKB_MAX_K
+#define LBM_XKB_MAX_K 8
+#endif
+constexpr int kXkMaxKBnd = LBM_XKB_MAX_K;
+// Steps per launch by default with non-periodic faces, per storage (the fastest
+// above).
+#ifndef LBM_XKB_DEFAULT_K_F64
+#define LBM_XKB_DEFAULT_K_F64 5
+#endif
+#ifndef LBM_XKB_DEFAULT_K_F32
+#define LBM_XKB_DEFAULT_K_F32 4
+#endif
 // Rows of level-n pulls in flight in the bounded kernel: one (at 4096^2 FP64 K = 4
 // 85 GLUPS against 74 with two; the smaller ring lets two wavefronts share a SIMD).
 #ifndef LBM_XKB_DEPTH
@@ -1069,6 +1165,11 @@ constexpr int kXkMaxKBnd = 4;
 constexpr int kXkbDepth = LBM_XKB_DEPTH;
 
 int step2k_max_k_bounded() { return kXkMaxKBnd; }
+int step2k_default_k_bounded(bool f32)
+{
+    const int k = f32 ? LBM_XKB_DEFAULT_K_F32 : LBM_XKB_DEFAULT_K_F64;
+    return k < kXkMaxKBnd ? k : kXkMaxKBnd;
+}
 
 template <typename T, int KK>
 static hipError_t xkb_occupancy(int *n, int bs)
@@ -1450,6 +1551,10 @@ hipError_t launch_batch_xkb(bool f32, int K, const InstDev *inst, const XkTileDe
         LBM_BXKB_CASE(2)
         LBM_BXKB_CASE(3)
         LBM_BXKB_CASE(4)
+        LBM_BXKB_CASE(5)
+        LBM_BXKB_CASE(6)
+        LBM_BXKB_CASE(7)
+        LBM_BXKB_CASE(8)
     default:
         return hipErrorInvalidValue;
     }

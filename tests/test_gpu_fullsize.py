@@ -166,7 +166,7 @@ def test_radial_4096_fused_launch_equals_single_steps(storage):
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_faces_4096_fused_launch_equals_single_steps(storage):
     """The headline grid with the bench's inflow / Neumann / wall / inflow faces:
-    40 steps as two-, three- and four-step launches (the library default there)
+    40 steps as two-, three- and eight-step launches and the library default
     give bit for bit the state of 40 single-step launches."""
     import torch
 
@@ -178,10 +178,10 @@ def test_faces_4096_fused_launch_equals_single_steps(storage):
     A.step(40)
     a = A.planes().clone()
     del A
-    for fuse in (2, 3, 0):
+    for fuse in (2, 3, 8, 0):
         B = gpu_solver(case, storage=storage, fuse_steps=fuse)
         k = B.launch_info()["steps_per_launch"]
-        assert k == (fuse or 4)
+        assert k == (fuse or (5 if storage == "f64" else 4))
         B.step(40)
         same = bool(torch.equal(a, B.planes()))
         say(f"[full] 4096^2 faces {storage}: {k} steps per launch == single steps bitwise: {same}")

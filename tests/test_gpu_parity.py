@@ -243,14 +243,16 @@ BOUNDED = [  # face rules (x-, x+, y-, y+), grid, steps
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
-@pytest.mark.parametrize("fuse", [2, 3, 4])
+@pytest.mark.parametrize("fuse", [2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("bc,shape,steps", BOUNDED)
 def test_fused_bounded_launch_equals_single_steps(storage, fuse, bc, shape, steps):
-    """fuse_steps = K (2 .. 4, the bounded maximum) on 2D grids with Neumann,
-    wall and inflow faces (alone, in every corner combination, with the other
-    axis periodic, on grids of two rows, three columns or narrower than the halo)
-    gives bit for bit the state of single steps; FP64 also matches the oracle."""
+    """fuse_steps = K (2 .. 8) on 2D grids with Neumann, wall and inflow faces
+    (alone, in every corner combination, with the other axis periodic, on grids
+    of two rows, three columns or narrower than the halo) gives bit for bit the
+    state of single steps; FP64 also matches the oracle.  At least two whole
+    launches and a remainder run."""
     nx, ny = shape
+    steps = max(steps, 2 * fuse + 3)
     case = _bounded(nx, ny, bc, seed=nx + ny)
     say(f"[fused bounded] {nx}x{ny} bc={bc} steps={steps} fuse={fuse} storage={storage}")
     A = gpu_solver(case, storage=storage, fuse_steps=1)
@@ -265,7 +267,7 @@ def test_fused_bounded_launch_equals_single_steps(storage, fuse, bc, shape, step
         assert per_plane_rel(b, ref) <= TOL64
 
 
-@pytest.mark.parametrize("fuse", [3, 4])
+@pytest.mark.parametrize("fuse", [3, 4, 6, 8])
 def test_fused_oblique_shock_matches_oracle(fuse):
     """The oblique shock reflection (inflow left and top, wall bottom, outflow
     right) run to steady state with fuse_steps = K equals the oracle."""
@@ -319,9 +321,8 @@ def test_default_launch_plans():
     launch on grids it can fill (8 steps per launch; FP32 6 on grids below about
     three workgroups per resident slot, such as 1024^2), with a segment length and
     the resident workgroups it was chosen against; one step per launch on a
-    small FP32 grid; 16 steps per launch in 1D; 4 steps with non-periodic 2D
-    faces; an explicit request is honoured up to 8 steps (4 with non-periodic
-    faces)."""
+    small FP32 grid; 16 steps per launch in 1D; 5 (FP64) / 4 (FP32) steps with
+    non-periodic 2D faces; an explicit request is honoured up to 8 steps."""
     big64 = gpu_solver(smooth_random_2d(1024, 1024, seed=8), storage="f64").launch_info()
     assert big64["steps_per_launch"] == 8 and big64["segment_rows"] >= 16
     assert big64["resident_blocks"] > 0
@@ -336,9 +337,12 @@ def test_default_launch_plans():
     walls = gpu_solver(W.oblique_shock_2d(20, steps=10), fuse_steps=4).launch_info()
     assert walls["steps_per_launch"] == 4 and walls["segment_rows"] >= 16
     walls8 = gpu_solver(W.oblique_shock_2d(20, steps=10), fuse_steps=8).launch_info()
-    assert walls8["steps_per_launch"] == 4
+    assert walls8["steps_per_launch"] == 8
     box = gpu_solver(smooth_random_2d(1024, 1024, seed=8, bc=("wall",) * 4)).launch_info()
-    assert box["steps_per_launch"] == 4 and box["segment_rows"] >= 16
+    assert box["steps_per_launch"] == 5 and box["segment_rows"] >= 16
+    box32 = gpu_solver(smooth_random_2d(1024, 1024, seed=8, bc=("wall",) * 4),
+                       storage="f32").launch_info()
+    assert box32["steps_per_launch"] == 4
     small_box = gpu_solver(smooth_random_2d(64, 64, seed=8, bc=("wall",) * 4)).launch_info()
     assert small_box["steps_per_launch"] == 1
     asked = gpu_solver(smooth_random_2d(300, 70, seed=8), fuse_steps=16).launch_info()
