@@ -111,8 +111,8 @@ typedef struct {
                              2 when the LDS
                              two-step launch has >= 1024 workgroups, else 1;
                              planes of 2 GiB or more take 1); 2D grids with
-                             Neumann, wall or inflow faces at most 8 (default 5
-                             for FP64, 4 for FP32 storage, when that launch fills
+                             Neumann, wall or inflow faces at most 8 (default 6
+                             for FP64, 5 for FP32 storage, when that launch fills
                              a third of the device, else 1; planes of 2 GiB or
                              more take 1); 1D grids any
                              (default 16).  lbm_launch_info reports the choice. */
@@ -245,7 +245,7 @@ typedef struct {
                                 single steps): the 2D instances as tiles of the
                                 wave-strip multi-step kernels (with any 2D
                                 instance that has Neumann, wall or inflow faces,
-                                by default 5 (FP64) / 4 (FP32) steps per launch
+                                by default 6 (FP64) / 5 (FP32) steps per launch
                                 for the whole batch),
                                 the 1D instances as
                                 1024-node tiles of the 1D multi-step kernel; graph
@@ -253,7 +253,7 @@ typedef struct {
                                 run as flat single steps.  block, tile_nodes, grid
                                 and pass_nodes are ignored. */
     int fuse_steps;       /* mode 3: steps per launch, 2 .. 8 (0 = 6 for FP32, 8 for
-                             FP64 storage, or with non-periodic 2D faces 4 / 5;
+                             FP64 storage, or with non-periodic 2D faces 5 / 6;
                              1 is rejected) */
 } lbm_batch_tuning;
 

@@ -22,6 +22,8 @@
 // and 24-row segments were fastest; segment lengths that are powers of two
 // (32, 64) were 15-20 % slower with FP32 storage, prefetching the next row's
 // pulls (more registers, fewer waves) slower still.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace lbm {
@@ -168,6 +170,10 @@ __global__ void __launch_bounds__(kX2Threads)
 #endif
 #ifndef LBM_XK_DELAY
 #define LBM_XK_DELAY 1
+#endif
+// Grids with non-periodic faces: x-face inflow values per lane (1) or uniform (0).
+#ifndef LBM_XKB_XIN_LANE
+#define LBM_XKB_XIN_LANE 1
 #endif
 // The same for grids with non-periodic faces.
 #ifndef LBM_XKB_DELAY
@@ -674,69 +680,104 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
         }
     }
     collide2d(v, P);  // level 1
+    // Levels 2 .. K.  Grids with non-periodic y faces: the rows near them (a
+    // uniform test per iteration) run a copy of the level loop with the y-face
+    // rules, so the other rows carry no per-level face conditions.
+    auto levels = [&](auto yc) __attribute__((always_inline)) {
+        constexpr bool Y = decltype(yc)::value;
 #pragma unroll
-    for (int k = 1; k < K; ++k) {
-        // v: level k, one row above the level-k+1 row computed here
+        for (int k = 1; k < K; ++k) {
+            // v: level k, one row above the level-k+1 row computed here
 #pragma unroll
-        for (int pl = 0; pl < 12; ++pl) v[pl] = (double)(T)v[pl];
-        double o[12];
-        if constexpr (BND) {
-            // rr: row of level k + 1 computed here; the level-k row in v is rr + 1
-            const int rr = i - k;
-            const bool ry0 = B.ky0 == BC_INFLOW && rr == 0;
-            const bool ry1 = B.ky1 != BC_PERIODIC && rr == G.ny - 1;
-            const bool vy0 = B.ky0 != BC_PERIODIC && rr + 1 == 0;
-            const bool vn1 = B.ky1 == BC_NEUMANN && rr + 1 == G.ny - 1;
-            // LDS level: this wavefront's six rows of level k (e1 planes c, e3
-            // planes 3 + c); X.r1 / X.r3 count from the component's e1 row and
-            // point at lane l - 1's e1 / lane l + 1's e3 of the previous row, or on
-            // a face lane at its own e1 / e3 (Neumann) or its own opposite plane
-            // (wall, whose normal momentum is negated here)
-            const bool lv = k - 1 < LB;
-            T *row = lds + X.row + (k - 1) * 6 * RW;
+            for (int pl = 0; pl < 12; ++pl) v[pl] = (double)(T)v[pl];
+            double o[12];
+            if constexpr (BND) {
+                // rr: row of level k + 1 computed here; the level-k row in v is rr + 1
+                const int rr = i - k;
+                const bool ry0 = Y && B.ky0 == BC_INFLOW && rr == 0;
+                const bool ry1 = Y && B.ky1 != BC_PERIODIC && rr == G.ny - 1;
+                const bool vy0 = Y && B.ky0 != BC_PERIODIC && rr + 1 == 0;
+                const bool vn1 = Y && B.ky1 == BC_NEUMANN && rr + 1 == G.ny - 1;
+                // LDS level: this wavefront's six rows of level k (e1 planes c, e3
+                // planes 3 + c); X.r1 / X.r3 count from the component's e1 row and
+                // point at lane l - 1's e1 / lane l + 1's e3 of the previous row, or on
+                // a face lane at its own e1 / e3 (Neumann) or its own opposite plane
+                // (wall, whose normal momentum is negated here)
+                const bool lv = k - 1 < LB;
+                T *row = lds + X.row + (k - 1) * 6 * RW;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const T uc = ec[k - 1][c];
-                double a1, a3;
+                for (int c = 0; c < 3; ++c) {
+                    const T uc = ec[k - 1][c];
+                    double a1, a3;
+                    if (lv) {
+                        const T t1 = row[c * RW + X.r1], t3 = row[c * RW + X.r3];
+                        a1 = (double)(c == 1 && bx0 && B.kx0 == BC_WALL ? -t1 : t1);
+                        a3 = (double)(c == 1 && bx1 && B.kx1 == BC_WALL ? -t3 : t3);
+                        if (bx0 && B.kx0 == BC_INFLOW) a1 = B.in1[c];
+                        if (bx1 && B.kx1 == BC_INFLOW) a3 = B.in3[c];
+                    } else {
+                        const T u1 = s1[k - 1][c], u3 = s3[k - 1][c];
+                        a1 = (double)xk_shr(u1);
+                        a3 = (double)xk_shl(u3);
+                        if (bx0)
+                            a1 = B.kx0 == BC_NEUMANN ? (double)u1
+                                 : B.kx0 == BC_WALL  ? (double)(c == 1 ? -u3 : u3)
+                                                     : B.in1[c];
+                        if (bx1)
+                            a3 = B.kx1 == BC_NEUMANN ? (double)u3
+                                 : B.kx1 == BC_WALL  ? (double)(c == 1 ? -u1 : u1)
+                                                     : B.in3[c];
+                    }
+                    double a2 = (double)em[k - 1][c], a4 = v[4 * c + 3];
+                    if (ry0) a2 = B.in2[c];
+                    if (ry1)
+                        a4 = B.ky1 == BC_INFLOW ? B.in4[c]
+                             : B.ky1 == BC_WALL ? (double)(c == 2 ? -uc : uc)
+                                                : (double)uc;
+                    o[4 * c + 0] = a1;
+                    o[4 * c + 1] = a2;
+                    o[4 * c + 2] = a3;
+                    o[4 * c + 3] = a4;
+                    const T w2 = (T)v[4 * c + 1], w4 = (T)v[4 * c + 3];
+                    em[k - 1][c] = vn1 ? w4 : w2;
+                    if (vy0) ec[k - 1][c] = B.ky0 == BC_WALL ? (c == 2 ? -w4 : w4) : w2;
+                    if (!lv) {
+                        s1[k - 1][c] = (T)v[4 * c + 0];
+                        s3[k - 1][c] = (T)v[4 * c + 2];
+                    }
+                }
                 if (lv) {
-                    const T t1 = row[c * RW + X.r1], t3 = row[c * RW + X.r3];
-                    a1 = (double)(c == 1 && bx0 && B.kx0 == BC_WALL ? -t1 : t1);
-                    a3 = (double)(c == 1 && bx1 && B.kx1 == BC_WALL ? -t3 : t3);
-                    if (bx0 && B.kx0 == BC_INFLOW) a1 = B.in1[c];
-                    if (bx1 && B.kx1 == BC_INFLOW) a3 = B.in3[c];
-                } else {
-                    const T u1 = s1[k - 1][c], u3 = s3[k - 1][c];
-                    a1 = (double)xk_shr(u1);
-                    a3 = (double)xk_shl(u3);
-                    if (bx0)
-                        a1 = B.kx0 == BC_NEUMANN ? (double)u1
-                             : B.kx0 == BC_WALL  ? (double)(c == 1 ? -u3 : u3)
-                                                 : B.in1[c];
-                    if (bx1)
-                        a3 = B.kx1 == BC_NEUMANN ? (double)u3
-                             : B.kx1 == BC_WALL  ? (double)(c == 1 ? -u1 : u1)
-                                                 : B.in3[c];
+                    // overwrite with this row once every lane has read the previous one
+                    __asm__ __volatile__("" ::: "memory");
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        row[c * RW + X.w1] = (T)v[4 * c + 0];
+                        row[(3 + c) * RW + X.w3] = (T)v[4 * c + 2];
+                    }
+                    __asm__ __volatile__("" ::: "memory");
                 }
-                double a2 = (double)em[k - 1][c], a4 = v[4 * c + 3];
-                if (ry0) a2 = B.in2[c];
-                if (ry1)
-                    a4 = B.ky1 == BC_INFLOW ? B.in4[c]
-                         : B.ky1 == BC_WALL ? (double)(c == 2 ? -uc : uc)
-                                            : (double)uc;
-                o[4 * c + 0] = a1;
-                o[4 * c + 1] = a2;
-                o[4 * c + 2] = a3;
-                o[4 * c + 3] = a4;
-                const T w2 = (T)v[4 * c + 1], w4 = (T)v[4 * c + 3];
-                em[k - 1][c] = vn1 ? w4 : w2;
-                if (vy0) ec[k - 1][c] = B.ky0 == BC_WALL ? (c == 2 ? -w4 : w4) : w2;
-                if (!lv) {
-                    s1[k - 1][c] = (T)v[4 * c + 0];
-                    s3[k - 1][c] = (T)v[4 * c + 2];
+            } else if (k - 1 < L) {
+                // this wavefront's LDS row of level k: planes e1 (c) and e3 (3 + c);
+                // read the previous row's neighbours, then overwrite with this row
+                // (the wavefront executes in lockstep and its LDS operations in
+                // order; the compiler barriers keep the reads before the writes and
+                // the writes before the next row's reads)
+                // (the per-lane offsets are loop invariant and the row index a
+                // constant, so each access is one address register plus an
+                // immediate offset)
+                T *row = lds + X.row + (k - 1) * 6 * RW;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    if constexpr (!PF) {
+                        pf1[c] = row[c * RW + X.r1];
+                        pf3[c] = row[(3 + c) * RW + X.r3];
+                    }
+                    o[4 * c + 0] = (double)pf1[c];
+                    o[4 * c + 1] = (double)em[k - 1][c];
+                    o[4 * c + 2] = (double)pf3[c];
+                    o[4 * c + 3] = v[4 * c + 3];
+                    em[k - 1][c] = (T)v[4 * c + 1];
                 }
-            }
-            if (lv) {
-                // overwrite with this row once every lane has read the previous one
                 __asm__ __volatile__("" ::: "memory");
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -744,75 +785,57 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
                     row[(3 + c) * RW + X.w3] = (T)v[4 * c + 2];
                 }
                 __asm__ __volatile__("" ::: "memory");
-            }
-        } else if (k - 1 < L) {
-            // this wavefront's LDS row of level k: planes e1 (c) and e3 (3 + c);
-            // read the previous row's neighbours, then overwrite with this row
-            // (the wavefront executes in lockstep and its LDS operations in
-            // order; the compiler barriers keep the reads before the writes and
-            // the writes before the next row's reads)
-            // (the per-lane offsets are loop invariant and the row index a
-            // constant, so each access is one address register plus an
-            // immediate offset)
-            T *row = lds + X.row + (k - 1) * 6 * RW;
+                if (PF && k < L) {
+                    // the next level's pulls, written one row ago
+                    T *nrow = row + 6 * RW;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                if constexpr (!PF) {
-                    pf1[c] = row[c * RW + X.r1];
-                    pf3[c] = row[(3 + c) * RW + X.r3];
+                    for (int c = 0; c < 3; ++c) {
+                        pf1[c] = nrow[c * RW + X.r1];
+                        pf3[c] = nrow[(3 + c) * RW + X.r3];
+                    }
                 }
-                o[4 * c + 0] = (double)pf1[c];
-                o[4 * c + 1] = (double)em[k - 1][c];
-                o[4 * c + 2] = (double)pf3[c];
-                o[4 * c + 3] = v[4 * c + 3];
-                em[k - 1][c] = (T)v[4 * c + 1];
-            }
-            __asm__ __volatile__("" ::: "memory");
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                row[c * RW + X.w1] = (T)v[4 * c + 0];
-                row[(3 + c) * RW + X.w3] = (T)v[4 * c + 2];
-            }
-            __asm__ __volatile__("" ::: "memory");
-            if (PF && k < L) {
-                // the next level's pulls, written one row ago
-                T *nrow = row + 6 * RW;
+            } else {
+                const bool el = SW > 1 && lane == 0 && X.w > 0;
+                const bool er = SW > 1 && lane == 63 && X.w < SW - 1;
+                const int kk = (k - 1 - L) * 12;  // this level's edge slots
+                if constexpr (SW > 1) __asm__ __volatile__("" ::: "memory");
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    pf1[c] = nrow[c * RW + X.r1];
-                    pf3[c] = nrow[(3 + c) * RW + X.r3];
+                    T a1 = s1[k - 1][c], a3 = s3[k - 1][c];
+                    if constexpr (SW > 1) {
+                        const T t1 = lds[X.er + kk + 2 * c], t3 = lds[X.er + kk + 2 * (3 + c)];
+                        a1 = el ? t1 : a1;
+                        a3 = er ? t3 : a3;
+                    }
+                    o[4 * c + 0] = (double)a1;
+                    o[4 * c + 1] = (double)em[k - 1][c];
+                    o[4 * c + 2] = (double)a3;
+                    o[4 * c + 3] = v[4 * c + 3];
+                    em[k - 1][c] = (T)v[4 * c + 1];
+                    s1[k - 1][c] = xk_xch((T)v[4 * c + 0], lane, 1);
+                    s3[k - 1][c] = xk_xch((T)v[4 * c + 2], lane, -1);
+                    if constexpr (SW > 1) {
+                        lds[X.ew1 + kk + 2 * c] = (T)v[4 * c + 0];
+                        lds[X.ew3 + kk + 2 * (3 + c)] = (T)v[4 * c + 2];
+                    }
                 }
+                if constexpr (SW > 1) __asm__ __volatile__("" ::: "memory");
             }
-        } else {
-            const bool el = SW > 1 && lane == 0 && X.w > 0;
-            const bool er = SW > 1 && lane == 63 && X.w < SW - 1;
-            const int kk = (k - 1 - L) * 12;  // this level's edge slots
-            if constexpr (SW > 1) __asm__ __volatile__("" ::: "memory");
+            collide2d(o, P);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                T a1 = s1[k - 1][c], a3 = s3[k - 1][c];
-                if constexpr (SW > 1) {
-                    const T t1 = lds[X.er + kk + 2 * c], t3 = lds[X.er + kk + 2 * (3 + c)];
-                    a1 = el ? t1 : a1;
-                    a3 = er ? t3 : a3;
-                }
-                o[4 * c + 0] = (double)a1;
-                o[4 * c + 1] = (double)em[k - 1][c];
-                o[4 * c + 2] = (double)a3;
-                o[4 * c + 3] = v[4 * c + 3];
-                em[k - 1][c] = (T)v[4 * c + 1];
-                s1[k - 1][c] = xk_xch((T)v[4 * c + 0], lane, 1);
-                s3[k - 1][c] = xk_xch((T)v[4 * c + 2], lane, -1);
-                if constexpr (SW > 1) {
-                    lds[X.ew1 + kk + 2 * c] = (T)v[4 * c + 0];
-                    lds[X.ew3 + kk + 2 * (3 + c)] = (T)v[4 * c + 2];
-                }
-            }
-            if constexpr (SW > 1) __asm__ __volatile__("" ::: "memory");
+            for (int pl = 0; pl < 12; ++pl) v[pl] = o[pl];
         }
-        collide2d(o, P);
-#pragma unroll
-        for (int pl = 0; pl < 12; ++pl) v[pl] = o[pl];
+    };
+    if constexpr (BND) {
+        // the levels' rows i - k (k = 1 .. K - 1) and i - k + 1 meet a face row
+        const bool yface = (B.ky0 != BC_PERIODIC && i >= -1 && i <= K - 1) ||
+                           (B.ky1 != BC_PERIODIC && i >= G.ny - 1 && i <= G.ny + K - 2);
+        if (yface)
+            levels(std::true_type{});
+        else
+            levels(std::false_type{});
+    } else {
+        levels(std::false_type{});
     }
     if constexpr (xk_delay<BND>()) {
 #pragma unroll
@@ -896,6 +919,16 @@ __device__ __forceinline__ void xk_wave(const T *__restrict__ src, T *__restrict
             Lp[p].r1 = bx0 ? (B.kx0 == BC_WALL ? 3 * 64 + lane : lane) : (lane - 1) & 63;
             Lp[p].r3 = bx1 ? (B.kx1 == BC_WALL ? lane : 3 * 64 + lane) : 3 * 64 + ((lane + 1) & 63);
         }
+#if LBM_XKB_XIN_LANE
+        // a lane needs at most one x face's inflow values (x- on bx0 lanes, x+ on
+        // bx1 lanes): keep that one per lane, which frees their scalar registers
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double x = bx0 ? B.in1[c] : B.in3[c];
+            B.in1[c] = x;
+            B.in3[c] = x;
+        }
+#endif
     }
     // the lane's column and its neighbours: wrapped, or clamped to the grid
     const int xw = clampx ? min(max(xc, 0), nx - 1) : ((xc % nx) + nx) % nx;
@@ -1139,12 +1172,13 @@ int step2k_blocks(const Geo &G, bool f32, int K, int seg)
 // returned wrong values over whole grids on the GPU (every face set, interior
 // nodes included) with no cause found in the source, so no instantiation above
 // K = 4 was built.  The present form (clamped 32-bit level-1 loads, the e1 / e3
-// exchange of the intermediate levels through LDS rows) equals single steps bit
-// for bit at every K = 2 .. 8.  Its registers still grow by about 30 (FP64) per
-// level, so one wavefront per SIMD from K = 6 (FP64) / 8 (FP32).  Measured at
-// 4096^2 with the faces above: FP64 K = 2 .. 8 -> 47, 68, 90, 109, 85, 84, 81
-// GLUPS, FP32 -> 72, 105, 133, 131, 123, 117, 94 (K = 4 with the exchange in
-// registers: 88 / 124).
+// exchange of the intermediate levels through LDS rows, the y-face rules only in
+// the iterations near a y face) equals single steps bit for bit at every K = 2 ..
+// 8.  Measured at 4096^2 with the faces above: FP64 K = 2 .. 8 -> 47, 67, 92, 115,
+// 132, 121, 115 GLUPS (one wavefront per SIMD from K = 7), FP32 -> 73, 105, 149,
+// 166, 156, 153, 155.  With the y-face rules in every iteration: FP64 90 / 109 / 85
+// at K = 4 / 5 / 6, FP32 133 / 131 / 123 (K = 4 with the exchange in registers:
+// 88 / 124).
 #ifndef LBM_XKB_MAX_K
 #define LBM_XKB_MAX_K 8
 #endif
@@ -1152,10 +1186,10 @@ constexpr int kXkMaxKBnd = LBM_XKB_MAX_K;
 // Steps per launch by default with non-periodic faces, per storage (the fastest
 // above).
 #ifndef LBM_XKB_DEFAULT_K_F64
-#define LBM_XKB_DEFAULT_K_F64 5
+#define LBM_XKB_DEFAULT_K_F64 6
 #endif
 #ifndef LBM_XKB_DEFAULT_K_F32
-#define LBM_XKB_DEFAULT_K_F32 4
+#define LBM_XKB_DEFAULT_K_F32 5
 #endif
 // Rows of level-n pulls in flight in the bounded kernel: one (at 4096^2 FP64 K = 4
 // 85 GLUPS against 74 with two; the smaller ring lets two wavefronts share a SIMD).

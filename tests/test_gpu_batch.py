@@ -204,7 +204,7 @@ def _faces_instances(seed):
 @pytest.mark.parametrize("fuse", [0, 2, 3, 4, 8])
 def test_batch_fused_mode_with_faces_equals_flat_mode(storage, fuse):
     """Mode 3 with 2D instances that have Neumann, wall or inflow faces (by default
-    the whole batch then takes 5 / 4 steps per launch) gives bit for bit the state of
+    the whole batch then takes 6 / 5 steps per launch) gives bit for bit the state of
     mode 2 after a step count that needs graph chunks, whole fused launches and
     leftover single steps; FP64 also matches the oracle per instance."""
     from paper_1401_0427_amd.lbm import Batch
