@@ -231,10 +231,7 @@ typedef struct {
                                 deadlock whatever the grid);
                              1: step-synchronous -- units of `block` nodes, one per
                                 workgroup in turn, one grid barrier per step (needs a
-                                fully resident grid; bounded waits, see lbm_batch_check).
-                                Currently DISABLED: lbm_batch_create returns LBM_EINVAL
-                                for mode 1 (an unexplained GPU memory fault on its first
-                                run with non-periodic faces);
+                                fully resident grid; bounded waits, see lbm_batch_check);
                              2: flat -- one ordinary launch per step over all instances,
                                 one workgroup per unit of `block` nodes; the launch
                                 boundary is the step barrier; chunks of 32 steps replay

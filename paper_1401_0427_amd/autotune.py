@@ -99,9 +99,8 @@ def tune_batch(seed=0, steps=96, blocks=(256, 512), tiles=(4096, 8192, 16384, 32
                grids=(0,), passes=(1, 2), storage="f32", modes=(0, 2, 3),
                unit_blocks=(128, 256, 512), fuses=(4, 5, 6, 8), log=print):
     """Sweep the batch modes in ``modes``: the dataflow mode (0) over workgroup
-    size, tile size, grid and nodes per pass; the step-synchronous (1, which the
-    library currently rejects) and flat (2) modes over workgroup size (= nodes
-    per unit); the fused mode (3) over steps per launch.  A configuration whose
+    size, tile size, grid and nodes per pass; the step-synchronous (1) and
+    flat (2) modes over workgroup size (= nodes per unit); the fused mode (3) over steps per launch.  A configuration whose
     run is aborted by the bounded waits is reported and skipped."""
     import torch
 

@@ -138,7 +138,6 @@ struct lbm_ctx {
     int dim;
     bool rest;  // rest-population scheme (D1Q3Q2 / D2Q5Q4Q4, MRT)
     Mrt M;
-    double *d_ghost;  // inflow equilibria of the rest-population schemes (4 x 13)
     bool f32;
     long ps;
     int np;
@@ -222,7 +221,6 @@ extern "C" void lbm_destroy(lbm_ctx *c)
     (void)hipFree(c->d_flag);
     (void)hipFree(c->d_partials);
     (void)hipFree(c->d_totals);
-    (void)hipFree(c->d_ghost);
     delete c;
 }
 
@@ -245,11 +243,6 @@ extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0
     const bool rest = rest_of(p->lattice);
     if ((rc = check_bcs(dim, p->bc, p->inflow))) return rc;
     double rates[10];
-    if (rest)
-        return fail(LBM_EINVAL,
-                    "the D1Q3Q2 / D2Q5Q4Q4 kernels are disabled: their first GPU run ended in an "
-                    "illegal memory access whose cause has not been found (the kernels and this "
-                    "API run clean under AddressSanitizer in a CPU build)");
     if (rest) {
         if (!(p->a >= 0.0) || !isfinite(p->a)) return fail(LBM_EINVAL, "rest weight a must be >= 0");
         for (int i = 0; i < 10; ++i) {
@@ -349,8 +342,7 @@ extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0
     if ((e = hipMalloc(&c->d_speed, sizeof(unsigned long long))) != hipSuccess ||
         (e = hipMalloc(&c->d_flag, 2 * sizeof(int))) != hipSuccess ||
         (e = hipMalloc(&c->d_partials, sizeof(double) * 3 * (size_t)nmb)) != hipSuccess ||
-        (e = hipMalloc(&c->d_totals, sizeof(double) * 4)) != hipSuccess ||
-        (e = hipMalloc(&c->d_ghost, sizeof(double) * 4 * 13)) != hipSuccess) {
+        (e = hipMalloc(&c->d_totals, sizeof(double) * 4)) != hipSuccess) {
         lbm_destroy(c);
         return fail(LBM_EDEVICE, "hipMalloc of scratch failed: %s", hipGetErrorString(e));
     }
@@ -358,7 +350,6 @@ extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0
     int bad = 0;
     if ((e = hipMemsetAsync(c->d_speed, 0, sizeof(unsigned long long), c->st)) != hipSuccess ||
         (e = hipMemsetAsync(c->d_flag, 0, 2 * sizeof(int), c->st)) != hipSuccess ||
-        (rest && (e = launch_inflow_ghost(dim, c->G, c->M, c->d_ghost, c->st)) != hipSuccess) ||
         (e = (rest ? launch_init_rest(dim, c->f32, c->buf[0], h0, qx0, qy0, c->G, c->M,
                                       c->d_speed, c->d_flag, c->st)
                    : launch_init(dim, c->f32, c->buf[0], h0, qx0, qy0, c->G, c->P, c->L,
@@ -389,7 +380,7 @@ extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0
 
 static hipError_t step_once(lbm_ctx *c, const void *src, void *dst, hipStream_t st)
 {
-    if (c->rest) return launch_step_rest(c->dim, c->f32, src, dst, c->G, c->M, c->d_ghost, st);
+    if (c->rest) return launch_step_rest(c->dim, c->f32, src, dst, c->G, c->M, st);
     return launch_step(c->dim, c->f32, src, dst, c->G, c->P, c->L, st);
 }
 

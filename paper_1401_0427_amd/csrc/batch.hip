@@ -257,62 +257,24 @@ __global__ void __launch_bounds__(512)
 // is bounded like the dataflow mode's, so a launch that is not fully resident
 // stops with the abort flag instead of hanging.
 
-// Boundary pulls of the batch kernels: inflow faces read precomputed
-// equilibria (ghost[face * 12 + plane]) instead of evaluating them.
-template <typename T>
-__device__ double pull_face2d_ghost(const T *__restrict__ src, const Geo &G,
-                                    const double *__restrict__ ghost, int pl, int face, int x,
-                                    int y, int sx, int sy)
-{
-    switch (G.bc[face]) {
-    case BC_PERIODIC:
-        sx = sx < 0 ? sx + G.nx : (sx >= G.nx ? sx - G.nx : sx);
-        sy = sy < 0 ? sy + G.ny : (sy >= G.ny ? sy - G.ny : sy);
-        return ld(src + pl * G.ps + (long)sy * G.nx + sx);
-    case BC_NEUMANN:
-        return ld(src + pl * G.ps + (long)y * G.nx + x);
-    case BC_WALL: {
-        const int k = pl >> 2, j = pl & 3;
-        const double v = ld(src + ((k << 2) | ((j + 2) & 3)) * G.ps + (long)y * G.nx + x);
-        return k == (face < 2 ? 1 : 2) ? -v : v;
-    }
-    default:
-        return ghost[face * 12 + pl];
-    }
-}
-
-template <typename T>
-__device__ double pull_face1d_ghost(const T *__restrict__ src, const Geo &G,
-                                    const double *__restrict__ ghost, int pl, int face, int x)
-{
-    switch (G.bc[face]) {
-    case BC_PERIODIC:
-        return ld(src + pl * G.ps + (face == 0 ? G.nx - 1 : 0));
-    case BC_NEUMANN:
-        return ld(src + pl * G.ps + x);
-    case BC_WALL: {
-        const double v = ld(src + (pl ^ 1) * G.ps + x);
-        return pl >= 2 ? -v : v;
-    }
-    default:
-        return ghost[face * 12 + pl];
-    }
-}
-
+// Boundary pulls: the same face rules as the single-grid kernels, with an
+// inflow face's equilibrium evaluated in registers.  (A precomputed table
+// loaded in the default case of the face switch was miscompiled: the
+// control-flow structurizer dropped the table address on one path into that
+// case, and the load went through an unassigned register.)
 template <typename T>
 __device__ __forceinline__ void node_sync(const T *__restrict__ s, T *__restrict__ d,
-                                          const InstDev &I, const double *__restrict__ ghost,
-                                          int k)
+                                          const InstDev &I, int k)
 {
     const Geo &G = I.G;
     const long ps = G.ps;
     if (I.dim == 1) {
         const int x = k;
         double f[4];
-        f[0] = x > 0 ? ld(s + x - 1) : pull_face1d_ghost(s, G, ghost, 0, 0, x);
-        f[2] = x > 0 ? ld(s + 2 * ps + x - 1) : pull_face1d_ghost(s, G, ghost, 2, 0, x);
-        f[1] = x < G.nx - 1 ? ld(s + ps + x + 1) : pull_face1d_ghost(s, G, ghost, 1, 1, x);
-        f[3] = x < G.nx - 1 ? ld(s + 3 * ps + x + 1) : pull_face1d_ghost(s, G, ghost, 3, 1, x);
+        f[0] = x > 0 ? ld(s + x - 1) : pull_face1d(s, G, I.P, 0, 0, x);
+        f[2] = x > 0 ? ld(s + 2 * ps + x - 1) : pull_face1d(s, G, I.P, 2, 0, x);
+        f[1] = x < G.nx - 1 ? ld(s + ps + x + 1) : pull_face1d(s, G, I.P, 1, 1, x);
+        f[3] = x < G.nx - 1 ? ld(s + 3 * ps + x + 1) : pull_face1d(s, G, I.P, 3, 1, x);
         collide1d(f, I.P);
 #pragma unroll
         for (int pl = 0; pl < 4; ++pl) sth<2>(d + pl * ps + x, f[pl]);
@@ -340,13 +302,13 @@ __device__ __forceinline__ void node_sync(const T *__restrict__ s, T *__restrict
         for (int c = 0; c < 3; ++c) {
             const int p = 4 * c;
             f[p] = x > 0 ? ld(s + p * ps + row + x - 1)
-                         : pull_face2d_ghost(s, G, ghost, p, 0, x, y, x - 1, y);
+                         : pull_face2d(s, G, I.P, p, 0, x, y, x - 1, y);
             f[p + 1] = y > 0 ? ld(s + (p + 1) * ps + row - nx + x)
-                             : pull_face2d_ghost(s, G, ghost, p + 1, 2, x, y, x, y - 1);
+                             : pull_face2d(s, G, I.P, p + 1, 2, x, y, x, y - 1);
             f[p + 2] = x < nx - 1 ? ld(s + (p + 2) * ps + row + x + 1)
-                                  : pull_face2d_ghost(s, G, ghost, p + 2, 1, x, y, x + 1, y);
+                                  : pull_face2d(s, G, I.P, p + 2, 1, x, y, x + 1, y);
             f[p + 3] = y < ny - 1 ? ld(s + (p + 3) * ps + row + nx + x)
-                                  : pull_face2d_ghost(s, G, ghost, p + 3, 3, x, y, x, y + 1);
+                                  : pull_face2d(s, G, I.P, p + 3, 3, x, y, x, y + 1);
         }
     }
     collide2d(f, I.P);
@@ -358,7 +320,7 @@ __device__ __forceinline__ void node_sync(const T *__restrict__ s, T *__restrict
 template <typename T>
 __global__ void __launch_bounds__(512)
     k_batch_sync(const InstDev *__restrict__ inst, const UnitDev *__restrict__ units, int nunits,
-                 int nsteps, const double *__restrict__ ghost, T *buf0, T *buf1, int cur,
+                 int nsteps, T *buf0, T *buf1, int cur,
                  unsigned *bar, int *abort_flag)
 {
     __shared__ int stop;
@@ -372,7 +334,7 @@ __global__ void __launch_bounds__(512)
             const InstDev I = inst[ud.inst];
             const int k = ud.k0 + (int)threadIdx.x;
             if (k < I.G.nx * I.G.ny)
-                node_sync(src + I.off, dst + I.off, I, ghost + (long)ud.inst * 48, k);
+                node_sync(src + I.off, dst + I.off, I, k);
         }
         // grid barrier: the workgroup barrier orders every wave's stores before
         // thread 0's agent-scope release (fetch-add); one acquire after the wait
@@ -400,25 +362,6 @@ __global__ void __launch_bounds__(512)
         }
         __syncthreads();
         if (__builtin_amdgcn_readfirstlane(stop) != 0) break;
-    }
-}
-
-// Inflow equilibria of every instance: ghost[i * 48 + face * 12 + plane].
-__global__ void k_batch_ghost(const InstDev *__restrict__ inst, int n, double *ghost)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const InstDev I = inst[i];
-    for (int face = 0; face < 4; ++face) {
-        double e[12];
-        for (int k = 0; k < 12; ++k) e[k] = 0.0;
-        if (I.G.bc[face] == BC_INFLOW) {
-            if (I.dim == 1)
-                feq1d(I.G.win[face][0], I.G.win[face][1], I.P, e);
-            else
-                feq2d(I.G.win[face][0], I.G.win[face][1], I.G.win[face][2], I.P, e);
-        }
-        for (int k = 0; k < 12; ++k) ghost[(long)i * 48 + face * 12 + k] = e[k];
     }
 }
 
@@ -485,7 +428,6 @@ struct lbm_batch {
     // step-synchronous mode
     UnitDev *d_units;
     int nunits;
-    double *d_ghost;
     unsigned *d_bar;
     int grid;
     // fused mode: K steps per launch pair (2D wave-strip tiles + 1D tiles)
@@ -548,7 +490,6 @@ extern "C" void lbm_batch_destroy(lbm_batch *b)
     (void)hipFree(b->d_next);
     (void)hipFree(b->d_abort);
     (void)hipFree(b->d_units);
-    (void)hipFree(b->d_ghost);
     (void)hipFree(b->d_bar);
     (void)hipFree(b->d_xtiles);
     (void)hipFree(b->d_xbtiles);
@@ -646,12 +587,6 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
                 return bfail(LBM_EINVAL, "instance %d: planes of 2 GiB or more (mode 3)", i);
         }
     }
-    if (tune.mode == 1)
-        return bfail(LBM_EINVAL,
-                     "tuning.mode 1 (step-synchronous) is disabled: its first GPU run with wall / "
-                     "inflow / Neumann faces ended in an illegal memory access whose cause has not "
-                     "been found (clean under AddressSanitizer and UBSan in a CPU build); use "
-                     "mode 0");
     if (tune.pass_nodes == 0) tune.pass_nodes = 1;
     if (tune.pass_nodes != 1 && tune.pass_nodes != 2)
         return bfail(LBM_EINVAL, "tuning.pass_nodes must be 1 or 2");
@@ -795,7 +730,6 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
         (e = hipMalloc(&b->d_next, sizeof(unsigned long long))) != hipSuccess ||
         (e = hipMalloc(&b->d_abort, sizeof(int))) != hipSuccess ||
         (e = hipMalloc(&b->d_units, sizeof(UnitDev) * hu.size())) != hipSuccess ||
-        (e = hipMalloc(&b->d_ghost, sizeof(double) * 48 * (size_t)n)) != hipSuccess ||
         (e = hipMalloc(&b->d_bar, sizeof(unsigned))) != hipSuccess ||
         (e = hipMalloc(&b->d_xtiles, sizeof(XkTileDev) * std::max<size_t>(1, hx.size()))) !=
             hipSuccess ||
@@ -819,9 +753,6 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
         lbm_batch_destroy(b);
         return bfail(LBM_EDEVICE, "batch setup failed: %s", hipGetErrorString(e));
     }
-    if (tune.mode == 1)
-        hipLaunchKernelGGL(k_batch_ghost, dim3((n + 63) / 64), dim3(64), 0, b->st, b->d_inst, n,
-                           b->d_ghost);
     if ((e = hipGetLastError()) != hipSuccess || (e = hipStreamSynchronize(b->st)) != hipSuccess) {
         lbm_batch_destroy(b);
         return bfail(LBM_EDEVICE, "batch setup failed: %s", hipGetErrorString(e));
@@ -898,12 +829,12 @@ static hipError_t enqueue_run(lbm_batch *b, long nsteps, hipStream_t st)
         hipLaunchKernelGGL(k_batch_sync_reset, dim3(1), dim3(64), 0, st, b->d_bar, b->d_abort);
         if (b->f32)
             hipLaunchKernelGGL(k_batch_sync<float>, dim3(b->grid), dim3(b->tune.block), 0, st,
-                               b->d_inst, b->d_units, b->nunits, (int)nsteps, b->d_ghost,
+                               b->d_inst, b->d_units, b->nunits, (int)nsteps,
                                (float *)b->buf[0], (float *)b->buf[1], b->cur, b->d_bar,
                                b->d_abort);
         else
             hipLaunchKernelGGL(k_batch_sync<double>, dim3(b->grid), dim3(b->tune.block), 0, st,
-                               b->d_inst, b->d_units, b->nunits, (int)nsteps, b->d_ghost,
+                               b->d_inst, b->d_units, b->nunits, (int)nsteps,
                                (double *)b->buf[0], (double *)b->buf[1], b->cur, b->d_bar,
                                b->d_abort);
         return hipGetLastError();

@@ -100,13 +100,11 @@ hipError_t launch_entropy(int dim, bool f32, const void *state, const Geo &G, do
                           double g, double *h_node, double *partials, hipStream_t st,
                           int *nblocks_out);
 
-hipError_t launch_inflow_ghost(int dim, const Geo &G, const Mrt &M, double *ghost,
-                               hipStream_t st);
 hipError_t launch_init_rest(int dim, bool f32, void *dst, const double *h0, const double *qx0,
                             const double *qy0, const Geo &G, const Mrt &M,
                             unsigned long long *speed_bits, int *bad, hipStream_t st);
 hipError_t launch_step_rest(int dim, bool f32, const void *src, void *dst, const Geo &G,
-                            const Mrt &M, const double *ghost, hipStream_t st);
+                            const Mrt &M, hipStream_t st);
 hipError_t launch_moments_rest(int dim, bool f32, const void *state, double *h, double *qx,
                                double *qy, double *partials, int *flag, const Geo &G,
                                hipStream_t st, int *nblocks_out);

@@ -140,11 +140,14 @@ __device__ __forceinline__ void collide_mrt2d(double *f, const Mrt &M)
 }
 
 // ---- pulls (rest plane 0 does not move) ---------------------------------------------
-// ghost: equilibrium populations of each inflow face, 13 per face.
+// An inflow face takes the equilibrium of its prescribed state, evaluated here in
+// registers.  (Returning a value loaded from a precomputed table in the default
+// case of the face switch made the compiler's control-flow structurizer drop the
+// table address on one of the paths into that case, so the load went through an
+// unassigned register.)
 template <typename T>
-__device__ double pull_rest_face2d(const T *__restrict__ src, const Geo &G,
-                                   const double *__restrict__ ghost, int pl, int face, int x, int y,
-                                   int sx, int sy)
+__device__ double pull_rest_face2d(const T *__restrict__ src, const Geo &G, const Mrt &M, int pl,
+                                   int face, int x, int y, int sx, int sy)
 {
     switch (G.bc[face]) {
     case BC_PERIODIC:
@@ -159,15 +162,17 @@ __device__ double pull_rest_face2d(const T *__restrict__ src, const Geo &G,
         const double v = ld(src + opp * G.ps + (long)y * G.nx + x);
         return k == (face < 2 ? 1 : 2) ? -v : v;
     }
-    default:
-        return ghost[face * 13 + pl];
+    default: {
+        double e[13];
+        feq_rest2d(G.win[face][0], G.win[face][1], G.win[face][2], M, e);
+        return e[pl];
+    }
     }
 }
 
 template <typename T>
-__device__ __forceinline__ void pull_rest2d(const T *__restrict__ src, const Geo &G,
-                                            const double *__restrict__ ghost, bool allper, int x,
-                                            int y, double *f)
+__device__ __forceinline__ void pull_rest2d(const T *__restrict__ src, const Geo &G, const Mrt &M,
+                                            bool allper, int x, int y, double *f)
 {
     const int nx = G.nx, ny = G.ny;
     const long ps = G.ps, row = (long)y * nx;
@@ -192,19 +197,19 @@ __device__ __forceinline__ void pull_rest2d(const T *__restrict__ src, const Geo
     for (int k = 0; k < 3; ++k) {
         const int p1 = 1 + 4 * k;
         f[p1] = x > 0 ? ld(src + p1 * ps + row + x - 1)
-                      : pull_rest_face2d(src, G, ghost, p1, 0, x, y, x - 1, y);
+                      : pull_rest_face2d(src, G, M, p1, 0, x, y, x - 1, y);
         f[p1 + 1] = y > 0 ? ld(src + (p1 + 1) * ps + row - nx + x)
-                          : pull_rest_face2d(src, G, ghost, p1 + 1, 2, x, y, x, y - 1);
+                          : pull_rest_face2d(src, G, M, p1 + 1, 2, x, y, x, y - 1);
         f[p1 + 2] = x < nx - 1 ? ld(src + (p1 + 2) * ps + row + x + 1)
-                               : pull_rest_face2d(src, G, ghost, p1 + 2, 1, x, y, x + 1, y);
+                               : pull_rest_face2d(src, G, M, p1 + 2, 1, x, y, x + 1, y);
         f[p1 + 3] = y < ny - 1 ? ld(src + (p1 + 3) * ps + row + nx + x)
-                               : pull_rest_face2d(src, G, ghost, p1 + 3, 3, x, y, x, y + 1);
+                               : pull_rest_face2d(src, G, M, p1 + 3, 3, x, y, x, y + 1);
     }
 }
 
 template <typename T>
-__device__ double pull_rest_face1d(const T *__restrict__ src, const Geo &G,
-                                   const double *__restrict__ ghost, int pl, int face, int x)
+__device__ double pull_rest_face1d(const T *__restrict__ src, const Geo &G, const Mrt &M, int pl,
+                                   int face, int x)
 {
     switch (G.bc[face]) {
     case BC_PERIODIC:
@@ -216,23 +221,25 @@ __device__ double pull_rest_face1d(const T *__restrict__ src, const Geo &G,
         const double v = ld(src + opp * G.ps + x);
         return pl >= 3 ? -v : v;
     }
-    default:
-        return ghost[face * 13 + pl];
+    default: {
+        double e[5];
+        feq_rest1d(G.win[face][0], G.win[face][1], M, e);
+        return e[pl];
+    }
     }
 }
 
 // ---- kernels -------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256) k_step_rest2d(const T *__restrict__ src, T *__restrict__ dst,
-                                                     Geo G, Mrt M, const double *__restrict__ ghost,
-                                                     int tiles_x, int allper)
+                                                     Geo G, Mrt M, int tiles_x, int allper)
 {
     const int t = blockIdx.x;
     const int y = t / tiles_x;
     const int x = (t - y * tiles_x) * 256 + threadIdx.x;
     if (x >= G.nx) return;
     double f[13];
-    pull_rest2d(src, G, ghost, allper != 0, x, y, f);
+    pull_rest2d(src, G, M, allper != 0, x, y, f);
     collide_mrt2d(f, M);
     T *o = dst + (long)y * G.nx + x;
 #pragma unroll
@@ -241,7 +248,7 @@ __global__ void __launch_bounds__(256) k_step_rest2d(const T *__restrict__ src, 
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_step_rest1d(const T *__restrict__ src, T *__restrict__ dst,
-                                                     Geo G, Mrt M, const double *__restrict__ ghost)
+                                                     Geo G, Mrt M)
 {
     const int x = blockIdx.x * 256 + threadIdx.x;
     if (x >= G.nx) return;
@@ -252,15 +259,15 @@ __global__ void __launch_bounds__(256) k_step_rest1d(const T *__restrict__ src, 
         f[1] = ld(src + ps + x - 1);
         f[3] = ld(src + 3 * ps + x - 1);
     } else {
-        f[1] = pull_rest_face1d(src, G, ghost, 1, 0, x);
-        f[3] = pull_rest_face1d(src, G, ghost, 3, 0, x);
+        f[1] = pull_rest_face1d(src, G, M, 1, 0, x);
+        f[3] = pull_rest_face1d(src, G, M, 3, 0, x);
     }
     if (x < G.nx - 1) {
         f[2] = ld(src + 2 * ps + x + 1);
         f[4] = ld(src + 4 * ps + x + 1);
     } else {
-        f[2] = pull_rest_face1d(src, G, ghost, 2, 1, x);
-        f[4] = pull_rest_face1d(src, G, ghost, 4, 1, x);
+        f[2] = pull_rest_face1d(src, G, M, 2, 1, x);
+        f[4] = pull_rest_face1d(src, G, M, 4, 1, x);
     }
     collide_mrt1d(f, M);
 #pragma unroll
@@ -301,22 +308,6 @@ __global__ void __launch_bounds__(256) k_init_rest(int dim, T *__restrict__ dst,
 #pragma unroll
         for (int pl = 0; pl < 13; ++pl) st(dst + pl * G.ps + i, f[pl]);
     }
-}
-
-// Equilibrium populations of every inflow face (13 slots per face).
-__global__ void k_inflow_ghost(int dim, Geo G, Mrt M, double *ghost)
-{
-    const int face = threadIdx.x;
-    if (face >= 4) return;
-    double e[13];
-    for (int k = 0; k < 13; ++k) e[k] = 0.0;
-    if (G.bc[face] == BC_INFLOW) {
-        if (dim == 1)
-            feq_rest1d(G.win[face][0], G.win[face][1], M, e);
-        else
-            feq_rest2d(G.win[face][0], G.win[face][1], G.win[face][2], M, e);
-    }
-    for (int k = 0; k < 13; ++k) ghost[face * 13 + k] = e[k];
 }
 
 // Conserved fields, per-block partial sums (fixed order) and the divergence flag.
@@ -366,13 +357,6 @@ __global__ void __launch_bounds__(256) k_moments_rest(int dim, const T *__restri
 }
 
 // ---- launchers -----------------------------------------------------------------------------
-hipError_t launch_inflow_ghost(int dim, const Geo &G, const Mrt &M, double *ghost,
-                               hipStream_t st)
-{
-    hipLaunchKernelGGL(k_inflow_ghost, dim3(1), dim3(64), 0, st, dim, G, M, ghost);
-    return hipGetLastError();
-}
-
 hipError_t launch_init_rest(int dim, bool f32, void *dst, const double *h0, const double *qx0,
                             const double *qy0, const Geo &G, const Mrt &M,
                             unsigned long long *speed_bits, int *bad, hipStream_t st)
@@ -388,7 +372,7 @@ hipError_t launch_init_rest(int dim, bool f32, void *dst, const double *h0, cons
 }
 
 hipError_t launch_step_rest(int dim, bool f32, const void *src, void *dst, const Geo &G,
-                            const Mrt &M, const double *ghost, hipStream_t st)
+                            const Mrt &M, hipStream_t st)
 {
     if (dim == 2) {
         const int tiles_x = (G.nx + 255) / 256;
@@ -396,18 +380,18 @@ hipError_t launch_step_rest(int dim, bool f32, const void *src, void *dst, const
                            G.bc[2] == BC_PERIODIC && G.bc[3] == BC_PERIODIC;
         if (f32)
             hipLaunchKernelGGL(k_step_rest2d<float>, dim3(tiles_x * G.ny), dim3(256), 0, st,
-                               (const float *)src, (float *)dst, G, M, ghost, tiles_x, allper);
+                               (const float *)src, (float *)dst, G, M, tiles_x, allper);
         else
             hipLaunchKernelGGL(k_step_rest2d<double>, dim3(tiles_x * G.ny), dim3(256), 0, st,
-                               (const double *)src, (double *)dst, G, M, ghost, tiles_x, allper);
+                               (const double *)src, (double *)dst, G, M, tiles_x, allper);
     } else {
         const int nb = (G.nx + 255) / 256;
         if (f32)
             hipLaunchKernelGGL(k_step_rest1d<float>, dim3(nb), dim3(256), 0, st,
-                               (const float *)src, (float *)dst, G, M, ghost);
+                               (const float *)src, (float *)dst, G, M);
         else
             hipLaunchKernelGGL(k_step_rest1d<double>, dim3(nb), dim3(256), 0, st,
-                               (const double *)src, (double *)dst, G, M, ghost);
+                               (const double *)src, (double *)dst, G, M);
     }
     return hipGetLastError();
 }

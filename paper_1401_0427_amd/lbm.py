@@ -380,9 +380,9 @@ class Batch:
                  mode=0, fuse_steps=0, device="cuda"):
         """``instances``: iterable of dicts with keys dim, nx, ny, lam, s, g, bc,
         inflow, h0, qx0, qy0 (numpy arrays of the instance's nodes).  ``mode`` 0 is
-        the dataflow persistent launch, 2 one flat launch per step, 3 ``fuse_steps``
-        steps per launch (0 = library default); mode 1 (step-synchronous) is
-        rejected by the library while it is switched off."""
+        the dataflow persistent launch, 1 the step-synchronous persistent launch
+        (one grid barrier per step), 2 one flat launch per step, 3 ``fuse_steps``
+        steps per launch (0 = library default)."""
         import torch
 
         _require_gpu(torch)

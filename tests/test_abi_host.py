@@ -92,19 +92,21 @@ def test_batch_layout_offsets(L):
     assert nb.value == (1024 * 4 + 16832 * 12 + 64 * 4) * 4
 
 
-def test_batch_create_rejects_disabled_step_synchronous_mode(L):
+def test_batch_create_rejects_bad_step_synchronous_tuning(L):
+    """Mode 1 (one grid barrier per step) needs a workgroup size that is a
+    multiple of 64 in [64, 512]; a bad one is rejected before any device call."""
     arr = (L.LbmInstance * 1)()
     arr[0].lattice, arr[0].nx, arr[0].ny = L.D2Q4x3, 64, 64
     arr[0].lam, arr[0].s, arr[0].g = 6.0, 1.8, 1.0
     nb, nodes = ctypes.c_size_t(), ctypes.c_long()
     lib = L.load()
     assert lib.lbm_batch_layout(arr, 1, L.F32, ctypes.byref(nb), ctypes.byref(nodes)) == 0
-    tune = L.LbmBatchTuning(256, 16384, 0, 1, 1, 0)
+    tune = L.LbmBatchTuning(100, 16384, 0, 1, 1, 0)
     b = ctypes.c_void_p()
     rc = lib.lbm_batch_create(arr, 1, L.F32, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000),
                               None, ctypes.byref(tune), ctypes.byref(b))
     assert rc == L.LBM_EINVAL and not b.value
-    assert "disabled" in L.last_error()
+    assert "block" in L.last_error()
 
 
 @pytest.mark.parametrize("bad", [dict(mode=3, fuse=1), dict(mode=3, fuse=9), dict(mode=4)])

@@ -46,17 +46,11 @@ def oracle_moments(d, steps):
     return oracle.moments(P, f)
 
 
-MODE1_OFF = pytest.mark.skip(
-    reason="step-synchronous batch mode disabled: its first GPU run (block 256, mixed wall / "
-           "inflow / Neumann faces) ended in an illegal memory access whose cause is not found "
-           "yet (clean under ASan and UBSan in a CPU build); not run on the GPU again until a "
-           "cause is shown")
-
 TUNES = [dict(block=256, tile_nodes=256), dict(block=64, tile_nodes=100),
          dict(block=512, tile_nodes=4096, grid=7),
-         pytest.param(dict(block=256, mode=1), marks=MODE1_OFF),
-         pytest.param(dict(block=64, mode=1, grid=5), marks=MODE1_OFF),
-         pytest.param(dict(block=512, mode=1), marks=MODE1_OFF),
+         dict(block=256, mode=1),
+         dict(block=64, mode=1, grid=5),
+         dict(block=512, mode=1),
          dict(block=256, mode=2), dict(block=64, mode=2), dict(block=512, mode=2)]
 
 
@@ -83,7 +77,7 @@ def test_batch_small_manifest_fp64_matches_oracle(tune, mixed_bc):
     assert worst <= 1e-12
 
 
-@pytest.mark.parametrize("mode", [0, pytest.param(1, marks=MODE1_OFF), 2])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_batch_run_twice_equals_one_long_run(mode):
     from paper_1401_0427_amd.lbm import Batch
 
@@ -98,7 +92,7 @@ def test_batch_run_twice_equals_one_long_run(mode):
         assert np.array_equal(to_np(a), to_np(b))
 
 
-@pytest.mark.parametrize("mode", [0, pytest.param(1, marks=MODE1_OFF), 2])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_batch_fp32_l1(mode):
     from paper_1401_0427_amd.lbm import Batch
 

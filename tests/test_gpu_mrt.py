@@ -9,12 +9,7 @@ import oracle
 from gpu_helpers import l1_rel, per_plane_rel, say, smooth_random_2d, to_np
 from paper_1401_0427_amd import workloads as W
 
-pytestmark = [
-    pytest.mark.gpu,
-    pytest.mark.skip(reason="D1Q3Q2 / D2Q5Q4Q4 GPU kernels disabled: their first GPU run ended in an "
-                            "illegal memory access whose cause is not found yet (clean under ASan "
-                            "in a CPU build); not run on the GPU again until a cause is shown"),
-]
+pytestmark = pytest.mark.gpu
 
 RATES2D = [1.7, 1.6, 1.2, 1.9, 1.5, 1.3, 1.1, 1.45, 1.55, 1.8]
 
