@@ -182,6 +182,77 @@ def test_mrt_rates_differ_from_bgk(orc):
         assert abs(fm[comp].sum() - f[comp].sum()) < 1e-14
 
 
+def _paper_moments(f, dim, lam):
+    """The paper's moment bases, written from their definitions: Sec. 2 for
+    D1Q3Q2 (conserved rho, q; non-conserved J_rho, eps_rho, J_q) and Sec. 3 for
+    D2Q5Q4Q4 (conserved rho, q_x, q_y; non-conserved J_x, J_y, eps_rho, XX_rho,
+    f_xx, f_xy, XX_u, f_yx, f_yy, XX_v), in the order of the MRT rates."""
+    if dim == 1:
+        f0, fp, fm, gp, gm = f
+        cons = np.array([f0 + fp + fm, gp + gm])
+        non = np.array([lam * (fp - fm), lam * lam * (fp + fm - 2.0 * f0), lam * (gp - gm)])
+        return cons, non
+    f0, f1, f2, f3, f4 = f[0:5]
+    gx, gy = f[5:9], f[9:13]
+    cons = np.array([f0 + f1 + f2 + f3 + f4, gx.sum(), gy.sum()])
+    non = np.array([lam * (f1 - f3), lam * (f2 - f4), f1 + f2 + f3 + f4 - 4.0 * f0,
+                    f1 - f2 + f3 - f4,
+                    lam * (gx[0] - gx[2]), lam * (gx[1] - gx[3]), gx[0] - gx[1] + gx[2] - gx[3],
+                    lam * (gy[0] - gy[2]), lam * (gy[1] - gy[3]), gy[0] - gy[1] + gy[2] - gy[3]])
+    return cons, non
+
+
+@pytest.mark.parametrize("dim,a", [(1, 0.0), (1, 0.15), (2, 0.0), (2, 0.05)])
+def test_mrt_distinct_rates_relax_each_moment_with_its_own_rate(orc, dim, a):
+    """Eq. 2-relaxation with one rate per moment: m_l* = m_l + s_l (m_l^eq - m_l)
+    for every non-conserved moment of the Sec. 2 / Sec. 3 bases, computed here
+    from the paper's definitions.  m_l^eq is taken as the moment of the
+    equilibrium distribution f^eq(W) (itself pinned to the gradients of the
+    potentials), and agrees with the printed equilibrium values (J^eq = q,
+    XX^eq = 0, f_xx^eq = rho u^2 + p, f_xy^eq = f_yx^eq = rho u v, f_yy^eq =
+    rho v^2 + p, J_q^eq = q u + p in 1D).  With rate 1 on moment l and distinct
+    rates elsewhere, moment l lands on its equilibrium and every other moment
+    follows its own rate, so any permutation of the rates fails; with all
+    rates 1 the collision returns f^eq(W)."""
+    lam, g, s = 4.0, 1.3, 1.5
+    nnon = 3 if dim == 1 else 10
+    rng = np.random.default_rng(41 + dim)
+    base = np.linspace(0.35, 1.85, nnon)
+    rng.shuffle(base)
+    Pb = orc.params(dim, 4, 4, lam=lam, s=s, g=g, a=a)
+    for h, qx, qy in zip(*_rand_states(rng, 40, dim)):
+        f0 = orc.feq(Pb, h, qx, qy)
+        f = f0 + rng.normal(0, 0.05, f0.size) * (np.abs(f0) + 0.1)
+        cons, m = _paper_moments(f, dim, lam)
+        feq = orc.feq(Pb, *cons)  # equilibrium of the conserved moments of f
+        _, meq = _paper_moments(feq, dim, lam)
+        rho = cons[0]
+        u = cons[1] / rho
+        v = cons[2] / rho if dim == 2 else 0.0
+        p = 0.5 * g * rho * rho
+        scale = np.abs(meq).max() + np.abs(m).max() + 1.0
+        if dim == 1:
+            printed = {0: cons[1], 2: cons[1] * u + p}
+        else:
+            printed = {0: cons[1], 1: cons[2], 3: 0.0, 4: rho * u * u + p, 5: rho * u * v,
+                       6: 0.0, 7: rho * u * v, 8: rho * v * v + p, 9: 0.0}
+        for l, val in printed.items():
+            assert abs(meq[l] - val) <= 1e-13 * scale, (l, meq[l], val)
+        for l in range(nnon):
+            rates = base.copy()
+            rates[l] = 1.0
+            P = orc.params(dim, 4, 4, lam=lam, s=s, g=g, a=a, mrt=True, rates=list(rates))
+            fs = orc.collide(P, f)
+            cons_s, ms = _paper_moments(fs, dim, lam)
+            np.testing.assert_allclose(cons_s, cons, rtol=0, atol=1e-14 * scale)
+            want = m + rates * (meq - m)
+            assert abs(ms[l] - meq[l]) <= 1e-13 * scale, (l, ms[l], meq[l])
+            np.testing.assert_allclose(ms, want, rtol=0, atol=1e-13 * scale)
+        P1 = orc.params(dim, 4, 4, lam=lam, s=s, g=g, a=a, mrt=True, rates=[1.0] * 10)
+        np.testing.assert_allclose(orc.collide(P1, f), feq, rtol=0,
+                                   atol=1e-14 * (np.abs(feq).max() + 1.0))
+
+
 # ----------------------------------------------------------- Lax-Friedrichs ----
 
 def _flux1d(h, q, g):
