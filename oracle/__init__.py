@@ -70,6 +70,10 @@ def lib():
                                         ctypes.c_double, dp, dp]
         _lib.orc_entropy.argtypes = [pp, dp, dp, dp, ctypes.POINTER(ctypes.c_long)]
         _lib.orc_entropy_pop.argtypes = [pp, ctypes.c_int, dp, dp, dp]
+        _lib.orc_set_threads.argtypes = [ctypes.c_int]
+        _lib.orc_set_threads.restype = None
+        _lib.orc_get_threads.argtypes = []
+        _lib.orc_get_threads.restype = ctypes.c_int
         for name in ("orc_feq", "orc_collide", "orc_run", "orc_advance", "orc_moments",
                      "orc_adjoint_step", "orc_loss_grad_2d", "orc_loss_cs_2d", "orc_entropy",
                      "orc_entropy_pop"):
@@ -105,6 +109,15 @@ def params(dim, nx, ny=1, lam=3.0, s=1.8, g=1.0, a=0.0, bc=("periodic",) * 4,
     for i in range(10):
         P.rates[i] = rr[i] if i < len(rr) else s
     return P
+
+
+def set_threads(n):
+    """Host threads of the oracle's parallel loops (results are independent of it)."""
+    lib().orc_set_threads(int(n))
+
+
+def get_threads():
+    return int(lib().orc_get_threads())
 
 
 def npop(dim):

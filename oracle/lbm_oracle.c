@@ -35,6 +35,7 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#include <omp.h>
 
 #define ORC_NPMAX 13
 enum { ORC_BC_PERIODIC = 0, ORC_BC_NEUMANN = 1, ORC_BC_WALL = 2, ORC_BC_INFLOW = 3 };
@@ -261,6 +262,11 @@ static void collide_field(const orc_params *P, double s, const orc_field *f, orc
 /* ---- exported API ------------------------------------------------------- */
 
 int orc_npop_of(int dim) { return orc_npop(dim); }
+
+/* Host threads of the parallel loops (results do not depend on it: every node
+ * is computed independently and the reductions are done in a fixed order). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_get_threads(void) { return omp_get_max_threads(); }
 
 /* Equilibrium distribution of one state W = (h, qx, qy) (qy ignored in 1D).
  * out receives orc_npop(dim) values in the population order above. */

@@ -1,5 +1,6 @@
-"""Host-side logic of bench.py (no GPU): the one-GPU guard, and the committed
-rocprofv3 counter summaries the bench line's `traffic` field is read from."""
+"""Host-side logic of bench.py (no GPU): the one-GPU guard, the committed
+rocprofv3 counter summaries the bench line's `traffic` field is read from, and
+the roofline object built from them and the live launch time."""
 import json
 import os
 import subprocess
@@ -44,12 +45,53 @@ def test_counter_summary_is_self_consistent(kind):
     assert f64["write_over_alg"] >= 0.99 and f64["read_over_alg"] >= 0.99
 
 
-def test_headline_traffic_matches_the_current_kernel_source():
-    """The wave-strip summary was taken on the kernel source as committed, so the
-    bench line carries its traffic; another grid or launch depth gets none."""
+def test_headline_traffic_is_used_only_for_the_kernel_source_it_was_taken_on():
+    """The bench line carries the committed wave-strip traffic only while the kernel
+    source hashes to the value recorded with the counters (else null), and never
+    for another grid or launch depth."""
     d = json.load(open(os.path.join(ROOT, "profiles", bench.KERNELS["wave_strip"][1])))
-    assert d["kernel_source_sha"] == bench._kernel_sha("wave_strip")
     t = bench._measured_traffic(d["n"], "wave_strip", d["steps_per_launch"])
-    assert t == d["traffic_bytes_per_launch_f64"]
+    if d["kernel_source_sha"] == bench._kernel_sha("wave_strip"):
+        assert t == d["traffic_bytes_per_launch_f64"]
+    else:
+        assert t is None
     assert bench._measured_traffic(d["n"] // 2, "wave_strip", d["steps_per_launch"]) is None
     assert bench._measured_traffic(d["n"], "wave_strip", d["steps_per_launch"] - 1) is None
+
+
+def _form(K, launches, full, ms_launch, n=4096):
+    return dict(steps_per_launch=K, launches=launches, full_launches=full,
+                ms_per_launch=ms_launch, bytes_per_lu=192)
+
+
+def test_roofline_of_a_partial_last_launch_uses_the_full_launches(monkeypatch):
+    """20 steps at 8 per launch are 3 launches (8 + 8 + 4); the roofline divides the
+    algorithmic bytes (and flops) of one full launch by the full launches' measured
+    duration."""
+    monkeypatch.setattr(bench, "_summary", lambda *a: None)
+    r = bench.roofline(_form(8, 3, 2, 0.8), 4096, "wave_strip")
+    alg = 4096 * 4096 * 192
+    assert r["bytes_per_launch"] == alg
+    assert r["hbm"]["achieved"] == pytest.approx(alg / 0.8e-3 / 1e9, rel=1e-4)
+    flops = bench.ALG_FLOPS_2D * 4096 * 4096 * 8 / 0.8e-3 / 1e12
+    assert r["alu"]["achieved"] == pytest.approx(flops, rel=1e-3)
+    assert r["bound"] == "alu" and r["frac"] == r["alu"]["frac"]
+    assert r["traffic"] is None and r["valu_busy"] is None
+
+
+def test_roofline_bound_follows_the_counters(monkeypatch):
+    """With SQ counters the bound is the roof the kernel uses more of: VALU issue
+    busy fraction against the DRAM bandwidth fraction."""
+    def fake(kind, which, n, K, busy=0.4):
+        if which == 1:
+            return {"traffic_bytes_per_launch_f64": 3.6e9}
+        return {"f64": {"valu_busy": busy}}
+
+    monkeypatch.setattr(bench, "_summary", lambda k, w, n, K: fake(k, w, n, K, 0.4))
+    r = bench.roofline(_form(8, 250, 250, 0.6), 4096, "wave_strip")
+    # 3.6e9 B in 0.6 ms = 6 TB/s = 0.75 of the peak, above 0.4 VALU busy
+    assert r["bound"] == "hbm" and r["dram_frac"] == pytest.approx(0.75, rel=1e-4)
+    assert r["unit"] == "GB/s" and r["traffic"] == 3.6e9
+    monkeypatch.setattr(bench, "_summary", lambda k, w, n, K: fake(k, w, n, K, 0.9))
+    r = bench.roofline(_form(8, 250, 250, 0.6), 4096, "wave_strip")
+    assert r["bound"] == "alu" and r["unit"] == "TFLOP/s" and r["valu_busy"] == 0.9
