@@ -186,6 +186,23 @@ int lbm_adjoint_terminal(lbm_ctx *ctx, const double *dLdh, void *lam_T);
 int lbm_adjoint_grad_w0(lbm_ctx *ctx, const void *lam0, const double *h0, const double *qx0,
                         const double *qy0, double *grad_h0, double *grad_qx0, double *grad_qy0);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): lbm_moments without a
+ * context and without any allocation.  p describes the state's layout (lattice,
+ * storage, nx, ny, plane_pad are read) and the stream (p->stream); state is a
+ * device buffer in that layout.  h, qx, qy (device doubles, nx*ny, any may be
+ * NULL) receive the conserved fields; totals_dev (device, 3 doubles, may be
+ * NULL) receives (sum h, sum qx, sum qy) by the same kernels and summation order
+ * as lbm_moments' totals, so the values are bitwise equal to them.  Nothing is
+ * allocated, nothing synchronises and no memset is issued: the call only
+ * enqueues kernels on p->stream, so it can be captured in a HIP graph.  The
+ * per-block partial sums use a fixed device array of the library (3 MiB per
+ * GPU, held until the process ends): LBM_EINVAL when totals_dev is given and
+ * nx*ny exceeds 33 554 432 nodes.  Calls that overlap on one GPU (concurrent
+ * streams or threads) share that array and race; order them on one stream. */
+int lbm_moments_noalloc(const lbm_params *p, const void *state, double *h, double *qx,
+                        double *qy, double *totals_dev);
+
 /* Discrete microscopic entropy H(f) = sum_x sum_j h_j(f_j(x)) (Sec. 1), h_j the
  * Legendre dual of the Perthame-Bouchut potential of population j at a = 0
  * (Sec. 2 eq. 2-potentiels-st-venant-1d-suite, Sec. 3 eqs. 3-st-venant-

@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "lbm.h"
@@ -636,5 +637,72 @@ extern "C" int lbm_sum(lbm_ctx *c, const double *partials, long n, double *out_h
     HIP_TRY(hipMemcpyAsync(out_host, c->d_totals + 3, sizeof(double), hipMemcpyDeviceToHost,
                            c->st));
     HIP_TRY(hipStreamSynchronize(c->st));
+    return LBM_OK;
+}
+
+// ------------------------------------------------------- allocation-free totals ----
+// Per-block partial sums of lbm_moments_noalloc live in this file-scope device
+// array: one copy per GPU, held until the process ends.  3 partials per block
+// of 256 nodes, so at most kNoAllocMaxNodes nodes.  Host code never uses the
+// array's name as a device address: the address is taken once per device with
+// hipGetSymbolAddress and kept in g_scratch.
+static constexpr long kNoAllocDoubles = 3L << 17;  // 3 MiB
+static constexpr long kNoAllocMaxNodes = kNoAllocDoubles / 3 * 256;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+static constexpr int kMaxDevices = 64;
+static double *g_scratch[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+// Device address of this GPU's copy of `scratch` (taken on the first call on a
+// device, with that device current).
+static int scratch_ptr(double **out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(LBM_EDEVICE, "device %d beyond the %d the library tracks", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(LBM_EDEVICE, "hipGetSymbolAddress of the totals scratch failed: %s",
+                        hipGetErrorString(e));
+        g_scratch[dev] = (double *)ptr;
+    }
+    *out = g_scratch[dev];
+    return LBM_OK;
+}
+
+extern "C" int lbm_moments_noalloc(const lbm_params *p, const void *state, double *h, double *qx,
+                                   double *qy, double *totals_dev)
+{
+    if (!p) return fail(LBM_EINVAL, "null params");
+    if (!state) return fail(LBM_EINVAL, "null state");
+    long ps;
+    int np;
+    int rc = layout_of(p->lattice, p->storage, p->nx, p->ny, p->plane_pad, &ps, &np, nullptr);
+    if (rc) return rc;
+    const long n = (long)p->nx * p->ny;
+    if (totals_dev && n > kNoAllocMaxNodes)
+        return fail(LBM_EINVAL,
+                    "lbm_moments_noalloc: %ld nodes exceed the %ld its fixed scratch supports "
+                    "(use lbm_moments)",
+                    n, kNoAllocMaxNodes);
+    const int dim = dim_of(p->lattice);
+    Geo G{};
+    G.nx = p->nx;
+    G.ny = p->ny;
+    G.ps = ps;
+    const bool f32 = p->storage == LBM_F32;
+    const hipStream_t st = (hipStream_t)p->stream;
+    double *sp = nullptr;
+    if (totals_dev && (rc = scratch_ptr(&sp))) return rc;
+    int nb = 0;
+    if (rest_of(p->lattice))
+        HIP_TRY(launch_moments_rest(dim, f32, state, h, qx, qy, sp, nullptr, G, st, &nb));
+    else
+        HIP_TRY(launch_moments(dim, f32, state, h, qx, qy, sp, G, st, &nb));
+    if (totals_dev) HIP_TRY(launch_sum(sp, nb, 3, 3, totals_dev, st));
     return LBM_OK;
 }

@@ -79,7 +79,7 @@ class LbmBatchTuning(ctypes.Structure):
 EXPORTS = [
     "lbm_layout", "lbm_init", "lbm_step", "lbm_step_buffers", "lbm_current",
     "lbm_launch_info", "lbm_export",
-    "lbm_import", "lbm_moments", "lbm_entropy", "lbm_adjoint_step", "lbm_adjoint_partials",
+    "lbm_import", "lbm_moments", "lbm_moments_noalloc", "lbm_entropy", "lbm_adjoint_step", "lbm_adjoint_partials",
     "lbm_adjoint_terminal", "lbm_adjoint_grad_w0", "lbm_sum", "lbm_destroy",
     "lbm_batch_layout", "lbm_batch_create", "lbm_batch_init", "lbm_batch_run",
     "lbm_batch_moments", "lbm_batch_current", "lbm_batch_info", "lbm_batch_check",
@@ -113,6 +113,7 @@ def load(path: str = LIB_PATH):
         "lbm_export": (ip, [vp, vp]),
         "lbm_import": (ip, [vp, vp]),
         "lbm_moments": (ip, [vp, vp, vp, vp, vp, dp]),
+        "lbm_moments_noalloc": (ip, [P, vp, vp, vp, vp, vp]),
         "lbm_entropy": (ip, [vp, vp, vp, dp, ctypes.POINTER(ctypes.c_long)]),
         "lbm_adjoint_step": (ip, [vp, vp, vp, vp, vp]),
         "lbm_adjoint_partials": (lp, [vp]),
@@ -211,6 +212,15 @@ def make_params(dim, nx, ny, lam, s, g=1.0, bc=("periodic",) * 4, inflow=None, s
     p.mem_hints = mem_hints
     p.fuse_steps = fuse_steps
     return p
+
+
+def moments_noalloc(p: LbmParams, state, h=None, qx=None, qy=None, totals=None):
+    """lbm_moments_noalloc: conserved fields and FP64 totals of a state in the
+    layout of ``p``, enqueued on ``p.stream`` with no allocation and no
+    synchronisation.  ``state``, ``h``, ``qx``, ``qy``, ``totals`` are device
+    tensors (float64 for the outputs; ``totals`` holds 3 values)."""
+    check(load().lbm_moments_noalloc(ctypes.byref(p), _ptr(state), _ptr(h), _ptr(qx), _ptr(qy),
+                                     _ptr(totals)), "lbm_moments_noalloc")
 
 
 def layout(p: LbmParams):
