@@ -249,82 +249,86 @@ def time_batched(torch, steps=1000):
 
 
 def time_adjoint(torch, n=1024, T=500, K=23, storage="f32"):
+    """The adjoint workload: 1024^2, T = 500, checkpoints every 23 steps, FP32
+    forward.  Timed: the forward rollout and the backward sweep (one library call
+    per checkpoint segment), with the adjoint stored like the state (the default)
+    and in FP64; the gradients of both against those of the FP64 forward (which
+    equals the CPU FP64 oracle's to 1e-15 in the tests); and the adjoint kernel
+    alone against the forward kernel, at 1024^2 and at 4096^2 (both HBM-bound)."""
     from paper_1401_0427_amd import workloads as W
     from paper_1401_0427_amd.adjoint import rollout
 
     c, ht0 = W.adjoint_case(n=n, steps=T)
     target = rollout(torch.as_tensor(ht0, device="cuda"), torch.tensor(c.s, dtype=torch.float64),
-                     T, K, lam=c.lam, storage=storage).detach()
-    h0 = torch.tensor(c.h0, dtype=torch.float64, device="cuda", requires_grad=True)
-    s = torch.tensor(c.s, dtype=torch.float64, device="cuda", requires_grad=True)
-    # one untimed gradient pass: the first backward pays one-time set-up
-    # (module loading, first allocations), which is not the method's cost
-    ((rollout(h0, s, T, K, lam=c.lam, storage=storage) - target) ** 2).sum().backward()
-    h0.grad = None
-    s.grad = None
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    hT = rollout(h0, s, T, K, lam=c.lam, storage=storage)
-    loss = ((hT - target) ** 2).sum()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    loss.backward()
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    # adjoint kernel alone: T adjoint steps on resident buffers
+                     T, K, lam=c.lam, storage="f64").detach()
+
+    def run(st, adj, timed=True):
+        h0 = torch.tensor(c.h0, dtype=torch.float64, device="cuda", requires_grad=True)
+        s = torch.tensor(c.s, dtype=torch.float64, device="cuda", requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hT = rollout(h0, s, T, K, lam=c.lam, storage=st, adjoint_storage=adj)
+        loss = ((hT - target) ** 2).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1, h0.grad.detach(), float(s.grad)
+
+    run(storage, None)  # untimed: one-time set-up (module loading, first allocations)
+    fwd_s, bwd_s, gh, gs = run(storage, None)
+    _, bwd64, gh64, gs64 = run(storage, "f64")
+    _, _, gh_ref, gs_ref = run("f64", None)
+
+    def rel(a, b):
+        return float((a - b).abs().max() / b.abs().max())
+
+    out = dict(n=n, T=T, K=K, storage=storage, adjoint_storage=storage, forward_s=fwd_s,
+               backward_s=bwd_s, grad_mlups=n * n * T / (fwd_s + bwd_s) / 1e6,
+               grad_h0_rel_vs_fp64=rel(gh, gh_ref), grad_s_rel_vs_fp64=abs(gs - gs_ref) / abs(gs_ref),
+               backward_s_adjoint_f64=bwd64, grad_h0_rel_vs_fp64_adjoint_f64=rel(gh64, gh_ref),
+               grad_s_rel_vs_fp64_adjoint_f64=abs(gs64 - gs_ref) / abs(gs_ref),
+               grad_s=gs, grad_h0_norm=float(gh.norm()))
+    # adjoint kernel alone: T adjoint steps on resident buffers, FP32 state, FP64
+    # and FP32 adjoint, against the forward kernel
     from paper_1401_0427_amd.lbm import Solver
 
-    S = Solver(2, n, n, lam=c.lam, s=c.s, h0=c.h0, storage=storage)
-    a, b, u = S.new_state(), S.new_state(), S.current()[0]
-    part = S.adjoint_partials()
-    S.adjoint_step(u, a, b, part)
     st = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(st)
-    for _ in range(T):
-        S.adjoint_step(u, a, b, part)
-        a, b = b, a
-    e1.record(st)
-    torch.cuda.synchronize()
-    adj_ms = e0.elapsed_time(e1) / T
-    e0.record(st)
-    S.step(T)
-    e1.record(st)
-    torch.cuda.synchronize()
-    fwd_ms = e0.elapsed_time(e1) / T
     es = 4 if storage == "f32" else 8
-    out = dict(n=n, T=T, K=K, storage=storage, forward_s=t1 - t0, backward_s=t2 - t1,
-               grad_mlups=n * n * T / (t2 - t0) / 1e6, adjoint_step_ms=adj_ms,
-               forward_step_ms=fwd_ms, adjoint_over_forward=adj_ms / fwd_ms,
-               adjoint_gbs=n * n * 36 * es / (adj_ms * 1e-3) / 1e9,
-               grad_s=float(s.grad), grad_h0_norm=float(h0.grad.norm()))
-    del S, a, b, u, part
-    # the adjoint kernel against the one-step forward kernel on a grid far beyond the
-    # 256 MB MALL (4096^2): both HBM-bound
-    nb, tb = 4096, 50
-    cb, _ = W.adjoint_case(n=nb, steps=tb)
-    S = Solver(2, nb, nb, lam=cb.lam, s=cb.s, h0=cb.h0, storage=storage, fuse_steps=1)
-    a, b, u = S.new_state(), S.new_state(), S.current()[0]
-    part = S.adjoint_partials()
-    S.adjoint_step(u, a, b, part)
-    torch.cuda.synchronize()
-    e0.record(st)
-    for _ in range(tb):
-        S.adjoint_step(u, a, b, part)
-        a, b = b, a
-    e1.record(st)
-    torch.cuda.synchronize()
-    adj_b = e0.elapsed_time(e1) / tb
-    e0.record(st)
-    S.step(tb)
-    e1.record(st)
-    torch.cuda.synchronize()
-    fwd_b = e0.elapsed_time(e1) / tb
-    out.update(adjoint_step_ms_4096=adj_b, forward_one_step_ms_4096=fwd_b,
-               adjoint_over_forward_4096=adj_b / fwd_b,
-               adjoint_gbs_4096=nb * nb * 36 * es / (adj_b * 1e-3) / 1e9,
-               forward_gbs_4096=nb * nb * 24 * es / (fwd_b * 1e-3) / 1e9)
+    for nb, tb, tag in ((n, T, ""), (4096, 50, "_4096")):
+        cb, _ = W.adjoint_case(n=nb, steps=tb)
+        for adj in ("f64", "f32"):
+            S = Solver(2, nb, nb, lam=cb.lam, s=cb.s, h0=cb.h0, storage=storage, fuse_steps=1,
+                       adjoint_storage=adj)
+            a, b, u = S.new_adjoint(), S.new_adjoint(), S.current()[0]
+            part = S.adjoint_partials()
+            S.adjoint_step(u, a, b, part)
+            torch.cuda.synchronize()
+            e0.record(st)
+            for _ in range(tb):
+                S.adjoint_step(u, a, b, part)
+                a, b = b, a
+            e1.record(st)
+            torch.cuda.synchronize()
+            adj_ms = e0.elapsed_time(e1) / tb
+            ea = 4 if adj == "f32" else 8
+            out[f"adjoint_step_ms{tag}_adjoint_{adj}"] = adj_ms
+            out[f"adjoint_gbs{tag}_adjoint_{adj}"] = nb * nb * 12 * (es + 2 * ea) / (adj_ms * 1e-3) / 1e9
+            if adj == "f64":
+                e0.record(st)
+                S.step(tb)
+                e1.record(st)
+                torch.cuda.synchronize()
+                fwd_ms = e0.elapsed_time(e1) / tb
+                out[f"forward_one_step_ms{tag}"] = fwd_ms
+                out[f"forward_gbs{tag}"] = nb * nb * 24 * es / (fwd_ms * 1e-3) / 1e9
+            del S, a, b, u, part
+        torch.cuda.empty_cache()
+    out["adjoint_over_forward"] = out["adjoint_step_ms_adjoint_f64"] / out["forward_one_step_ms"]
+    out["adjoint_over_forward_4096"] = (out["adjoint_step_ms_4096_adjoint_f64"]
+                                        / out["forward_one_step_ms_4096"])
     return out
 
 

@@ -118,6 +118,9 @@ typedef struct {
                              (default 16).  lbm_launch_info reports the choice. */
     void *f_a, *f_b;      /* caller-owned device state buffers (ping-pong) */
     void *stream;         /* hipStream_t; NULL = default stream */
+    int adjoint_storage;  /* element type of adjoint buffers: 0 = the state's,
+                             LBM_F64, or LBM_F32 (only with LBM_F32 states).  A
+                             float state with LBM_F64 keeps lambda in double. */
 } lbm_params;
 
 /* Size of one state buffer for the given parameters (only lattice, storage, nx,
@@ -163,26 +166,45 @@ int lbm_import(lbm_ctx *ctx, const void *src);
 int lbm_moments(lbm_ctx *ctx, const void *state, double *h, double *qx, double *qy,
                 double *totals_host);
 
-/* Discrete adjoint of one step (2D, periodic faces only).  With C the
+/* Discrete adjoint of one step (2D, periodic faces only): the transpose of the
+ * Jacobian of one step of the scheme (Sec. 3 equilibria at a = 0, relaxation of
+ * eq. 2-relaxation with all rates equal, then streaming).  With C the
  * collision, S the pull-stream and u^{n+1} = C(S(u^n)):
  *   v = S(f_n); mu = (d f^eq / d W (W(v)))^T lam_np1 per node;
  *   vt = (1 - s) lam_np1 + s mu (mu broadcast over each component's planes);
  *   lam_n = S^T vt (push to x - e_j);
  *   dLds_partials[b] += sum over block b of lam_np1 . (f^eq(W(v)) - v).
- * f_n, lam_np1, lam_n: caller buffers in the state layout and storage type
- * (lam_n must not alias the others).  dLds_partials: device double array of
- * lbm_adjoint_partials(ctx) entries, accumulated (zero it before the first
- * step).  LBM_EINVAL for 1D or non-periodic contexts. */
+ * f_n: a caller buffer in the state layout and storage type; lam_np1, lam_n:
+ * caller buffers in the state layout whose elements are of the context's
+ * adjoint storage (lbm_params.adjoint_storage; lam_n must not alias the
+ * others).  dLds_partials: device double array of lbm_adjoint_partials(ctx)
+ * entries, accumulated in double (zero it before the first step).  LBM_EINVAL
+ * for 1D or non-periodic contexts. */
 int lbm_adjoint_step(lbm_ctx *ctx, const void *f_n, const void *lam_np1, void *lam_n,
                      double *dLds_partials);
 long lbm_adjoint_partials(lbm_ctx *ctx);
 
+/* Backward sweep over one checkpoint segment in one call (2D, periodic faces),
+ * for checkpointed gradients: from the state ck at level n0 (a caller buffer
+ * in the state layout), recompute levels n0 + 1 .. n0 + nsteps - 1 by single
+ * steps into work (nsteps - 1 consecutive state buffers of lbm_layout bytes
+ * each; may be NULL when nsteps == 1), then apply nsteps adjoint steps
+ * (lbm_adjoint_step) from lam^{n0 + nsteps}, held in lam_a, down to lam^{n0},
+ * alternating between lam_a and lam_b (adjoint storage, not aliasing ck or
+ * work).  *lam_out receives 0 when lam^{n0} ends in lam_a (nsteps even), 1 when
+ * in lam_b.  Only enqueues kernels on the context's stream.  LBM_EINVAL for
+ * nsteps < 1, null buffers or the contexts lbm_adjoint_step rejects. */
+int lbm_adjoint_segment(lbm_ctx *ctx, const void *ck, int nsteps, void *work, void *lam_a,
+                        void *lam_b, double *dLds_partials, int *lam_out);
+
 /* Terminal adjoint for a loss of the final height: lam_T = dL/dh broadcast to
- * the four h planes, zero on the momentum planes.  dLdh: device doubles, nx*ny. */
+ * the four h planes, zero on the momentum planes (adjoint storage).  dLdh:
+ * device doubles, nx*ny. */
 int lbm_adjoint_terminal(lbm_ctx *ctx, const double *dLdh, void *lam_T);
 
 /* Gradient with respect to the initial fields: (dL/dh0, dL/dqx0, dL/dqy0) =
- * J(W0)^T lam0 per node, J = d f^eq / d W.  Outputs may be NULL. */
+ * J(W0)^T lam0 per node, J = d f^eq / d W (the Sec. 3 equilibria at a = 0);
+ * lam0 in adjoint storage.  Outputs may be NULL. */
 int lbm_adjoint_grad_w0(lbm_ctx *ctx, const void *lam0, const double *h0, const double *qx0,
                         const double *qy0, double *grad_h0, double *grad_qx0, double *grad_qy0);
 

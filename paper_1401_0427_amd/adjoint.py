@@ -4,13 +4,15 @@
 initial height field h0 and the relaxation rate s.  Forward: T steps of the
 fused stream + collide kernel, keeping a copy of the state every K steps.
 Backward: for each K-step segment in reverse, recompute its states from the
-checkpoint (one extra forward step per adjoint step), then apply the
-hand-written adjoint kernel step by step (``lbm_adjoint_step``), accumulating
-dL/ds in FP64 per workgroup; finally dL/dh0 = J(W0)^T lam^0.
+checkpoint (one extra forward step per adjoint step) and apply the
+hand-written adjoint kernel step by step -- one library call per segment
+(``lbm_adjoint_segment``) that enqueues all of it -- accumulating dL/ds in FP64
+per workgroup; finally dL/dh0 = J(W0)^T lam^0.
 
 Only the 2D lattice with periodic faces has an adjoint.  Initial momentum is
-zero (the adjoint workload); the state storage may be FP64 or FP32 (the adjoint
-is stored like the state, arithmetic and the s-gradient stay FP64).
+zero (the adjoint workload); the state storage may be FP64 or FP32.  The
+adjoint is stored like the state unless asked otherwise (``adjoint_storage="f64"``
+keeps it in FP64 for an FP32 state); arithmetic and the s-gradient are FP64.
 """
 from __future__ import annotations
 
@@ -23,10 +25,10 @@ from .lbm import Solver
 
 class _Rollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, h0, s, T, K, lam, g, storage, block):
+    def forward(ctx, h0, s, T, K, lam, g, storage, block, adjoint_storage):
         n = h0.shape
         solver = Solver(2, n[1], n[0], lam=lam, s=float(s), g=g, h0=h0.detach(),
-                        storage=storage, block=block)
+                        storage=storage, block=block, adjoint_storage=adjoint_storage)
         cks = {0: solver.current()[0].clone()}
         t = 0
         while t < T:
@@ -45,33 +47,31 @@ class _Rollout(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_hT):
         solver, cks, T, K = ctx.solver, ctx.cks, ctx.T, ctx.K
-        lam_hi = solver.new_state()
-        lam_lo = solver.new_state()
-        solver.adjoint_terminal(grad_hT.contiguous(), lam_hi)
+        lam = [solver.new_adjoint(), solver.new_adjoint()]
+        solver.adjoint_terminal(grad_hT.contiguous(), lam[0])
         partials = solver.adjoint_partials()
-        seg_starts = sorted(cks)
-        seg = [solver.new_state() for _ in range(K)]
-        for s0 in reversed(seg_starts):
-            s1 = min(s0 + K, T)
-            seg[0].copy_(cks[s0])
-            for t in range(s0 + 1, s1):
-                solver.step_buffers(seg[t - s0 - 1], seg[t - s0])
-            for t in range(s1 - 1, s0 - 1, -1):
-                solver.adjoint_step(seg[t - s0], lam_hi, lam_lo, partials)
-                lam_hi, lam_lo = lam_lo, lam_hi
-        gh0 = solver.adjoint_grad_w0(lam_hi)[0]
+        work = solver.new_state(max(1, K - 1))
+        cur = 0
+        for s0 in reversed(sorted(cks)):
+            n = min(s0 + K, T) - s0
+            out = solver.adjoint_segment(cks[s0], n, work, lam[cur], lam[1 - cur], partials)
+            cur = cur if out == 0 else 1 - cur
+        gh0 = solver.adjoint_grad_w0(lam[cur])[0]
         gs = solver.sum(partials)
         ctx.solver = None
         ctx.cks = None
         grad_s = torch.tensor(gs, dtype=torch.float64, device=gh0.device)
-        return gh0, grad_s, None, None, None, None, None, None
+        return gh0, grad_s, None, None, None, None, None, None, None
 
 
 def rollout(h0: torch.Tensor, s: torch.Tensor, T: int, K: int | None = None, lam: float = 3.0,
-            g: float = 1.0, storage: str = "f64", block: int = 256) -> torch.Tensor:
+            g: float = 1.0, storage: str = "f64", block: int = 256,
+            adjoint_storage: str | None = None) -> torch.Tensor:
     """h(T) from W0 = (h0, 0, 0) on the periodic unit square; differentiable in
     h0 (2D float64 CUDA tensor) and s (0-dim float64 tensor).  K defaults to
-    about sqrt(T)."""
+    about sqrt(T).  ``adjoint_storage``: element type of the adjoint buffers
+    (None = the state's, "f64", or "f32" with FP32 state storage)."""
     if K is None:
         K = max(1, int(round(math.sqrt(T))))
-    return _Rollout.apply(h0, s, int(T), int(K), float(lam), float(g), storage, int(block))
+    return _Rollout.apply(h0, s, int(T), int(K), float(lam), float(g), storage, int(block),
+                          adjoint_storage)

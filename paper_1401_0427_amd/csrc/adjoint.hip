@@ -16,7 +16,9 @@
 // (Lxx: x-moment of the gx family, Lyx: y-moment of gx, Lxy: x-moment of gy).
 //
 // Each workgroup adds its share of dL/ds to its own FP64 slot (no atomics), so
-// the gradient is deterministic.
+// the gradient is deterministic.  The adjoint may be stored in another type than
+// the state (TA = double for a float state keeps lambda in double; the
+// arithmetic is double throughout).
 #include "internal.h"
 
 namespace lbm {
@@ -38,9 +40,9 @@ __device__ __forceinline__ void adj_mu(const double *l, double h, double qx, dou
     my = P.c * Lyh + 0.25 * L0y + P.c * (2.0 * v * Lyy + u * cross);
 }
 
-template <typename T>
+template <typename T, typename TA>
 __global__ void __launch_bounds__(256) k_adj2d(const T *__restrict__ un,
-                                               const T *__restrict__ lam1, T *__restrict__ lam0,
+                                               const TA *__restrict__ lam1, TA *__restrict__ lam0,
                                                double *__restrict__ partials, Geo G, Phys P,
                                                int tiles_x, int ntiles)
 {
@@ -77,7 +79,7 @@ __global__ void __launch_bounds__(256) k_adj2d(const T *__restrict__ un,
         const double oms = 1.0 - P.s;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            T *b = lam0 + (4 * k) * ps;
+            TA *b = lam0 + (4 * k) * ps;
             sth<2>(b + row + xm, oms * l[4 * k + 0] + P.s * mu[k]);
             sth<2>(b + ps + rm + x, oms * l[4 * k + 1] + P.s * mu[k]);
             sth<2>(b + 2 * ps + row + xp, oms * l[4 * k + 2] + P.s * mu[k]);
@@ -135,18 +137,23 @@ long adjoint_blocks(const Geo &G)
     return (long)tiles_x * G.ny;
 }
 
-hipError_t launch_adjoint(bool f32, const void *un, const void *lam1, void *lam0,
+hipError_t launch_adjoint(bool f32, bool a32, const void *un, const void *lam1, void *lam0,
                           double *partials, const Geo &G, const Phys &P, hipStream_t st)
 {
     const int tiles_x = (G.nx + 255) / 256;
     const int ntiles = tiles_x * G.ny;
-    if (f32)
-        hipLaunchKernelGGL(k_adj2d<float>, dim3(ntiles), dim3(256), 0, st, (const float *)un,
-                           (const float *)lam1, (float *)lam0, partials, G, P, tiles_x, ntiles);
+    if (f32 && a32)
+        hipLaunchKernelGGL((k_adj2d<float, float>), dim3(ntiles), dim3(256), 0, st,
+                           (const float *)un, (const float *)lam1, (float *)lam0, partials, G, P,
+                           tiles_x, ntiles);
+    else if (f32)
+        hipLaunchKernelGGL((k_adj2d<float, double>), dim3(ntiles), dim3(256), 0, st,
+                           (const float *)un, (const double *)lam1, (double *)lam0, partials, G,
+                           P, tiles_x, ntiles);
     else
-        hipLaunchKernelGGL(k_adj2d<double>, dim3(ntiles), dim3(256), 0, st, (const double *)un,
-                           (const double *)lam1, (double *)lam0, partials, G, P, tiles_x,
-                           ntiles);
+        hipLaunchKernelGGL((k_adj2d<double, double>), dim3(ntiles), dim3(256), 0, st,
+                           (const double *)un, (const double *)lam1, (double *)lam0, partials, G,
+                           P, tiles_x, ntiles);
     return hipGetLastError();
 }
 

@@ -140,6 +140,7 @@ struct lbm_ctx {
     bool rest;  // rest-population scheme (D1Q3Q2 / D2Q5Q4Q4, MRT)
     Mrt M;
     bool f32;
+    bool a32;  // adjoint buffers hold floats (else doubles)
     long ps;
     int np;
     size_t bytes;
@@ -262,6 +263,11 @@ extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0
         return fail(LBM_EINVAL, "nodes_per_thread must be 1, 2 or 4 (got %d)", npt);
     if (p->check_every < 0) return fail(LBM_EINVAL, "check_every must be >= 0");
     if (p->mem_hints > 7) return fail(LBM_EINVAL, "mem_hints must be < 8");
+    if (p->adjoint_storage != 0 && p->adjoint_storage != LBM_F64 && p->adjoint_storage != LBM_F32)
+        return fail(LBM_EINVAL, "adjoint_storage must be 0, LBM_F64 or LBM_F32 (got %d)",
+                    p->adjoint_storage);
+    if (p->adjoint_storage == LBM_F32 && p->storage != LBM_F32)
+        return fail(LBM_EINVAL, "a float adjoint needs float state storage");
     if (p->fuse_steps < 0 || p->fuse_steps > kMaxFuse1d)
         return fail(LBM_EINVAL, "fuse_steps must be in 0 .. %d (got %d)", kMaxFuse1d,
                     p->fuse_steps);
@@ -282,6 +288,7 @@ extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0
         for (int i = 0; i < 10; ++i) c->M.rate[i] = rates[i];
     }
     c->f32 = p->storage == LBM_F32;
+    c->a32 = p->adjoint_storage == 0 ? c->f32 : p->adjoint_storage == LBM_F32;
     c->ps = ps;
     c->np = np;
     c->bytes = bytes;
@@ -603,7 +610,36 @@ extern "C" int lbm_adjoint_step(lbm_ctx *c, const void *f_n, const void *lam_np1
     if (!f_n || !lam_np1 || !lam_n || !dLds_partials) return fail(LBM_EINVAL, "null argument");
     if (lam_n == f_n || lam_n == lam_np1)
         return fail(LBM_EINVAL, "lam_n must not alias f_n or lam_np1");
-    HIP_TRY(launch_adjoint(c->f32, f_n, lam_np1, lam_n, dLds_partials, c->G, c->P, c->st));
+    HIP_TRY(launch_adjoint(c->f32, c->a32, f_n, lam_np1, lam_n, dLds_partials, c->G, c->P,
+                           c->st));
+    return LBM_OK;
+}
+
+extern "C" int lbm_adjoint_segment(lbm_ctx *c, const void *ck, int nsteps, void *work,
+                                   void *lam_a, void *lam_b, double *dLds_partials, int *lam_out)
+{
+    int rc = check_adjoint_ctx(c);
+    if (rc) return rc;
+    if (nsteps < 1) return fail(LBM_EINVAL, "nsteps must be >= 1");
+    if (!ck || !lam_a || !lam_b || !dLds_partials || !lam_out || (nsteps > 1 && !work))
+        return fail(LBM_EINVAL, "null argument");
+    if (lam_a == lam_b || lam_a == ck || lam_b == ck || lam_a == work || lam_b == work)
+        return fail(LBM_EINVAL, "lam_a / lam_b must not alias each other, ck or work");
+    // level n0 + i: ck for i = 0, else work slot i - 1
+    auto level = [&](int i) -> const void * {
+        return i == 0 ? ck : (const void *)((char *)work + (size_t)(i - 1) * c->bytes);
+    };
+    for (int i = 1; i < nsteps; ++i)
+        HIP_TRY(step_once(c, level(i - 1), (void *)level(i), c->st));
+    void *hi = lam_a, *lo = lam_b;
+    for (int i = nsteps - 1; i >= 0; --i) {
+        HIP_TRY(launch_adjoint(c->f32, c->a32, level(i), hi, lo, dLds_partials, c->G, c->P,
+                               c->st));
+        void *t = hi;
+        hi = lo;
+        lo = t;
+    }
+    *lam_out = hi == lam_a ? 0 : 1;
     return LBM_OK;
 }
 
@@ -612,7 +648,7 @@ extern "C" int lbm_adjoint_terminal(lbm_ctx *c, const double *dLdh, void *lam_T)
     int rc = check_adjoint_ctx(c);
     if (rc) return rc;
     if (!dLdh || !lam_T) return fail(LBM_EINVAL, "null argument");
-    HIP_TRY(launch_adjoint_terminal(c->f32, dLdh, lam_T, c->G, c->st));
+    HIP_TRY(launch_adjoint_terminal(c->a32, dLdh, lam_T, c->G, c->st));
     return LBM_OK;
 }
 
@@ -623,7 +659,7 @@ extern "C" int lbm_adjoint_grad_w0(lbm_ctx *c, const void *lam0, const double *h
     int rc = check_adjoint_ctx(c);
     if (rc) return rc;
     if (!lam0 || !h0) return fail(LBM_EINVAL, "null argument");
-    HIP_TRY(launch_adjoint_grad_w0(c->f32, lam0, h0, qx0, qy0, grad_h0, grad_qx0, grad_qy0,
+    HIP_TRY(launch_adjoint_grad_w0(c->a32, lam0, h0, qx0, qy0, grad_h0, grad_qx0, grad_qy0,
                                    c->G, c->P, c->st));
     return LBM_OK;
 }

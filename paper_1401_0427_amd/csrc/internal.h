@@ -63,7 +63,9 @@ hipError_t launch_check(int dim, bool f32, const void *state, const Geo &G, int 
                         hipStream_t st);
 int moments_blocks(const Geo &G);
 
-hipError_t launch_adjoint(bool f32, const void *un, const void *lam1, void *lam0,
+// f32: state storage float; a32: adjoint storage float (double otherwise; a float
+// adjoint needs a float state)
+hipError_t launch_adjoint(bool f32, bool a32, const void *un, const void *lam1, void *lam0,
                           double *partials, const Geo &G, const Phys &P, hipStream_t st);
 long adjoint_blocks(const Geo &G);
 hipError_t launch_adjoint_terminal(bool f32, const double *dLdh, void *lam, const Geo &G,

@@ -53,6 +53,7 @@ class LbmParams(ctypes.Structure):
         ("f_a", ctypes.c_void_p),
         ("f_b", ctypes.c_void_p),
         ("stream", ctypes.c_void_p),
+        ("adjoint_storage", ctypes.c_int),
     ]
 
 
@@ -78,7 +79,7 @@ class LbmBatchTuning(ctypes.Structure):
 
 EXPORTS = [
     "lbm_layout", "lbm_init", "lbm_step", "lbm_step_buffers", "lbm_current",
-    "lbm_launch_info", "lbm_export",
+    "lbm_launch_info", "lbm_export", "lbm_adjoint_segment",
     "lbm_import", "lbm_moments", "lbm_moments_noalloc", "lbm_entropy", "lbm_adjoint_step", "lbm_adjoint_partials",
     "lbm_adjoint_terminal", "lbm_adjoint_grad_w0", "lbm_sum", "lbm_destroy",
     "lbm_batch_layout", "lbm_batch_create", "lbm_batch_init", "lbm_batch_run",
@@ -117,6 +118,7 @@ def load(path: str = LIB_PATH):
         "lbm_entropy": (ip, [vp, vp, vp, dp, ctypes.POINTER(ctypes.c_long)]),
         "lbm_adjoint_step": (ip, [vp, vp, vp, vp, vp]),
         "lbm_adjoint_partials": (lp, [vp]),
+        "lbm_adjoint_segment": (ip, [vp, vp, ip, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int)]),
         "lbm_adjoint_terminal": (ip, [vp, vp, vp]),
         "lbm_adjoint_grad_w0": (ip, [vp, vp, vp, vp, vp, vp, vp, vp]),
         "lbm_sum": (ip, [vp, vp, lp, dp]),
@@ -185,7 +187,7 @@ def _bc_codes(bc):
 
 def make_params(dim, nx, ny, lam, s, g=1.0, bc=("periodic",) * 4, inflow=None, storage="f64",
                 check_every=0, block=256, npt=1, plane_pad=-1, mem_hints=-1, rest=False, a=0.0,
-                rates=None, fuse_steps=0) -> LbmParams:
+                rates=None, fuse_steps=0, adjoint_storage=None) -> LbmParams:
     """Parameter block; ``rest`` selects the rest-population schemes D1Q3Q2 /
     D2Q5Q4Q4 (weight ``a``, MRT ``rates``; 0 / missing rates take ``s``)."""
     p = LbmParams()
@@ -211,6 +213,7 @@ def make_params(dim, nx, ny, lam, s, g=1.0, bc=("periodic",) * 4, inflow=None, s
     p.plane_pad = plane_pad
     p.mem_hints = mem_hints
     p.fuse_steps = fuse_steps
+    p.adjoint_storage = {None: 0, "f64": F64, "f32": F32}.get(adjoint_storage, adjoint_storage)
     return p
 
 
@@ -236,7 +239,7 @@ class Solver:
     def __init__(self, dim, nx, ny=1, lam=3.0, s=1.8, g=1.0, bc=("periodic",) * 4, inflow=None,
                  h0=None, qx0=None, qy0=None, storage="f64", check_every=0, block=256, npt=1,
                  plane_pad=-1, mem_hints=-1, rest=False, a=0.0, rates=None, fuse_steps=0,
-                 device="cuda"):
+                 adjoint_storage=None, device="cuda"):
         import torch
 
         _require_gpu(torch)
@@ -245,9 +248,13 @@ class Solver:
         self.dim = dim
         self.nx, self.ny = nx, (ny if dim == 2 else 1)
         self.params = make_params(dim, nx, ny, lam, s, g, bc, inflow, storage, check_every, block,
-                                  npt, plane_pad, mem_hints, rest, a, rates, fuse_steps)
+                                  npt, plane_pad, mem_hints, rest, a, rates, fuse_steps,
+                                  adjoint_storage)
         self.ps, self.nplanes, self.nbytes = layout(self.params)
         self.dtype = torch.float32 if self.params.storage == F32 else torch.float64
+        a32 = self.params.adjoint_storage == F32 or (self.params.adjoint_storage == 0
+                                                     and self.params.storage == F32)
+        self.adj_dtype = torch.float32 if a32 else torch.float64
         self.device = torch.device(device)
         self.fa = torch.empty(self.nplanes * self.ps, dtype=self.dtype, device=self.device)
         self.fb = torch.empty_like(self.fa)
@@ -298,8 +305,14 @@ class Solver:
             return buf.as_strided((self.nplanes, self.nx), (self.ps, 1))
         return buf.as_strided((self.nplanes, self.ny, self.nx), (self.ps, self.nx, 1))
 
-    def new_state(self):
-        return self.torch.zeros(self.nplanes * self.ps, dtype=self.dtype, device=self.device)
+    def new_state(self, count=1):
+        """Zeroed buffer of ``count`` consecutive states in this layout."""
+        return self.torch.zeros(count * self.nplanes * self.ps, dtype=self.dtype,
+                                device=self.device)
+
+    def new_adjoint(self):
+        """Zeroed adjoint buffer (state layout, the context's adjoint storage)."""
+        return self.torch.zeros(self.nplanes * self.ps, dtype=self.adj_dtype, device=self.device)
 
     def export(self, dst):
         check(load().lbm_export(self.ctx, _ptr(dst)), "lbm_export")
@@ -348,6 +361,15 @@ class Solver:
     def adjoint_step(self, f_n, lam_np1, lam_n, partials):
         check(load().lbm_adjoint_step(self.ctx, _ptr(f_n), _ptr(lam_np1), _ptr(lam_n),
                                       _ptr(partials)), "lbm_adjoint_step")
+
+    def adjoint_segment(self, ck, nsteps, work, lam_a, lam_b, partials):
+        """lbm_adjoint_segment: recompute a checkpoint segment into ``work`` and run
+        its ``nsteps`` adjoint steps; returns 0 / 1 = lam_a / lam_b holds the result."""
+        out = ctypes.c_int(-1)
+        check(load().lbm_adjoint_segment(self.ctx, _ptr(ck), int(nsteps), _ptr(work), _ptr(lam_a),
+                                         _ptr(lam_b), _ptr(partials), ctypes.byref(out)),
+              "lbm_adjoint_segment")
+        return out.value
 
     def adjoint_terminal(self, dLdh, lam_T):
         dLdh = dLdh.to(dtype=self.torch.float64).contiguous()

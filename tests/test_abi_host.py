@@ -47,7 +47,8 @@ def test_layout_pads_planes(L):
                                  dict(nx=1), dict(bc=("periodic", "wall", "periodic", "periodic")),
                                  dict(block=100), dict(npt=3), dict(fuse_steps=17),
                                  dict(fuse_steps=32), dict(fuse_steps=-1),
-                                 dict(bc=("inflow", "wall", "periodic", "periodic"), inflow={0: (0.0, 0, 0)})])
+                                 dict(bc=("inflow", "wall", "periodic", "periodic"), inflow={0: (0.0, 0, 0)}),
+                                 dict(adjoint_storage="f32"), dict(adjoint_storage=16)])
 def test_init_rejects_bad_parameters_without_touching_memory(L, bad):
     kw = dict(dim=2, nx=64, ny=64, lam=6.0, s=1.8)
     kw.update(bad)
