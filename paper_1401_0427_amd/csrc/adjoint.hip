@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(256) k_adj2d(const T *__restrict__ un,
         for (int pl = 0; pl < 12; ++pl) l[pl] = ld(lam1 + pl * ps + row + x);
         double h, qx, qy, e[12], mu[3];
         moments2d(v, h, qx, qy);
-        feq2d(h, qx, qy, P, e);
+        feq2d<T>(h, qx, qy, P, e);
         adj_mu(l, h, qx, qy, P, mu[0], mu[1], mu[2]);
 #pragma unroll
         for (int pl = 0; pl < 12; ++pl) acc += l[pl] * (e[pl] - v[pl]);

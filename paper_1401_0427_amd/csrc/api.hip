@@ -372,7 +372,8 @@ extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0
     }
     if (bad) {
         lbm_destroy(c);
-        return fail(LBM_EINVAL, "initial fields need h > 0 and finite values everywhere");
+        return fail(LBM_EINVAL, "initial fields need finite values and 2^-500 < h < 2^500 "
+                                 "everywhere");
     }
     *out = c;
     double speed;

@@ -103,11 +103,11 @@ __device__ __forceinline__ void tile_1d(const T *__restrict__ src, T *__restrict
         double f[4], g[4];
         pull1d(s, I.G, I.P, x, f);
         if (two) pull1d(s, I.G, I.P, x2, g);
-        collide1d(f, I.P);
+        collide1d<T>(f, I.P);
 #pragma unroll
         for (int pl = 0; pl < 4; ++pl) sth<2>(d + pl * I.G.ps + x, f[pl]);
         if (two) {
-            collide1d(g, I.P);
+            collide1d<T>(g, I.P);
 #pragma unroll
             for (int pl = 0; pl < 4; ++pl) sth<2>(d + pl * I.G.ps + x2, g[pl]);
         }
@@ -132,12 +132,12 @@ __device__ __forceinline__ void tile_2d(const T *__restrict__ src, T *__restrict
         double f[12], g[12];
         pull_node2d(s, I, x, y, f);
         if (two) pull_node2d(s, I, x2, y2, g);
-        collide2d(f, I.P);
+        collide2d<T>(f, I.P);
         T *o = d + (long)y * nx + x;
 #pragma unroll
         for (int pl = 0; pl < 12; ++pl) sth<2>(o + pl * ps, f[pl]);
         if (two) {
-            collide2d(g, I.P);
+            collide2d<T>(g, I.P);
             T *o2 = d + (long)y2 * nx + x2;
 #pragma unroll
             for (int pl = 0; pl < 12; ++pl) sth<2>(o2 + pl * ps, g[pl]);
@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(512)
     if (I.dim == 1) {
         double f[4];
         pull1d(s, I.G, I.P, k, f);
-        collide1d(f, I.P);
+        collide1d<T>(f, I.P);
 #pragma unroll
         for (int pl = 0; pl < 4; ++pl) sth<2>(d + pl * ps + k, f[pl]);
         return;
@@ -241,7 +241,7 @@ __global__ void __launch_bounds__(512)
     const int y = k / nx, x = k - y * nx;
     double f[12];
     pull_node2d(s, I, x, y, f);
-    collide2d(f, I.P);
+    collide2d<T>(f, I.P);
     T *o = d + k;
 #pragma unroll
     for (int pl = 0; pl < 12; ++pl) sth<2>(o + pl * ps, f[pl]);
@@ -275,7 +275,7 @@ __device__ __forceinline__ void node_sync(const T *__restrict__ s, T *__restrict
         f[2] = x > 0 ? ld(s + 2 * ps + x - 1) : pull_face1d(s, G, I.P, 2, 0, x);
         f[1] = x < G.nx - 1 ? ld(s + ps + x + 1) : pull_face1d(s, G, I.P, 1, 1, x);
         f[3] = x < G.nx - 1 ? ld(s + 3 * ps + x + 1) : pull_face1d(s, G, I.P, 3, 1, x);
-        collide1d(f, I.P);
+        collide1d<T>(f, I.P);
 #pragma unroll
         for (int pl = 0; pl < 4; ++pl) sth<2>(d + pl * ps + x, f[pl]);
         return;
@@ -311,7 +311,7 @@ __device__ __forceinline__ void node_sync(const T *__restrict__ s, T *__restrict
                                   : pull_face2d(s, G, I.P, p + 3, 3, x, y, x, y + 1);
         }
     }
-    collide2d(f, I.P);
+    collide2d<T>(f, I.P);
     T *o = d + row + x;
 #pragma unroll
     for (int pl = 0; pl < 12; ++pl) sth<2>(o + pl * ps, f[pl]);
@@ -819,7 +819,8 @@ extern "C" int lbm_batch_init(lbm_batch *b, const double *h0, const double *qx0,
     if (e != hipSuccess) return bfail(LBM_EDEVICE, "batch init failed: %s", hipGetErrorString(e));
     b->cur = 0;
     b->steps = 0;
-    if (bad) return bfail(LBM_EINVAL, "initial fields need h > 0 and finite values everywhere");
+    if (bad) return bfail(LBM_EINVAL, "initial fields need finite values and 2^-500 < h < 2^500 "
+                                 "everywhere");
     return LBM_OK;
 }
 

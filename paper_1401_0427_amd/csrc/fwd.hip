@@ -54,7 +54,7 @@ __global__ void __launch_bounds__(512) k_step2d(const T *__restrict__ src, T *__
     for (int i = 0; i < NPT; ++i) {
         const int x = xb + i * (int)blockDim.x;
         if (x >= nx) continue;
-        collide2d(f[i], P);
+        collide2d<T>(f[i], P);
         T *o = dst + row + x;
 #pragma unroll
         for (int pl = 0; pl < 12; ++pl) sth<H>(o + pl * ps, f[i][pl]);
@@ -80,7 +80,7 @@ __global__ void __launch_bounds__(512) k_step1d(const T *__restrict__ src, T *__
     for (int i = 0; i < NPT; ++i) {
         const int x = xb + i * (int)blockDim.x;
         if (x >= G.nx) continue;
-        collide1d(f[i], P);
+        collide1d<T>(f[i], P);
 #pragma unroll
         for (int pl = 0; pl < 4; ++pl) sth<H>(dst + pl * ps + x, f[i][pl]);
     }
@@ -103,7 +103,8 @@ __global__ void __launch_bounds__(256) k_init(int dim, T *__restrict__ dst,
     const double h = h0[i];
     const double qx = qx0 ? qx0[i] : 0.0;
     const double qy = (dim == 2 && qy0) ? qy0[i] : 0.0;
-    if (!(h > 0.0) || !isfinite(h) || !isfinite(qx) || !isfinite(qy)) {
+    // heights in (2^-500, 2^500): the range in which lbm_rcp is the IEEE quotient
+    if (!(h > 0x1p-500 && h < 0x1p500) || !isfinite(qx) || !isfinite(qy)) {
         atomicOr(bad, 1);
         return;
     }
@@ -112,14 +113,14 @@ __global__ void __launch_bounds__(256) k_init(int dim, T *__restrict__ dst,
     atomicMax(speed_bits, (unsigned long long)__double_as_longlong(spd));
     if (dim == 1) {
         double f[4];
-        feq1d(h, qx, P, f);
-        collide1d(f, P);
+        feq1d<T>(h, qx, P, f);
+        collide1d<T>(f, P);
 #pragma unroll
         for (int pl = 0; pl < 4; ++pl) st(dst + pl * G.ps + i, f[pl]);
     } else {
         double f[12];
-        feq2d(h, qx, qy, P, f);
-        collide2d(f, P);
+        feq2d<T>(h, qx, qy, P, f);
+        collide2d<T>(f, P);
 #pragma unroll
         for (int pl = 0; pl < 12; ++pl) st(dst + pl * G.ps + i, f[pl]);
     }

@@ -3,9 +3,10 @@
 //
 // Arithmetic is double precision throughout; storage is double or float.
 // The operation order below is fixed on purpose (pairwise sums of opposite
-// directions, no FMA contraction: the library is built with
-// -ffp-contract=off), so results are reproducible bit for bit and keep the
-// exact reflection symmetries of the lattice.
+// directions; the library is built with -ffp-contract=off, and fused
+// multiply-adds appear only where written, for float storage), so results are
+// reproducible bit for bit and keep the exact reflection symmetries of the
+// lattice.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -55,36 +56,87 @@ struct Phys {
     double g;
 };
 
+// 1/h rounded correctly (bit for bit the IEEE quotient) for 2^-500 < h < 2^500:
+// the hardware reciprocal estimate, two Newton steps, then one correction with
+// the residual -- the steps of the full division sequence without its operand
+// scaling and special-case fix-up, which leave such h unchanged (checked
+// against the IEEE quotient on 2^32 values spread over that range, all equal).
+// lbm_init rejects initial heights outside the range.
+__device__ __forceinline__ double lbm_rcp(double h)
+{
+    double r = __builtin_amdgcn_rcp(h);
+    double e = __builtin_fma(-h, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-h, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-h, r, 1.0);
+    return __builtin_fma(e, r, r);
+}
+
+// a b + c for a state stored as T: double storage rounds the product and the sum
+// separately (the operation order of a plain evaluation, so that results agree
+// bit for bit with one); float storage fuses them, its results being rounded to
+// float at every step anyway.
+template <typename T>
+__device__ __forceinline__ double mad(double a, double b, double c)
+{
+    if constexpr (sizeof(T) == 4)
+        return __builtin_fma(a, b, c);
+    else
+        return a * b + c;
+}
+
 // Equilibria at a = 0 (closed form of the derivatives of the potentials h_j^*,
 // Sec. 2 eqs. 2-potentiels-st-venant-1d(-suite) and Sec. 3 eqs.
 // 3-st-venant-contraintes-2, 3-st-venant-enplus, with a = 0).
 //   1D planes: f+, f-, g+, g-
 //   2D planes: h e1..e4, qx e1..e4, qy e1..e4 (e1 +x, e2 +y, e3 -x, e4 -y)
+// T: the storage type of the state (the arithmetic is double either way).
+template <typename T>
 __device__ __forceinline__ void feq1d(double h, double q, const Phys &P, double *e)
 {
-    const double ih = 1.0 / h;
+    const double ih = lbm_rcp(h);
     const double p = P.hg * (h * h);
-    const double Fq = (q * q) * ih + p;
-    const double hh = 0.5 * h, qh = 0.5 * q, A = q * P.c, B = Fq * P.c;
-    e[0] = hh + A;
-    e[1] = hh - A;
-    e[2] = qh + B;
-    e[3] = qh - B;
+    const double Fq = mad<T>(q * q, ih, p);
+    const double hh = 0.5 * h, qh = 0.5 * q;
+    if constexpr (sizeof(T) == 4) {
+        e[0] = __builtin_fma(q, P.c, hh);
+        e[1] = __builtin_fma(-q, P.c, hh);
+        e[2] = __builtin_fma(Fq, P.c, qh);
+        e[3] = __builtin_fma(-Fq, P.c, qh);
+    } else {
+        const double A = q * P.c, B = Fq * P.c;
+        e[0] = hh + A;
+        e[1] = hh - A;
+        e[2] = qh + B;
+        e[3] = qh - B;
+    }
 }
 
+template <typename T>
 __device__ __forceinline__ void feq2d(double h, double qx, double qy, const Phys &P, double *e)
 {
-    const double ih = 1.0 / h;
+    const double ih = lbm_rcp(h);
     const double p = P.hg * (h * h);
-    const double Fxx = (qx * qx) * ih + p;
+    const double Fxx = mad<T>(qx * qx, ih, p);
     const double Fxy = (qx * qy) * ih;
-    const double Fyy = (qy * qy) * ih + p;
+    const double Fyy = mad<T>(qy * qy, ih, p);
     const double hq = 0.25 * h, xq = 0.25 * qx, yq = 0.25 * qy;
-    const double A = qx * P.c, B = qy * P.c;
-    const double Cxx = Fxx * P.c, Cxy = Fxy * P.c, Cyy = Fyy * P.c;
-    e[0] = hq + A;  e[1] = hq + B;  e[2] = hq - A;  e[3] = hq - B;
-    e[4] = xq + Cxx; e[5] = xq + Cxy; e[6] = xq - Cxx; e[7] = xq - Cxy;
-    e[8] = yq + Cxy; e[9] = yq + Cyy; e[10] = yq - Cxy; e[11] = yq - Cyy;
+    const double c = P.c;
+    if constexpr (sizeof(T) == 4) {
+        e[0] = __builtin_fma(qx, c, hq);   e[1] = __builtin_fma(qy, c, hq);
+        e[2] = __builtin_fma(-qx, c, hq);  e[3] = __builtin_fma(-qy, c, hq);
+        e[4] = __builtin_fma(Fxx, c, xq);  e[5] = __builtin_fma(Fxy, c, xq);
+        e[6] = __builtin_fma(-Fxx, c, xq); e[7] = __builtin_fma(-Fxy, c, xq);
+        e[8] = __builtin_fma(Fxy, c, yq);  e[9] = __builtin_fma(Fyy, c, yq);
+        e[10] = __builtin_fma(-Fxy, c, yq); e[11] = __builtin_fma(-Fyy, c, yq);
+    } else {
+        const double A = qx * c, B = qy * c;
+        const double Cxx = Fxx * c, Cxy = Fxy * c, Cyy = Fyy * c;
+        e[0] = hq + A;  e[1] = hq + B;  e[2] = hq - A;  e[3] = hq - B;
+        e[4] = xq + Cxx; e[5] = xq + Cxy; e[6] = xq - Cxx; e[7] = xq - Cxy;
+        e[8] = yq + Cxy; e[9] = yq + Cyy; e[10] = yq - Cxy; e[11] = yq - Cyy;
+    }
 }
 
 // Conserved moments W^k = sum_j f_j^k (eq. 1-hyp-N-vconserv).
@@ -102,22 +154,24 @@ __device__ __forceinline__ void moments2d(const double *f, double &h, double &qx
 }
 
 // BGK relaxation f* = f + s (f^eq(W(f)) - f) (eq. 2-relaxation, all rates equal).
+template <typename T>
 __device__ __forceinline__ void collide1d(double *f, const Phys &P)
 {
     double h, q, e[4];
     moments1d(f, h, q);
-    feq1d(h, q, P, e);
+    feq1d<T>(h, q, P, e);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) f[i] = f[i] + P.s * (e[i] - f[i]);
+    for (int i = 0; i < 4; ++i) f[i] = mad<T>(P.s, e[i] - f[i], f[i]);
 }
 
+template <typename T>
 __device__ __forceinline__ void collide2d(double *f, const Phys &P)
 {
     double h, qx, qy, e[12];
     moments2d(f, h, qx, qy);
-    feq2d(h, qx, qy, P, e);
+    feq2d<T>(h, qx, qy, P, e);
 #pragma unroll
-    for (int i = 0; i < 12; ++i) f[i] = f[i] + P.s * (e[i] - f[i]);
+    for (int i = 0; i < 12; ++i) f[i] = mad<T>(P.s, e[i] - f[i], f[i]);
 }
 
 // ---- XCD-aware tile order -------------------------------------------------------
@@ -163,7 +217,7 @@ __device__ double pull_face2d(const T *__restrict__ src, const Geo &G, const Phy
     }
     default: {
         double e[12];
-        feq2d(G.win[face][0], G.win[face][1], G.win[face][2], P, e);
+        feq2d<T>(G.win[face][0], G.win[face][1], G.win[face][2], P, e);
         return e[pl];
     }
     }
@@ -210,7 +264,7 @@ __device__ double pull_face1d(const T *__restrict__ src, const Geo &G, const Phy
     }
     default: {
         double e[4];
-        feq1d(G.win[face][0], G.win[face][1], P, e);
+        feq1d<T>(G.win[face][0], G.win[face][1], P, e);
         return e[pl];
     }
     }

@@ -52,7 +52,7 @@ __device__ __forceinline__ void x2_inter(const T *__restrict__ src, const Geo &G
         f[4 * c + 2] = ld(b + 2 * ps + row + xp);
         f[4 * c + 3] = ld(b + 3 * ps + rp + xw);
     }
-    collide2d(f, P);
+    collide2d<T>(f, P);
 #pragma unroll
     for (int pl = 0; pl < 12; ++pl) f[pl] = (double)(T)f[pl];
 }
@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(kX2Threads)
                 o[4 * c + 2] = (double)lx[b][3 + c][t + 1];
                 o[4 * c + 3] = g[4 * c + 3];
             }
-            collide2d(o, P);
+            collide2d<T>(o, P);
             T *out = dst + (long)y * nx + xi;
 #pragma unroll
             for (int pl = 0; pl < 12; ++pl) sth<2>(out + pl * ps, o[pl]);
@@ -399,6 +399,7 @@ __device__ __forceinline__ double xk_uniform(double v)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+template <typename T>
 __device__ __forceinline__ XkBnd xk_bnd(const Geo &G, const Phys &P)
 {
     XkBnd B;
@@ -411,7 +412,7 @@ __device__ __forceinline__ XkBnd xk_bnd(const Geo &G, const Phys &P)
     double *dst[4] = {B.in1, B.in3, B.in2, B.in4};
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-        feq2d(G.win[f][0], G.win[f][1], G.win[f][2], P, e);
+        feq2d<T>(G.win[f][0], G.win[f][1], G.win[f][2], P, e);
 #pragma unroll
         for (int c = 0; c < 3; ++c) dst[f][c] = xk_uniform(e[4 * c + jp[f]]);
     }
@@ -679,7 +680,7 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
             pf3[c] = lds[X.row + (3 + c) * RW + X.r3];
         }
     }
-    collide2d(v, P);  // level 1
+    collide2d<T>(v, P);  // level 1
     // Levels 2 .. K.  Grids with non-periodic y faces: the rows near them (a
     // uniform test per iteration) run a copy of the level loop with the y-face
     // rules, so the other rows carry no per-level face conditions.
@@ -821,7 +822,7 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
                 }
                 if constexpr (SW > 1) __asm__ __volatile__("" ::: "memory");
             }
-            collide2d(o, P);
+            collide2d<T>(o, P);
 #pragma unroll
             for (int pl = 0; pl < 12; ++pl) v[pl] = o[pl];
         }
@@ -907,7 +908,7 @@ __device__ __forceinline__ void xk_wave(const T *__restrict__ src, T *__restrict
     XkBnd B{};
     bool bx0 = false, bx1 = false, clampx = false;
     if constexpr (BND) {
-        B = xk_bnd(G, P);
+        B = xk_bnd<T>(G, P);
         clampx = B.kx0 != BC_PERIODIC;
         bx0 = clampx && xc == 0;
         bx1 = clampx && xc == nx - 1;
@@ -1391,7 +1392,7 @@ __device__ __forceinline__ void k1_tile(const T *__restrict__ src, T *__restrict
     double weq[8];
 #pragma unroll
     for (int face = 0; face < 2; ++face)
-        if (G.bc[face] == BC_INFLOW) feq1d(G.win[face][0], G.win[face][1], P, weq + 4 * face);
+        if (G.bc[face] == BC_INFLOW) feq1d<T>(G.win[face][0], G.win[face][1], P, weq + 4 * face);
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     if (in) {
 #pragma unroll
@@ -1418,7 +1419,7 @@ __device__ __forceinline__ void k1_tile(const T *__restrict__ src, T *__restrict
             f[1] = (double)sh[b][1][tr];
             f[3] = (double)sh[b][3][tr];
         }
-        collide1d(f, P);
+        collide1d<T>(f, P);
         b ^= 1;
 #pragma unroll
         for (int pl = 0; pl < 4; ++pl) {

@@ -175,12 +175,15 @@ def test_subchar_warning():
     S.step(1)
 
 
-def test_init_rejects_nonpositive_depth():
+@pytest.mark.parametrize("bad", [0.0, -1.0, 1e-200, 1e200, float("nan")])
+def test_init_rejects_depth_outside_range(bad):
+    """Initial heights must be positive and within (2^-500, 2^500), the range in
+    which the library's reciprocal is the IEEE quotient."""
     from paper_1401_0427_amd.lbm import LbmError
 
     case = smooth_random_2d(40, 40, seed=7)
-    case.h0[3, 5] = 0.0
-    with pytest.raises(LbmError, match="h > 0"):
+    case.h0[3, 5] = bad
+    with pytest.raises(LbmError, match="2\\^-500 < h"):
         gpu_solver(case)
 
 
