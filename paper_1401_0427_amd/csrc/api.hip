@@ -179,16 +179,10 @@ static const int kFuseMinBlocks = 1024;
 // levels in LDS).
 static const int kDefaultFuse1d = 16;
 static const int kMaxFuse1d = 16;
-#ifndef LBM_FUSE_SEG
-#define LBM_FUSE_SEG 24
-#endif
-static const int kFuseSeg = LBM_FUSE_SEG;  // rows per workgroup segment of the LDS two-step launch
-#ifndef LBM_XK_SEG
-#define LBM_XK_SEG 160
-#endif
+static const int kFuseSeg = 24;  // rows per workgroup segment of the LDS two-step launch
 // Rows per wavefront segment of the wave-strip launch when the device cannot be
 // queried (else chosen per grid at init, step2k_seg).
-static const int kXkSeg = LBM_XK_SEG;
+static const int kXkSeg = 160;
 // Default steps per launch on all-periodic 2D grids (wave-strip kernel).
 // FP64: 8 (GLUPS at 1024^2 / 2048^2 / 3072^2 / 4096^2 for K = 6, 7, 8: 75, 81,
 // 79 / 119, 134, 136 / 136, 155, 167 / 139, 160, 176; one step at 4096^2: 29).
@@ -200,16 +194,13 @@ static const int kDefaultFuse2dF32 = 8;
 static const int kDefaultFuse2dF32Small = 6;
 // With non-periodic faces the wave-strip kernel takes at most
 // step2k_max_k_bounded() (8) steps per launch, and step2k_default_k_bounded() by
-// default (FP64 6, FP32 5): at 4096^2 (inflow / Neumann / wall faces) FP64 132
-// GLUPS (one step: 28), FP32 166 (59).
+// default (FP64 6, FP32 8): at 4096^2 (inflow / Neumann / wall faces) FP64 133
+// GLUPS (one step: 28), FP32 177-179 (one step: 59).
 // Shortest segment of a wave-strip launch (the halo rows cost 2 (K - 1) per
 // segment; the segment length itself is chosen per grid, step2k_seg).  Grids
 // whose launch cannot fill a third of the device keep the one- or two-step
 // launches by default.
 static const int kXkMinSeg = 16;
-#ifndef LBM_FUSE2_LDS
-#define LBM_FUSE2_LDS 1  // two steps per launch: the LDS strip kernel (faster at K = 2)
-#endif
 // 2D all-periodic: steps per launch at most (wave-strip kernel: K = 2 .. 8)
 static const int kMaxFuse2d = 8;
 
@@ -300,7 +291,7 @@ extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0
         const bool allper = p->bc[0] == LBM_BC_PERIODIC && p->bc[1] == LBM_BC_PERIODIC &&
                             p->bc[2] == LBM_BC_PERIODIC && p->bc[3] == LBM_BC_PERIODIC;
         int want = p->fuse_steps;
-        c->x2 = allper && LBM_FUSE2_LDS;
+        c->x2 = allper;  // two steps per launch: the LDS strip kernel (faster at K = 2)
         if (rest)
             c->fuse = 1;
         else if (dim == 1)

@@ -28,10 +28,7 @@
 
 namespace lbm {
 
-#ifndef LBM_X2_THREADS
-#define LBM_X2_THREADS 512
-#endif
-constexpr int kX2Threads = LBM_X2_THREADS;  // threads (columns) per workgroup
+constexpr int kX2Threads = 512;  // threads (columns) per workgroup
 constexpr int kX2Out = kX2Threads - 2;
 
 // Post-collision level-n+1 node (xw, yw) of the all-periodic grid, rounded to T.
@@ -155,74 +152,33 @@ __global__ void __launch_bounds__(kX2Threads)
 // loop is unrolled by two with the roles of the row registers swapped, so no
 // register is copied from one row to the next; plane addresses are a uniform
 // base plus a 32-bit byte offset (planes below 2 GiB).
-#ifndef LBM_XK_WAVES
-#define LBM_XK_WAVES 4
-#endif
-#ifndef LBM_XK_REMAP
-#define LBM_XK_REMAP 1
-#endif
 // Rows of level-n pulls in flight ahead of the row being computed.  Measured at
 // 4096^2, alternating runs on one device: FP64 K = 8 174-176 GLUPS with one row,
 // 171-173 with two; FP32 (256-lane strips, K = 8) 223 either way, with 154
 // instead of 178 registers.
-#ifndef LBM_XK_DEPTH
-#define LBM_XK_DEPTH 1
-#endif
-#ifndef LBM_XK_DELAY
-#define LBM_XK_DELAY 1
-#endif
-// Grids with non-periodic faces: x-face inflow values per lane (1) or uniform (0).
-#ifndef LBM_XKB_XIN_LANE
-#define LBM_XKB_XIN_LANE 1
-#endif
-// The same for grids with non-periodic faces.
-#ifndef LBM_XKB_DELAY
-#define LBM_XKB_DELAY 1
-#endif
-template <bool BND>
-constexpr bool xk_delay()
-{
-    return BND ? LBM_XKB_DELAY != 0 : LBM_XK_DELAY != 0;
-}
-// FP64 launches of at least LBM_XK_LDS_MIN_K steps exchange the e1 / e3 planes of
-// their first LBM_XK_LDS_LEVELS intermediate levels through a per-wavefront LDS row
+// FP64 launches of at least kXkLdsMinK steps exchange the e1 / e3 planes of
+// their first kXkLdsLevelsF64 intermediate levels through a per-wavefront LDS row
 // instead of cross-lane permutes into registers; 0 levels = off.  At K = 8 this
 // takes the kernel from 332 registers (one wavefront per SIMD) to 231 (two):
 // 171 vs 157 GLUPS at 4096^2 (4, 5 or 6 levels alike; 6 uses 72 KiB of LDS per
 // workgroup, two workgroups per compute unit).
-#ifndef LBM_XK_LDS_LEVELS
-#define LBM_XK_LDS_LEVELS 6
-#endif
+constexpr int kXkLdsLevelsF64 = 6;
 // LDS exchange levels read one level ahead, for FP32 launches of at most this
 // many steps (0: never).  Measured at 2048^2, FP32 K = 6: 159-160 GLUPS against
 // 151; FP32 K = 8 at 4096^2: 221 against 224; FP64 K = 8 unchanged (177).
-#ifndef LBM_XK_LDS_PREFETCH_F32_MAXK
-#define LBM_XK_LDS_PREFETCH_F32_MAXK 6
-#endif
-#ifndef LBM_XK_LDS_MIN_K
-#define LBM_XK_LDS_MIN_K 7
-#endif
-#ifndef LBM_XK_LDS_LEVELS_F32
-#define LBM_XK_LDS_LEVELS_F32 0  // the same for FP32 launches (0 = off)
-#endif
+constexpr int kXkLdsPrefetchF32MaxK = 6;
+constexpr int kXkLdsMinK = 7;
+constexpr int kXkLdsLevelsF32 = 0;  // the same for FP32 launches (0 = off)
 // Output strips start and end on this many bytes (0: no alignment), and the
 // stores are non-temporal (1) or not (0), per storage type.  Measured at 4096^2:
 // FP64 -- 64-byte strips with non-temporal stores (94 vs 77 GLUPS unaligned);
 // FP32 -- unaligned strips with ordinary stores, whose partly written segments
 // at strip edges merge in L2 (140 vs 122 GLUPS for 64-byte strips).
-#ifndef LBM_XK_ALIGN_F64
-#define LBM_XK_ALIGN_F64 64
-#endif
-#ifndef LBM_XK_NT_F64
-#define LBM_XK_NT_F64 1
-#endif
-#ifndef LBM_XK_ALIGN_F32
-#define LBM_XK_ALIGN_F32 0
-#endif
-#ifndef LBM_XK_NT_F32
-#define LBM_XK_NT_F32 0
-#endif
-constexpr int kXkWaves = LBM_XK_WAVES;  // wavefronts per workgroup
+constexpr int kXkAlignF64 = 64;
+constexpr int kXkNtF64 = 1;
+constexpr int kXkAlignF32 = 0;
+constexpr int kXkNtF32 = 0;
+constexpr int kXkWaves = 4;  // wavefronts per workgroup
 // Wide strips, per storage type: the all-periodic single-grid launch gives each
 // workgroup one strip of 64 x kXkWaves lanes (0: one 64-lane strip per
 // wavefront).  Wavefronts then meet inside a strip and exchange their edge
@@ -231,44 +187,34 @@ constexpr int kXkWaves = LBM_XK_WAVES;  // wavefronts per workgroup
 // 64 x kXkWaves.  Measured at 4096^2, alternating runs on one device: FP32 K = 6
 // 208 GLUPS with 64-lane strips, 219-221 wide, K = 8 wide 222-224; FP64 no gain
 // (K = 8: 158-164 wide against 163-166, K = 7: 134-149 against 143).
-#ifndef LBM_XK_WIDE_F64
-#define LBM_XK_WIDE_F64 0
-#endif
-#ifndef LBM_XK_WIDE_F32
-#define LBM_XK_WIDE_F32 1
-#endif
+constexpr int kXkWideF64 = 0;
+constexpr int kXkWideF32 = 1;
 template <typename T>
 constexpr int xk_sw()
 {
-    return (sizeof(T) == 8 ? LBM_XK_WIDE_F64 : LBM_XK_WIDE_F32) ? kXkWaves : 1;
+    return (sizeof(T) == 8 ? kXkWideF64 : kXkWideF32) ? kXkWaves : 1;
 }
-constexpr int kXkDepth = LBM_XK_DEPTH;  // rows of level-n pulls in flight
+constexpr int kXkDepth = 1;  // rows of level-n pulls in flight
 // Wide strips in the batched launch (all-periodic instances), per storage type as
 // for single grids: 1 = the storage type's xk_sw, 0 = 64-lane strips.  The
 // 256-instance manifest (FP32, K = 8, fused against flat mode bit for bit): 184
 // GLUPS with 256-lane strips, 170 with 64-lane strips.
-#ifndef LBM_XK_BATCH_WIDE
-#define LBM_XK_BATCH_WIDE 1
-#endif
+constexpr int kXkBatchWide = 1;
 template <typename T>
 constexpr int xk_batch_sw()
 {
-    return LBM_XK_BATCH_WIDE ? xk_sw<T>() : 1;
+    return kXkBatchWide ? xk_sw<T>() : 1;
 }
 // Rows of level-n pulls in flight in the batched launch, per storage type.  The
 // same manifest, FP32: 64-lane strips 164-172 GLUPS with two rows, 155 with one;
 // 256-lane strips 184 with one row (154 registers, three wavefronts per SIMD),
 // 179 with two (183 registers).
-#ifndef LBM_XK_BATCH_DEPTH
-#define LBM_XK_BATCH_DEPTH 2
-#endif
-#ifndef LBM_XK_BATCH_DEPTH_F32
-#define LBM_XK_BATCH_DEPTH_F32 (LBM_XK_BATCH_WIDE && LBM_XK_WIDE_F32 ? 1 : 2)
-#endif
+constexpr int kXkBatchDepthF64 = 2;
+constexpr int kXkBatchDepthF32 = 1;
 template <typename T>
 constexpr int xk_batch_depth()
 {
-    return sizeof(T) == 4 ? LBM_XK_BATCH_DEPTH_F32 : LBM_XK_BATCH_DEPTH;
+    return sizeof(T) == 4 ? kXkBatchDepthF32 : kXkBatchDepthF64;
 }
 
 // Workgroup b runs on XCD b % 8 (round-robin dispatch).  Give XCD x the
@@ -302,9 +248,6 @@ __device__ __forceinline__ double xk_from(double v, int lane, int shift)
 // The same exchange through DPP wave shifts (a VALU move, no LDS access):
 // xk_shr gives lane l the value of lane l - 1, xk_shl that of lane l + 1; the
 // end lanes receive 0.
-#ifndef LBM_XK_DPP
-#define LBM_XK_DPP 0  // 1: the all-periodic kernels exchange through DPP as well
-#endif
 template <int CTRL>
 __device__ __forceinline__ float xk_dpp(float v)
 {
@@ -331,10 +274,7 @@ __device__ __forceinline__ T xk_shl(T v)
 template <typename T>
 __device__ __forceinline__ T xk_xch(T v, int lane, int shift)
 {
-    if constexpr (LBM_XK_DPP != 0)
-        return shift > 0 ? xk_shr(v) : xk_shl(v);
-    else
-        return xk_from(v, lane, shift);
+    return xk_from(v, lane, shift);
 }
 
 template <typename T>
@@ -461,35 +401,31 @@ __device__ __forceinline__ void xk_store(__amdgpu_buffer_rsrc_t r, unsigned off,
 {
     __builtin_amdgcn_raw_buffer_store_b64(
         __builtin_bit_cast(__attribute__((ext_vector_type(2))) int, v), r, off, 0,
-        LBM_XK_NT_F64 ? 2 : 0);
+        kXkNtF64 ? 2 : 0);
 }
 __device__ __forceinline__ void xk_store(__amdgpu_buffer_rsrc_t r, unsigned off, float v)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(v), r, off, 0, LBM_XK_NT_F32 ? 2 : 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(v), r, off, 0, kXkNtF32 ? 2 : 0);
 }
 
 // Intermediate levels whose e1 / e3 exchange goes through LDS.
 template <typename T, int K>
 constexpr int xk_lds_levels()
 {
-    constexpr int L = sizeof(T) == 8 ? LBM_XK_LDS_LEVELS : LBM_XK_LDS_LEVELS_F32;
-    return K >= LBM_XK_LDS_MIN_K ? (L < K - 1 ? L : K - 1) : 0;
+    constexpr int L = sizeof(T) == 8 ? kXkLdsLevelsF64 : kXkLdsLevelsF32;
+    return K >= kXkLdsMinK ? (L < K - 1 ? L : K - 1) : 0;
 }
 // Elements per LDS row of an exchange level (wide strips: two edge slots).
 constexpr int xk_lds_width(int sw) { return sw > 1 ? 66 : 64; }
 // Intermediate levels exchanged through LDS rows on wide strips, at most:
 // FP64 6 (with 66-element rows, 4 wavefronts take 76 KiB and two workgroups
 // share a compute unit), FP32 7.
-#ifndef LBM_XK_WIDE_LDS_F64
-#define LBM_XK_WIDE_LDS_F64 6
-#endif
-#ifndef LBM_XK_WIDE_LDS_F32
-#define LBM_XK_WIDE_LDS_F32 7
-#endif
+constexpr int kXkWideLdsF64 = 6;
+constexpr int kXkWideLdsF32 = 7;
 template <typename T, int K, int SW>
 constexpr int xk_lds_levels_sw()
 {
-    constexpr int cap = sizeof(T) == 8 ? LBM_XK_WIDE_LDS_F64 : LBM_XK_WIDE_LDS_F32;
+    constexpr int cap = sizeof(T) == 8 ? kXkWideLdsF64 : kXkWideLdsF32;
     return SW > 1 ? (K - 1 < cap ? K - 1 : cap) : xk_lds_levels<T, K>();
 }
 // Wide strips: edge slots per wavefront of the register levels, and its junk area.
@@ -516,23 +452,17 @@ constexpr int xk_lds_elems()
 
 // Grids with non-periodic faces: intermediate levels whose e1 / e3 exchange goes
 // through a per-wavefront LDS row (a face lane reads its own slot instead of its
-// neighbour's), at most LBM_XKB_LDS_LEVELS (FP64) / LBM_XKB_LDS_LEVELS_F32, in
-// launches of at least LBM_XKB_LDS_MIN_K steps; the other levels exchange in
+// neighbour's), at most kXkbLdsLevelsF64 (FP64) / kXkbLdsLevelsF32, in
+// launches of at least kXkbLdsMinK steps; the other levels exchange in
 // registers (DPP).
-#ifndef LBM_XKB_LDS_LEVELS
-#define LBM_XKB_LDS_LEVELS 6
-#endif
-#ifndef LBM_XKB_LDS_LEVELS_F32
-#define LBM_XKB_LDS_LEVELS_F32 7
-#endif
-#ifndef LBM_XKB_LDS_MIN_K
-#define LBM_XKB_LDS_MIN_K 2
-#endif
+constexpr int kXkbLdsLevelsF64 = 6;
+constexpr int kXkbLdsLevelsF32 = 7;
+constexpr int kXkbLdsMinK = 2;
 template <typename T, int K>
 constexpr int xkb_lds_levels()
 {
-    constexpr int L = sizeof(T) == 8 ? LBM_XKB_LDS_LEVELS : LBM_XKB_LDS_LEVELS_F32;
-    return K >= LBM_XKB_LDS_MIN_K ? (L < K - 1 ? L : K - 1) : 0;
+    constexpr int L = sizeof(T) == 8 ? kXkbLdsLevelsF64 : kXkbLdsLevelsF32;
+    return K >= kXkbLdsMinK ? (L < K - 1 ? L : K - 1) : 0;
 }
 template <typename T, int K>
 constexpr int xkb_lds_elems()
@@ -550,7 +480,7 @@ constexpr int xkb_lds_elems()
 template <typename T, int K, bool BND = false, int SW = 1>
 constexpr int xk_wo()
 {
-    constexpr int A = (sizeof(T) == 8 ? LBM_XK_ALIGN_F64 : LBM_XK_ALIGN_F32) / (int)sizeof(T);
+    constexpr int A = (sizeof(T) == 8 ? kXkAlignF64 : kXkAlignF32) / (int)sizeof(T);
     constexpr int halo = 2 * (K - 1) + (BND ? 1 : 0), a = A > 1 ? A : 1;
     return (64 * SW - halo) / a * a;
 }
@@ -654,16 +584,14 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
             if (by1 && B.ky1 == BC_INFLOW) v[4 * c + 3] = B.in4[c];
         }
     }
-    if constexpr (xk_delay<BND>()) {
-        // The previous row's outputs are stored only now, after this row's loaded
-        // values have been consumed: the wait for those loads (issued D rows ago)
-        // then finds no fresh stores issued after them, and the memory counter,
-        // which counts stores and loads together, does not stall on this row's
-        // stores.  The scheduling barrier keeps that order.
-        __builtin_amdgcn_sched_barrier(0);
+    // The previous row's outputs are stored only now, after this row's loaded
+    // values have been consumed: the wait for those loads (issued D rows ago)
+    // then finds no fresh stores issued after them, and the memory counter,
+    // which counts stores and loads together, does not stall on this row's
+    // stores.  The scheduling barrier keeps that order.
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int pl = 0; pl < 12; ++pl) xk_store(orsrc[pl], pend_off, pend[pl]);
-    }
+    for (int pl = 0; pl < 12; ++pl) xk_store(orsrc[pl], pend_off, pend[pl]);
     if constexpr (BND)
         xk_load_clamp(src, ps, G, B, inext, xm, xw, xp, nxt);
     else
@@ -671,7 +599,7 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
     // LDS exchange levels: each level's e1 / e3 pulls are read one level ahead
     // (before the previous level's arithmetic), so the LDS latency overlaps it
     constexpr int RW = xk_lds_width(SW);
-    constexpr bool PF = sizeof(T) == 4 && K <= LBM_XK_LDS_PREFETCH_F32_MAXK;
+    constexpr bool PF = sizeof(T) == 4 && K <= kXkLdsPrefetchF32MaxK;
     T pf1[3], pf3[3];
     if constexpr (L > 0 && PF) {
 #pragma unroll
@@ -838,14 +766,9 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
     } else {
         levels(std::false_type{});
     }
-    if constexpr (xk_delay<BND>()) {
 #pragma unroll
-        for (int pl = 0; pl < 12; ++pl) pend[pl] = (T)v[pl];
-        pend_off = ooff;
-    } else {
-#pragma unroll
-        for (int pl = 0; pl < 12; ++pl) xk_store(orsrc[pl], ooff, (T)v[pl]);
-    }
+    for (int pl = 0; pl < 12; ++pl) pend[pl] = (T)v[pl];
+    pend_off = ooff;
 }
 
 constexpr int xk_gcd(int a, int b) { return b == 0 ? a : xk_gcd(b, a % b); }
@@ -920,7 +843,6 @@ __device__ __forceinline__ void xk_wave(const T *__restrict__ src, T *__restrict
             Lp[p].r1 = bx0 ? (B.kx0 == BC_WALL ? 3 * 64 + lane : lane) : (lane - 1) & 63;
             Lp[p].r3 = bx1 ? (B.kx1 == BC_WALL ? lane : 3 * 64 + lane) : 3 * 64 + ((lane + 1) & 63);
         }
-#if LBM_XKB_XIN_LANE
         // a lane needs at most one x face's inflow values (x- on bx0 lanes, x+ on
         // bx1 lanes): keep that one per lane, which frees their scalar registers
 #pragma unroll
@@ -929,7 +851,6 @@ __device__ __forceinline__ void xk_wave(const T *__restrict__ src, T *__restrict
             B.in1[c] = x;
             B.in3[c] = x;
         }
-#endif
     }
     // the lane's column and its neighbours: wrapped, or clamped to the grid
     const int xw = clampx ? min(max(xc, 0), nx - 1) : ((xc % nx) + nx) % nx;
@@ -1005,10 +926,8 @@ __device__ __forceinline__ void xk_wave(const T *__restrict__ src, T *__restrict
                               X);
         }
     }
-    if constexpr (xk_delay<BND>()) {
 #pragma unroll
-        for (int pl = 0; pl < 12; ++pl) xk_store(orsrc[pl], pend_off, pend[pl]);
-    }
+    for (int pl = 0; pl < 12; ++pl) xk_store(orsrc[pl], pend_off, pend[pl]);
 }
 
 template <typename T, int K, int D>
@@ -1022,7 +941,7 @@ __global__ void __launch_bounds__(64 * kXkWaves)
         constexpr int SW = xk_sw<T>();
         constexpr int rows = xk_wide_rows<T, K, SW>();
         __shared__ T lds[kXkWaves * rows];
-        const int tile = xk_tile(blockIdx.x, nstrips * nseg, LBM_XK_REMAP != 0);
+        const int tile = xk_tile(blockIdx.x, nstrips * nseg, true);
         const int strip = tile % nstrips;
         const int y0 = (tile / nstrips) * seg;
         xk_wave<T, K, D, false, SW>(src, dst, G, P, strip, y0, min(y0 + seg, G.ny), lds,
@@ -1030,7 +949,7 @@ __global__ void __launch_bounds__(64 * kXkWaves)
     } else {
         __shared__ T xs[kXkWaves][xk_lds_elems<T, K>()];
         const int ngroups = (nstrips + kXkWaves - 1) / kXkWaves;
-        const int tile = xk_tile(blockIdx.x, ngroups * nseg, LBM_XK_REMAP != 0);
+        const int tile = xk_tile(blockIdx.x, ngroups * nseg, true);
         const int strip = (tile % ngroups) * kXkWaves + (threadIdx.x >> 6);
         if (strip >= nstrips) return;  // whole wavefront; nothing here waits on others
         const int y0 = (tile / ngroups) * seg;
@@ -1048,7 +967,7 @@ __global__ void __launch_bounds__(64 * kXkWaves)
     __shared__ T xs[kXkWaves][xkb_lds_elems<T, K>()];
     const int ngroups = (nstrips + kXkWaves - 1) / kXkWaves;
     const int nseg = (G.ny + seg - 1) / seg;
-    const int tile = xk_tile(blockIdx.x, ngroups * nseg, LBM_XK_REMAP != 0);
+    const int tile = xk_tile(blockIdx.x, ngroups * nseg, true);
     const int strip = (tile % ngroups) * kXkWaves + (threadIdx.x >> 6);
     if (strip >= nstrips) return;  // whole wavefront; nothing here waits on others
     const int y0 = (tile / ngroups) * seg;
@@ -1063,7 +982,7 @@ __global__ void __launch_bounds__(64 * kXkWaves)
     k_batch_xk(const InstDev *__restrict__ inst, const XkTileDev *__restrict__ tiles, int ntiles,
                const T *__restrict__ src, T *__restrict__ dst)
 {
-    const XkTileDev td = tiles[xk_tile(blockIdx.x, ntiles, LBM_XK_REMAP != 0)];
+    const XkTileDev td = tiles[xk_tile(blockIdx.x, ntiles, true)];
     const InstDev &I = inst[td.inst];
     if constexpr (xk_batch_sw<T>() > 1) {
         // every wavefront runs to the end (barriers)
@@ -1091,7 +1010,7 @@ __global__ void __launch_bounds__(64 * kXkWaves)
                 int ntiles, const T *__restrict__ src, T *__restrict__ dst)
 {
     __shared__ T xs[kXkWaves][xkb_lds_elems<T, K>()];
-    const XkTileDev td = tiles[xk_tile(blockIdx.x, ntiles, LBM_XK_REMAP != 0)];
+    const XkTileDev td = tiles[xk_tile(blockIdx.x, ntiles, true)];
     const InstDev &I = inst[td.inst];
     const int strip = td.strip0 + (int)(threadIdx.x >> 6);
     if (strip >= td.nstrips) return;
@@ -1180,29 +1099,23 @@ int step2k_blocks(const Geo &G, bool f32, int K, int seg)
 // 166, 156, 153, 155.  With the y-face rules in every iteration: FP64 90 / 109 / 85
 // at K = 4 / 5 / 6, FP32 133 / 131 / 123 (K = 4 with the exchange in registers:
 // 88 / 124).
-#ifndef LBM_XKB_MAX_K
-#define LBM_XKB_MAX_K 8
-#endif
-constexpr int kXkMaxKBnd = LBM_XKB_MAX_K;
+constexpr int kXkMaxKBnd = 8;
 // Steps per launch by default with non-periodic faces, per storage (the fastest
-// above).
-#ifndef LBM_XKB_DEFAULT_K_F64
-#define LBM_XKB_DEFAULT_K_F64 6
-#endif
-#ifndef LBM_XKB_DEFAULT_K_F32
-#define LBM_XKB_DEFAULT_K_F32 5
-#endif
+// at 4096^2: FP64 K = 4 .. 8 81, 114, 133, 120, 115 GLUPS; FP32, whose arithmetic
+// uses fused multiply-adds, 144, 174, 173, 174, 177-179).  A copy of the strip
+// loop without the x-face rules for the strips that touch no x face (chosen per
+// wavefront) measured FP64 128 at K = 6 (more registers in the kernel holding
+// both copies) and FP32 185 at K = 8, so it is not used.
+constexpr int kXkbDefaultKF64 = 6;
+constexpr int kXkbDefaultKF32 = 8;
 // Rows of level-n pulls in flight in the bounded kernel: one (at 4096^2 FP64 K = 4
 // 85 GLUPS against 74 with two; the smaller ring lets two wavefronts share a SIMD).
-#ifndef LBM_XKB_DEPTH
-#define LBM_XKB_DEPTH 1
-#endif
-constexpr int kXkbDepth = LBM_XKB_DEPTH;
+constexpr int kXkbDepth = 1;
 
 int step2k_max_k_bounded() { return kXkMaxKBnd; }
 int step2k_default_k_bounded(bool f32)
 {
-    const int k = f32 ? LBM_XKB_DEFAULT_K_F32 : LBM_XKB_DEFAULT_K_F64;
+    const int k = f32 ? kXkbDefaultKF32 : kXkbDefaultKF64;
     return k < kXkMaxKBnd ? k : kXkMaxKBnd;
 }
 
