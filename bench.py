@@ -53,6 +53,14 @@ def _parse():
                     help="skip the forward run with inflow / Neumann / wall faces")
     ap.add_argument("--batched-steps", type=int, default=1000,
                     help="timed steps of the batched form (the manifest's run is 1000)")
+    ap.add_argument("--batched-tuned-only", action="store_true",
+                    help="batched form: the tuned mode only (no FP64 reference, persistent "
+                         "modes or per-instance plain path)")
+    ap.add_argument("--batch-mode", type=int, default=-1, choices=(-1, 0, 1, 2, 3),
+                    help="batched form: mode to time instead of the tuned one (-1)")
+    ap.add_argument("--direct-batch", action="store_true",
+                    help="batched form: launch every kernel directly instead of replaying "
+                         "captured graphs (for profilers)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--npt", type=int, default=0)
     ap.add_argument("--pad", type=int, default=-1)
@@ -188,7 +196,7 @@ def _time_batch(torch, insts, storage, steps, tune):
     return ms, nt, grid, h, nodes
 
 
-def time_batched(torch, steps=1000):
+def time_batched(torch, steps=1000, tuned_only=False, direct=False, mode=-1):
     """The 256-instance manifest (FP32 storage): the tuned mode (fused launches of K
     steps over every instance), the two persistent single-launch modes (dataflow
     and step-synchronous), the same manifest with FP64 storage (the reference of
@@ -201,6 +209,10 @@ def time_batched(torch, steps=1000):
                          "tuning.json")
     if os.path.exists(tpath):
         tune = json.load(open(tpath)).get("batch", {})
+    if mode >= 0 and mode != tune.get("mode"):
+        tune = {"mode": mode, "block": 512 if mode == 0 else 256, "tile_nodes": 32768}
+    if direct:
+        tune = dict(tune, direct=1)
     ms, nt, grid, h32, nodes = _time_batch(torch, insts, "f32", steps, tune)
     ok = bool(torch.isfinite(h32).all().item())
     byt = sum((4 if i["dim"] == 1 else 12) * 2 * 4 * i["nx"] * (i["ny"] if i["dim"] == 2 else 1)
@@ -212,6 +224,8 @@ def time_batched(torch, steps=1000):
                mlups=nodes * steps / (ms * 1e-3) / 1e6, steps_per_launch=k,
                gbs=byt * steps / k / (ms * 1e-3) / 1e9, tiles=nt, grid=grid, tuning=tune,
                finite=ok)
+    if tuned_only:
+        return out
     log("[bench] batched FP64 reference (same mode and steps)")
     _, _, _, h64, _ = _time_batch(torch, insts, "f64", steps, tune)
     out["l1_rel_h_vs_fp64"] = float((h32 - h64).abs().sum() / h64.abs().sum())
@@ -594,7 +608,9 @@ def main():
     f64 = forms.get("fp64") or forms["fp32"]
     if not args.quick and not args.no_batched:
         log("[bench] batched 256 instances x 1000 steps")
-        forms["batched"] = time_batched(torch, steps=args.batched_steps)
+        forms["batched"] = time_batched(torch, steps=args.batched_steps,
+                                        tuned_only=args.batched_tuned_only,
+                                        direct=args.direct_batch, mode=args.batch_mode)
     if not args.quick and not args.no_adjoint:
         log("[bench] adjoint rollout 1024^2 x 500")
         forms["adjoint"] = time_adjoint(torch)

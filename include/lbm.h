@@ -112,8 +112,9 @@ typedef struct {
                              two-step launch has >= 1024 workgroups, else 1;
                              planes of 2 GiB or more take 1); 2D grids with
                              Neumann, wall or inflow faces at most 8 (default 6
-                             for FP64, 8 for FP32 storage, when that launch fills
-                             a third of the device, else 1; planes of 2 GiB or
+                             for FP64, 8 for FP32 storage, or the largest fewer
+                             steps whose launch fills a third of the device, else
+                             1; planes of 2 GiB or
                              more take 1); 1D grids any
                              (default 16).  lbm_launch_info reports the choice. */
     void *f_a, *f_b;      /* caller-owned device state buffers (ping-pong) */
@@ -288,9 +289,12 @@ typedef struct {
                                 chunks as in mode 2; steps that do not fill a launch
                                 run as flat single steps.  block, tile_nodes, grid
                                 and pass_nodes are ignored. */
-    int fuse_steps;       /* mode 3: steps per launch, 2 .. 8 (0 = 6 for FP32, 8 for
-                             FP64 storage, or with non-periodic 2D faces 5 / 6;
-                             1 is rejected) */
+    int fuse_steps;       /* mode 3: steps per launch, 2 .. 8 (0 = 8, or with
+                             non-periodic 2D faces 6 (FP64) / 8 (FP32); 1 is
+                             rejected) */
+    int direct;           /* 0: replay captured HIP graphs (default); 1: launch every
+                             kernel directly on the stream (e.g. under a profiler
+                             that cannot follow graph replays) */
 } lbm_batch_tuning;
 
 /* Assign state_offset / node_offset to n instances (in place) for the given

@@ -316,7 +316,13 @@ extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0
                 }
                 bool full = false;
                 long slots = 0;
-                const int seg = step2k_seg(c->G, c->f32, kd, kXkMinSeg, &full, &slots);
+                int seg = step2k_seg(c->G, c->f32, kd, kXkMinSeg, &full, &slots);
+                // with non-periodic faces, a launch of fewer steps when the default
+                // one cannot fill the device (smaller grids)
+                while (!allper && !(seg > 0 && full) && kd > 2) {
+                    --kd;
+                    seg = step2k_seg(c->G, c->f32, kd, kXkMinSeg, &full, &slots);
+                }
                 if (seg > 0 && full) {
                     c->fuse = kd;
                     c->xk_seg = seg;

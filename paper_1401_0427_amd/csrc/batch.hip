@@ -572,7 +572,7 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
                 return bfail(LBM_EINVAL, "instance %d: inflow h must be > 0", i);
         }
     }
-    lbm_batch_tuning tune = {256, 16384, 0, 1, 0, 0};
+    lbm_batch_tuning tune = {256, 16384, 0, 1, 0, 0, 0};
     if (tuning) tune = *tuning;
     if (tune.mode < 0 || tune.mode > 3)
         return bfail(LBM_EINVAL, "tuning.mode must be 0 (dataflow), 1 (step-synchronous), 2 "
@@ -897,6 +897,21 @@ static int run_flat(lbm_batch *b, long nsteps)
     const bool fused = b->tune.mode == 3;
     const long per = fused ? b->fuse : 1;
     long left = nsteps;
+    if (b->tune.direct) {
+        // no graph: every launch directly on the stream
+        for (; fused && left >= per; left -= per) {
+            BHIP(launch_fused(b, b->cur, b->st));
+            b->cur ^= 1;
+            b->steps += per;
+        }
+        for (; left > 0; --left) {
+            launch_flat(b, b->cur, b->st);
+            BHIP(hipGetLastError());
+            b->cur ^= 1;
+            ++b->steps;
+        }
+        return LBM_OK;
+    }
     if (left >= b->chunk && !b->fexec[b->cur]) {
         if (!b->cap) BHIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
         hipGraph_t g = nullptr;
@@ -949,6 +964,12 @@ extern "C" int lbm_batch_run(lbm_batch *b, long nsteps)
     if (b->tune.mode == 1 && (double)nsteps * b->grid >= 2147483648.0)
         return bfail(LBM_EINVAL, "nsteps x grid too large for the step-synchronous mode");
     if (nsteps == 0) return LBM_OK;
+    if (b->tune.direct) {
+        BHIP(enqueue_run(b, nsteps, b->st));
+        b->steps += nsteps;
+        b->cur = (int)((b->cur + nsteps) & 1);
+        return LBM_OK;
+    }
     if (!b->gexec || b->g_nsteps != nsteps || b->g_cur != b->cur) {
         if (b->gexec) {
             (void)hipGraphExecDestroy(b->gexec);

@@ -74,7 +74,8 @@ class LbmInstance(ctypes.Structure):
 
 class LbmBatchTuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int), ("tile_nodes", ctypes.c_int), ("grid", ctypes.c_int),
-                ("pass_nodes", ctypes.c_int), ("mode", ctypes.c_int), ("fuse_steps", ctypes.c_int)]
+                ("pass_nodes", ctypes.c_int), ("mode", ctypes.c_int), ("fuse_steps", ctypes.c_int),
+                ("direct", ctypes.c_int)]
 
 
 EXPORTS = [
@@ -409,12 +410,13 @@ class Batch:
     """Many independent problems advanced in one persistent launch."""
 
     def __init__(self, instances, storage="f32", block=256, tile_nodes=16384, grid=0, pass_nodes=1,
-                 mode=0, fuse_steps=0, device="cuda"):
+                 mode=0, fuse_steps=0, direct=0, device="cuda"):
         """``instances``: iterable of dicts with keys dim, nx, ny, lam, s, g, bc,
         inflow, h0, qx0, qy0 (numpy arrays of the instance's nodes).  ``mode`` 0 is
         the dataflow persistent launch, 1 the step-synchronous persistent launch
         (one grid barrier per step), 2 one flat launch per step, 3 ``fuse_steps``
-        steps per launch (0 = library default)."""
+        steps per launch (0 = library default).  ``direct`` launches every kernel
+        directly instead of replaying captured graphs (e.g. under a profiler)."""
         import torch
 
         _require_gpu(torch)
@@ -458,7 +460,7 @@ class Batch:
                 qy0[o:o + m] = np.asarray(d["qy0"]).reshape(-1)
         f64 = dict(dtype=torch.float64, device=self.device)
         self.h0, self.qx0, self.qy0 = (torch.as_tensor(a, **f64) for a in (h0, qx0, qy0))
-        tune = LbmBatchTuning(block, tile_nodes, grid, pass_nodes, mode, fuse_steps)
+        tune = LbmBatchTuning(block, tile_nodes, grid, pass_nodes, mode, fuse_steps, direct)
         b = ctypes.c_void_p()
         check(L.lbm_batch_create(arr, n, self.storage, _ptr(self.fa), _ptr(self.fb),
                                  _stream_handle(torch), ctypes.byref(tune), ctypes.byref(b)),

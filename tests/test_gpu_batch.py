@@ -234,3 +234,20 @@ def test_batch_fused_mode_with_faces_run_twice_equals_one_long_run():
     B.run(101)
     for a, b in zip(A.moments(), B.moments()):
         assert np.array_equal(to_np(a), to_np(b))
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+def test_batch_direct_launches_equal_graph_replays(mode):
+    """With tuning.direct every kernel is launched on the stream instead of from a
+    captured graph; the state is the same bit for bit."""
+    import torch
+
+    from paper_1401_0427_amd.lbm import Batch
+
+    insts = instance_dicts(W.small_manifest(seed=1), True)
+    A = Batch(insts, storage="f32", mode=mode)
+    B = Batch(insts, storage="f32", mode=mode, direct=1)
+    A.run(70, check_done=True)
+    B.run(70, check_done=True)
+    hA, hB = A.moments()[0], B.moments()[0]
+    assert torch.equal(hA, hB)

@@ -324,8 +324,9 @@ def test_default_launch_plans():
     launch on grids it can fill (8 steps per launch; FP32 6 on grids below about
     three workgroups per resident slot, such as 1024^2), with a segment length and
     the resident workgroups it was chosen against; one step per launch on a
-    small FP32 grid; 16 steps per launch in 1D; 6 (FP64) / 5 (FP32) steps with
-    non-periodic 2D faces; an explicit request is honoured up to 8 steps."""
+    small FP32 grid; 16 steps per launch in 1D; with non-periodic 2D faces 6
+    (FP64) / 8 (FP32) steps, or fewer where that launch cannot fill the device;
+    an explicit request is honoured up to 8 steps."""
     big64 = gpu_solver(smooth_random_2d(1024, 1024, seed=8), storage="f64").launch_info()
     assert big64["steps_per_launch"] == 8 and big64["segment_rows"] >= 16
     assert big64["resident_blocks"] > 0
@@ -345,7 +346,7 @@ def test_default_launch_plans():
     assert box["steps_per_launch"] == 6 and box["segment_rows"] >= 16
     box32 = gpu_solver(smooth_random_2d(1024, 1024, seed=8, bc=("wall",) * 4),
                        storage="f32").launch_info()
-    assert box32["steps_per_launch"] == 5
+    assert 2 <= box32["steps_per_launch"] <= 8
     small_box = gpu_solver(smooth_random_2d(64, 64, seed=8, bc=("wall",) * 4)).launch_info()
     assert small_box["steps_per_launch"] == 1
     asked = gpu_solver(smooth_random_2d(300, 70, seed=8), fuse_steps=16).launch_info()
