@@ -56,7 +56,7 @@ def _parse():
     ap.add_argument("--batched-tuned-only", action="store_true",
                     help="batched form: the tuned mode only (no FP64 reference, persistent "
                          "modes or per-instance plain path)")
-    ap.add_argument("--batch-mode", type=int, default=-1, choices=(-1, 0, 1, 2, 3),
+    ap.add_argument("--batch-mode", type=int, default=-1, choices=(-1, 0, 1, 2, 3, 4),
                     help="batched form: mode to time instead of the tuned one (-1)")
     ap.add_argument("--direct-batch", action="store_true",
                     help="batched form: launch every kernel directly instead of replaying "
@@ -198,9 +198,10 @@ def _time_batch(torch, insts, storage, steps, tune):
 
 def time_batched(torch, steps=1000, tuned_only=False, direct=False, mode=-1):
     """The 256-instance manifest (FP32 storage): the tuned mode (fused launches of K
-    steps over every instance), the two persistent single-launch modes (dataflow
-    and step-synchronous), the same manifest with FP64 storage (the reference of
-    the FP32 L1 error, same steps and mode), and the plain path per instance."""
+    steps over every instance), the three persistent single-launch modes
+    (dataflow, step-synchronous, and the fused tiles with a grid barrier per K-step
+    pass), the same manifest with FP64 storage (the reference of the FP32 L1 error,
+    same steps and mode), and the plain path per instance."""
     from paper_1401_0427_amd.lbm import Solver
 
     insts = _manifest_instances()
@@ -210,20 +211,21 @@ def time_batched(torch, steps=1000, tuned_only=False, direct=False, mode=-1):
     if os.path.exists(tpath):
         tune = json.load(open(tpath)).get("batch", {})
     if mode >= 0 and mode != tune.get("mode"):
-        tune = {"mode": mode, "block": 512 if mode == 0 else 256, "tile_nodes": 32768}
+        tune = {"mode": mode, "block": 512 if mode == 0 else 256, "tile_nodes": 32768,
+                "fuse_steps": tune.get("fuse_steps", 0) if mode >= 3 else 0}
     if direct:
         tune = dict(tune, direct=1)
     ms, nt, grid, h32, nodes = _time_batch(torch, insts, "f32", steps, tune)
     ok = bool(torch.isfinite(h32).all().item())
     byt = sum((4 if i["dim"] == 1 else 12) * 2 * 4 * i["nx"] * (i["ny"] if i["dim"] == 2 else 1)
               for i in insts)
-    # algorithmic bytes per launch: each launch reads and writes every instance's
-    # state once, whatever the number of steps it advances
-    k = (tune.get("fuse_steps") or 8) if tune.get("mode") == 3 else 1
+    # algorithmic bytes per launch (persistent fused mode: per pass): each reads and
+    # writes every instance's state once, whatever the number of steps it advances
+    k = (tune.get("fuse_steps") or 8) if tune.get("mode") in (3, 4) else 1
     out = dict(instances=len(insts), nodes=nodes, steps=steps, ms=ms, ms_per_step=ms / steps,
                mlups=nodes * steps / (ms * 1e-3) / 1e6, steps_per_launch=k,
                gbs=byt * steps / k / (ms * 1e-3) / 1e9, tiles=nt, grid=grid, tuning=tune,
-               finite=ok)
+               finite=ok, traffic=_batch_traffic())
     if tuned_only:
         return out
     log("[bench] batched FP64 reference (same mode and steps)")
@@ -234,7 +236,8 @@ def time_batched(torch, steps=1000, tuned_only=False, direct=False, mode=-1):
     # the persistent forms: every step of every instance in ONE kernel launch
     pers = {}
     for name, t in (("dataflow", dict(mode=0, block=512, tile_nodes=32768, pass_nodes=1)),
-                    ("step_synchronous", dict(mode=1, block=256))):
+                    ("step_synchronous", dict(mode=1, block=256)),
+                    ("fused_passes", dict(mode=4, fuse_steps=tune.get("fuse_steps") or 8))):
         log(f"[bench] batched persistent {name}")
         pms, pnt, pgrid, ph, _ = _time_batch(torch, insts, "f32", steps, t)
         pers[name] = dict(ms_per_step=pms / steps, mlups=nodes * steps / (pms * 1e-3) / 1e6,
@@ -354,7 +357,7 @@ KERNELS = {
     "lds_two_step": (("tblock.hip", "lbm_device.h"), "k_step2d_x2_fwd_4096_traffic.json",
                      "k_step2d_x2_fwd_4096_sq.json",
                      "k_step2d_x2<double> (two pull-stream + BGK collide steps per launch)"),
-    "wave_strip": (("tblock.hip", "lbm_device.h"), "k_step2d_xk_fwd_4096_traffic.json",
+    "wave_strip": (("tblock.hip", "xk_wave.h", "lbm_device.h"), "k_step2d_xk_fwd_4096_traffic.json",
                    "k_step2d_xk_fwd_4096_sq.json",
                    "k_step2d_xk<double, {K}> ({K} pull-stream + BGK collide steps per launch, "
                    "one wavefront per column strip)"),
@@ -435,14 +438,41 @@ def roofline(f64, n, kind):
             "per_step_equivalent_gbs": round(hbm_gbs * K, 1)}
 
 
-def _kernel_sha(kind="one_step"):
+def _sources_sha(files):
     import hashlib
 
     root = os.path.dirname(os.path.abspath(__file__))
     h = hashlib.sha256()
-    for f in KERNELS[kind][0]:
+    for f in files:
         h.update(open(os.path.join(root, "paper_1401_0427_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
+
+
+def _kernel_sha(kind="one_step"):
+    return _sources_sha(KERNELS[kind][0])
+
+
+# Sources of the batched kernels (fused, flat and persistent fused modes).
+BATCH_SOURCES = ("batch.hip", "pbatch.hip", "tblock.hip", "xk_wave.h", "internal.h",
+                 "lbm_device.h")
+
+
+def _batch_traffic():
+    """Committed DRAM counter summary of the batched kernels on the manifest (bytes
+    per launch, per pass for the persistent kernel), if taken on the current
+    sources; else None."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                        "k_batch_manifest256_traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_source_sha") != _sources_sha(BATCH_SOURCES):
+        return None
+    per = {k: {"read_bytes": v["read_bytes"], "write_bytes": v["write_bytes"],
+               "over_compulsory": round((v["read_bytes"] + v["write_bytes"]) /
+                                        v["algorithmic_bytes"], 4), "per": v.get("per")}
+           for k, v in d["kernels"].items()}
+    return {"compulsory_bytes_per_pass": d["compulsory_bytes_per_pass"], "kernels": per}
 
 
 def _cpu_model():

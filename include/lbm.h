@@ -269,9 +269,10 @@ typedef struct {
     int mode;             /* 0: dataflow -- tiles advance when their neighbours have
                                 finished the previous step (no grid barrier; cannot
                                 deadlock whatever the grid);
-                             1: step-synchronous -- units of `block` nodes, one per
-                                workgroup in turn, one grid barrier per step (needs a
-                                fully resident grid; bounded waits, see lbm_batch_check);
+                             1: step-synchronous -- units of `block` nodes, claimed
+                                by the workgroups in order, 8 to a work item; a step
+                                closes when all its items are complete (any grid,
+                                resident or not; bounded waits, see lbm_batch_check);
                              2: flat -- one ordinary launch per step over all instances,
                                 one workgroup per unit of `block` nodes; the launch
                                 boundary is the step barrier; chunks of 32 steps replay
@@ -288,9 +289,19 @@ typedef struct {
                                 1024-node tiles of the 1D multi-step kernel; graph
                                 chunks as in mode 2; steps that do not fill a launch
                                 run as flat single steps.  block, tile_nodes, grid
-                                and pass_nodes are ignored. */
-    int fuse_steps;       /* mode 3: steps per launch, 2 .. 8 (0 = 8, or with
-                             non-periodic 2D faces 6 (FP64) / 8 (FP32); 1 is
+                                and pass_nodes are ignored;
+                             4: persistent fused -- the tiles of mode 3 (1D tiles of
+                                256 nodes) in ONE launch for all the steps of a run:
+                                fuse_steps steps per pass; the workgroups claim the
+                                tiles of a pass in order and a pass closes when all
+                                are complete (256-thread workgroups, by default as
+                                many as the occupancy query reports resident; `grid`
+                                caps it; bounded waits, see lbm_batch_check); steps
+                                that do not fill a pass run as flat single steps
+                                after it.  Bitwise identical to modes 2 and 3.
+                                block, tile_nodes and pass_nodes are ignored. */
+    int fuse_steps;       /* modes 3, 4: steps per launch / pass, 2 .. 8 (0 = 8, or
+                             with non-periodic 2D faces 6 (FP64) / 8 (FP32); 1 is
                              rejected) */
     int direct;           /* 0: replay captured HIP graphs (default); 1: launch every
                              kernel directly on the stream (e.g. under a profiler
@@ -311,10 +322,11 @@ int lbm_batch_create(const lbm_instance *inst, int n, int storage, void *f_a, vo
 int lbm_batch_init(lbm_batch *b, const double *h0, const double *qx0, const double *qy0);
 
 /* Advance every instance by nsteps in the mode chosen at creation (tuning.mode):
- * dataflow -- ONE persistent kernel launch (replayed from a captured HIP graph);
- * flat -- one launch per step (graph chunks of 32 steps); fused -- one launch
- * pair (2D, 1D) per fuse_steps steps (graph chunks).  Stream-ordered;
- * lbm_batch_check reports whether a dataflow launch completed. */
+ * dataflow, step-synchronous, persistent fused -- ONE persistent kernel launch
+ * (replayed from a captured HIP graph; persistent fused: plus single steps for a
+ * remainder below fuse_steps); flat -- one launch per step (graph chunks of 32
+ * steps); fused -- one launch pair (2D, 1D) per fuse_steps steps (graph chunks).
+ * Stream-ordered; lbm_batch_check reports whether a persistent launch completed. */
 int lbm_batch_run(lbm_batch *b, long nsteps);
 
 /* Synchronise the stream and report whether the last run completed: the
@@ -328,9 +340,10 @@ int lbm_batch_moments(lbm_batch *b, double *h, double *qx, double *qy);
 /* Current state buffer of the batch. */
 int lbm_batch_current(lbm_batch *b, void **state, long *steps_done);
 
-/* Number of work tiles (dataflow, fused) or units (step-synchronous, flat), and
- * the workgroups of the persistent launch (dataflow, step-synchronous) or of one
- * launch (flat; fused: both launches of a step group). */
+/* Number of work tiles (dataflow, fused, persistent fused) or units
+ * (step-synchronous, flat), and the workgroups of the persistent launch
+ * (dataflow, step-synchronous, persistent fused) or of one launch (flat; fused:
+ * both launches of a step group). */
 int lbm_batch_info(lbm_batch *b, int *ntiles, int *grid);
 
 void lbm_batch_destroy(lbm_batch *b);

@@ -96,12 +96,13 @@ def _manifest_dicts(man):
 
 
 def tune_batch(seed=0, steps=96, blocks=(256, 512), tiles=(4096, 8192, 16384, 32768),
-               grids=(0,), passes=(1, 2), storage="f32", modes=(0, 2, 3),
+               grids=(0,), passes=(1, 2), storage="f32", modes=(0, 2, 3, 4),
                unit_blocks=(128, 256, 512), fuses=(4, 5, 6, 8), log=print):
     """Sweep the batch modes in ``modes``: the dataflow mode (0) over workgroup
-    size, tile size, grid and nodes per pass; the step-synchronous (1) and
-    flat (2) modes over workgroup size (= nodes per unit); the fused mode (3) over steps per launch.  A configuration whose
-    run is aborted by the bounded waits is reported and skipped."""
+    size, tile size, grid and nodes per pass; the step-synchronous (1) and flat
+    (2) modes over workgroup size (= nodes per unit); the fused mode (3) and its
+    persistent form (4) over steps per launch / pass.  A configuration whose run
+    is aborted by the bounded waits is reported and skipped."""
     import torch
 
     from . import workloads as W
@@ -120,10 +121,11 @@ def tune_batch(seed=0, steps=96, blocks=(256, 512), tiles=(4096, 8192, 16384, 32
     if 2 in modes:
         for block in unit_blocks:
             configs.append(dict(mode=2, block=block, tile_nodes=block, grid=0, pass_nodes=1))
-    if 3 in modes:
-        for fuse in fuses:
-            configs.append(dict(mode=3, fuse_steps=fuse, block=256, tile_nodes=256, grid=0,
-                                pass_nodes=1))
+    for m in (3, 4):
+        if m in modes:
+            for fuse in fuses:
+                configs.append(dict(mode=m, fuse_steps=fuse, block=256, tile_nodes=256, grid=0,
+                                    pass_nodes=1))
     rows = []
     for cfg in configs:
         B = Batch(insts, storage=storage, **cfg)

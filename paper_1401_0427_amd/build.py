@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["api.hip", "fwd.hip", "adjoint.hip", "batch.hip", "mrt.hip", "entropy.hip", "tblock.hip"]
+SOURCES = ["api.hip", "fwd.hip", "adjoint.hip", "batch.hip", "mrt.hip", "entropy.hip", "tblock.hip",
+           "pbatch.hip"]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 

@@ -44,7 +44,6 @@ struct TileDev {
 // The wait is bounded: after kSpinLimit polls, or once any workgroup has raised
 // the abort flag, it gives up and raises the flag, so every wave of the launch
 // always reaches the kernel's exit.  Returns 1 when aborting.
-static constexpr int kSpinLimit = 1 << 22;
 
 __device__ __forceinline__ int wait_ge(int *done, int t, int n, int *abort_flag)
 {
@@ -249,13 +248,15 @@ __global__ void __launch_bounds__(512)
 
 // ---- step-synchronous mode ------------------------------------------------------------
 // Each step's nodes are cut into units of blockDim consecutive (flat) nodes of
-// one instance; unit u is processed by workgroup u mod G, so at any moment the
-// G workgroups work on one contiguous window of units (the memory order of the
-// plain kernel) with one node per thread.  A grid barrier closes every step:
-// one agent-scope release and one acquire per workgroup per step.  The barrier
-// needs every workgroup resident (grid sized from the occupancy query); its wait
-// is bounded like the dataflow mode's, so a launch that is not fully resident
-// stops with the abort flag instead of hanging.
+// one instance, kSyncUnitsPerItem units to a work item; workgroups claim the
+// items of a step in order, so at any moment they work on one contiguous window
+// of units (the memory order of the plain kernel) with one node per thread.  A
+// step closes when all its items are complete (pass_claim / pass_complete: one
+// agent-scope release and one acquire per workgroup per step).  No wait depends
+// on a workgroup that has not started, so the grid need not be resident (the
+// occupancy query that sizes it ignores the scalar registers, which can admit
+// fewer workgroups than it reports); every wait is bounded like the dataflow
+// mode's.
 
 // Boundary pulls: the same face rules as the single-grid kernels, with an
 // inflow face's equilibrium evaluated in registers.  (A precomputed table
@@ -317,58 +318,48 @@ __device__ __forceinline__ void node_sync(const T *__restrict__ s, T *__restrict
     for (int pl = 0; pl < 12; ++pl) sth<2>(o + pl * ps, f[pl]);
 }
 
+// Units of the step-synchronous mode claimed together (one work item).
+constexpr int kSyncUnitsPerItem = 8;
+
 template <typename T>
 __global__ void __launch_bounds__(512)
     k_batch_sync(const InstDev *__restrict__ inst, const UnitDev *__restrict__ units, int nunits,
-                 int nsteps, T *buf0, T *buf1, int cur,
-                 unsigned *bar, int *abort_flag)
+                 int nsteps, T *buf0, T *buf1, int cur, unsigned long long *ctr, int *abort_flag)
 {
-    __shared__ int stop;
-    const unsigned G = gridDim.x;
+    const long long nitems = (nunits + kSyncUnitsPerItem - 1) / kSyncUnitsPerItem;
+    long long pending = -1;
     for (int n = 0; n < nsteps; ++n) {
         const bool odd = ((cur + n) & 1) != 0;
         const T *src = odd ? buf1 : buf0;
         T *dst = odd ? buf0 : buf1;
-        for (int u = blockIdx.x; u < nunits; u += (int)G) {
-            const UnitDev ud = units[u];
-            const InstDev I = inst[ud.inst];
-            const int k = ud.k0 + (int)threadIdx.x;
-            if (k < I.G.nx * I.G.ny)
-                node_sync(src + I.off, dst + I.off, I, k);
-        }
-        // grid barrier: the workgroup barrier orders every wave's stores before
-        // thread 0's agent-scope release (fetch-add); one acquire after the wait
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            const unsigned target = (unsigned)(n + 1) * G;
-            int a = 0;
-            for (int it = 0;; ++it) {
-                if (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target)
-                    break;
-                if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-                    a = 1;
-                    break;
-                }
-                if (it >= kSpinLimit) {
-                    __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    a = 1;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
+        const long long base = (long long)n * nitems, end = base + nitems;
+        int mine = 0;
+        for (;;) {
+            if (pending < 0) pending = pass_claim(ctr);
+            if (pending >= end) break;  // kept for a later step
+            const int u0 = (int)(pending - base) * kSyncUnitsPerItem;
+            pending = -1;
+            const int u1 = min(u0 + kSyncUnitsPerItem, nunits);
+            for (int u = u0; u < u1; ++u) {
+                const UnitDev ud = units[u];
+                const InstDev I = inst[ud.inst];
+                const int k = ud.k0 + (int)threadIdx.x;
+                if (k < I.G.nx * I.G.ny)
+                    node_sync(src + I.off, dst + I.off, I, k);
             }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            stop = a;
+            ++mine;
         }
-        __syncthreads();
-        if (__builtin_amdgcn_readfirstlane(stop) != 0) break;
+        if (pass_complete(ctr + 1, mine, (unsigned long long)end, abort_flag)) break;
     }
 }
 
-__global__ void k_batch_sync_reset(unsigned *bar, int *abort_flag)
+// Zero the claim and completion counters and the abort flag of a persistent
+// launch (a kernel, so that it can sit in a captured graph).
+__global__ void k_batch_sync_reset(unsigned long long *ctr, int *abort_flag)
 {
     if (threadIdx.x == 0) {
-        *bar = 0u;
+        ctr[0] = 0ull;
+        ctr[1] = 0ull;
         *abort_flag = 0;
     }
 }
@@ -428,7 +419,7 @@ struct lbm_batch {
     // step-synchronous mode
     UnitDev *d_units;
     int nunits;
-    unsigned *d_bar;
+    unsigned long long *d_ctr;  // step-synchronous / persistent fused: claim, completion
     int grid;
     // fused mode: K steps per launch pair (2D wave-strip tiles + 1D tiles)
     XkTileDev *d_xtiles;
@@ -490,7 +481,7 @@ extern "C" void lbm_batch_destroy(lbm_batch *b)
     (void)hipFree(b->d_next);
     (void)hipFree(b->d_abort);
     (void)hipFree(b->d_units);
-    (void)hipFree(b->d_bar);
+    (void)hipFree(b->d_ctr);
     (void)hipFree(b->d_xtiles);
     (void)hipFree(b->d_xbtiles);
     (void)hipFree(b->d_ktiles);
@@ -508,13 +499,8 @@ static bool inst_bounded(const lbm_instance &I)
            !(I.bc[0] == 0 && I.bc[1] == 0 && I.bc[2] == 0 && I.bc[3] == 0);
 }
 
-static int fused_seg(bool f32, int K, const std::vector<lbm_instance> &inst)
+static int fused_seg(bool f32, int K, const std::vector<lbm_instance> &inst, long slots)
 {
-    int dev = 0, ncu = 0;
-    long slots = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
-        slots = (long)ncu * batch_xk_per_cu(f32, K);
     int maxny = 0;
     for (const lbm_instance &I : inst)
         if (I.lattice == LBM_D2Q4x3) maxny = std::max(maxny, I.ny);
@@ -574,17 +560,19 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
     }
     lbm_batch_tuning tune = {256, 16384, 0, 1, 0, 0, 0};
     if (tuning) tune = *tuning;
-    if (tune.mode < 0 || tune.mode > 3)
+    if (tune.mode < 0 || tune.mode > 4)
         return bfail(LBM_EINVAL, "tuning.mode must be 0 (dataflow), 1 (step-synchronous), 2 "
-                                 "(flat) or 3 (fused)");
-    if (tune.mode == 3) {
+                                 "(flat), 3 (fused) or 4 (persistent fused)");
+    const bool fusedm = tune.mode == 3 || tune.mode == 4;
+    if (fusedm) {
         if (tune.fuse_steps < 0 || tune.fuse_steps == 1 || tune.fuse_steps > 8)
             return bfail(LBM_EINVAL, "tuning.fuse_steps must be 0 or in 2 .. 8 (got %d)",
                          tune.fuse_steps);
         for (int i = 0; i < n; ++i) {
             const lbm_instance &I = inst[i];
             if ((long)I.nx * I.ny * (storage == LBM_F32 ? 4 : 8) >= (1L << 31))
-                return bfail(LBM_EINVAL, "instance %d: planes of 2 GiB or more (mode 3)", i);
+                return bfail(LBM_EINVAL, "instance %d: planes of 2 GiB or more (modes 3, 4)",
+                             i);
         }
     }
     if (tune.pass_nodes == 0) tune.pass_nodes = 1;
@@ -688,16 +676,37 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
     std::vector<XkTileDev> hx, hxb;
     std::vector<K1TileDev> hk;
     b->chunk = 32;
-    if (tune.mode == 3) {
-        int K = tune.fuse_steps ? tune.fuse_steps : (b->f32 ? 6 : 8);
+    int dev = 0, ncu = 0, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (ncu <= 0) ncu = 256;
+    if (fusedm) {
+        int K = tune.fuse_steps ? tune.fuse_steps : 8;
         bool anyb = false;
         for (int i = 0; i < n; ++i) anyb = anyb || inst_bounded(inst[i]);
         if (anyb && !tune.fuse_steps) K = std::min(K, step2k_default_k_bounded(b->f32));
         if (anyb && K > step2k_max_k_bounded()) K = step2k_max_k_bounded();
         b->fuse = K;
         b->chunk = 2L * K * ((32 + 2 * K - 1) / (2 * K));
-        b->xk_seg = fused_seg(b->f32, K, inst);
-        const int wo = batch_xk_out(b->f32, K), n1 = batch_1k_out(K);
+        long slots;
+        if (tune.mode == 4) {
+            // persistent grid: the resident workgroups the occupancy query reports
+            // (the launch completes with any grid)
+            per_cu = batch_pfused_per_cu(b->f32, K, anyb);
+            if (per_cu <= 0) {
+                lbm_batch_destroy(b);
+                return bfail(LBM_EDEVICE, "no resident workgroup for the persistent kernel");
+            }
+            long g = (long)ncu * per_cu;
+            if (tune.grid > 0 && tune.grid < g) g = tune.grid;
+            b->grid = (int)g;
+            slots = g;
+        } else {
+            slots = (long)ncu * batch_xk_per_cu(b->f32, K);
+        }
+        b->xk_seg = fused_seg(b->f32, K, inst, slots);
+        const int wo = batch_xk_out(b->f32, K);
+        const int n1 = tune.mode == 4 ? batch_p1k_out(K) : batch_1k_out(K);
         const int wob = anyb ? batch_xkb_out(b->f32, K) : wo;
         for (int i = 0; i < n; ++i) {
             const lbm_instance &I = inst[i];
@@ -730,7 +739,7 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
         (e = hipMalloc(&b->d_next, sizeof(unsigned long long))) != hipSuccess ||
         (e = hipMalloc(&b->d_abort, sizeof(int))) != hipSuccess ||
         (e = hipMalloc(&b->d_units, sizeof(UnitDev) * hu.size())) != hipSuccess ||
-        (e = hipMalloc(&b->d_bar, sizeof(unsigned))) != hipSuccess ||
+        (e = hipMalloc(&b->d_ctr, 2 * sizeof(unsigned long long))) != hipSuccess ||
         (e = hipMalloc(&b->d_xtiles, sizeof(XkTileDev) * std::max<size_t>(1, hx.size()))) !=
             hipSuccess ||
         (e = hipMalloc(&b->d_xbtiles, sizeof(XkTileDev) * std::max<size_t>(1, hxb.size()))) !=
@@ -758,9 +767,6 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
         return bfail(LBM_EDEVICE, "batch setup failed: %s", hipGetErrorString(e));
     }
     // persistent grid: fill the device
-    int dev = 0, ncu = 0, per_cu = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (tune.mode >= 2)
         per_cu = 1;  // ordinary launches: one workgroup per unit / tile
     else if (tune.mode == 1 && b->f32)
@@ -775,11 +781,11 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<double, 2>, tune.block, 0);
     else
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<double, 1>, tune.block, 0);
-    if (ncu <= 0) ncu = 256;
     if (per_cu <= 0) per_cu = 1;
-    b->grid = tune.mode == 2 ? b->nunits
-              : tune.mode == 3 ? b->nxtiles + b->nxbtiles + b->nktiles
-                               : (tune.grid > 0 ? tune.grid : ncu * per_cu);
+    if (tune.mode != 4)
+        b->grid = tune.mode == 2 ? b->nunits
+                  : tune.mode == 3 ? b->nxtiles + b->nxbtiles + b->nktiles
+                                   : (tune.grid > 0 ? tune.grid : ncu * per_cu);
     *out = b;
     return LBM_OK;
 }
@@ -824,19 +830,49 @@ extern "C" int lbm_batch_init(lbm_batch *b, const double *h0, const double *qx0,
     return LBM_OK;
 }
 
+static void launch_flat(lbm_batch *b, int cur, hipStream_t st);
+
+// Buffer swaps of nsteps steps: one per step, except in the persistent fused
+// mode (one per K-step pass, then one per leftover single step).
+static long batch_flips(const lbm_batch *b, long nsteps)
+{
+    return b->tune.mode == 4 ? nsteps / b->fuse + nsteps % b->fuse : nsteps;
+}
+
 static hipError_t enqueue_run(lbm_batch *b, long nsteps, hipStream_t st)
 {
+    if (b->tune.mode == 4) {
+        // one persistent launch of nsteps / K passes, then the leftover steps as
+        // single flat launches (the same state bit for bit)
+        const long np = nsteps / b->fuse, rem = nsteps % b->fuse;
+        int c = b->cur;
+        if (np > 0) {
+            hipLaunchKernelGGL(k_batch_sync_reset, dim3(1), dim3(64), 0, st, b->d_ctr,
+                               b->d_abort);
+            hipError_t e = launch_batch_pfused(
+                b->f32, b->fuse, b->nxbtiles > 0, b->grid, b->d_inst, b->d_xtiles, b->nxtiles,
+                b->d_xbtiles, b->nxbtiles, b->d_ktiles, b->nktiles, (int)np, b->buf[0],
+                b->buf[1], c, b->d_ctr, b->d_abort, st);
+            if (e != hipSuccess) return e;
+            c = (int)((c + np) & 1);
+        }
+        for (long k = 0; k < rem; ++k) {
+            launch_flat(b, c, st);
+            c ^= 1;
+        }
+        return hipGetLastError();
+    }
     if (b->tune.mode == 1) {
-        hipLaunchKernelGGL(k_batch_sync_reset, dim3(1), dim3(64), 0, st, b->d_bar, b->d_abort);
+        hipLaunchKernelGGL(k_batch_sync_reset, dim3(1), dim3(64), 0, st, b->d_ctr, b->d_abort);
         if (b->f32)
             hipLaunchKernelGGL(k_batch_sync<float>, dim3(b->grid), dim3(b->tune.block), 0, st,
                                b->d_inst, b->d_units, b->nunits, (int)nsteps,
-                               (float *)b->buf[0], (float *)b->buf[1], b->cur, b->d_bar,
+                               (float *)b->buf[0], (float *)b->buf[1], b->cur, b->d_ctr,
                                b->d_abort);
         else
             hipLaunchKernelGGL(k_batch_sync<double>, dim3(b->grid), dim3(b->tune.block), 0, st,
                                b->d_inst, b->d_units, b->nunits, (int)nsteps,
-                               (double *)b->buf[0], (double *)b->buf[1], b->cur, b->d_bar,
+                               (double *)b->buf[0], (double *)b->buf[1], b->cur, b->d_ctr,
                                b->d_abort);
         return hipGetLastError();
     }
@@ -960,14 +996,12 @@ extern "C" int lbm_batch_run(lbm_batch *b, long nsteps)
 {
     if (!b) return bfail(LBM_ESTATE, "null batch");
     if (nsteps < 0 || nsteps > (1L << 30)) return bfail(LBM_EINVAL, "bad nsteps");
-    if (b->tune.mode >= 2) return run_flat(b, nsteps);
-    if (b->tune.mode == 1 && (double)nsteps * b->grid >= 2147483648.0)
-        return bfail(LBM_EINVAL, "nsteps x grid too large for the step-synchronous mode");
+    if (b->tune.mode == 2 || b->tune.mode == 3) return run_flat(b, nsteps);
     if (nsteps == 0) return LBM_OK;
     if (b->tune.direct) {
         BHIP(enqueue_run(b, nsteps, b->st));
         b->steps += nsteps;
-        b->cur = (int)((b->cur + nsteps) & 1);
+        b->cur = (int)((b->cur + batch_flips(b, nsteps)) & 1);
         return LBM_OK;
     }
     if (!b->gexec || b->g_nsteps != nsteps || b->g_cur != b->cur) {
@@ -996,7 +1030,7 @@ extern "C" int lbm_batch_run(lbm_batch *b, long nsteps)
     }
     BHIP(hipGraphLaunch(b->gexec, b->st));
     b->steps += nsteps;
-    b->cur = (int)((b->cur + nsteps) & 1);
+    b->cur = (int)((b->cur + batch_flips(b, nsteps)) & 1);
     return LBM_OK;
 }
 
@@ -1007,8 +1041,9 @@ extern "C" int lbm_batch_check(lbm_batch *b)
     BHIP(hipMemcpyAsync(&flag, b->d_abort, sizeof flag, hipMemcpyDeviceToHost, b->st));
     BHIP(hipStreamSynchronize(b->st));
     if (flag)
-        return bfail(LBM_EDEVICE, "batched run aborted: a tile dependency was not satisfied "
-                                  "within the scheduler's wait limit (state is invalid)");
+        return bfail(LBM_EDEVICE, "batched run aborted: a wait of the persistent launch (tile "
+                                  "dependency or grid barrier) did not end within its limit "
+                                  "(state is invalid)");
     return LBM_OK;
 }
 
@@ -1042,7 +1077,7 @@ extern "C" int lbm_batch_info(lbm_batch *b, int *ntiles, int *grid)
     if (!b) return bfail(LBM_ESTATE, "null batch");
     if (ntiles)
         *ntiles = b->tune.mode == 0 ? b->ntiles
-                  : b->tune.mode == 3 ? b->nxtiles + b->nxbtiles + b->nktiles
+                  : b->tune.mode >= 3 ? b->nxtiles + b->nxbtiles + b->nktiles
                                       : b->nunits;
     if (grid) *grid = b->grid;
     return LBM_OK;

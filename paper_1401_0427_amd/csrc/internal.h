@@ -41,6 +41,70 @@ struct K1TileDev {
     int ob;
 };
 
+// Polls at most of a bounded wait in a persistent launch.
+constexpr int kSpinLimit = 1 << 22;
+
+// Work distribution of a persistent launch that advances in passes (one step, or
+// K steps) over nitems work items each.  A 64-bit claim counter hands out item
+// indices in order (pass p owns [p nitems, (p + 1) nitems)); a workgroup that
+// finds the pass exhausted adds the number of items it completed to a 64-bit
+// completion counter and waits until the pass's total is reached.  No wait
+// depends on a workgroup that has not started, so a launch completes whatever
+// number of its workgroups are resident at once (residency decides only the
+// speed); an index claimed beyond the pass is kept for the pass it belongs to.
+
+// Claim the next index (the same value on every lane of the workgroup).  The
+// leading barrier also ends every wave's use of the LDS by the previous item.
+__device__ __forceinline__ long long pass_claim(unsigned long long *next)
+{
+    __shared__ unsigned long long s_claim;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        s_claim = __hip_atomic_fetch_add(next, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const unsigned long long v = s_claim;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+// Report `mine` completed items and wait until `target` items in all are
+// complete.  The workgroup barrier orders every wave's stores before thread 0's
+// agent-scope release (the fetch-add; fence cumulativity); thread 0 then polls
+// with relaxed loads and issues one agent-scope acquire for the workgroup.  The
+// wait is bounded: after kSpinLimit polls, or once any workgroup has raised the
+// abort flag, it raises the flag and gives up.  Returns nonzero (the same on
+// every lane of the workgroup) when the launch is aborting.
+__device__ __forceinline__ int pass_complete(unsigned long long *done, int mine,
+                                             unsigned long long target, int *abort_flag)
+{
+    __shared__ int s_stop;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(done, (unsigned long long)mine, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        int a = 0;
+        for (int it = 0;; ++it) {
+            if (__hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target)
+                break;
+            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                a = 1;
+                break;
+            }
+            if (it >= kSpinLimit) {
+                __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                a = 1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        s_stop = a;
+    }
+    __syncthreads();
+    return __builtin_amdgcn_readfirstlane(s_stop);
+}
+
 // Launch shape of the plain forward / adjoint kernels.
 struct Launch {
     int block;  // threads per workgroup
@@ -96,6 +160,17 @@ hipError_t launch_batch_xkb(bool f32, int K, const InstDev *inst, const XkTileDe
                             int ntiles, const void *src, void *dst, hipStream_t st);
 hipError_t launch_batch_1k(bool f32, int K, const InstDev *inst, const K1TileDev *tiles,
                            int ntiles, const void *src, void *dst, hipStream_t st);
+
+// Persistent batched launch (pbatch.hip): npasses passes of K steps over every
+// tile of the three tables (2D all-periodic, 2D with other faces, 1D) in one
+// launch; ctr = {claim counter, completion counter}, zero before the launch.
+int batch_p1k_out(int K);  // output nodes per 1D tile of the persistent launch
+int batch_pfused_per_cu(bool f32, int K, bool bnd);
+hipError_t launch_batch_pfused(bool f32, int K, bool bnd, int grid, const InstDev *inst,
+                               const XkTileDev *xt, int nxt, const XkTileDev *xbt, int nxbt,
+                               const K1TileDev *kt, int nkt, int npasses, void *buf0,
+                               void *buf1, int cur, unsigned long long *ctr, int *abort_flag,
+                               hipStream_t st);
 hipError_t launch_step2k(bool f32, const void *src, void *dst, const Geo &G, const Phys &P,
                          int K, int seg, hipStream_t st);
 hipError_t launch_entropy(int dim, bool f32, const void *state, const Geo &G, double lambda,

@@ -415,8 +415,10 @@ class Batch:
         inflow, h0, qx0, qy0 (numpy arrays of the instance's nodes).  ``mode`` 0 is
         the dataflow persistent launch, 1 the step-synchronous persistent launch
         (one grid barrier per step), 2 one flat launch per step, 3 ``fuse_steps``
-        steps per launch (0 = library default).  ``direct`` launches every kernel
-        directly instead of replaying captured graphs (e.g. under a profiler)."""
+        steps per launch (0 = library default), 4 the tiles of mode 3 in one
+        persistent launch (``fuse_steps`` steps per pass, one grid barrier per
+        pass).  ``direct`` launches every kernel directly instead of replaying
+        captured graphs (e.g. under a profiler)."""
         import torch
 
         _require_gpu(torch)

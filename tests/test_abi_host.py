@@ -110,10 +110,11 @@ def test_batch_create_rejects_bad_step_synchronous_tuning(L):
     assert "block" in L.last_error()
 
 
-@pytest.mark.parametrize("bad", [dict(mode=3, fuse=1), dict(mode=3, fuse=9), dict(mode=4)])
+@pytest.mark.parametrize("bad", [dict(mode=3, fuse=1), dict(mode=3, fuse=9), dict(mode=4, fuse=1),
+                                 dict(mode=4, fuse=9), dict(mode=5), dict(mode=-1)])
 def test_batch_create_rejects_bad_fused_mode(L, bad):
-    """Mode 3 takes 2 .. 8 steps per launch (0: its default); unknown modes are
-    rejected."""
+    """Modes 3 and 4 take 2 .. 8 steps per launch / pass (0: the default);
+    unknown modes are rejected."""
     arr = (L.LbmInstance * 1)()
     arr[0].lattice, arr[0].nx, arr[0].ny = L.D2Q4x3, 64, 64
     arr[0].lam, arr[0].s, arr[0].g = 6.0, 1.8, 1.0

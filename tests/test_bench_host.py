@@ -95,3 +95,24 @@ def test_roofline_bound_follows_the_counters(monkeypatch):
     monkeypatch.setattr(bench, "_summary", lambda k, w, n, K: fake(k, w, n, K, 0.9))
     r = bench.roofline(_form(8, 250, 250, 0.6), 4096, "wave_strip")
     assert r["bound"] == "alu" and r["unit"] == "TFLOP/s" and r["valu_busy"] == 0.9
+
+
+def test_batched_counter_summary_is_self_consistent_and_keyed_to_the_sources():
+    """The batched kernels' DRAM summary: bytes = counter x 1024 / copy-probe scale,
+    compulsory bytes = every instance's state read and written once per pass (FP32:
+    48 B per 2D node, 16 B per 1D node each way); carried only for the current
+    batched sources."""
+    d = json.load(open(os.path.join(ROOT, "profiles", "k_batch_manifest256_traffic.json")))
+    assert d["compulsory_bytes_per_pass"] == 2 * (d["nodes_2d"] * 48 + d["nodes_1d"] * 16)
+    probe = d["copy_probe"]
+    for name, k in d["kernels"].items():
+        assert k["read_bytes"] == pytest.approx(k["FETCH_SIZE_KiB"] * 1024 / probe["fetch_scale"],
+                                                rel=1e-4)
+        assert k["write_bytes"] == pytest.approx(k["WRITE_SIZE_KiB"] * 1024 / probe["write_scale"],
+                                                 rel=1e-4)
+        assert k["write_over_alg"] >= 0.95, name
+    t = bench._batch_traffic()
+    if d["kernel_source_sha"] == bench._sources_sha(bench.BATCH_SOURCES):
+        assert set(t["kernels"]) == set(d["kernels"])
+    else:
+        assert t is None

@@ -236,7 +236,7 @@ def test_batch_fused_mode_with_faces_run_twice_equals_one_long_run():
         assert np.array_equal(to_np(a), to_np(b))
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4])
 def test_batch_direct_launches_equal_graph_replays(mode):
     """With tuning.direct every kernel is launched on the stream instead of from a
     captured graph; the state is the same bit for bit."""
@@ -251,3 +251,78 @@ def test_batch_direct_launches_equal_graph_replays(mode):
     B.run(70, check_done=True)
     hA, hB = A.moments()[0], B.moments()[0]
     assert torch.equal(hA, hB)
+
+
+@pytest.mark.parametrize("faces", [False, True])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("fuse", [0, 3, 8])
+def test_batch_persistent_fused_mode_equals_flat_mode(storage, fuse, faces):
+    """Mode 4 (the fused tiles in one persistent launch, fuse_steps steps per
+    pass, a grid barrier between passes) gives bit for bit the state of mode 2
+    after a step count that leaves a remainder of single steps; the launch
+    completes (no bounded wait expired); FP64 also matches the oracle per
+    instance."""
+    from paper_1401_0427_amd.lbm import Batch
+
+    insts = _faces_instances(seed=8) if faces else _fused_instances(seed=9)
+    steps = 157
+    say(f"[batch persistent fused] {len(insts)} instances, {steps} steps, fuse {fuse}, "
+        f"{storage}, faces={faces}")
+    A = Batch(insts, storage=storage, mode=2)
+    B = Batch(insts, storage=storage, mode=4, fuse_steps=fuse)
+    nt, grid = B.info()
+    say(f"  tiles {nt}, grid {grid}")
+    assert grid > 0
+    A.run(steps)
+    B.run(steps, check_done=True)
+    for i in range(len(insts)):
+        assert np.array_equal(to_np(A.instance_planes(i)), to_np(B.instance_planes(i))), i
+    if storage == "f64":
+        mom = [to_np(t) for t in B.moments()]
+        worst = 0.0
+        for i, d in enumerate(insts):
+            ref = oracle_moments(d, steps)
+            got = [B.instance_view(i, t) for t in mom[: 2 if d["dim"] == 1 else 3]]
+            worst = max(worst, max(normwise_rel(a, b) for a, b in zip(got, ref)))
+        say(f"  worst instance rel err {worst:.3e}")
+        assert worst <= 1e-12
+
+
+@pytest.mark.parametrize("grid", [0, 1, 8, 24])
+def test_batch_persistent_fused_mode_run_twice_and_small_grids(grid):
+    """Mode 4 run as 51 + 50 steps equals one run of 101 and mode 3's state, also
+    with a grid capped far below the item count (each workgroup then runs many
+    items per pass; one workgroup runs them all)."""
+    from paper_1401_0427_amd.lbm import Batch
+
+    insts = _faces_instances(seed=7)  # (a seed whose instances all stay finite)
+    A = Batch(insts, storage="f64", mode=4, grid=grid)
+    B = Batch(insts, storage="f64", mode=4, grid=grid)
+    C = Batch(insts, storage="f64", mode=3)
+    if grid:
+        assert A.info()[1] == grid
+    A.run(51, check_done=True)
+    A.run(50, check_done=True)
+    B.run(101, check_done=True)
+    C.run(101)
+    for a, b, c in zip(A.moments(), B.moments(), C.moments()):
+        assert np.isfinite(to_np(a)).all()
+        assert np.array_equal(to_np(a), to_np(b))
+        assert np.array_equal(to_np(a), to_np(c))
+
+
+@pytest.mark.parametrize("grid", [1, 3, 100000])
+def test_batch_step_synchronous_mode_any_grid(grid):
+    """Mode 1 completes and matches mode 2 bit for bit with a single workgroup,
+    with a few, and with a grid far larger than the device holds at once (the
+    workgroups that start late find every item of the step claimed)."""
+    from paper_1401_0427_amd.lbm import Batch
+
+    insts = instance_dicts(W.small_manifest(seed=11), True)
+    A = Batch(insts, storage="f64", mode=2)
+    B = Batch(insts, storage="f64", mode=1, grid=grid)
+    assert B.info()[1] == grid
+    A.run(23)
+    B.run(23, check_done=True)
+    for i in range(len(insts)):
+        assert np.array_equal(to_np(A.instance_planes(i)), to_np(B.instance_planes(i))), i
