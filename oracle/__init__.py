@@ -66,6 +66,8 @@ def lib():
         _lib.orc_moments.argtypes = [pp, dp, dp, dp, dp]
         _lib.orc_adjoint_step.argtypes = [pp, dp, dp, dp, dp]
         _lib.orc_loss_grad_2d.argtypes = [pp, dp, dp, ctypes.c_long, ctypes.c_int, dp, dp, dp]
+        _lib.orc_loss_grad.argtypes = [pp, dp, dp, ctypes.c_long, ctypes.c_int, dp, dp, dp]
+        _lib.orc_step_cs.argtypes = [pp, dp, dp, ctypes.c_double, ctypes.c_double, dp]
         _lib.orc_loss_cs_2d.argtypes = [pp, dp, dp, ctypes.c_double, dp, ctypes.c_long,
                                         ctypes.c_double, dp, dp]
         _lib.orc_entropy.argtypes = [pp, dp, dp, dp, ctypes.POINTER(ctypes.c_long)]
@@ -75,8 +77,8 @@ def lib():
         _lib.orc_get_threads.argtypes = []
         _lib.orc_get_threads.restype = ctypes.c_int
         for name in ("orc_feq", "orc_collide", "orc_run", "orc_advance", "orc_moments",
-                     "orc_adjoint_step", "orc_loss_grad_2d", "orc_loss_cs_2d", "orc_entropy",
-                     "orc_entropy_pop"):
+                     "orc_adjoint_step", "orc_loss_grad_2d", "orc_loss_grad", "orc_step_cs",
+                     "orc_loss_cs_2d", "orc_entropy", "orc_entropy_pop"):
             getattr(_lib, name).restype = ctypes.c_int
     return _lib
 
@@ -177,8 +179,14 @@ def moments(P: OrcParams, f):
     return h.reshape(P.ny, P.nx), qx.reshape(P.ny, P.nx), qy.reshape(P.ny, P.nx)
 
 
+def _field_shape(P):
+    np_ = 5 if P.dim == 1 else 13
+    return (np_, P.nx) if P.dim == 1 else (np_, P.ny, P.nx)
+
+
 def adjoint_step(P: OrcParams, un, lam_np1):
-    """One adjoint step (13-population layout): returns (lam_n, dL/ds contribution)."""
+    """One adjoint step (population-major layout: 5 populations in 1D, 13 in 2D),
+    any face rules: returns (lam_n, dL/ds contribution)."""
     un = _f64(un).reshape(-1)
     lam_np1 = _f64(lam_np1).reshape(-1)
     lam_n = np.zeros_like(lam_np1)
@@ -187,7 +195,33 @@ def adjoint_step(P: OrcParams, un, lam_np1):
                                 ctypes.byref(gs))
     if rc != 0:
         raise ValueError(f"orc_adjoint_step failed ({rc})")
-    return lam_n.reshape(13, P.ny, P.nx), gs.value
+    return lam_n.reshape(_field_shape(P)), gs.value
+
+
+def step_directional(P: OrcParams, u, du=None, ds=0.0, eps=1e-30):
+    """Directional derivative of one step between post-collision levels along
+    (du, ds), by complex step of the forward code."""
+    u = _f64(u).reshape(-1)
+    du = None if du is None else _f64(du).reshape(-1)
+    out = np.zeros_like(u)
+    rc = lib().orc_step_cs(ctypes.byref(P), _dp(u), _dp(du), float(ds), float(eps), _dp(out))
+    if rc != 0:
+        raise ValueError(f"orc_step_cs failed ({rc})")
+    return out.reshape(_field_shape(P))
+
+
+def loss_grad(P: OrcParams, h0, hhat, T, K=23):
+    """(loss, dL/dh0, dL/ds) for L = sum (h(T) - hhat)^2 from W0 = (h0, 0, 0), 1D or
+    2D, any face rules."""
+    h0 = _f64(h0).reshape(-1)
+    hhat = _f64(hhat).reshape(-1)
+    g = np.zeros_like(h0)
+    loss, gs = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    rc = lib().orc_loss_grad(ctypes.byref(P), _dp(h0), _dp(hhat), int(T), int(K),
+                             ctypes.byref(loss), _dp(g), ctypes.byref(gs))
+    if rc != 0:
+        raise ValueError(f"orc_loss_grad failed ({rc})")
+    return loss.value, (g if P.dim == 1 else g.reshape(P.ny, P.nx)), gs.value
 
 
 def loss_grad_2d(P: OrcParams, h0, hhat, T, K=23):
@@ -204,7 +238,8 @@ def loss_grad_2d(P: OrcParams, h0, hhat, T, K=23):
 
 
 def loss_complex_step_2d(P: OrcParams, h0, hhat, T, dh0=None, ds=0.0, eps=1e-30):
-    """(loss, directional derivative) by complex step along (dh0, ds)."""
+    """(loss, directional derivative) by complex step along (dh0, ds); 1D or 2D,
+    any face rules (the name predates the 1D case)."""
     h0 = _f64(h0).reshape(-1)
     hhat = _f64(hhat).reshape(-1)
     dh0 = None if dh0 is None else _f64(dh0).reshape(-1)

@@ -358,13 +358,17 @@ int orc_moments(const orc_params *P, const double *f, double *h, double *qx, dou
     return 0;
 }
 
-/* ---- discrete adjoint (a = 0, BGK, 2D, periodic) --------------------------
+/* ---- discrete adjoint (a = 0, BGK, 1D and 2D, every face rule) -----------
  * Forward, post-collision state u: u^0 = C(f^eq(W0)), u^{n+1} = C(S(u^n)),
- * C(v) = (1-s) v + s f^eq(W(v)), S the pull-stream, loss
- * L = sum_x (h(u^T)(x) - hhat(x))^2.  With lam^{n} = dL/du^n:
+ * C(v) = (1-s) v + s f^eq(W(v)), S the pull-stream with the face rules of
+ * pull(), loss L = sum_x (h(u^T)(x) - hhat(x))^2.  With lam^{n} = dL/du^n:
  *   v(x) = S(u^n)(x);  mu_k(x) = sum_q lam^{n+1}_q(x) d f^eq_q / d W_k (W(v(x)));
  *   vt_p(x) = (1-s) lam^{n+1}_p(x) + s mu_{comp(p)}(x);
- *   lam^n_p(x - e_p) = vt_p(x)          (transpose of the pull-stream);
+ *   lam^n = S^T vt: every vt_p(x) is added to the slot of u^n that pull()
+ *     reads for population p at x -- the upstream node x - e_p inside the
+ *     domain or across a periodic face, the node's own p across a Neumann
+ *     face, its own opposite population (sign flipped for the normal momentum)
+ *     across a wall; across an inflow face nothing (the ghost is a constant);
  *   dL/ds += sum_x sum_p lam^{n+1}_p(x) (f^eq_p(W(v(x))) - v_p(x));
  *   dL/dW0(x) = J(W0(x))^T lam^0(x),   J = d f^eq / d W.
  * Partial derivatives of the 2D equilibrium at a = 0 (u = qx/h, v = qy/h):
@@ -372,7 +376,9 @@ int orc_moments(const orc_params *P, const double *f, double *h, double *qx, dou
  *            gy: -uv c on 1,3, (gh - v^2) c on 2,4
  *   d/dqx  : f_{1,3} +-c; gx 1/4 plus 2u c (1,3), v c (2,4); gy v c (1,3)
  *   d/dqy  : f_{2,4} +-c; gy 1/4 plus u c (1,3), 2v c (2,4); gx u c (2,4)
- * with c = 1/(2 lambda) and the sign of e_j along the flux direction. */
+ * with c = 1/(2 lambda) and the sign of e_j along the flux direction.  1D
+ * (f_+- = h/2 +- q c, g_+- = q/2 +- (q^2/h + (g/2) h^2) c, u = q/h):
+ *   d/dh : f_+- 1/2;  g_+- +-(g h - u^2) c;   d/dq : f_+- +-c;  g_+- 1/2 +- 2 u c. */
 static void adj_mu_2d(const orc_params *P, const double *W, const double *lam, double *mu)
 {
     const double c = 0.5 / P->lambda, g = P->g;
@@ -388,66 +394,176 @@ static void adj_mu_2d(const orc_params *P, const double *W, const double *lam, d
     mu[2] = c * Lyh + 0.25 * L0y + c * (2.0 * v * Lyy + u * Lxy + u * Lyx);
 }
 
+static void adj_mu_1d(const orc_params *P, const double *W, const double *lam, double *mu)
+{
+    const double c = 0.5 / P->lambda, g = P->g;
+    double h = W[0], u = W[1] / h;
+    double L0f = lam[1] + lam[2], L1f = lam[1] - lam[2];
+    double L0g = lam[3] + lam[4], L1g = lam[3] - lam[4];
+    mu[0] = 0.5 * L0f + c * (g * h - u * u) * L1g;
+    mu[1] = c * L1f + 0.5 * L0g + 2.0 * u * c * L1g;
+}
+
+static void adj_mu(const orc_params *P, const double *W, const double *lam, double *mu)
+{
+    if (P->dim == 1)
+        adj_mu_1d(P, W, lam, mu);
+    else
+        adj_mu_2d(P, W, lam, mu);
+}
+
 static int adj_supported(const orc_params *P)
 {
     if (check_params(P)) return 0;
-    if (P->dim != 2 || P->a != 0.0 || P->mrt) return 0;
-    for (int f = 0; f < 4; ++f) if (P->bc[f] != ORC_BC_PERIODIC) return 0;
-    return 1;
+    return P->a == 0.0 && !P->mrt;
+}
+
+/* Transpose of pull(): add val to the slot of the field that
+ * pull(P, field, ., p, x, y) reads (nothing across an inflow face). */
+static void pull_transpose(const orc_params *P, double *const *lam, int p, int x, int y,
+                           double val)
+{
+    int nx = P->nx, ny = P->ny;
+    int sx = x - orc_ex(P->dim, p), sy = y - orc_ey(P->dim, p);
+    int face = -1;
+    if (sx < 0) face = 0;
+    else if (sx >= nx) face = 1;
+    else if (sy < 0) face = 2;
+    else if (sy >= ny) face = 3;
+    if (face < 0) {
+        lam[p][(long)sy * nx + sx] += val;
+        return;
+    }
+    switch (P->bc[face]) {
+    case ORC_BC_PERIODIC:
+        sx = (sx + nx) % nx;
+        sy = (sy + ny) % ny;
+        lam[p][(long)sy * nx + sx] += val;
+        return;
+    case ORC_BC_NEUMANN:
+        lam[p][(long)y * nx + x] += val;
+        return;
+    case ORC_BC_WALL: {
+        int q = orc_opposite(P->dim, p);
+        int normal = (face < 2) ? 1 : 2;
+        lam[q][(long)y * nx + x] += (orc_comp(P->dim, p) == normal) ? -val : val;
+        return;
+    }
+    default: /* ORC_BC_INFLOW */
+        return;
+    }
+}
+
+static void inflow_feq_d(const orc_params *P, double *feq_in)
+{
+    for (int face = 0; face < 4; ++face)
+        if (P->bc[face] == ORC_BC_INFLOW) {
+            double Win[3] = {P->inflow[face][0], P->inflow[face][1], P->inflow[face][2]};
+            feq_node_d(P, Win, feq_in + face * ORC_NPMAX);
+        }
 }
 
 /* One adjoint step: given the forward post-collision state u^n and lam^{n+1},
  * write lam^n and add this step's contribution to *dLds (all arrays
- * population-major, 13 populations; the rest population's adjoint is carried
- * for exactness but never reaches the gradients at a = 0). */
+ * population-major, npop populations: 5 in 1D, 13 in 2D; the rest population's
+ * adjoint is carried for exactness but never reaches the gradients at a = 0). */
 int orc_adjoint_step(const orc_params *P, const double *un, const double *lam_np1,
                      double *lam_n, double *dLds)
 {
     if (!adj_supported(P) || !un || !lam_np1 || !lam_n) return -1;
-    const int np = 13, nx = P->nx, ny = P->ny;
+    const int np = orc_npop(P->dim), nx = P->nx, ny = P->ny;
     const long n = (long)nx * ny;
     const double s = P->s;
-    double acc = 0.0;
+    double feq_in[4 * ORC_NPMAX];
+    inflow_feq_d(P, feq_in);
+    double *U[ORC_NPMAX], *Ln[ORC_NPMAX];
+    for (int q = 0; q < np; ++q) {
+        U[q] = (double *)un + (long)q * n;
+        Ln[q] = lam_n + (long)q * n;
+    }
+    double *vt = (double *)malloc(sizeof(double) * (size_t)np * (size_t)n);
     double *row_acc = (double *)calloc((size_t)ny, sizeof(double));
-    if (!row_acc) return -2;
+    if (!vt || !row_acc) {
+        free(vt);
+        free(row_acc);
+        return -2;
+    }
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y) {
         double racc = 0.0;
         for (int x = 0; x < nx; ++x) {
             long i = (long)y * nx + x;
-            double v[13], lam[13], W[3], feq[13], mu[3];
+            double v[ORC_NPMAX], lam[ORC_NPMAX], W[3], feq[ORC_NPMAX], mu[3];
             for (int q = 0; q < np; ++q) {
-                int sx = (x - orc_ex(2, q) + nx) % nx, sy = (y - orc_ey(2, q) + ny) % ny;
-                v[q] = un[(long)q * n + (long)sy * nx + sx];
+                v[q] = pull_d(P, U, feq_in, q, x, y);
                 lam[q] = lam_np1[(long)q * n + i];
             }
-            moments_node_d(2, v, W);
-            feq2d_d(P, W[0], W[1], W[2], feq);
-            adj_mu_2d(P, W, lam, mu);
+            moments_node_d(P->dim, v, W);
+            feq_node_d(P, W, feq);
+            adj_mu(P, W, lam, mu);
             for (int q = 0; q < np; ++q) {
                 racc += lam[q] * (feq[q] - v[q]);
-                double vt = (1.0 - s) * lam[q] + s * mu[orc_comp(2, q)];
-                int tx = (x - orc_ex(2, q) + nx) % nx, ty = (y - orc_ey(2, q) + ny) % ny;
-                lam_n[(long)q * n + (long)ty * nx + tx] = vt;
+                vt[(long)q * n + i] = (1.0 - s) * lam[q] + s * mu[orc_comp(P->dim, q)];
             }
         }
         row_acc[y] = racc;
     }
+    /* lam^n = S^T vt, in node order */
+    memset(lam_n, 0, sizeof(double) * (size_t)np * (size_t)n);
+    for (long i = 0; i < n; ++i) {
+        const int y = (int)(i / nx), x = (int)(i % nx);
+        for (int q = 0; q < np; ++q) pull_transpose(P, Ln, q, x, y, vt[(long)q * n + i]);
+    }
+    double acc = 0.0;
     for (int y = 0; y < ny; ++y) acc += row_acc[y];
     free(row_acc);
+    free(vt);
     if (dLds) *dLds += acc;
     return 0;
 }
 
-/* Loss and gradients for the adjoint workload: W0 = (h0, 0, 0), T steps,
- * L = sum (h(u^T) - hhat)^2.  Forward states are checkpointed every K steps
- * and recomputed segment by segment in the backward sweep.
- * grad_h0 (n) and *grad_s receive dL/dh0 and dL/ds; *loss the loss. */
-int orc_loss_grad_2d(const orc_params *P, const double *h0, const double *hhat, long T, int K,
-                     double *loss, double *grad_h0, double *grad_s)
+/* Directional derivative of one step u -> C(S(u)) between post-collision levels
+ * along (du, ds), by complex step of the same forward code (pull and BGK
+ * collision in complex arithmetic): out = Im(C_{s + i eps ds}(S(u + i eps du))) / eps.
+ * Independent of the hand-derived adjoint above. */
+int orc_step_cs(const orc_params *P, const double *u, const double *du, double ds, double eps,
+                double *out)
+{
+    if (check_params(P) || P->mrt || !u || !out || !(eps > 0)) return -1;
+    const int np = orc_npop(P->dim), nx = P->nx;
+    const long n = (long)nx * P->ny;
+    double _Complex *mem = (double _Complex *)malloc(sizeof(double _Complex) * (size_t)np * (size_t)n);
+    if (!mem) return -2;
+    double _Complex *U[ORC_NPMAX];
+    for (int q = 0; q < np; ++q) U[q] = mem + (long)q * n;
+    for (long k = 0; k < (long)np * n; ++k) mem[k] = u[k] + I * (eps * (du ? du[k] : 0.0));
+    double _Complex feq_in[4 * ORC_NPMAX];
+    for (int face = 0; face < 4; ++face)
+        if (P->bc[face] == ORC_BC_INFLOW) {
+            double _Complex Win[3] = {P->inflow[face][0], P->inflow[face][1], P->inflow[face][2]};
+            feq_node_c(P, Win, feq_in + face * ORC_NPMAX);
+        }
+    const double _Complex s = P->s + I * (eps * ds);
+    for (long i = 0; i < n; ++i) {
+        const int y = (int)(i / nx), x = (int)(i % nx);
+        double _Complex v[ORC_NPMAX], fs[ORC_NPMAX];
+        for (int q = 0; q < np; ++q) v[q] = pull_c(P, U, feq_in, q, x, y);
+        collide_node_c(P, s, v, fs);
+        for (int q = 0; q < np; ++q) out[(long)q * n + i] = cimag(fs[q]) / eps;
+    }
+    free(mem);
+    return 0;
+}
+
+/* Loss and gradients for the adjoint workload: W0 = (h0, 0, 0) (1D: (h0, 0)),
+ * T steps, L = sum (h(u^T) - hhat)^2, any face rules.  Forward states are
+ * checkpointed every K steps and recomputed segment by segment in the backward
+ * sweep.  grad_h0 (n) and *grad_s receive dL/dh0 and dL/ds; *loss the loss. */
+int orc_loss_grad(const orc_params *P, const double *h0, const double *hhat, long T, int K,
+                  double *loss, double *grad_h0, double *grad_s)
 {
     if (!adj_supported(P) || !h0 || !hhat || T < 0 || K < 1) return -1;
-    const int np = 13;
+    const int np = orc_npop(P->dim);
     const long n = (long)P->nx * P->ny;
     const size_t bytes = sizeof(double) * (size_t)np * (size_t)n;
     long nck = T / K + 1;
@@ -464,7 +580,7 @@ int orc_loss_grad_2d(const orc_params *P, const double *h0, const double *hhat, 
         orc_field f0, fs;
         field_alloc(&f0, np, n);
         fs.np = np; fs.n = n; fs.mem = cur;
-        for (int q = 0; q < ORC_NPMAX; ++q) fs.p[q] = cur + (long)q * n;
+        for (int q = 0; q < ORC_NPMAX; ++q) fs.p[q] = q < np ? cur + (long)q * n : NULL;
         init_eq_d(P, h0, NULL, NULL, f0.p);
         collide_field(P, P->s, &f0, &fs);
         field_free(&f0);
@@ -474,16 +590,17 @@ int orc_loss_grad_2d(const orc_params *P, const double *h0, const double *hhat, 
         orc_advance(P, cur, 1);
         if ((t + 1) % K == 0 && (t + 1) / K < nck) memcpy(ck + (size_t)((t + 1) / K) * np * n, cur, bytes);
     }
-    /* terminal adjoint */
+    /* terminal adjoint: dL/du^T = 2 (h - hhat) on every population of h */
     double L = 0.0;
     memset(lamA, 0, bytes);
     for (long i = 0; i < n; ++i) {
-        double fl[13], W[3];
+        double fl[ORC_NPMAX], W[3];
         for (int q = 0; q < np; ++q) fl[q] = cur[(long)q * n + i];
-        moments_node_d(2, fl, W);
+        moments_node_d(P->dim, fl, W);
         double r = W[0] - hhat[i];
         L += r * r;
-        for (int q = 0; q <= 4; ++q) lamA[(long)q * n + i] = 2.0 * r;
+        for (int q = 0; q < np; ++q)
+            if (orc_comp(P->dim, q) == 0) lamA[(long)q * n + i] = 2.0 * r;
     }
     double gs = 0.0;
     double *lam_hi = lamA, *lam_lo = lamB;
@@ -501,9 +618,9 @@ int orc_loss_grad_2d(const orc_params *P, const double *h0, const double *hhat, 
     }
     /* dL/dh0 = mu_h(lam^0; W0) */
     for (long i = 0; i < n; ++i) {
-        double lam[13], W[3] = {h0[i], 0.0, 0.0}, mu[3];
+        double lam[ORC_NPMAX], W[3] = {h0[i], 0.0, 0.0}, mu[3];
         for (int q = 0; q < np; ++q) lam[q] = lam_hi[(long)q * n + i];
-        adj_mu_2d(P, W, lam, mu);
+        adj_mu(P, W, lam, mu);
         if (grad_h0) grad_h0[i] = mu[0];
     }
     if (loss) *loss = L;
@@ -512,15 +629,23 @@ int orc_loss_grad_2d(const orc_params *P, const double *h0, const double *hhat, 
     return 0;
 }
 
+/* The 2D name of the same function (kept for existing callers). */
+int orc_loss_grad_2d(const orc_params *P, const double *h0, const double *hhat, long T, int K,
+                     double *loss, double *grad_h0, double *grad_s)
+{
+    if (!P || P->dim != 2) return -1;
+    return orc_loss_grad(P, h0, hhat, T, K, loss, grad_h0, grad_s);
+}
+
 /* Loss of the same workload evaluated in complex arithmetic at
  * (h0 + i eps dh0, s + i eps ds): the complex-step directional derivative
  * Im(L)/eps of the forward program, independent of the hand-derived adjoint.
- * Periodic 2D or any supported BC; small grids only (no checkpointing). */
+ * 1D or 2D, any face rules; small grids only (no checkpointing). */
 int orc_loss_cs_2d(const orc_params *P, const double *h0, const double *dh0, double ds,
                    const double *hhat, long T, double eps, double *loss, double *dloss)
 {
-    if (check_params(P) || P->dim != 2 || P->mrt || !h0 || !hhat) return -1;
-    const int np = 13;
+    if (check_params(P) || P->mrt || !h0 || !hhat) return -1;
+    const int np = orc_npop(P->dim);
     const long n = (long)P->nx * P->ny;
     double _Complex *mem = (double _Complex *)malloc(sizeof(double _Complex) * 3 * np * (size_t)n);
     double _Complex *hc = (double _Complex *)malloc(sizeof(double _Complex) * (size_t)n);
@@ -543,10 +668,10 @@ int orc_loss_cs_2d(const orc_params *P, const double *h0, const double *dh0, dou
     }
     double _Complex L = 0.0;
     for (long i = 0; i < n; ++i) {
-        double _Complex fl[13], fs[13], W[3];
+        double _Complex fl[ORC_NPMAX], fs[ORC_NPMAX], W[3];
         for (int q = 0; q < np; ++q) fl[q] = cur[q][i];
         collide_node_c(P, s, fl, fs);
-        moments_node_c(2, fs, W);
+        moments_node_c(P->dim, fs, W);
         double _Complex r = W[0] - hhat[i];
         L += r * r;
     }

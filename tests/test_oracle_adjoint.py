@@ -92,3 +92,69 @@ def test_single_adjoint_step_is_transpose(orc):
     lhs = float((Jdu[1:] * w[1:]).sum())
     rhs = float((du[1:] * lam_n[1:]).sum())
     assert abs(lhs - rhs) <= 1e-7 * (abs(lhs) + 1.0)
+
+
+FACE_SETS_1D = [("periodic", "periodic"), ("neumann", "neumann"), ("wall", "wall"),
+                ("inflow", "wall"), ("neumann", "inflow"), ("wall", "neumann")]
+FACE_SETS_2D = [("periodic",) * 4, ("wall", "wall", "wall", "wall"),
+                ("neumann", "neumann", "neumann", "neumann"),
+                ("inflow", "neumann", "wall", "inflow"), ("periodic", "periodic", "wall", "neumann"),
+                ("wall", "inflow", "periodic", "periodic")]
+
+
+def _faced(orc, dim, faces, n=(9, 7), lam=4.0, s=1.7):
+    bc = tuple(faces) + (("periodic", "periodic") if dim == 1 else ())
+    inflow = {f: (1.1, 0.15 * (1 - 2 * (f % 2)), 0.05) for f in range(4) if bc[f] == "inflow"}
+    nx, ny = (n[0] * 3, 1) if dim == 1 else n
+    return orc.params(dim, nx, ny, lam=lam, s=s, bc=bc, inflow=inflow)
+
+
+def _state(orc, P, rng, steps=4):
+    shape = (P.nx,) if P.dim == 1 else (P.ny, P.nx)
+    h0 = 1.0 + 0.2 * rng.random(shape)
+    qx0 = 0.1 * rng.standard_normal(shape)
+    qy0 = 0.1 * rng.standard_normal(shape) if P.dim == 2 else None
+    return orc.run(P, h0, qx0, qy0, steps)
+
+
+@pytest.mark.parametrize("dim,faces", [(1, f) for f in FACE_SETS_1D] + [(2, f) for f in FACE_SETS_2D])
+def test_adjoint_step_is_the_exact_transpose_with_faces(orc, dim, faces):
+    """For one step u -> C(S(u)) with every face rule: <w, J du> = <J^T w, du> and
+    <w, d/ds C(S(u))> = the step's dL/ds term, where J du and the s-derivative
+    come from a complex step of the forward code (its pull and collision), not
+    from the hand-derived transpose.  A wrong target, face, sign or opposite
+    population in the transpose breaks the first identity."""
+    P = _faced(orc, dim, faces)
+    rng = np.random.default_rng(17 + dim)
+    u = _state(orc, P, rng)
+    du = rng.standard_normal(u.shape)  # the rest population included
+    w = rng.standard_normal(u.shape)
+    Jdu = orc.step_directional(P, u, du=du)
+    lam_n, gs = orc.adjoint_step(P, u, w)
+    lhs, rhs = float((w * Jdu).sum()), float((lam_n * du).sum())
+    scale = float(np.abs(w * Jdu).sum())
+    assert abs(lhs - rhs) <= 1e-13 * scale
+    ds_dir = orc.step_directional(P, u, du=None, ds=1.0)
+    assert abs(float((w * ds_dir).sum()) - gs) <= 1e-13 * float(np.abs(w * ds_dir).sum())
+
+
+@pytest.mark.parametrize("dim,faces", [(1, FACE_SETS_1D[3]), (1, FACE_SETS_1D[4]),
+                                       (2, FACE_SETS_2D[3]), (2, FACE_SETS_2D[4])])
+def test_gradient_with_faces_matches_complex_step(orc, dim, faces):
+    """The checkpointed gradient of L = sum (h(T) - hhat)^2 with respect to h0 and s
+    on grids with inflow / wall / Neumann faces equals the complex-step
+    directional derivative of the forward program."""
+    P = _faced(orc, dim, faces, n=(12, 10))
+    rng = np.random.default_rng(23)
+    shape = (P.nx,) if dim == 1 else (P.ny, P.nx)
+    h0 = 1.0 + 0.15 * rng.random(shape)
+    T = 23
+    hhat = orc.moments(P, orc.run(P, h0 + 0.05 * rng.standard_normal(shape), None, None, T))[0]
+    loss, gh, gs = orc.loss_grad(P, h0, hhat, T, K=5)
+    for _ in range(3):
+        dh = rng.standard_normal(shape)
+        ds = float(rng.standard_normal())
+        l_cs, d_cs = orc.loss_complex_step_2d(P, h0, hhat, T, dh0=dh, ds=ds)
+        assert abs(l_cs - loss) <= 1e-12 * loss
+        d_adj = float((gh * dh).sum()) + gs * ds
+        assert abs(d_adj - d_cs) <= 1e-10 * (abs(d_cs) + abs(gs * ds))
