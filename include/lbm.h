@@ -167,25 +167,31 @@ int lbm_import(lbm_ctx *ctx, const void *src);
 int lbm_moments(lbm_ctx *ctx, const void *state, double *h, double *qx, double *qy,
                 double *totals_host);
 
-/* Discrete adjoint of one step (2D, periodic faces only): the transpose of the
- * Jacobian of one step of the scheme (Sec. 3 equilibria at a = 0, relaxation of
- * eq. 2-relaxation with all rates equal, then streaming).  With C the
- * collision, S the pull-stream and u^{n+1} = C(S(u^n)):
+/* Discrete adjoint of one step (D1Q2x2 and D2Q4x3, every face rule): the
+ * transpose of the Jacobian of one step of the scheme (Sec. 2 / Sec. 3
+ * equilibria at a = 0, relaxation of eq. 2-relaxation with all rates equal, then
+ * streaming with the face rules).  With C the collision, S the pull-stream and
+ * u^{n+1} = C(S(u^n)):
  *   v = S(f_n); mu = (d f^eq / d W (W(v)))^T lam_np1 per node;
  *   vt = (1 - s) lam_np1 + s mu (mu broadcast over each component's planes);
- *   lam_n = S^T vt (push to x - e_j);
+ *   lam_n = S^T vt: vt_j(x) goes where the pull of plane j at x read -- the
+ *     upstream node x - e_j (across a periodic face: wrapped), across a Neumann
+ *     face the node's own plane j, across a wall its own opposite plane with the
+ *     momentum normal to the face negated, across an inflow face nowhere;
  *   dLds_partials[b] += sum over block b of lam_np1 . (f^eq(W(v)) - v).
  * f_n: a caller buffer in the state layout and storage type; lam_np1, lam_n:
  * caller buffers in the state layout whose elements are of the context's
  * adjoint storage (lbm_params.adjoint_storage; lam_n must not alias the
  * others).  dLds_partials: device double array of lbm_adjoint_partials(ctx)
- * entries, accumulated in double (zero it before the first step).  LBM_EINVAL
- * for 1D or non-periodic contexts. */
+ * entries, accumulated in double (zero it before the first step).  Enqueues one
+ * kernel, plus one per Neumann face.  LBM_EINVAL for the rest-population
+ * lattices. */
 int lbm_adjoint_step(lbm_ctx *ctx, const void *f_n, const void *lam_np1, void *lam_n,
                      double *dLds_partials);
 long lbm_adjoint_partials(lbm_ctx *ctx);
 
-/* Backward sweep over one checkpoint segment in one call (2D, periodic faces),
+/* Backward sweep over one checkpoint segment in one call (the contexts of
+ * lbm_adjoint_step),
  * for checkpointed gradients: from the state ck at level n0 (a caller buffer
  * in the state layout), recompute levels n0 + 1 .. n0 + nsteps - 1 by single
  * steps into work (nsteps - 1 consecutive state buffers of lbm_layout bytes
@@ -199,13 +205,14 @@ int lbm_adjoint_segment(lbm_ctx *ctx, const void *ck, int nsteps, void *work, vo
                         void *lam_b, double *dLds_partials, int *lam_out);
 
 /* Terminal adjoint for a loss of the final height: lam_T = dL/dh broadcast to
- * the four h planes, zero on the momentum planes (adjoint storage).  dLdh:
- * device doubles, nx*ny. */
+ * the h planes (2D four, 1D two), zero on the momentum planes (adjoint
+ * storage).  dLdh: device doubles, nx*ny. */
 int lbm_adjoint_terminal(lbm_ctx *ctx, const double *dLdh, void *lam_T);
 
 /* Gradient with respect to the initial fields: (dL/dh0, dL/dqx0, dL/dqy0) =
- * J(W0)^T lam0 per node, J = d f^eq / d W (the Sec. 3 equilibria at a = 0);
- * lam0 in adjoint storage.  Outputs may be NULL. */
+ * J(W0)^T lam0 per node, J = d f^eq / d W (the Sec. 2 / Sec. 3 equilibria at
+ * a = 0; in 1D qx is q and qy is unused); lam0 in adjoint storage.  Outputs may
+ * be NULL. */
 int lbm_adjoint_grad_w0(lbm_ctx *ctx, const void *lam0, const double *h0, const double *qx0,
                         const double *qy0, double *grad_h0, double *grad_qx0, double *grad_qy0);
 

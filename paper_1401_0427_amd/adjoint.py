@@ -9,10 +9,11 @@ hand-written adjoint kernel step by step -- one library call per segment
 (``lbm_adjoint_segment``) that enqueues all of it -- accumulating dL/ds in FP64
 per workgroup; finally dL/dh0 = J(W0)^T lam^0.
 
-Only the 2D lattice with periodic faces has an adjoint.  Initial momentum is
-zero (the adjoint workload); the state storage may be FP64 or FP32.  The
-adjoint is stored like the state unless asked otherwise (``adjoint_storage="f64"``
-keeps it in FP64 for an FP32 state); arithmetic and the s-gradient are FP64.
+The 2D (D2Q4 x 3) and 1D (D1Q2 x 2) lattices have an adjoint, with any face rules
+(periodic, Neumann, wall, inflow).  Initial momentum is zero (the adjoint
+workload); the state storage may be FP64 or FP32.  The adjoint is stored like
+the state unless asked otherwise (``adjoint_storage="f64"`` keeps it in FP64 for
+an FP32 state); arithmetic and the s-gradient are FP64.
 """
 from __future__ import annotations
 
@@ -25,10 +26,12 @@ from .lbm import Solver
 
 class _Rollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, h0, s, T, K, lam, g, storage, block, adjoint_storage):
+    def forward(ctx, h0, s, T, K, lam, g, storage, block, adjoint_storage, bc, inflow):
         n = h0.shape
-        solver = Solver(2, n[1], n[0], lam=lam, s=float(s), g=g, h0=h0.detach(),
-                        storage=storage, block=block, adjoint_storage=adjoint_storage)
+        dim = h0.dim()
+        solver = Solver(dim, n[-1], n[0] if dim == 2 else 1, lam=lam, s=float(s), g=g,
+                        bc=bc, inflow=inflow, h0=h0.detach(), storage=storage, block=block,
+                        adjoint_storage=adjoint_storage)
         cks = {0: solver.current()[0].clone()}
         t = 0
         while t < T:
@@ -61,17 +64,20 @@ class _Rollout(torch.autograd.Function):
         ctx.solver = None
         ctx.cks = None
         grad_s = torch.tensor(gs, dtype=torch.float64, device=gh0.device)
-        return gh0, grad_s, None, None, None, None, None, None, None
+        return gh0, grad_s, None, None, None, None, None, None, None, None, None
 
 
 def rollout(h0: torch.Tensor, s: torch.Tensor, T: int, K: int | None = None, lam: float = 3.0,
             g: float = 1.0, storage: str = "f64", block: int = 256,
-            adjoint_storage: str | None = None) -> torch.Tensor:
-    """h(T) from W0 = (h0, 0, 0) on the periodic unit square; differentiable in
-    h0 (2D float64 CUDA tensor) and s (0-dim float64 tensor).  K defaults to
-    about sqrt(T).  ``adjoint_storage``: element type of the adjoint buffers
-    (None = the state's, "f64", or "f32" with FP32 state storage)."""
+            adjoint_storage: str | None = None, bc=("periodic",) * 4,
+            inflow=None) -> torch.Tensor:
+    """h(T) from W0 = (h0, 0, 0) (1D: (h0, 0)); differentiable in h0 (a 2D
+    (ny, nx) or 1D (nx,) float64 CUDA tensor) and s (0-dim float64 tensor).  K
+    defaults to about sqrt(T).  ``bc`` = faces (x-, x+, y-, y+) by name,
+    ``inflow`` = {face: (h, qx, qy)} as for Solver.  ``adjoint_storage``: element
+    type of the adjoint buffers (None = the state's, "f64", or "f32" with FP32
+    state storage)."""
     if K is None:
         K = max(1, int(round(math.sqrt(T))))
     return _Rollout.apply(h0, s, int(T), int(K), float(lam), float(g), storage, int(block),
-                          adjoint_storage)
+                          adjoint_storage, tuple(bc), inflow)

@@ -158,6 +158,7 @@ struct lbm_ctx {
     int *d_flag;
     double *d_partials;  // moments partials (3 per block)
     double *d_totals;    // 3 doubles
+    double *d_adj_side;  // adjoint: own contributions of Neumann face nodes (if any)
     // captured step chunks, one per starting buffer
     hipStream_t cap;
     hipGraphExec_t chunk[2];
@@ -214,6 +215,7 @@ extern "C" void lbm_destroy(lbm_ctx *c)
     (void)hipFree(c->d_flag);
     (void)hipFree(c->d_partials);
     (void)hipFree(c->d_totals);
+    (void)hipFree(c->d_adj_side);
     delete c;
 }
 
@@ -348,6 +350,14 @@ extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0
         (e = hipMalloc(&c->d_flag, 2 * sizeof(int))) != hipSuccess ||
         (e = hipMalloc(&c->d_partials, sizeof(double) * 3 * (size_t)nmb)) != hipSuccess ||
         (e = hipMalloc(&c->d_totals, sizeof(double) * 4)) != hipSuccess) {
+        lbm_destroy(c);
+        return fail(LBM_EDEVICE, "hipMalloc of scratch failed: %s", hipGetErrorString(e));
+    }
+    bool neumann = false;
+    for (int f = 0; f < (dim == 1 ? 2 : 4); ++f) neumann = neumann || c->G.bc[f] == BC_NEUMANN;
+    if (neumann && !rest &&
+        (e = hipMalloc(&c->d_adj_side, sizeof(double) * 12 * (size_t)adjoint_side_len(c->G))) !=
+            hipSuccess) {
         lbm_destroy(c);
         return fail(LBM_EDEVICE, "hipMalloc of scratch failed: %s", hipGetErrorString(e));
     }
@@ -590,11 +600,9 @@ static int check_adjoint_ctx(lbm_ctx *c)
 {
     int rc = check_ctx(c);
     if (rc) return rc;
-    if (c->p.lattice != LBM_D2Q4x3)
-        return fail(LBM_EINVAL, "the adjoint is implemented for the D2Q4x3 lattice");
-    for (int f = 0; f < 4; ++f)
-        if (c->G.bc[f] != BC_PERIODIC)
-            return fail(LBM_EINVAL, "the adjoint is implemented for periodic faces only");
+    if (c->p.lattice != LBM_D2Q4x3 && c->p.lattice != LBM_D1Q2x2)
+        return fail(LBM_EINVAL, "the adjoint is implemented for the D1Q2x2 and D2Q4x3 lattices "
+                                "(a = 0, BGK)");
     return LBM_OK;
 }
 
@@ -608,8 +616,8 @@ extern "C" int lbm_adjoint_step(lbm_ctx *c, const void *f_n, const void *lam_np1
     if (!f_n || !lam_np1 || !lam_n || !dLds_partials) return fail(LBM_EINVAL, "null argument");
     if (lam_n == f_n || lam_n == lam_np1)
         return fail(LBM_EINVAL, "lam_n must not alias f_n or lam_np1");
-    HIP_TRY(launch_adjoint(c->f32, c->a32, f_n, lam_np1, lam_n, dLds_partials, c->G, c->P,
-                           c->st));
+    HIP_TRY(launch_adjoint(c->dim, c->f32, c->a32, f_n, lam_np1, lam_n, dLds_partials,
+                           c->d_adj_side, c->G, c->P, c->st));
     return LBM_OK;
 }
 
@@ -631,8 +639,8 @@ extern "C" int lbm_adjoint_segment(lbm_ctx *c, const void *ck, int nsteps, void 
         HIP_TRY(step_once(c, level(i - 1), (void *)level(i), c->st));
     void *hi = lam_a, *lo = lam_b;
     for (int i = nsteps - 1; i >= 0; --i) {
-        HIP_TRY(launch_adjoint(c->f32, c->a32, level(i), hi, lo, dLds_partials, c->G, c->P,
-                               c->st));
+        HIP_TRY(launch_adjoint(c->dim, c->f32, c->a32, level(i), hi, lo, dLds_partials,
+                               c->d_adj_side, c->G, c->P, c->st));
         void *t = hi;
         hi = lo;
         lo = t;
@@ -646,7 +654,7 @@ extern "C" int lbm_adjoint_terminal(lbm_ctx *c, const double *dLdh, void *lam_T)
     int rc = check_adjoint_ctx(c);
     if (rc) return rc;
     if (!dLdh || !lam_T) return fail(LBM_EINVAL, "null argument");
-    HIP_TRY(launch_adjoint_terminal(c->a32, dLdh, lam_T, c->G, c->st));
+    HIP_TRY(launch_adjoint_terminal(c->dim, c->a32, dLdh, lam_T, c->G, c->st));
     return LBM_OK;
 }
 
@@ -657,7 +665,8 @@ extern "C" int lbm_adjoint_grad_w0(lbm_ctx *c, const void *lam0, const double *h
     int rc = check_adjoint_ctx(c);
     if (rc) return rc;
     if (!lam0 || !h0) return fail(LBM_EINVAL, "null argument");
-    HIP_TRY(launch_adjoint_grad_w0(c->a32, lam0, h0, qx0, qy0, grad_h0, grad_qx0, grad_qy0,
+    HIP_TRY(launch_adjoint_grad_w0(c->dim, c->a32, lam0, h0, qx0, qy0, grad_h0, grad_qx0,
+                                   grad_qy0,
                                    c->G, c->P, c->st));
     return LBM_OK;
 }

@@ -128,13 +128,16 @@ hipError_t launch_check(int dim, bool f32, const void *state, const Geo &G, int 
 int moments_blocks(const Geo &G);
 
 // f32: state storage float; a32: adjoint storage float (double otherwise; a float
-// adjoint needs a float state)
-hipError_t launch_adjoint(bool f32, bool a32, const void *un, const void *lam1, void *lam0,
-                          double *partials, const Geo &G, const Phys &P, hipStream_t st);
+// adjoint needs a float state).  side: adjoint_side_len(G) x 4 faces x 3 doubles of
+// scratch for the Neumann faces (may be null when no face is Neumann).
+hipError_t launch_adjoint(int dim, bool f32, bool a32, const void *un, const void *lam1,
+                          void *lam0, double *partials, double *side, const Geo &G,
+                          const Phys &P, hipStream_t st);
+int adjoint_side_len(const Geo &G);
 long adjoint_blocks(const Geo &G);
-hipError_t launch_adjoint_terminal(bool f32, const double *dLdh, void *lam, const Geo &G,
-                                   hipStream_t st);
-hipError_t launch_adjoint_grad_w0(bool f32, const void *lam0, const double *h0,
+hipError_t launch_adjoint_terminal(int dim, bool f32, const double *dLdh, void *lam,
+                                   const Geo &G, hipStream_t st);
+hipError_t launch_adjoint_grad_w0(int dim, bool f32, const void *lam0, const double *h0,
                                   const double *qx0, const double *qy0, double *gh, double *gqx,
                                   double *gqy, const Geo &G, const Phys &P, hipStream_t st);
 

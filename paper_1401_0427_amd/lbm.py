@@ -381,9 +381,10 @@ class Solver:
         h0 = self.h0 if h0 is None else h0
         qx0 = self.qx0 if qx0 is None else qx0
         qy0 = self.qy0 if qy0 is None else qy0
-        shape = (self.ny, self.nx)
+        shape = (self.nx,) if self.dim == 1 else (self.ny, self.nx)
         gh = torch.empty(shape, dtype=torch.float64, device=self.device)
-        gx, gy = torch.empty_like(gh), torch.empty_like(gh)
+        gx = torch.empty_like(gh)
+        gy = torch.empty_like(gh) if self.dim == 2 else None
         check(load().lbm_adjoint_grad_w0(self.ctx, _ptr(lam0), _ptr(h0), _ptr(qx0), _ptr(qy0),
                                          _ptr(gh), _ptr(gx), _ptr(gy)), "lbm_adjoint_grad_w0")
         return gh, gx, gy

@@ -166,10 +166,100 @@ def test_adjoint_segment_equals_single_steps(storage, adj):
         assert torch.equal(got, a) and torch.equal(pa, pb), n
 
 
-def test_adjoint_rejects_non_periodic():
-    from paper_1401_0427_amd.lbm import LbmError
+FACES_1D = [("neumann", "neumann"), ("wall", "wall"), ("inflow", "wall"), ("neumann", "inflow"),
+            ("periodic", "periodic")]
+FACES_2D = [("wall", "wall", "wall", "wall"), ("neumann", "neumann", "neumann", "neumann"),
+            ("inflow", "neumann", "wall", "inflow"), ("periodic", "periodic", "wall", "neumann"),
+            ("wall", "inflow", "periodic", "periodic")]
 
-    case = smooth_random_2d(40, 40, seed=1, bc=("wall", "wall", "periodic", "periodic"))
-    S = gpu_solver(case)
-    with pytest.raises(LbmError, match="periodic"):
-        S.adjoint_step(S.current()[0], S.new_state(), S.new_state(), S.adjoint_partials())
+
+def _inflow(bc):
+    return {f: (1.1, 0.15 * (1 - 2 * (f % 2)), 0.05) for f in range(4) if bc[f] == "inflow"}
+
+
+def _face_case(dim, faces, seed, nx=300, ny=41):
+    if dim == 2:
+        return smooth_random_2d(nx // 4 + 3, ny, seed=seed, lam=5.0, s=1.6, bc=faces,
+                                inflow=_inflow(faces))
+    bc = tuple(faces) + ("periodic", "periodic")
+    rng = np.random.default_rng(seed)
+    x = W.cell_centres(nx)
+    h = 1.0 + 0.3 * np.exp(-((x - 0.4) ** 2) / 0.01) + 0.02 * rng.random(nx)
+    q = 0.1 * np.sin(2 * np.pi * x) + 0.02 * rng.standard_normal(nx)
+    return W.Case(1, nx, 1, 5.0, 1.6, 0, bc=bc, inflow=_inflow(bc), h0=h, qx0=q, qy0=None,
+                  name=f"face1d_{nx}")
+
+
+@pytest.mark.parametrize("dim,faces", [(1, f) for f in FACES_1D] + [(2, f) for f in FACES_2D])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_adjoint_step_with_faces_matches_oracle(dim, faces, storage):
+    """One adjoint step on 1D and 2D grids with Neumann, wall, inflow and periodic
+    faces (the transpose of the pull with its face rules, Neumann face nodes
+    completed by a second kernel) against the oracle's adjoint on the same state
+    and adjoint input: <= 1e-12 per plane and for dL/ds (FP64 adjoint; with FP32
+    state storage the state is read from float, the same values the oracle gets)."""
+    import torch
+
+    case = _face_case(dim, faces, seed=12)
+    S = gpu_solver(case, storage=storage, adjoint_storage="f64")
+    S.step(9)
+    un = to_np(S.planes()).astype(np.float64)
+    rng = np.random.default_rng(13)
+    lam1 = rng.standard_normal(un.shape)
+    lam1_t = S.new_adjoint()
+    S.planes(lam1_t).copy_(torch.as_tensor(lam1))
+    lam0_t = S.new_adjoint()
+    lam0_t.fill_(np.nan)  # every slot must be written
+    partials = S.adjoint_partials()
+    S.adjoint_step(S.current()[0], lam1_t, lam0_t, partials)
+    gs = S.sum(partials)
+    P = oracle.params(dim, case.nx, case.ny, lam=case.lam, s=case.s, g=case.g, bc=case.bc,
+                      inflow=case.inflow)
+    ref, gs_ref = oracle.adjoint_step(P, _with_rest(un), _with_rest(lam1))
+    got = to_np(S.planes(lam0_t))
+    assert np.isfinite(got).all()
+    err = max(normwise_rel(a, b) for a, b in zip(got, ref[1:]))
+    say(f"[adjoint step {dim}D {faces} {storage}] lam rel err {err:.3e}, dL/ds {gs:.15e} "
+        f"vs {gs_ref:.15e}")
+    assert err <= 1e-12
+    assert abs(gs - gs_ref) <= 1e-12 * abs(gs_ref)
+
+
+@pytest.mark.parametrize("dim,faces,K", [(1, FACES_1D[2], 7), (1, FACES_1D[3], 5),
+                                         (2, FACES_2D[2], 7), (2, FACES_2D[3], 4)])
+def test_rollout_gradient_with_faces_matches_oracle(dim, faces, K):
+    """dL/dh0 and dL/ds of L = sum (h(T) - hhat)^2 through the checkpointed rollout
+    on grids with faces (FP64) against the oracle's checkpointed adjoint (itself
+    pinned to complex-step derivatives of the forward program)."""
+    import torch
+
+    from paper_1401_0427_amd.adjoint import rollout
+
+    T = 37
+    rng = np.random.default_rng(31 + dim)
+    if dim == 1:
+        nx, ny = 400, 1
+        bc = tuple(faces) + ("periodic", "periodic")
+        h0 = 1.0 + 0.2 * np.exp(-((W.cell_centres(nx) - 0.5) ** 2) / 0.01)
+    else:
+        nx, ny = 60, 44
+        bc = faces
+        x, y = W.cell_centres(nx), W.cell_centres(ny)
+        X, Y = np.meshgrid(x, y)
+        h0 = 1.0 + 0.2 * np.exp(-((X - 0.5) ** 2 + (Y - 0.45) ** 2) / 0.02)
+    inflow = _inflow(bc)
+    P = oracle.params(dim, nx, ny, lam=4.0, s=1.7, bc=bc, inflow=inflow)
+    target0 = h0 + 0.05 * rng.standard_normal(h0.shape)
+    hhat = oracle.moments(P, oracle.run(P, target0, None, None, T))[0]
+    l_ref, gh_ref, gs_ref = oracle.loss_grad(P, h0, hhat, T, K=5)
+    h0_t = torch.tensor(h0, dtype=torch.float64, device="cuda", requires_grad=True)
+    s_t = torch.tensor(1.7, dtype=torch.float64, device="cuda", requires_grad=True)
+    hT = rollout(h0_t, s_t, T, K, lam=4.0, bc=bc, inflow=inflow)
+    loss = ((hT - torch.as_tensor(hhat, device="cuda")) ** 2).sum()
+    loss.backward()
+    e_h = normwise_rel(to_np(h0_t.grad), gh_ref)
+    e_s = abs(float(s_t.grad) - gs_ref) / abs(gs_ref)
+    say(f"[rollout grad {dim}D {faces}] loss {float(loss):.15e} vs {l_ref:.15e}; "
+        f"grad_h0 rel {e_h:.3e}; grad_s rel {e_s:.3e}")
+    assert abs(float(loss) - l_ref) <= 1e-12 * l_ref
+    assert e_h <= 1e-10 and e_s <= 1e-10
