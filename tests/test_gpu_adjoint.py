@@ -132,18 +132,20 @@ def test_rollout_gradient_fp32_storage_reported(adj):
 
 
 @pytest.mark.parametrize("storage,adj", [("f64", None), ("f32", "f32"), ("f32", "f64")])
-def test_adjoint_segment_equals_single_steps(storage, adj):
+@pytest.mark.parametrize("fuse", [0, 8])
+def test_adjoint_segment_equals_single_steps(storage, adj, fuse):
     """lbm_adjoint_segment (recompute a checkpoint segment, then its adjoint steps,
     in one call) gives bit for bit what single steps (lbm_step_buffers) and
-    lbm_adjoint_step give, for odd and even segment lengths."""
+    lbm_adjoint_step give, for odd and even segment lengths, in the context's
+    default launch plan and with 8 steps per launch."""
     import torch
 
     case = smooth_random_2d(70, 54, seed=5)
-    S = gpu_solver(case, storage=storage, adjoint_storage=adj)
+    S = gpu_solver(case, storage=storage, adjoint_storage=adj, fuse_steps=fuse)
     S.step(3)
     ck = S.current()[0].clone()
     rng = np.random.default_rng(9)
-    for n in (1, 4, 7):
+    for n in (1, 4, 7, 20):
         lam0 = torch.as_tensor(rng.standard_normal(S.nplanes * S.ps), device="cuda").to(S.adj_dtype)
         # single calls
         states = [ck]
