@@ -17,9 +17,11 @@ Beside it on the same JSON line:
   forms.wall_1d_*  1D wall reflection, 2^20 nodes (MALL-resident)
   forms.batched  256 mixed 1D / 2D Riemann problems, FP32 storage, 1000 steps, in
                  the tuned mode (K steps per launch over every instance, graph
-                 replayed); beside it the two single-launch persistent modes
-                 (dataflow, step-synchronous), the FP64 reference of the FP32 L1
-                 error and the plain path launched per instance
+                 replayed); beside it the three single-launch persistent modes
+                 (the same tiles with one pass per K steps, dataflow,
+                 step-synchronous), the FP64 reference of the FP32 L1 error, the
+                 committed DRAM counters of the batched kernels and the plain path
+                 launched per instance
   forms.adjoint  2D 1024^2 gradient rollout (T = 500, checkpoints every 23 steps)
   roofline       the dominant kernel (the full K-step FP64 launches of the timed
                  region) against its binding roof -- FP64 VALU issue or HBM, named
