@@ -23,8 +23,8 @@ Beside it on the same JSON line:
                  committed DRAM counters of the batched kernels and the plain path
                  launched per instance
   forms.adjoint  2D 1024^2 gradient rollout (T = 500, checkpoints every 23 steps)
-  roofline       the dominant kernel (the full K-step FP64 launches of the timed
-                 region) against its binding roof -- FP64 VALU issue or HBM, named
+  roofline       the dominant kernel (the FP64 launches of the timed region's most
+                 frequent steps per launch) against its binding roof -- FP64 VALU issue or HBM, named
                  from committed rocprofv3 counters -- with both roofs' figures
   cpu_baseline   the CPU FP64 oracle on bounded samples of every workload, at one
                  host thread and at all threads it is given
@@ -88,11 +88,12 @@ def time_forward(torch, n, storage, steps, warmup, block, npt, pad, fuse=1, keep
                  bc=("periodic",) * 4, inflow=None):
     """Forward steps of the headline workload; ``fuse`` = steps per launch asked
     for (0 = the library's choice; lbm_launch_info reports what runs).  The timed
-    region issues the library's own plan -- launches of K steps and one shorter
-    launch for the remainder, as lbm_step(steps) does -- one launch per lbm_step
-    call, with a HIP event on the launch stream after each, so the average
-    duration of the full K-step launches (the dominant kernel) is measured
-    directly.  With ``keep_h`` the final height field is returned under "h"."""
+    region issues the library's own plan for ``steps`` steps (lbm_launch_plan:
+    launches of K steps, a remainder of two or more spread evenly over the last
+    launches) one launch per lbm_step call, with a HIP event on the launch stream
+    after each, so the average duration of the launches of the dominant kernel
+    (the most frequent steps per launch of the plan) is measured directly.  With
+    ``keep_h`` the final height field is returned under "h"."""
     from paper_1401_0427_amd import workloads as W
     from paper_1401_0427_amd.lbm import Solver
 
@@ -104,7 +105,9 @@ def time_forward(torch, n, storage, steps, warmup, block, npt, pad, fuse=1, keep
     S.step(warmup)
     torch.cuda.synchronize()
     st = torch.cuda.current_stream()
-    pieces = [K] * (steps // K) + ([steps % K] if steps % K else [])
+    pieces = S.launch_plan(steps)
+    # the dominant kernel: the most frequent launch depth (ties: the deeper one)
+    Kd = max(set(pieces), key=lambda k: (pieces.count(k), k))
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(pieces) + 1)]
     t0 = time.perf_counter()
     ev[0].record(st)
@@ -115,7 +118,7 @@ def time_forward(torch, n, storage, steps, warmup, block, npt, pad, fuse=1, keep
     wall = time.perf_counter() - t0
     ms = ev[0].elapsed_time(ev[-1])
     dur = [ev[i].elapsed_time(ev[i + 1]) for i in range(len(pieces))]
-    full = [d for d, k in zip(dur, pieces) if k == K]
+    full = [d for d, k in zip(dur, pieces) if k == Kd]
     (h, _, _), tot = S.moments(totals=True)
     ok = bool(torch.isfinite(h).all().item()) and tot[0] > 0
     nodes = n * n
@@ -125,7 +128,8 @@ def time_forward(torch, n, storage, steps, warmup, block, npt, pad, fuse=1, keep
     # the number of steps the launch advances
     return dict(ms_per_step=ms / steps, mlups=nodes * steps / (ms * 1e-3) / 1e6,
                 **out_h, steps_per_launch=K, launches=len(pieces),
-                launch_steps=sorted(set(pieces), reverse=True),
+                launch_steps={str(k): pieces.count(k) for k in sorted(set(pieces), reverse=True)},
+                dominant_steps=Kd, periodic=all(b == "periodic" for b in bc),
                 segment_rows=info["segment_rows"], resident_blocks=info["resident_blocks"],
                 ms_per_launch=(sum(full) / len(full)) if full else ms / len(pieces),
                 full_launches=len(full),
@@ -375,10 +379,12 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x
 
 
 def kernel_kind(form):
-    """Which FP64 step kernel a timed forward form ran (from its launch plan)."""
-    if form["steps_per_launch"] == 1:
+    """Which FP64 step kernel ran the dominant launches of a timed forward form:
+    one step per launch, the LDS two-step kernel (two-step launches on
+    all-periodic grids), else the wave-strip K-step kernel."""
+    if form["dominant_steps"] == 1:
         return "one_step"
-    if form["steps_per_launch"] == 2 and form["resident_blocks"] == 0:
+    if form["dominant_steps"] == 2 and form["periodic"]:
         return "lds_two_step"
     return "wave_strip"
 
@@ -387,15 +393,20 @@ def _summary(kind, which, n, K):
     """A committed rocprofv3 summary (JSON) of the FP64 step kernel -- ``which`` 1
     = traffic, 2 = SQ instruction counters -- if it was taken for this grid,
     launch depth and the current kernel source; else None."""
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                        KERNELS[kind][which])
-    if not os.path.exists(path):
-        return None
-    d = json.load(open(path))
-    if (d.get("n") != n or d.get("kernel_source_sha") != _kernel_sha(kind)
-            or d.get("steps_per_launch", K) != K):
-        return None
-    return d
+    prof = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
+    name = KERNELS[kind][which]
+    # the summary of the library's default depth, else one taken at K steps per
+    # launch (the same name with _k<K> before the counter kind)
+    stem, tail = name.rsplit("_", 1)
+    for cand in (name, f"{stem}_k{K}_{tail}"):
+        path = os.path.join(prof, cand)
+        if not os.path.exists(path):
+            continue
+        d = json.load(open(path))
+        if (d.get("n") == n and d.get("kernel_source_sha") == _kernel_sha(kind)
+                and d.get("steps_per_launch", K) == K):
+            return d
+    return None
 
 
 def _measured_traffic(n, kind, K):
@@ -406,12 +417,12 @@ def _measured_traffic(n, kind, K):
 
 
 def roofline(f64, n, kind):
-    """Roofline object of the dominant kernel (the full K-step FP64 launches of the
-    timed region).  Both roofs are computed from the live launch time; the bound
+    """Roofline object of the dominant kernel (the FP64 launches of the timed
+    region's most frequent depth K).  Both roofs are computed from the live launch time; the bound
     named is the one the kernel uses more of: the FP64 VALU issue (busy fraction
     from the committed SQ counter summary) or HBM (DRAM bytes from the committed
     traffic summary, else the algorithmic bytes)."""
-    K = f64["steps_per_launch"]
+    K = f64["dominant_steps"]
     ms_launch = f64["ms_per_launch"]
     nodes = n * n
     alg_bytes = nodes * f64["bytes_per_lu"]

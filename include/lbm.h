@@ -129,15 +129,21 @@ typedef struct {
 int lbm_layout(const lbm_params *p, long *plane_stride, int *n_planes, size_t *bytes);
 
 /* Validate p, create a context and write the level-0 state into p->f_a:
- * f*(0) = C(f^eq(W0)).  h0, qx0, qy0: device double arrays of nx*ny values
- * row-major [y][x] (qx0 / qy0 may be NULL for zero; qy0 ignored in 1D).
+ * f*(0) = C(f^eq(W0)), the post-collision state of the equilibrium of the
+ * initial conserved fields (Sec. 2: f^eq from the kinetic potentials; Sec. 3 for
+ * 2D).  h0, qx0, qy0: device double arrays of nx*ny values row-major [y][x]
+ * (qx0 / qy0 may be NULL for zero; qy0 ignored in 1D).
  * Synchronises the stream once to check min h0 > 0 (else LBM_EINVAL) and the
  * monotonicity bound (LBM_WARN_SUBCHAR, context still created). */
 int lbm_init(const lbm_params *p, const double *h0, const double *qx0, const double *qy0,
              lbm_ctx **out);
 
 /* Advance nsteps fused pull-stream + collide steps (ping-pong between f_a and
- * f_b).  Stream-ordered; with check_every > 0 it synchronises at each check. */
+ * f_b): the transport along the lattice velocities then the relaxation of Sec. 2
+ * eq. 2-relaxation (Sec. 3 for the D2Q4 vectorial scheme), with the face rules of
+ * the Sec. 3 boundary paragraph.  Launches as lbm_launch_plan lists them; the
+ * state does not depend on the plan.  Stream-ordered; with check_every > 0 it
+ * synchronises at each check. */
 int lbm_step(lbm_ctx *ctx, long nsteps);
 
 /* One step from src into dst (both caller-owned buffers in the context's
@@ -154,6 +160,18 @@ int lbm_current(lbm_ctx *ctx, void **state, long *steps_done);
  * the device at once, which the segment length was chosen against (0 otherwise). */
 int lbm_launch_info(lbm_ctx *ctx, int *steps_per_launch, int *segment_rows,
                     long *resident_blocks);
+
+/* The launches lbm_step(ctx, nsteps) issues from the context's current step
+ * count, in order (each advances the steps of the scheme of Sec. 2 eq.
+ * 2-relaxation some number of times; the state after any plan is bitwise the
+ * same): ks[i] = steps of launch i, for i < min(launches, cap); *n_launches =
+ * the number of launches (may be NULL).  Launches inside captured chunks are
+ * listed one by one.  Launches of steps_per_launch steps, except that on 2D grids
+ * a remainder of two or more steps is spread over the last launches so their
+ * step counts differ by at most one (20 steps at 8 per launch: 7, 7, 6), and a
+ * remainder of one step is one one-step launch.  No device work.  LBM_EINVAL for
+ * nsteps < 0, cap < 0, or cap > 0 with ks NULL. */
+int lbm_launch_plan(lbm_ctx *ctx, long nsteps, int *ks, int cap, long *n_launches);
 
 /* Copy the current state to dst / overwrite it from src (device, same layout). */
 int lbm_export(lbm_ctx *ctx, void *dst);

@@ -165,6 +165,7 @@ struct lbm_ctx {
     int chunk_len;
     int xk_seg;     // rows per segment of the wave-strip K-step launch
     long xk_slots;  // its resident workgroups on the device
+    int xk_seg_k[17];  // rows per segment of a wave-strip launch of k <= fuse steps
 };
 
 // Steps per captured graph: the smallest multiple of twice the steps per launch that is
@@ -337,6 +338,17 @@ extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0
             c->fuse = 1;
         }
     }
+    // launches of fewer steps (the plan's shorter launches) take the segment
+    // length chosen for their own depth: their kernels hold fewer registers, so
+    // more workgroups are resident than for the full-depth launch
+    for (int k = 0; k <= 16; ++k) c->xk_seg_k[k] = 0;
+    if (dim == 2 && c->xk_seg > 0)
+        for (int k = 2; k <= c->fuse && k <= kMaxFuse2d; ++k) {
+            if (k == 2 && c->x2) continue;
+            const int sk = k == c->fuse ? c->xk_seg
+                                        : step2k_seg(c->G, c->f32, k, kXkMinSeg, nullptr, nullptr);
+            c->xk_seg_k[k] = sk > 0 ? sk : c->xk_seg;
+        }
     c->buf[0] = p->f_a;
     c->buf[1] = p->f_b;
     c->cur = 0;
@@ -407,8 +419,8 @@ static hipError_t step_k(lbm_ctx *c, int k, const void *src, void *dst, hipStrea
     if (c->dim == 2) {
         if (c->x2 && k == 2)
             return launch_step2x(c->f32, src, dst, c->G, c->P, kFuseSeg, st);
-        return launch_step2k(c->f32, src, dst, c->G, c->P, k, c->xk_seg > 0 ? c->xk_seg : kXkSeg,
-                             st);
+        const int seg = c->xk_seg_k[k] > 0 ? c->xk_seg_k[k] : c->xk_seg > 0 ? c->xk_seg : kXkSeg;
+        return launch_step2k(c->f32, src, dst, c->G, c->P, k, seg, st);
     }
     return launch_step1k(c->f32, src, dst, c->G, c->P, k, st);
 }
@@ -465,38 +477,115 @@ static int ensure_chunk(lbm_ctx *c, int from)
     return LBM_OK;
 }
 
+// Steps of the next launch when `todo` steps remain outside the captured chunks.
+// Launches of `fuse` steps, except on 2D grids a remainder of two or more steps
+// is spread over the last launches so that their step counts differ by at most
+// one: a 2D K-step launch takes nearly the same time for every K from 3 to 8
+// (the state is read and written once), so 20 steps run as 7 + 7 + 6 rather
+// than 8 + 8 + 4 (4096^2 FP64: 2.18 vs 2.29 ms).  A remainder of one step takes
+// the one-step kernel, the cheapest launch.
+static int next_launch_steps(const lbm_ctx *c, long todo)
+{
+    const long F = c->fuse;
+    if (todo <= 1 || F <= 1) return (int)(todo < 1 ? todo : 1);
+    const long r = todo % F;
+    if (c->dim != 2 || r <= 1) return (int)(todo < F ? todo : F);
+    const long launches = (todo + F - 1) / F;
+    return (int)((todo + launches - 1) / launches);
+}
+
+// Whether the next chunk_len / fuse launches of a `todo`-step run are all of
+// `fuse` steps (then a captured chunk can run them); todo >= chunk_len.
+static bool chunk_is_full(const lbm_ctx *c, long todo)
+{
+    for (int i = 0; i < c->chunk_len / c->fuse; ++i, todo -= c->fuse)
+        if (next_launch_steps(c, todo) != c->fuse) return false;
+    return true;
+}
+
+// The launches of nsteps steps from the context's step count, in order: chunk()
+// for a captured chunk of chunk_len steps, launch(k) for one launch of k steps,
+// check(at) for a state check after step `at`.  Stops at the first non-zero return.
+template <typename Chunk, typename Launch, typename Check>
+static int walk_plan(const lbm_ctx *c, long nsteps, Chunk &&chunk, Launch &&launch,
+                     Check &&check)
+{
+    long done = 0, steps = c->steps;
+    int rc;
+    while (done < nsteps) {
+        long todo = nsteps - done;
+        if (c->p.check_every > 0) {
+            const long to_check = c->p.check_every - (steps % c->p.check_every);
+            if (todo > to_check) todo = to_check;
+        }
+        // chunks of full launches through the captured graph, the rest launch by launch
+        while (todo > 0) {
+            if (todo >= c->chunk_len && chunk_is_full(c, todo)) {
+                if ((rc = chunk())) return rc;
+                todo -= c->chunk_len;
+                done += c->chunk_len;
+                steps += c->chunk_len;
+                continue;
+            }
+            const int k = next_launch_steps(c, todo);
+            if ((rc = launch(k))) return rc;
+            todo -= k;
+            done += k;
+            steps += k;
+        }
+        if (c->p.check_every > 0 && steps % c->p.check_every == 0)
+            if ((rc = check(steps))) return rc;
+    }
+    return LBM_OK;
+}
+
 extern "C" int lbm_step(lbm_ctx *c, long nsteps)
 {
     int rc = check_ctx(c);
     if (rc) return rc;
     if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
-    long done = 0;
-    while (done < nsteps) {
-        long todo = nsteps - done;
-        if (c->p.check_every > 0) {
-            const long to_check = c->p.check_every - (c->steps % c->p.check_every);
-            if (todo > to_check) todo = to_check;
-        }
-        // whole chunks through the captured graph, the rest launch by launch
-        while (todo >= c->chunk_len) {
-            if ((rc = ensure_chunk(c, c->cur))) return rc;
+    return walk_plan(
+        c, nsteps,
+        [&]() -> int {
+            int r = ensure_chunk(c, c->cur);
+            if (r) return r;
             HIP_TRY(hipGraphLaunch(c->chunk[c->cur], c->st));
-            todo -= c->chunk_len;
-            done += c->chunk_len;
             c->steps += c->chunk_len;  // chunk length is even: c->cur unchanged
-        }
-        while (todo > 0) {
-            const int k = (int)(todo < c->fuse ? todo : c->fuse);
+            return LBM_OK;
+        },
+        [&](int k) -> int {
             HIP_TRY(step_k(c, k, c->buf[c->cur], c->buf[c->cur ^ 1], c->st));
             c->cur ^= 1;
-            todo -= k;
-            done += k;
             c->steps += k;
-        }
-        if (c->p.check_every > 0 && c->steps % c->p.check_every == 0)
-            if ((rc = check_state(c, c->steps))) return rc;
-    }
-    return LBM_OK;
+            return LBM_OK;
+        },
+        [&](long at) -> int { return check_state(c, at); });
+}
+
+extern "C" int lbm_launch_plan(lbm_ctx *c, long nsteps, int *ks, int cap, long *n_launches)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+    if (cap < 0 || (cap > 0 && !ks)) return fail(LBM_EINVAL, "ks must hold cap >= 0 entries");
+    long n = 0;
+    auto put = [&](int k) {
+        if (n < cap) ks[n] = k;
+        ++n;
+    };
+    rc = walk_plan(
+        c, nsteps,
+        [&]() -> int {
+            for (int i = 0; i < c->chunk_len / c->fuse; ++i) put(c->fuse);
+            return LBM_OK;
+        },
+        [&](int k) -> int {
+            put(k);
+            return LBM_OK;
+        },
+        [&](long) -> int { return LBM_OK; });
+    if (n_launches) *n_launches = n;
+    return rc;
 }
 
 extern "C" int lbm_step_buffers(lbm_ctx *c, const void *src, void *dst)

@@ -80,7 +80,7 @@ class LbmBatchTuning(ctypes.Structure):
 
 EXPORTS = [
     "lbm_layout", "lbm_init", "lbm_step", "lbm_step_buffers", "lbm_current",
-    "lbm_launch_info", "lbm_export", "lbm_adjoint_segment",
+    "lbm_launch_info", "lbm_launch_plan", "lbm_export", "lbm_adjoint_segment",
     "lbm_import", "lbm_moments", "lbm_moments_noalloc", "lbm_entropy", "lbm_adjoint_step", "lbm_adjoint_partials",
     "lbm_adjoint_terminal", "lbm_adjoint_grad_w0", "lbm_sum", "lbm_destroy",
     "lbm_batch_layout", "lbm_batch_create", "lbm_batch_init", "lbm_batch_run",
@@ -111,6 +111,8 @@ def load(path: str = LIB_PATH):
         "lbm_step_buffers": (ip, [vp, vp, vp]),
         "lbm_current": (ip, [vp, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_long)]),
         "lbm_launch_info": (ip, [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                 ctypes.POINTER(ctypes.c_long)]),
+        "lbm_launch_plan": (ip, [vp, lp, ctypes.POINTER(ctypes.c_int), ip,
                                  ctypes.POINTER(ctypes.c_long)]),
         "lbm_export": (ip, [vp, vp]),
         "lbm_import": (ip, [vp, vp]),
@@ -297,6 +299,16 @@ class Solver:
                                      ctypes.byref(res)), "lbm_launch_info")
         return dict(steps_per_launch=k.value, segment_rows=seg.value,
                     resident_blocks=res.value)
+
+    def launch_plan(self, nsteps):
+        """Steps of each launch that step(nsteps) issues from the current step count."""
+        n = ctypes.c_long()
+        check(load().lbm_launch_plan(self.ctx, nsteps, None, 0, ctypes.byref(n)),
+              "lbm_launch_plan")
+        ks = (ctypes.c_int * max(n.value, 1))()
+        check(load().lbm_launch_plan(self.ctx, nsteps, ks, n.value, ctypes.byref(n)),
+              "lbm_launch_plan")
+        return list(ks[:n.value])
 
     def planes(self, buf=None):
         """(nplanes, ny, nx) view (1D: (nplanes, nx)) of a state buffer."""

@@ -56,24 +56,38 @@ def test_headline_traffic_is_used_only_for_the_kernel_source_it_was_taken_on():
     else:
         assert t is None
     assert bench._measured_traffic(d["n"] // 2, "wave_strip", d["steps_per_launch"]) is None
-    assert bench._measured_traffic(d["n"], "wave_strip", d["steps_per_launch"] - 1) is None
+    assert bench._measured_traffic(d["n"], "wave_strip", 3) is None
+    # a summary taken at another depth (same name with _k<K>) serves that depth only
+    stem, tail = bench.KERNELS["wave_strip"][1].rsplit("_", 1)
+    for K in range(2, 9):
+        path = os.path.join(ROOT, "profiles", f"{stem}_k{K}_{tail}")
+        if K == d["steps_per_launch"] or not os.path.exists(path):
+            continue
+        dk = json.load(open(path))
+        assert dk["steps_per_launch"] == K
+        t = bench._measured_traffic(dk["n"], "wave_strip", K)
+        if dk["kernel_source_sha"] == bench._kernel_sha("wave_strip"):
+            assert t == dk["traffic_bytes_per_launch_f64"]
+        else:
+            assert t is None
 
 
-def _form(K, launches, full, ms_launch, n=4096):
+def _form(K, launches, full, ms_launch, n=4096, Kd=None):
     return dict(steps_per_launch=K, launches=launches, full_launches=full,
-                ms_per_launch=ms_launch, bytes_per_lu=192)
+                ms_per_launch=ms_launch, bytes_per_lu=192, dominant_steps=Kd or K,
+                periodic=True)
 
 
-def test_roofline_of_a_partial_last_launch_uses_the_full_launches(monkeypatch):
-    """20 steps at 8 per launch are 3 launches (8 + 8 + 4); the roofline divides the
-    algorithmic bytes (and flops) of one full launch by the full launches' measured
-    duration."""
+def test_roofline_of_the_dominant_launch_depth(monkeypatch):
+    """20 steps at 8 per launch are 3 launches (7 + 7 + 6); the roofline divides the
+    algorithmic bytes (and flops: 7 steps) of one launch of the dominant depth by
+    those launches' measured duration."""
     monkeypatch.setattr(bench, "_summary", lambda *a: None)
-    r = bench.roofline(_form(8, 3, 2, 0.8), 4096, "wave_strip")
+    r = bench.roofline(_form(8, 3, 2, 0.8, Kd=7), 4096, "wave_strip")
     alg = 4096 * 4096 * 192
-    assert r["bytes_per_launch"] == alg
+    assert r["bytes_per_launch"] == alg and r["steps_per_launch"] == 7
     assert r["hbm"]["achieved"] == pytest.approx(alg / 0.8e-3 / 1e9, rel=1e-4)
-    flops = bench.ALG_FLOPS_2D * 4096 * 4096 * 8 / 0.8e-3 / 1e12
+    flops = bench.ALG_FLOPS_2D * 4096 * 4096 * 7 / 0.8e-3 / 1e12
     assert r["alu"]["achieved"] == pytest.approx(flops, rel=1e-3)
     assert r["bound"] == "alu" and r["frac"] == r["alu"]["frac"]
     assert r["traffic"] is None and r["valu_busy"] is None

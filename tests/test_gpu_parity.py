@@ -352,3 +352,40 @@ def test_default_launch_plans():
     asked = gpu_solver(smooth_random_2d(300, 70, seed=8), fuse_steps=16).launch_info()
     assert asked["steps_per_launch"] == 8
     say(f"[plans] 1024^2 f64 {big64}, f32 {big32}, 256^2 f32 {small32}")
+
+
+def test_launch_plan_spreads_the_remainder_and_keeps_the_state():
+    """lbm_launch_plan lists the launches lbm_step issues.  2D at 8 steps per
+    launch: a remainder of two or more steps is spread evenly over the last
+    launches (20 -> 7, 7, 6; 10 -> 5, 5; 26 -> 7, 7, 6, 6), a remainder of one is a
+    one-step launch (17 -> 8, 8, 1), captured chunks count launch by launch (64 ->
+    eight launches of 8); 1D keeps the plain split (20 at 16 per launch -> 16, 4).
+    The state after step(n) is bitwise the state after n single steps, on a ragged
+    periodic grid in both storages and on a grid with faces (6 per launch: 20 ->
+    5, 5, 5, 5)."""
+    import torch
+
+    per = smooth_random_2d(300, 70, seed=12)
+    S = gpu_solver(per, fuse_steps=8)
+    assert S.launch_plan(20) == [7, 7, 6]
+    assert S.launch_plan(10) == [5, 5]
+    assert S.launch_plan(26) == [7, 7, 6, 6]
+    assert S.launch_plan(17) == [8, 8, 1]
+    assert S.launch_plan(64) == [8] * 8
+    assert S.launch_plan(42) == [7] * 6  # not a chunk of four 8s then 5 + 5
+    long_plan = S.launch_plan(2002)
+    assert (len(long_plan) == 251 and sum(long_plan) == 2002
+            and set(long_plan) == {7, 8} and long_plan[:200] == [8] * 200)
+    assert S.launch_plan(0) == [] and S.launch_plan(1) == [1] and S.launch_plan(8) == [8]
+    assert gpu_solver(W.dam_break_1d(1000)).launch_plan(20) == [16, 4]
+    walls = W.oblique_shock_2d(20, steps=10)
+    Sw = gpu_solver(walls, fuse_steps=6)
+    assert Sw.launch_plan(20) == [5, 5, 5, 5]
+    for case, storage, fuse, n in ((per, "f64", 8, 20), (per, "f32", 8, 26), (per, "f64", 8, 17),
+                                   (walls, "f64", 6, 20)):
+        A = gpu_solver(case, storage=storage, fuse_steps=fuse)
+        B = gpu_solver(case, storage=storage, fuse_steps=1)
+        A.step(n)
+        B.step(n)
+        torch.cuda.synchronize()
+        assert torch.equal(A.planes(), B.planes()), (storage, fuse, n)
