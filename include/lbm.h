@@ -111,7 +111,7 @@ typedef struct {
                              2 when the LDS
                              two-step launch has >= 1024 workgroups, else 1;
                              planes of 2 GiB or more take 1); 2D grids with
-                             Neumann, wall or inflow faces at most 8 (default 6
+                             Neumann, wall or inflow faces at most 8 (default 7
                              for FP64, 8 for FP32 storage, or the largest fewer
                              steps whose launch fills a third of the device, else
                              1; planes of 2 GiB or
@@ -308,7 +308,7 @@ typedef struct {
                                 single steps): the 2D instances as tiles of the
                                 wave-strip multi-step kernels (with any 2D
                                 instance that has Neumann, wall or inflow faces,
-                                by default 6 (FP64) / 8 (FP32) steps per launch
+                                by default 7 (FP64) / 8 (FP32) steps per launch
                                 for the whole batch),
                                 the 1D instances as
                                 1024-node tiles of the 1D multi-step kernel; graph

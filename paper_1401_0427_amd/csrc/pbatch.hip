@@ -38,7 +38,7 @@ __global__ void __launch_bounds__(kPThreads)
 {
     constexpr int SW = xk_batch_sw<T>();
     constexpr int D = xk_batch_depth<T>();
-    __shared__ T lds[pfused_lds_elems<T, K, BND>()];
+    __shared__ __align__(16) T lds[pfused_lds_elems<T, K, BND>()];
     const int wave = (int)(threadIdx.x >> 6);
     const long long nitems = nxt + nxbt + (nkt + kP1kPerItem - 1) / kP1kPerItem;
     long long pending = -1;

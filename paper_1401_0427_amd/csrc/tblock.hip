@@ -169,7 +169,7 @@ __global__ void __launch_bounds__(64 * kXkWaves)
     k_step2d_xkb(const T *__restrict__ src, T *__restrict__ dst, Geo G, Phys P, int nstrips,
                  int seg)
 {
-    __shared__ T xs[kXkWaves][xkb_lds_elems<T, K>()];
+    __shared__ __align__(16) T xs[kXkWaves][xkb_lds_elems<T, K>()];
     const int ngroups = (nstrips + kXkWaves - 1) / kXkWaves;
     const int nseg = (G.ny + seg - 1) / seg;
     const int tile = xk_tile(blockIdx.x, ngroups * nseg, true);
@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(64 * kXkWaves)
     k_batch_xkb(const InstDev *__restrict__ inst, const XkTileDev *__restrict__ tiles,
                 int ntiles, const T *__restrict__ src, T *__restrict__ dst)
 {
-    __shared__ T xs[kXkWaves][xkb_lds_elems<T, K>()];
+    __shared__ __align__(16) T xs[kXkWaves][xkb_lds_elems<T, K>()];
     const XkTileDev td = tiles[xk_tile(blockIdx.x, ntiles, true)];
     const InstDev &I = inst[td.inst];
     const int strip = td.strip0 + (int)(threadIdx.x >> 6);

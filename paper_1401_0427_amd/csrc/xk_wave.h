@@ -338,10 +338,14 @@ constexpr int xkb_lds_levels()
     constexpr int L = sizeof(T) == 8 ? kXkbLdsLevelsF64 : kXkbLdsLevelsF32;
     return K >= kXkbLdsMinK ? (L < K - 1 ? L : K - 1) : 0;
 }
+// Per wavefront, after the exchange rows: the inflow equilibria of the y faces'
+// e2 / e4 planes (doubles at table entries 6 .. 11), read where a y-face row uses
+// them, so they hold no registers across the row loop.
+constexpr int kXkbFaceTab = 12;
 template <typename T, int K>
 constexpr int xkb_lds_elems()
 {
-    return xkb_lds_levels<T, K>() > 0 ? xkb_lds_levels<T, K>() * 6 * 64 : 1;
+    return xkb_lds_levels<T, K>() * 6 * 64 + kXkbFaceTab * (int)(8 / sizeof(T));
 }
 
 // Output columns per strip: 64 lanes minus K - 1 halo lanes per side, rounded
@@ -425,6 +429,7 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
 {
     constexpr int L = BND ? 0 : xk_lds_levels_sw<T, K, SW>();
     constexpr int LB = BND ? xkb_lds_levels<T, K>() : 0;
+    const double *ftab = reinterpret_cast<const double *>(lds + LB * 6 * 64);  // kXkbFaceTab
     double v[12];
 #pragma unroll
     for (int pl = 0; pl < 12; ++pl) v[pl] = (double)cur[pl];
@@ -454,8 +459,8 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
         for (int c = 0; c < 3; ++c) {
             if (bx0 && B.kx0 == BC_INFLOW) v[4 * c + 0] = B.in1[c];
             if (bx1 && B.kx1 == BC_INFLOW) v[4 * c + 2] = B.in3[c];
-            if (by0 && B.ky0 == BC_INFLOW) v[4 * c + 1] = B.in2[c];
-            if (by1 && B.ky1 == BC_INFLOW) v[4 * c + 3] = B.in4[c];
+            if (by0 && B.ky0 == BC_INFLOW) v[4 * c + 1] = ftab[6 + c];
+            if (by1 && B.ky1 == BC_INFLOW) v[4 * c + 3] = ftab[9 + c];
         }
     }
     // The previous row's outputs are stored only now, after this row's loaded
@@ -497,9 +502,11 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
             if constexpr (BND) {
                 // rr: row of level k + 1 computed here; the level-k row in v is rr + 1
                 const int rr = i - k;
-                const bool ry0 = Y && B.ky0 == BC_INFLOW && rr == 0;
                 const bool ry1 = Y && B.ky1 != BC_PERIODIC && rr == G.ny - 1;
                 const bool vy0 = Y && B.ky0 != BC_PERIODIC && rr + 1 == 0;
+                // a y- inflow value reaches row 0 through the e2 slot of row -1 (vy0);
+                // with FP32 storage it is not a storage value, so row 0 takes it here
+                const bool ry0 = sizeof(T) == 4 && Y && B.ky0 == BC_INFLOW && rr == 0;
                 const bool vn1 = Y && B.ky1 == BC_NEUMANN && rr + 1 == G.ny - 1;
                 // LDS level: this wavefront's six rows of level k (e1 planes c, e3
                 // planes 3 + c); X.r1 / X.r3 count from the component's e1 row and
@@ -532,9 +539,9 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
                                                      : B.in3[c];
                     }
                     double a2 = (double)em[k - 1][c], a4 = v[4 * c + 3];
-                    if (ry0) a2 = B.in2[c];
+                    if (ry0) a2 = ftab[6 + c];
                     if (ry1)
-                        a4 = B.ky1 == BC_INFLOW ? B.in4[c]
+                        a4 = B.ky1 == BC_INFLOW ? ftab[9 + c]
                              : B.ky1 == BC_WALL ? (double)(c == 2 ? -uc : uc)
                                                 : (double)uc;
                     o[4 * c + 0] = a1;
@@ -543,7 +550,10 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
                     o[4 * c + 3] = a4;
                     const T w2 = (T)v[4 * c + 1], w4 = (T)v[4 * c + 3];
                     em[k - 1][c] = vn1 ? w4 : w2;
-                    if (vy0) ec[k - 1][c] = B.ky0 == BC_WALL ? (c == 2 ? -w4 : w4) : w2;
+                    if (vy0)
+                        ec[k - 1][c] = B.ky0 == BC_WALL ? (c == 2 ? -w4 : w4)
+                                       : B.ky0 == BC_INFLOW && sizeof(T) == 8 ? (T)ftab[6 + c]
+                                                                              : w2;
                     if (!lv) {
                         s1[k - 1][c] = (T)v[4 * c + 0];
                         s3[k - 1][c] = (T)v[4 * c + 2];
@@ -717,6 +727,15 @@ __device__ __forceinline__ void xk_wave(const T *__restrict__ src, T *__restrict
             Lp[p].r1 = bx0 ? (B.kx0 == BC_WALL ? 3 * 64 + lane : lane) : (lane - 1) & 63;
             Lp[p].r3 = bx1 ? (B.kx1 == BC_WALL ? lane : 3 * 64 + lane) : 3 * 64 + ((lane + 1) & 63);
         }
+        // the y faces' inflow values go to the wavefront's LDS table (kXkbFaceTab)
+        {
+            double *ft = reinterpret_cast<double *>(lds + xkb_lds_levels<T, K>() * 6 * 64);
+            if (lane < 3) {
+                ft[6 + lane] = lane == 0 ? B.in2[0] : lane == 1 ? B.in2[1] : B.in2[2];
+                ft[9 + lane] = lane == 0 ? B.in4[0] : lane == 1 ? B.in4[1] : B.in4[2];
+            }
+            __asm__ __volatile__("" ::: "memory");
+        }
         // a lane needs at most one x face's inflow values (x- on bx0 lanes, x+ on
         // bx1 lanes): keep that one per lane, which frees their scalar registers
 #pragma unroll
@@ -821,12 +840,16 @@ __device__ __forceinline__ void xk_wave(const T *__restrict__ src, T *__restrict
 // 88 / 124).
 constexpr int kXkMaxKBnd = 8;
 // Steps per launch by default with non-periodic faces, per storage (the fastest
-// at 4096^2: FP64 K = 4 .. 8 81, 114, 133, 120, 115 GLUPS; FP32, whose arithmetic
-// uses fused multiply-adds, 144, 174, 173, 174, 177-179).  A copy of the strip
-// loop without the x-face rules for the strips that touch no x face (chosen per
-// wavefront) measured FP64 128 at K = 6 (more registers in the kernel holding
-// both copies) and FP32 185 at K = 8, so it is not used.
-constexpr int kXkbDefaultKF64 = 6;
+// at 4096^2 with the y faces' inflow values in LDS: FP64 K = 4 .. 8 90, 114, 131,
+// 143, 114 GLUPS, K = 7 at 221 registers and two wavefronts per SIMD, K = 8 at one;
+// FP32, whose arithmetic uses fused multiply-adds, 149, 169, 168, 170, 172).  A copy
+// of the strip loop without the x-face rules for the strips that touch no x face
+// (chosen per wavefront) measured FP64 128 at K = 6 with the inflow values in
+// registers (more registers in the kernel holding both copies) and FP32 185 at K =
+// 8; with them in LDS, a form whose x-face strips take the y-face copy in every row
+// measured FP64 127 at K = 7, FP32 152 at K = 8 (those strips set the launch time:
+// the launch is one round of workgroups), so it is not used.
+constexpr int kXkbDefaultKF64 = 7;
 constexpr int kXkbDefaultKF32 = 8;
 // Rows of level-n pulls in flight in the bounded kernel: one (at 4096^2 FP64 K = 4
 // 85 GLUPS against 74 with two; the smaller ring lets two wavefronts share a SIMD).

@@ -324,7 +324,7 @@ def test_default_launch_plans():
     launch on grids it can fill (8 steps per launch; FP32 6 on grids below about
     three workgroups per resident slot, such as 1024^2), with a segment length and
     the resident workgroups it was chosen against; one step per launch on a
-    small FP32 grid; 16 steps per launch in 1D; with non-periodic 2D faces 6
+    small FP32 grid; 16 steps per launch in 1D; with non-periodic 2D faces 7
     (FP64) / 8 (FP32) steps, or fewer where that launch cannot fill the device;
     an explicit request is honoured up to 8 steps."""
     big64 = gpu_solver(smooth_random_2d(1024, 1024, seed=8), storage="f64").launch_info()
@@ -343,7 +343,7 @@ def test_default_launch_plans():
     walls8 = gpu_solver(W.oblique_shock_2d(20, steps=10), fuse_steps=8).launch_info()
     assert walls8["steps_per_launch"] == 8
     box = gpu_solver(smooth_random_2d(1024, 1024, seed=8, bc=("wall",) * 4)).launch_info()
-    assert box["steps_per_launch"] == 6 and box["segment_rows"] >= 16
+    assert box["steps_per_launch"] == 7 and box["segment_rows"] >= 16
     box32 = gpu_solver(smooth_random_2d(1024, 1024, seed=8, bc=("wall",) * 4),
                        storage="f32").launch_info()
     assert 2 <= box32["steps_per_launch"] <= 8
