@@ -196,8 +196,8 @@ static const int kDefaultFuse2dF32 = 8;
 static const int kDefaultFuse2dF32Small = 6;
 // With non-periodic faces the wave-strip kernel takes at most
 // step2k_max_k_bounded() (8) steps per launch, and step2k_default_k_bounded() by
-// default (FP64 7, FP32 8): at 4096^2 (inflow / Neumann / wall faces) FP64 143
-// GLUPS (one step: 28), FP32 172 (one step: 59).
+// default (FP64 7, FP32 8): at 4096^2 (inflow / Neumann / wall faces) FP64 147
+// GLUPS (one step: 28), FP32 171 (one step: 59).
 // Shortest segment of a wave-strip launch (the halo rows cost 2 (K - 1) per
 // segment; the segment length itself is chosen per grid, step2k_seg).  Grids
 // whose launch cannot fill a third of the device keep the one- or two-step

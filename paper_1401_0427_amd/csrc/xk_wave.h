@@ -338,6 +338,16 @@ constexpr int xkb_lds_levels()
     constexpr int L = sizeof(T) == 8 ? kXkbLdsLevelsF64 : kXkbLdsLevelsF32;
     return K >= kXkbLdsMinK ? (L < K - 1 ? L : K - 1) : 0;
 }
+// Elements per exchange row of the bounded kernel: one slot per lane and, for
+// FP64 storage, slot 64 holding the inflow equilibrium of the row's plane at the
+// x face it is read through (e1 rows: x-, e3 rows: x+), so an inflow face lane
+// pulls it with its ordinary LDS read.  (With FP32 storage the inflow value is
+// not a storage value; the face lane takes it by a select.)
+template <typename T>
+constexpr int xkb_row_width()
+{
+    return sizeof(T) == 8 ? 65 : 64;
+}
 // Per wavefront, after the exchange rows: the inflow equilibria of the y faces'
 // e2 / e4 planes (doubles at table entries 6 .. 11), read where a y-face row uses
 // them, so they hold no registers across the row loop.
@@ -345,7 +355,17 @@ constexpr int kXkbFaceTab = 12;
 template <typename T, int K>
 constexpr int xkb_lds_elems()
 {
-    return xkb_lds_levels<T, K>() * 6 * 64 + kXkbFaceTab * (int)(8 / sizeof(T));
+    return xkb_lds_levels<T, K>() * 6 * xkb_row_width<T>() + kXkbFaceTab * (int)(8 / sizeof(T));
+}
+
+// v with its sign bit flipped where m has it (m: 0 or 0x80000000 per lane).
+__device__ __forceinline__ double xk_xsign(double v, unsigned m)
+{
+    return __longlong_as_double(__double_as_longlong(v) ^ ((long long)m << 32));
+}
+__device__ __forceinline__ float xk_xsign(float v, unsigned m)
+{
+    return __int_as_float(__float_as_int(v) ^ (int)m);
 }
 
 // Output columns per strip: 64 lanes minus K - 1 halo lanes per side, rounded
@@ -429,7 +449,12 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
 {
     constexpr int L = BND ? 0 : xk_lds_levels_sw<T, K, SW>();
     constexpr int LB = BND ? xkb_lds_levels<T, K>() : 0;
-    const double *ftab = reinterpret_cast<const double *>(lds + LB * 6 * 64);  // kXkbFaceTab
+    const double *ftab =
+        reinterpret_cast<const double *>(lds + LB * 6 * xkb_row_width<T>());  // kXkbFaceTab
+    // x walls on the LDS levels: the face lane's read takes its own opposite
+    // plane; the normal momentum (component 1) changes sign
+    const unsigned m1 = bx0 && B.kx0 == BC_WALL ? 0x80000000u : 0u;
+    const unsigned m3 = bx1 && B.kx1 == BC_WALL ? 0x80000000u : 0u;
     double v[12];
 #pragma unroll
     for (int pl = 0; pl < 12; ++pl) v[pl] = (double)cur[pl];
@@ -477,7 +502,7 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
         xk_load(src, ps, onext, nxt);
     // LDS exchange levels: each level's e1 / e3 pulls are read one level ahead
     // (before the previous level's arithmetic), so the LDS latency overlaps it
-    constexpr int RW = xk_lds_width(SW);
+    constexpr int RW = BND ? xkb_row_width<T>() : xk_lds_width(SW);
     constexpr bool PF = sizeof(T) == 4 && K <= kXkLdsPrefetchF32MaxK;
     T pf1[3], pf3[3];
     if constexpr (L > 0 && PF) {
@@ -511,8 +536,9 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
                 // LDS level: this wavefront's six rows of level k (e1 planes c, e3
                 // planes 3 + c); X.r1 / X.r3 count from the component's e1 row and
                 // point at lane l - 1's e1 / lane l + 1's e3 of the previous row, or on
-                // a face lane at its own e1 / e3 (Neumann) or its own opposite plane
-                // (wall, whose normal momentum is negated here)
+                // a face lane at its own e1 / e3 (Neumann), its own opposite plane
+                // (wall, whose normal momentum is negated here) or the row's inflow
+                // slot (FP64)
                 const bool lv = k - 1 < LB;
                 T *row = lds + X.row + (k - 1) * 6 * RW;
 #pragma unroll
@@ -521,10 +547,12 @@ __device__ __forceinline__ void xk_row(const T *__restrict__ src, long ps, const
                     double a1, a3;
                     if (lv) {
                         const T t1 = row[c * RW + X.r1], t3 = row[c * RW + X.r3];
-                        a1 = (double)(c == 1 && bx0 && B.kx0 == BC_WALL ? -t1 : t1);
-                        a3 = (double)(c == 1 && bx1 && B.kx1 == BC_WALL ? -t3 : t3);
-                        if (bx0 && B.kx0 == BC_INFLOW) a1 = B.in1[c];
-                        if (bx1 && B.kx1 == BC_INFLOW) a3 = B.in3[c];
+                        a1 = (double)(c == 1 ? xk_xsign(t1, m1) : t1);
+                        a3 = (double)(c == 1 ? xk_xsign(t3, m3) : t3);
+                        if constexpr (sizeof(T) == 4) {
+                            if (bx0 && B.kx0 == BC_INFLOW) a1 = B.in1[c];
+                            if (bx1 && B.kx1 == BC_INFLOW) a3 = B.in3[c];
+                        }
                     } else {
                         const T u1 = s1[k - 1][c], u3 = s3[k - 1][c];
                         a1 = (double)xk_shr(u1);
@@ -721,15 +749,33 @@ __device__ __forceinline__ void xk_wave(const T *__restrict__ src, T *__restrict
         bx1 = clampx && xc == nx - 1;
         // LDS levels (xk_row): both read offsets count from the component's e1 row
         // (the e3 row is 3 rows further); a face lane reads its own slot, a wall
-        // lane the opposite plane's
+        // lane the opposite plane's, an inflow lane (FP64) the row's inflow slot
+        constexpr int RWB = xkb_row_width<T>();
+        constexpr bool slot = RWB > 64;
+        const int s1 = B.kx0 == BC_WALL ? 3 * RWB + lane : slot && B.kx0 == BC_INFLOW ? 64 : lane;
+        const int s3 = B.kx1 == BC_WALL ? lane
+                       : slot && B.kx1 == BC_INFLOW ? 3 * RWB + 64
+                                                    : 3 * RWB + lane;
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
-            Lp[p].r1 = bx0 ? (B.kx0 == BC_WALL ? 3 * 64 + lane : lane) : (lane - 1) & 63;
-            Lp[p].r3 = bx1 ? (B.kx1 == BC_WALL ? lane : 3 * 64 + lane) : 3 * 64 + ((lane + 1) & 63);
+            Lp[p].r1 = bx0 ? s1 : (lane - 1) & 63;
+            Lp[p].r3 = bx1 ? s3 : 3 * RWB + ((lane + 1) & 63);
+        }
+        if constexpr (slot) {
+            // the inflow slots of every exchange row (row 6 k + q of level k + 1:
+            // q < 3 e1 plane q, else e3 plane q - 3), never overwritten
+            constexpr int nrows = 6 * xkb_lds_levels<T, K>();
+            if (lane < nrows) {
+                const int q = lane % 6;
+                const double x = q == 0 ? B.in1[0] : q == 1 ? B.in1[1] : q == 2 ? B.in1[2]
+                                 : q == 3 ? B.in3[0] : q == 4 ? B.in3[1] : B.in3[2];
+                lds[lane * RWB + 64] = (T)x;
+            }
         }
         // the y faces' inflow values go to the wavefront's LDS table (kXkbFaceTab)
         {
-            double *ft = reinterpret_cast<double *>(lds + xkb_lds_levels<T, K>() * 6 * 64);
+            double *ft = reinterpret_cast<double *>(lds + xkb_lds_levels<T, K>() * 6 *
+                                                              xkb_row_width<T>());
             if (lane < 3) {
                 ft[6 + lane] = lane == 0 ? B.in2[0] : lane == 1 ? B.in2[1] : B.in2[2];
                 ft[9 + lane] = lane == 0 ? B.in4[0] : lane == 1 ? B.in4[1] : B.in4[2];
@@ -840,9 +886,11 @@ __device__ __forceinline__ void xk_wave(const T *__restrict__ src, T *__restrict
 // 88 / 124).
 constexpr int kXkMaxKBnd = 8;
 // Steps per launch by default with non-periodic faces, per storage (the fastest
-// at 4096^2 with the y faces' inflow values in LDS: FP64 K = 4 .. 8 90, 114, 131,
-// 143, 114 GLUPS, K = 7 at 221 registers and two wavefronts per SIMD, K = 8 at one;
-// FP32, whose arithmetic uses fused multiply-adds, 149, 169, 168, 170, 172).  A copy
+// at 4096^2 with the y faces' inflow values in LDS and the x faces' rules in the
+// LDS reads (inflow slots, sign masks): FP64 K = 4 .. 8 92, 116, 134, 147, 119
+// GLUPS, K = 7 at 241 registers and two wavefronts per SIMD, K = 8 at one (143 at
+// K = 7 with the x-face selects); FP32, whose arithmetic uses fused multiply-adds,
+// 148, 170, 169, 169, 171).  A copy
 // of the strip loop without the x-face rules for the strips that touch no x face
 // (chosen per wavefront) measured FP64 128 at K = 6 with the inflow values in
 // registers (more registers in the kernel holding both copies) and FP32 185 at K =
