@@ -222,6 +222,26 @@ long lbm_adjoint_partials(lbm_ctx *ctx);
 int lbm_adjoint_segment(lbm_ctx *ctx, const void *ck, int nsteps, void *work, void *lam_a,
                         void *lam_b, double *dLds_partials, int *lam_out);
 
+/* Every level of a run kept, for gradients without recomputation when they fit
+ * in device memory: nsteps single steps (lbm_step_buffers; the scheme of Sec. 2
+ * eq. 2-relaxation) from the state `from`, writing level i into slot i - 1 of
+ * levels (nsteps consecutive state buffers of lbm_layout bytes each), i = 1 ..
+ * nsteps.  Does not touch the context's own buffers or step count.  Only
+ * enqueues kernels.  LBM_EINVAL for nsteps < 0, null buffers, or `from`
+ * overlapping levels. */
+int lbm_step_levels(lbm_ctx *ctx, const void *from, int nsteps, void *levels);
+
+/* Backward sweep over stored levels (the transposed steps of lbm_adjoint_step,
+ * Sec. 2 eq. 2-relaxation): levels holds the forward states of levels n0 .. n0 +
+ * nsteps - 1 in nsteps consecutive state buffers (as lbm_step_levels writes
+ * them); applies nsteps adjoint steps from lam^{n0 + nsteps}, held in lam_a, down
+ * to lam^{n0}, alternating between lam_a and lam_b (adjoint storage, neither
+ * inside levels); *lam_out as for lbm_adjoint_segment.  Only enqueues kernels.
+ * LBM_EINVAL for nsteps < 1, null buffers, aliasing, or the contexts
+ * lbm_adjoint_step rejects. */
+int lbm_adjoint_levels(lbm_ctx *ctx, const void *levels, int nsteps, void *lam_a, void *lam_b,
+                       double *dLds_partials, int *lam_out);
+
 /* Terminal adjoint for a loss of the final height: lam_T = dL/dh broadcast to
  * the h planes (2D four, 1D two), zero on the momentum planes (adjoint
  * storage).  dLdh: device doubles, nx*ny. */

@@ -710,6 +710,25 @@ extern "C" int lbm_adjoint_step(lbm_ctx *c, const void *f_n, const void *lam_np1
     return LBM_OK;
 }
 
+// nsteps adjoint steps from lam^{n0 + nsteps} in lam_a down to lam^{n0}, level
+// n0 + i of the forward state at level(i); *lam_out = 0 when lam^{n0} ends in
+// lam_a, 1 when in lam_b.
+template <typename Level>
+static int adjoint_sweep(lbm_ctx *c, Level &&level, int nsteps, void *lam_a, void *lam_b,
+                         double *dLds_partials, int *lam_out)
+{
+    void *hi = lam_a, *lo = lam_b;
+    for (int i = nsteps - 1; i >= 0; --i) {
+        HIP_TRY(launch_adjoint(c->dim, c->f32, c->a32, level(i), hi, lo, dLds_partials,
+                               c->d_adj_side, c->G, c->P, c->st));
+        void *t = hi;
+        hi = lo;
+        lo = t;
+    }
+    *lam_out = hi == lam_a ? 0 : 1;
+    return LBM_OK;
+}
+
 extern "C" int lbm_adjoint_segment(lbm_ctx *c, const void *ck, int nsteps, void *work,
                                    void *lam_a, void *lam_b, double *dLds_partials, int *lam_out)
 {
@@ -726,16 +745,48 @@ extern "C" int lbm_adjoint_segment(lbm_ctx *c, const void *ck, int nsteps, void 
     };
     for (int i = 1; i < nsteps; ++i)
         HIP_TRY(step_once(c, level(i - 1), (void *)level(i), c->st));
-    void *hi = lam_a, *lo = lam_b;
-    for (int i = nsteps - 1; i >= 0; --i) {
-        HIP_TRY(launch_adjoint(c->dim, c->f32, c->a32, level(i), hi, lo, dLds_partials,
-                               c->d_adj_side, c->G, c->P, c->st));
-        void *t = hi;
-        hi = lo;
-        lo = t;
+    return adjoint_sweep(c, level, nsteps, lam_a, lam_b, dLds_partials, lam_out);
+}
+
+// Whether [a, a + na) and [b, b + nb) share a byte.
+static bool overlaps(const void *a, size_t na, const void *b, size_t nb)
+{
+    const char *x = (const char *)a, *y = (const char *)b;
+    return x < y + nb && y < x + na;
+}
+
+extern "C" int lbm_step_levels(lbm_ctx *c, const void *from, int nsteps, void *levels)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+    if (nsteps == 0) return LBM_OK;
+    if (!from || !levels) return fail(LBM_EINVAL, "null buffer");
+    if (overlaps(from, c->bytes, levels, (size_t)nsteps * c->bytes))
+        return fail(LBM_EINVAL, "from must not overlap levels");
+    const void *prev = from;
+    for (int i = 0; i < nsteps; ++i) {
+        void *dst = (char *)levels + (size_t)i * c->bytes;
+        HIP_TRY(step_once(c, prev, dst, c->st));
+        prev = dst;
     }
-    *lam_out = hi == lam_a ? 0 : 1;
     return LBM_OK;
+}
+
+extern "C" int lbm_adjoint_levels(lbm_ctx *c, const void *levels, int nsteps, void *lam_a,
+                                  void *lam_b, double *dLds_partials, int *lam_out)
+{
+    int rc = check_adjoint_ctx(c);
+    if (rc) return rc;
+    if (nsteps < 1) return fail(LBM_EINVAL, "nsteps must be >= 1");
+    if (!levels || !lam_a || !lam_b || !dLds_partials || !lam_out)
+        return fail(LBM_EINVAL, "null argument");
+    const size_t span = (size_t)nsteps * c->bytes;
+    if (lam_a == lam_b || overlaps(lam_a, c->bytes, levels, span) ||
+        overlaps(lam_b, c->bytes, levels, span))
+        return fail(LBM_EINVAL, "lam_a / lam_b must not alias each other or the levels");
+    auto level = [&](int i) -> const void * { return (const char *)levels + (size_t)i * c->bytes; };
+    return adjoint_sweep(c, level, nsteps, lam_a, lam_b, dLds_partials, lam_out);
 }
 
 extern "C" int lbm_adjoint_terminal(lbm_ctx *c, const double *dLdh, void *lam_T)

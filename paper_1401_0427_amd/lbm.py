@@ -81,6 +81,7 @@ class LbmBatchTuning(ctypes.Structure):
 EXPORTS = [
     "lbm_layout", "lbm_init", "lbm_step", "lbm_step_buffers", "lbm_current",
     "lbm_launch_info", "lbm_launch_plan", "lbm_export", "lbm_adjoint_segment",
+    "lbm_step_levels", "lbm_adjoint_levels",
     "lbm_import", "lbm_moments", "lbm_moments_noalloc", "lbm_entropy", "lbm_adjoint_step", "lbm_adjoint_partials",
     "lbm_adjoint_terminal", "lbm_adjoint_grad_w0", "lbm_sum", "lbm_destroy",
     "lbm_batch_layout", "lbm_batch_create", "lbm_batch_init", "lbm_batch_run",
@@ -115,6 +116,8 @@ def load(path: str = LIB_PATH):
         "lbm_launch_plan": (ip, [vp, lp, ctypes.POINTER(ctypes.c_int), ip,
                                  ctypes.POINTER(ctypes.c_long)]),
         "lbm_export": (ip, [vp, vp]),
+        "lbm_step_levels": (ip, [vp, vp, ip, vp]),
+        "lbm_adjoint_levels": (ip, [vp, vp, ip, vp, vp, vp, ctypes.POINTER(ctypes.c_int)]),
         "lbm_import": (ip, [vp, vp]),
         "lbm_moments": (ip, [vp, vp, vp, vp, vp, dp]),
         "lbm_moments_noalloc": (ip, [P, vp, vp, vp, vp, vp]),
@@ -382,6 +385,21 @@ class Solver:
         check(load().lbm_adjoint_segment(self.ctx, _ptr(ck), int(nsteps), _ptr(work), _ptr(lam_a),
                                          _ptr(lam_b), _ptr(partials), ctypes.byref(out)),
               "lbm_adjoint_segment")
+        return out.value
+
+    def step_levels(self, src, nsteps, levels):
+        """lbm_step_levels: ``nsteps`` single steps from ``src``, level i into slot
+        i - 1 of ``levels``."""
+        check(load().lbm_step_levels(self.ctx, _ptr(src), int(nsteps), _ptr(levels)),
+              "lbm_step_levels")
+
+    def adjoint_levels(self, levels, nsteps, lam_a, lam_b, partials):
+        """lbm_adjoint_levels: ``nsteps`` adjoint steps over stored levels; returns
+        0 / 1 = lam_a / lam_b holds the result."""
+        out = ctypes.c_int(-1)
+        check(load().lbm_adjoint_levels(self.ctx, _ptr(levels), int(nsteps), _ptr(lam_a),
+                                        _ptr(lam_b), _ptr(partials), ctypes.byref(out)),
+              "lbm_adjoint_levels")
         return out.value
 
     def adjoint_terminal(self, dLdh, lam_T):

@@ -69,7 +69,7 @@ def _gpu_grad(c, hhat, T, K, storage="f64"):
     return float(loss), to_np(h0.grad), float(s.grad)
 
 
-@pytest.mark.parametrize("n,T,K", [(32, 60, 7), (48, 41, 41)])
+@pytest.mark.parametrize("n,T,K", [(32, 60, 7), (48, 41, 41), (32, 60, 1), (32, 60, None)])
 def test_rollout_gradient_matches_oracle_fp64(n, T, K):
     c, P, hhat = _problem(n, T)
     say(f"[rollout grad] n={n} T={T} K={K}")
@@ -166,6 +166,80 @@ def test_adjoint_segment_equals_single_steps(storage, adj, fuse):
         got = la if out == 0 else lb
         assert out == n % 2
         assert torch.equal(got, a) and torch.equal(pa, pb), n
+
+
+@pytest.mark.parametrize("storage,adj", [("f64", None), ("f32", "f32"), ("f32", "f64")])
+def test_step_levels_and_adjoint_levels_equal_single_calls(storage, adj):
+    """lbm_step_levels writes the levels single steps (lbm_step_buffers) give, bit
+    for bit, and lbm_adjoint_levels over them gives what lbm_adjoint_step does step
+    by step; buffers that overlap are rejected."""
+    import torch
+
+    from paper_1401_0427_amd.lbm import LbmError
+
+    case = smooth_random_2d(70, 54, seed=6, bc=("inflow", "neumann", "wall", "neumann"),
+                            inflow={0: (1.1, 0.15, 0.05)})
+    S = gpu_solver(case, storage=storage, adjoint_storage=adj)
+    S.step(2)
+    ck = S.current()[0].clone()
+    nb = S.nplanes * S.ps
+    rng = np.random.default_rng(3)
+    for n in (1, 6, 9):
+        levels = S.new_state(n)
+        S.step_levels(ck, n, levels)
+        prev = ck
+        states = [ck]
+        for i in range(n):
+            nxt = S.new_state()
+            S.step_buffers(prev, nxt)
+            assert torch.equal(nxt, levels[i * nb:(i + 1) * nb]), (n, i)
+            prev = nxt
+            states.append(nxt)
+        lam0 = torch.as_tensor(rng.standard_normal(nb), device="cuda").to(S.adj_dtype)
+        a, b = lam0.clone(), S.new_adjoint()
+        pa = S.adjoint_partials()
+        for t in range(n - 1, -1, -1):
+            S.adjoint_step(states[t], a, b, pa)
+            a, b = b, a
+        la, lb = lam0.clone(), S.new_adjoint()
+        pb = S.adjoint_partials()
+        # levels n0 .. n0 + n - 1: the checkpoint, then the first n - 1 stored levels
+        lv = S.new_state(n)
+        lv[:nb].copy_(ck)
+        if n > 1:
+            lv[nb:].copy_(levels[:(n - 1) * nb])
+        out = S.adjoint_levels(lv, n, la, lb, pb)
+        assert out == n % 2
+        assert torch.equal(la if out == 0 else lb, a) and torch.equal(pa, pb), n
+    levels = S.new_state(3)
+    with pytest.raises(LbmError):
+        S.step_levels(levels[nb:2 * nb], 2, levels)
+    with pytest.raises(LbmError):
+        S.adjoint_levels(levels, 3, levels[nb:2 * nb], S.new_adjoint(), S.adjoint_partials())
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_rollout_every_level_equals_checkpointed(storage):
+    """Keeping every level (K = 1: no recomputation) and checkpointing every 7 steps
+    give the same loss and gradients bit for bit (every level is bitwise the same),
+    with faces."""
+    import torch
+
+    from paper_1401_0427_amd.adjoint import rollout
+
+    c, P, hhat = _problem(40, 33, seed=5)
+    bc = ("wall", "inflow", "neumann", "wall")
+    inflow = {1: (1.05, -0.1, 0.0)}
+    res = []
+    for K in (1, 7):
+        h0 = torch.tensor(c.h0, dtype=torch.float64, device="cuda", requires_grad=True)
+        s = torch.tensor(c.s, dtype=torch.float64, device="cuda", requires_grad=True)
+        hT = rollout(h0, s, 33, K, lam=c.lam, storage=storage, bc=bc, inflow=inflow)
+        loss = ((hT - torch.as_tensor(hhat, device="cuda")) ** 2).sum()
+        loss.backward()
+        res.append((hT.detach().clone(), h0.grad.clone(), s.grad.clone()))
+    assert torch.equal(res[0][0], res[1][0])
+    assert torch.equal(res[0][1], res[1][1]) and torch.equal(res[0][2], res[1][2])
 
 
 FACES_1D = [("neumann", "neumann"), ("wall", "wall"), ("inflow", "wall"), ("neumann", "inflow"),
