@@ -346,7 +346,7 @@ typedef struct {
                                 after it.  Bitwise identical to modes 2 and 3.
                                 block, tile_nodes and pass_nodes are ignored. */
     int fuse_steps;       /* modes 3, 4: steps per launch / pass, 2 .. 8 (0 = 8, or
-                             with non-periodic 2D faces 6 (FP64) / 8 (FP32); 1 is
+                             with non-periodic 2D faces 7 (FP64) / 8 (FP32); 1 is
                              rejected) */
     int direct;           /* 0: replay captured HIP graphs (default); 1: launch every
                              kernel directly on the stream (e.g. under a profiler
