@@ -268,7 +268,8 @@ def test_adjoint_full_1024_fp64_matches_oracle_and_fd():
     steps; gradients of sum (h(T) - hhat)^2 w.r.t. h0 and s vs the FP64 oracle
     gradient and a central difference of the GPU loss (rel <= 1e-6); the FP32
     forward's gradient error vs the oracle is stated, with the adjoint in FP64
-    and in FP32, and bounded by the forward's rounding (1e-4 for h0, 2e-4 for s)."""
+    and in FP32, and bounded by the forward's rounding (1e-4 for h0, 2e-4 for s);
+    the default form (every level kept when they fit) gives bitwise the same."""
     import torch
 
     from paper_1401_0427_amd.adjoint import rollout
@@ -280,10 +281,10 @@ def test_adjoint_full_1024_fp64_matches_oracle_and_fd():
     l_ref, gh_ref, gs_ref = oracle.loss_grad_2d(P, c.h0, hhat, T, K=K)
     target = torch.as_tensor(hhat, device="cuda")
 
-    def grads(storage, adj=None):
+    def grads(storage, adj=None, k=K):
         h0 = torch.tensor(c.h0, dtype=torch.float64, device="cuda", requires_grad=True)
         s = torch.tensor(c.s, dtype=torch.float64, device="cuda", requires_grad=True)
-        loss = ((rollout(h0, s, T, K, lam=c.lam, storage=storage, adjoint_storage=adj)
+        loss = ((rollout(h0, s, T, k, lam=c.lam, storage=storage, adjoint_storage=adj)
                  - target) ** 2).sum()
         loss.backward()
         return float(loss), to_np(h0.grad), float(s.grad)
@@ -313,6 +314,15 @@ def test_adjoint_full_1024_fp64_matches_oracle_and_fd():
         # the FP32 rounding of the forward states sets these (1.44e-5 / 5.05e-5 measured,
         # alike for both adjoint storages): above the 1e-6 of the FP64 path, bounded here
         assert e32h < 1e-4 and e32s < 2e-4
+    # the library's default form keeps every level here (501 FP32 levels, 24 GB): the
+    # same levels, so bitwise the same gradients as the checkpointed form
+    from paper_1401_0427_amd.adjoint import rollout_steps_between_checkpoints
+
+    kd = rollout_steps_between_checkpoints((n, n), T, "f32")
+    loss_d, gh_d, gs_d = grads("f32", "f32", None)
+    say(f"  default form (K = {kd}): loss {loss_d:.12e}, bitwise equal to K = {K}: "
+        f"{np.array_equal(gh_d, gh32) and gs_d == gs32}")
+    assert loss_d == loss32 and np.array_equal(gh_d, gh32) and gs_d == gs32
 
 
 def _smooth_2d(n, seed):
