@@ -272,15 +272,15 @@ def time_batched(torch, steps=1000, tuned_only=False, direct=False, mode=-1):
 
 
 def time_adjoint(torch, n=1024, T=500, K=23, storage="f32"):
-    """The adjoint workload: 1024^2, T = 500, FP32 forward.  Timed: the forward
-    rollout and the backward sweep in the library's default form (every level kept
-    when the 501 levels fit in half the free device memory -- 24 GB here -- and one
-    library call for the whole backward sweep), and with checkpoints every K = 23
-    steps (the backward recomputes each segment: one library call per segment);
-    with the adjoint stored like the state (the default) and in FP64; the gradients
-    against those of the FP64 forward (which equals the CPU FP64 oracle's to 1e-15
-    in the tests); and the adjoint kernel alone against the forward kernel, at
-    1024^2 and at 4096^2 (both HBM-bound)."""
+    """The adjoint workload: 1024^2, T = 500, FP32 forward, checkpoints every K = 23
+    steps.  Timed: the forward rollout and the backward sweep (the backward
+    recomputes each segment: one library call per segment), with the adjoint stored
+    like the state (the default) and in FP64; beside it the form that keeps every
+    level (K = 1: the 501 levels take 24 GB, and one library call runs the whole
+    backward sweep with no recomputation), when they fit; the gradients against
+    those of the FP64 forward (which equals the CPU FP64 oracle's to 1e-15 in the
+    tests); and the adjoint kernel alone against the forward kernel, at 1024^2 and
+    at 4096^2 (both HBM-bound)."""
     from paper_1401_0427_amd import workloads as W
     from paper_1401_0427_amd.adjoint import rollout
 
@@ -302,22 +302,26 @@ def time_adjoint(torch, n=1024, T=500, K=23, storage="f32"):
         t2 = time.perf_counter()
         return t1 - t0, t2 - t1, h0.grad.detach(), float(s.grad)
 
-    run(storage, None)  # untimed: one-time set-up (module loading, first allocations)
-    fwd_s, bwd_s, gh, gs = run(storage, None)
-    fwd_ck, bwd_ck, gh_ck, gs_ck = run(storage, None, K)
-    _, bwd64, gh64, gs64 = run(storage, "f64")
+    from paper_1401_0427_amd.adjoint import every_level_fits
+
+    run(storage, None, K)  # untimed: one-time set-up (module loading, first allocations)
+    fwd_s, bwd_s, gh, gs = run(storage, None, K)
+    _, bwd64, gh64, gs64 = run(storage, "f64", K)
     _, _, gh_ref, gs_ref = run("f64", None, K)
-    from paper_1401_0427_amd.adjoint import rollout_steps_between_checkpoints
-    k_default = rollout_steps_between_checkpoints(c.h0.shape, T, storage)
+    every = None
+    if every_level_fits(c.h0.shape, T, storage):
+        run(storage, None, 1)  # untimed: first allocation of the levels
+        fwd_1, bwd_1, gh_1, gs_1 = run(storage, None, 1)
+        every = dict(K=1, forward_s=fwd_1, backward_s=bwd_1,
+                     grad_mlups=n * n * T / (fwd_1 + bwd_1) / 1e6,
+                     same_gradients=bool(torch.equal(gh, gh_1)) and gs == gs_1)
 
     def rel(a, b):
         return float((a - b).abs().max() / b.abs().max())
 
-    out = dict(n=n, T=T, K=k_default, storage=storage, adjoint_storage=storage, forward_s=fwd_s,
+    out = dict(n=n, T=T, K=K, storage=storage, adjoint_storage=storage, forward_s=fwd_s,
                backward_s=bwd_s, grad_mlups=n * n * T / (fwd_s + bwd_s) / 1e6,
-               checkpointed=dict(K=K, forward_s=fwd_ck, backward_s=bwd_ck,
-                                 grad_mlups=n * n * T / (fwd_ck + bwd_ck) / 1e6,
-                                 same_gradients=bool(torch.equal(gh, gh_ck)) and gs == gs_ck),
+               every_level=every,
                grad_h0_rel_vs_fp64=rel(gh, gh_ref), grad_s_rel_vs_fp64=abs(gs - gs_ref) / abs(gs_ref),
                backward_s_adjoint_f64=bwd64, grad_h0_rel_vs_fp64_adjoint_f64=rel(gh64, gh_ref),
                grad_s_rel_vs_fp64_adjoint_f64=abs(gs64 - gs_ref) / abs(gs_ref),

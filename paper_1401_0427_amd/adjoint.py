@@ -1,15 +1,16 @@
 """Gradients of a final-height misfit through the lattice Boltzmann rollout.
 
 ``rollout(h0, s, T, ...)`` returns h(T) as a differentiable function of the
-initial height field h0 and the relaxation rate s.  When the T + 1 levels of the
-run fit in half the free device memory (1024^2 FP32 x 500 steps: 24 GB) the
-forward keeps every level (single steps written level by level,
-``lbm_step_levels``) and the backward applies the hand-written adjoint kernel
-over them in one library call (``lbm_adjoint_levels``), with no recomputation.
-Otherwise (or with K > 1) the forward keeps a copy of the state every K steps
-and the backward, for each K-step segment in reverse, recomputes its states from
-the checkpoint (one extra forward step per adjoint step) and applies the adjoint
-steps -- one library call per segment (``lbm_adjoint_segment``).  Either way dL/ds
+initial height field h0 and the relaxation rate s.  The forward keeps a copy of
+the state every K steps (by default K is about sqrt(T)) and the backward, for
+each K-step segment in reverse, recomputes its states from the checkpoint (one
+extra forward step per adjoint step) and applies the hand-written adjoint kernel
+step by step -- one library call per segment (``lbm_adjoint_segment``).  With K =
+1 the forward keeps every level instead (single steps written level by level,
+``lbm_step_levels``) and the backward applies the adjoint over them in one
+library call (``lbm_adjoint_levels``), with no recomputation: the faster form
+whenever the T + 1 states fit in device memory (``every_level_fits``; 1024^2 FP32
+x 500 steps: 24 GB of an MI355X's 288).  Either way dL/ds
 accumulates in FP64 per workgroup, and finally dL/dh0 = J(W0)^T lam^0.  Every
 level is bitwise the same in both forms (multi-step launches equal single steps),
 so are the gradients.
@@ -92,25 +93,24 @@ def rollout(h0: torch.Tensor, s: torch.Tensor, T: int, K: int | None = None, lam
             inflow=None) -> torch.Tensor:
     """h(T) from W0 = (h0, 0, 0) (1D: (h0, 0)); differentiable in h0 (a 2D
     (ny, nx) or 1D (nx,) float64 CUDA tensor) and s (0-dim float64 tensor).  K =
-    steps between checkpoints; K = 1 keeps every level (no recomputation in the
-    backward).  By default K = 1 when T + 1 states fit in half the free device
-    memory, else about sqrt(T).  ``bc`` = faces (x-, x+, y-, y+) by name,
+    steps between checkpoints (default about sqrt(T)); K = 1 keeps every level (no
+    recomputation in the backward).  ``bc`` = faces (x-, x+, y-, y+) by name,
     ``inflow`` = {face: (h, qx, qy)} as for Solver.  ``adjoint_storage``: element
     type of the adjoint buffers (None = the state's, "f64", or "f32" with FP32
     state storage)."""
     if K is None:
-        K = rollout_steps_between_checkpoints(tuple(h0.shape), T, storage, h0.device)
+        K = max(1, int(round(math.sqrt(T))))
     return _Rollout.apply(h0, s, int(T), int(K), float(lam), float(g), storage, int(block),
                           adjoint_storage, tuple(bc), inflow)
 
 
-def rollout_steps_between_checkpoints(shape, T: int, storage: str = "f64", device=None) -> int:
-    """The rollout's default K for a field of ``shape`` ((ny, nx) or (nx,)): 1 (every
-    level kept) when T + 1 states fit in half the free device memory, else about
-    sqrt(T)."""
+def every_level_fits(shape, T: int, storage: str = "f64", device=None) -> bool:
+    """Whether the T + 1 states of a rollout over a field of ``shape`` ((ny, nx) or
+    (nx,)) fit in half the free device memory, so that K = 1 (every level kept, no
+    recomputation) can be used."""
     nx = shape[-1]
     ny = shape[0] if len(shape) == 2 else 1
     planes = 12 if len(shape) == 2 else 4
     state_bytes = planes * nx * ny * (4 if storage == "f32" else 8)
     free = torch.cuda.mem_get_info(device)[0]
-    return 1 if (T + 1) * state_bytes <= free // 2 else max(1, int(round(math.sqrt(T))))
+    return (T + 1) * state_bytes <= free // 2

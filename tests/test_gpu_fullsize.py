@@ -269,7 +269,7 @@ def test_adjoint_full_1024_fp64_matches_oracle_and_fd():
     gradient and a central difference of the GPU loss (rel <= 1e-6); the FP32
     forward's gradient error vs the oracle is stated, with the adjoint in FP64
     and in FP32, and bounded by the forward's rounding (1e-4 for h0, 2e-4 for s);
-    the default form (every level kept when they fit) gives bitwise the same."""
+    the form that keeps every level (K = 1) gives bitwise the same."""
     import torch
 
     from paper_1401_0427_amd.adjoint import rollout
@@ -314,13 +314,10 @@ def test_adjoint_full_1024_fp64_matches_oracle_and_fd():
         # the FP32 rounding of the forward states sets these (1.44e-5 / 5.05e-5 measured,
         # alike for both adjoint storages): above the 1e-6 of the FP64 path, bounded here
         assert e32h < 1e-4 and e32s < 2e-4
-    # the library's default form keeps every level here (501 FP32 levels, 24 GB): the
-    # same levels, so bitwise the same gradients as the checkpointed form
-    from paper_1401_0427_amd.adjoint import rollout_steps_between_checkpoints
-
-    kd = rollout_steps_between_checkpoints((n, n), T, "f32")
-    loss_d, gh_d, gs_d = grads("f32", "f32", None)
-    say(f"  default form (K = {kd}): loss {loss_d:.12e}, bitwise equal to K = {K}: "
+    # keeping every level (501 FP32 levels, 24 GB): the same levels, so bitwise the
+    # same gradients as the checkpointed form
+    loss_d, gh_d, gs_d = grads("f32", "f32", 1)
+    say(f"  every level kept (K = 1): loss {loss_d:.12e}, bitwise equal to K = {K}: "
         f"{np.array_equal(gh_d, gh32) and gs_d == gs32}")
     assert loss_d == loss32 and np.array_equal(gh_d, gh32) and gs_d == gs32
 
