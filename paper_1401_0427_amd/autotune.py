@@ -102,7 +102,8 @@ def tune_batch(seed=0, steps=96, blocks=(256, 512), tiles=(4096, 8192, 16384, 32
     size, tile size, grid and nodes per pass; the step-synchronous (1) and flat
     (2) modes over workgroup size (= nodes per unit); the fused mode (3) and its
     persistent form (4) over steps per launch / pass.  A configuration whose run
-    is aborted by the bounded waits is reported and skipped."""
+    is aborted by the bounded waits is reported and skipped.  The fastest wins,
+    except that the persistent fused form is preferred within 1 % of it."""
     import torch
 
     from . import workloads as W
@@ -145,6 +146,13 @@ def tune_batch(seed=0, steps=96, blocks=(256, 512), tiles=(4096, 8192, 16384, 32
         rows.append(r)
         log(json.dumps(r))
     best = max(rows, key=lambda r: r["mlups"])
+    # one persistent launch for the whole run (mode 4) is the form the batch is
+    # meant to take: it is chosen when it is within 1 % of the fastest
+    pf = [r for r in rows if r["mode"] == 4]
+    if pf:
+        bpf = max(pf, key=lambda r: r["mlups"])
+        if bpf["mlups"] >= 0.99 * best["mlups"]:
+            best = bpf
     return best, rows
 
 

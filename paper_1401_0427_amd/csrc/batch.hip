@@ -353,15 +353,13 @@ __global__ void __launch_bounds__(512)
     }
 }
 
-// Zero the claim and completion counters and the abort flag of a persistent
-// launch (a kernel, so that it can sit in a captured graph).
+// Zero the claim and completion counters (kPersistentCounters: the step-synchronous
+// kernel uses the first two, the persistent fused kernel all) and the abort flag of
+// a persistent launch (a kernel, so that it can sit in a captured graph).
 __global__ void k_batch_sync_reset(unsigned long long *ctr, int *abort_flag)
 {
-    if (threadIdx.x == 0) {
-        ctr[0] = 0ull;
-        ctr[1] = 0ull;
-        *abort_flag = 0;
-    }
+    if (threadIdx.x < kPersistentCounters) ctr[threadIdx.x] = 0ull;
+    if (threadIdx.x == 0) *abort_flag = 0;
 }
 
 // Zero the per-tile counters and the work counter (a kernel, so that it can sit
@@ -419,7 +417,7 @@ struct lbm_batch {
     // step-synchronous mode
     UnitDev *d_units;
     int nunits;
-    unsigned long long *d_ctr;  // step-synchronous / persistent fused: claim, completion
+    unsigned long long *d_ctr;  // persistent launches: claim counters, completion (kPersistentCounters)
     int grid;
     // fused mode: K steps per launch pair (2D wave-strip tiles + 1D tiles)
     XkTileDev *d_xtiles;
@@ -739,7 +737,8 @@ extern "C" int lbm_batch_create(const lbm_instance *inst_in, int n, int storage,
         (e = hipMalloc(&b->d_next, sizeof(unsigned long long))) != hipSuccess ||
         (e = hipMalloc(&b->d_abort, sizeof(int))) != hipSuccess ||
         (e = hipMalloc(&b->d_units, sizeof(UnitDev) * hu.size())) != hipSuccess ||
-        (e = hipMalloc(&b->d_ctr, 2 * sizeof(unsigned long long))) != hipSuccess ||
+        (e = hipMalloc(&b->d_ctr, kPersistentCounters * sizeof(unsigned long long))) !=
+            hipSuccess ||
         (e = hipMalloc(&b->d_xtiles, sizeof(XkTileDev) * std::max<size_t>(1, hx.size()))) !=
             hipSuccess ||
         (e = hipMalloc(&b->d_xbtiles, sizeof(XkTileDev) * std::max<size_t>(1, hxb.size()))) !=

@@ -43,6 +43,10 @@ struct K1TileDev {
 
 // Polls at most of a bounded wait in a persistent launch.
 constexpr int kSpinLimit = 1 << 22;
+// Claim queues of the persistent fused batch kernel (one per XCD); its counters are
+// kPQueues claim counters followed by the completion counter.
+constexpr int kPQueues = 8;
+constexpr int kPersistentCounters = kPQueues + 1;
 
 // Work distribution of a persistent launch that advances in passes (one step, or
 // K steps) over nitems work items each.  A 64-bit claim counter hands out item

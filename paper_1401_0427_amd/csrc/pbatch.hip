@@ -2,9 +2,14 @@
 // launch.  The work of K steps (one pass) is the fused mode's tile tables: 2D
 // wave-strip tiles of all-periodic instances, 2D tiles of instances with other
 // faces, and 1D LDS tiles (here of 256 nodes, kP1kPerItem to a work item).
-// Workgroups claim the items of a pass in order (the heavy 2D tiles first) and a
-// pass closes when all its items are complete, before the next pass reads what
-// it wrote; the buffers swap every pass (pass_claim / pass_complete: the launch
+// The items of a pass are split into nq = min(kPQueues, grid) claim queues, each
+// kind of item into nq contiguous shares (so neighbouring strips of an instance
+// share a queue), and workgroup b claims from queue b mod nq in order (its heavy
+// 2D tiles first): with eight queues, queue x is served by the workgroups on XCD
+// x (workgroups are placed on the XCDs round robin), so the halo columns two
+// neighbouring strips both read are fetched once into that XCD's L2.  A pass
+// closes when all its items are complete, before the next pass reads what it
+// wrote; the buffers swap every pass (pass_claim / pass_complete: the launch
 // completes whatever number of its workgroups are resident).  Each tile computes
 // exactly what its own launch in the fused mode computes (the same device code),
 // so the state equals that of K-step launches, and of single steps, bit for bit.
@@ -15,6 +20,15 @@ namespace lbm {
 
 constexpr int kPThreads = 64 * kXkWaves;  // threads per workgroup
 constexpr int kP1kPerItem = 16;           // 1D tiles per work item
+static_assert(kPQueues == 8, "claim queues: one per XCD");
+
+// Queue x's share of n items split over nq queues: [*start, *start + *count).
+__device__ __forceinline__ void pq_share(int n, int nq, int x, int *start, int *count)
+{
+    const int q = n / nq, r = n % nq;
+    *start = x * q + (x < r ? x : r);
+    *count = q + (x < r ? 1 : 0);
+}
 
 // LDS of the largest tile kind the kernel runs (one array, reused by every item).
 template <typename T, int K, bool BND>
@@ -40,19 +54,31 @@ __global__ void __launch_bounds__(kPThreads)
     constexpr int D = xk_batch_depth<T>();
     __shared__ __align__(16) T lds[pfused_lds_elems<T, K, BND>()];
     const int wave = (int)(threadIdx.x >> 6);
-    const long long nitems = nxt + nxbt + (nkt + kP1kPerItem - 1) / kP1kPerItem;
+    const int nk1 = (nkt + kP1kPerItem - 1) / kP1kPerItem;
+    const long long nitems = (long long)nxt + nxbt + nk1;
+    const int nq = (int)gridDim.x < kPQueues ? (int)gridDim.x : kPQueues;
+    const int q = (int)(blockIdx.x % (unsigned)nq);
+    int s2, c2, sb, cb, s1, c1;
+    pq_share(nxt, nq, q, &s2, &c2);
+    pq_share(nxbt, nq, q, &sb, &cb);
+    pq_share(nk1, nq, q, &s1, &c1);
+    const long long nmine = (long long)c2 + cb + c1;  // this queue's items per pass
     long long pending = -1;
     for (int p = 0; p < npasses; ++p) {
         const bool odd = ((cur + p) & 1) != 0;
         const T *src = odd ? buf1 : buf0;
         T *dst = odd ? buf0 : buf1;
-        const long long base = (long long)p * nitems, end = base + nitems;
+        const long long base = (long long)p * nmine, end = base + nmine;
         int mine = 0;
         for (;;) {
-            if (pending < 0) pending = pass_claim(ctr);  // (its barrier frees the LDS)
-            if (pending >= end) break;                    // kept for a later pass
-            const int v = (int)(pending - base);
+            if (pending < 0) pending = pass_claim(ctr + q);  // (its barrier frees the LDS)
+            if (pending >= end) break;                        // kept for a later pass
+            const int c = (int)(pending - base);
             pending = -1;
+            // the item: this queue's share of 2D tiles, then of bounded tiles, then
+            // of 1D items; v numbers it as before (2D, bounded, 1D)
+            const int v = c < c2 ? s2 + c : c < c2 + cb ? nxt + sb + (c - c2)
+                                                        : nxt + nxbt + s1 + (c - c2 - cb);
             if (v < nxt) {
                 const XkTileDev td = xt[v];
                 const InstDev &I = inst[td.inst];
@@ -89,7 +115,9 @@ __global__ void __launch_bounds__(kPThreads)
             }
             ++mine;
         }
-        if (pass_complete(ctr + 1, mine, (unsigned long long)end, abort_flag)) break;
+        if (pass_complete(ctr + kPQueues, mine, (unsigned long long)((p + 1) * nitems),
+                          abort_flag))
+            break;
     }
 }
 
