@@ -378,6 +378,12 @@ def test_launch_plan_spreads_the_remainder_and_keeps_the_state():
             and set(long_plan) == {7, 8} and long_plan[:200] == [8] * 200)
     assert S.launch_plan(0) == [] and S.launch_plan(1) == [1] and S.launch_plan(8) == [8]
     assert gpu_solver(W.dam_break_1d(1000)).launch_plan(20) == [16, 4]
+    # state checks every 9 steps split a run into windows, each planned on its own
+    # (a 9-step window: 8 + 1, the remainder of one step in the one-step kernel)
+    Sc = gpu_solver(per, fuse_steps=8, check_every=9)
+    assert Sc.launch_plan(20) == [8, 1, 8, 1, 2]
+    Sc.step(3)
+    assert Sc.launch_plan(20) == [6, 8, 1, 5]
     walls = W.oblique_shock_2d(20, steps=10)
     Sw = gpu_solver(walls, fuse_steps=6)
     assert Sw.launch_plan(20) == [5, 5, 5, 5]
