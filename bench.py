@@ -15,6 +15,8 @@ Beside it on the same JSON line:
   forms.*_faces  the same grid with inflow / Neumann / wall faces
   forms.*_one_step_per_launch  the same with one step per launch
   forms.wall_1d_*  1D wall reflection, 2^20 nodes (MALL-resident)
+  forms.dam_break_1d  the 1D dam break as stated (1000 nodes, 400 steps, FP64): the
+                 whole run's time, set by launch latency
   forms.batched  256 mixed 1D / 2D Riemann problems, FP32 storage, 1000 steps, in
                  the tuned mode (K steps per launch over every instance, graph
                  replayed); beside it the three single-launch persistent modes
@@ -163,6 +165,34 @@ def time_1d(torch, storage, steps=2000, warmup=64, fuse=0):
     return dict(nodes=c.nx, steps=steps, ms_per_step=ms / steps,
                 mlups=c.nx * steps / (ms * 1e-3) / 1e6, effective_gbs=c.nx * bpl * steps / (ms * 1e-3) / 1e9,
                 bytes_per_lu=bpl, finite=ok, h=h.clone())
+
+
+def time_dam_break_1d(torch, reps=20):
+    """The 1D dam break as stated (1000 nodes, 400 steps, FP64, Neumann ends), the
+    whole run timed from its initial state ``reps`` times: far too small to fill a GPU
+    (one workgroup per launch), so launch latency sets the rate."""
+    from paper_1401_0427_amd import workloads as W
+    from paper_1401_0427_amd.lbm import Solver
+
+    c = W.dam_break_1d()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    S = Solver(1, c.nx, 1, lam=c.lam, s=c.s, bc=c.bc, h0=c.h0, qx0=c.qx0, storage="f64")
+    init = S.current()[0].clone()
+    S.step(c.steps)  # untimed: first launches
+    best = None
+    for _ in range(reps):
+        S.import_(init)
+        torch.cuda.synchronize()
+        e0.record(st)
+        S.step(c.steps)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    return dict(nodes=c.nx, steps=c.steps, ms_run=best, ms_per_step=best / c.steps,
+                mlups=c.nx * c.steps / (best * 1e-3) / 1e6,
+                launches=len(S.launch_plan(c.steps)))
 
 
 def _manifest_instances():
@@ -650,6 +680,8 @@ def main():
         for storage in ("f64", "f32"):
             log(f"[bench] 1D wall reflection 2^20 {storage.upper()}")
             forms["wall_1d_" + storage] = time_1d(torch, storage)
+        log("[bench] 1D dam break 1000 nodes x 400 steps")
+        forms["dam_break_1d"] = time_dam_break_1d(torch)
     # FP32 storage against FP64 storage after the same steps of the same form (the
     # FP64 path equals the CPU FP64 oracle to <= 1e-12 in the parity tests): L1
     # relative error of h, bounded by 1e-5

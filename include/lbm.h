@@ -102,7 +102,7 @@ typedef struct {
                              bit 2: plain workgroup order (no XCD-aware tile remap);
                              < 0 = library default */
     int fuse_steps;       /* steps per launch (temporal blocking; bitwise identical
-                             to single steps): 0 = library default, else 1 .. 16.
+                             to single steps): 0 = library default, else 1 .. 1024.
                              2D all-periodic grids fuse at most 8 (larger values
                              take 8; default 8 -- FP32: 6 unless the 8-step
                              launch has three workgroups per resident slot,
@@ -115,8 +115,12 @@ typedef struct {
                              for FP64, 8 for FP32 storage, or the largest fewer
                              steps whose launch fills a third of the device, else
                              1; planes of 2 GiB or
-                             more take 1); 1D grids any
-                             (default 16).  lbm_launch_info reports the choice. */
+                             more take 1); 1D grids at most 16 (larger values
+                             take 16; default 16), except a 1D domain with
+                             non-periodic ends of at most 1024 nodes (one LDS
+                             tile, nothing lost at its ends), which takes any up
+                             to 1024 (default 1024).  lbm_launch_info reports
+                             the choice. */
     void *f_a, *f_b;      /* caller-owned device state buffers (ping-pong) */
     void *stream;         /* hipStream_t; NULL = default stream */
     int adjoint_storage;  /* element type of adjoint buffers: 0 = the state's,

@@ -181,6 +181,10 @@ static const int kFuseMinBlocks = 1024;
 // levels in LDS).
 static const int kDefaultFuse1d = 16;
 static const int kMaxFuse1d = 16;
+// 1D domains with non-periodic ends that fit one tile (step1k_whole): steps per
+// launch by default and at most (nothing is lost at the tile's ends; the 1000-node
+// dam break of 400 steps runs in one launch).
+static const int kFuse1dWhole = 1024;
 static const int kFuseSeg = 24;  // rows per workgroup segment of the LDS two-step launch
 // Rows per wavefront segment of the wave-strip launch when the device cannot be
 // queried (else chosen per grid at init, step2k_seg).
@@ -262,8 +266,8 @@ extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0
                     p->adjoint_storage);
     if (p->adjoint_storage == LBM_F32 && p->storage != LBM_F32)
         return fail(LBM_EINVAL, "a float adjoint needs float state storage");
-    if (p->fuse_steps < 0 || p->fuse_steps > kMaxFuse1d)
-        return fail(LBM_EINVAL, "fuse_steps must be in 0 .. %d (got %d)", kMaxFuse1d,
+    if (p->fuse_steps < 0 || p->fuse_steps > kFuse1dWhole)
+        return fail(LBM_EINVAL, "fuse_steps must be in 0 .. %d (got %d)", kFuse1dWhole,
                     p->fuse_steps);
 
     lbm_ctx *c = new (std::nothrow) lbm_ctx();
@@ -297,8 +301,10 @@ extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0
         c->x2 = allper;  // two steps per launch: the LDS strip kernel (faster at K = 2)
         if (rest)
             c->fuse = 1;
+        else if (dim == 1 && step1k_whole(c->G))
+            c->fuse = want ? want : kFuse1dWhole;
         else if (dim == 1)
-            c->fuse = want ? want : kDefaultFuse1d;
+            c->fuse = want ? (want > kMaxFuse1d ? kMaxFuse1d : want) : kDefaultFuse1d;
         else if ((size_t)ps * (c->f32 ? 4 : 8) < ((size_t)1 << 31)) {
             const int kmax = allper ? kMaxFuse2d : step2k_max_k_bounded();
             if (want) {

@@ -146,6 +146,10 @@ hipError_t launch_adjoint_grad_w0(int dim, bool f32, const void *lam0, const dou
                                   double *gqy, const Geo &G, const Phys &P, hipStream_t st);
 
 int step2x_blocks(const Geo &G, int seg);
+// 1D K-step launch: tiles of kK1Threads nodes with 2 K halo nodes (K < 512), or,
+// for a domain with non-periodic ends of at most kK1Threads nodes (step1k_whole),
+// one whole-domain tile and any K.
+bool step1k_whole(const Geo &G);
 hipError_t launch_step1k(bool f32, const void *src, void *dst, const Geo &G, const Phys &P,
                          int K, hipStream_t st);
 hipError_t launch_step2x(bool f32, const void *src, void *dst, const Geo &G, const Phys &P,

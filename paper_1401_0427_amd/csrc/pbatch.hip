@@ -108,8 +108,8 @@ __global__ void __launch_bounds__(kPThreads)
                 for (int i = i0; i < i1; ++i) {
                     const K1TileDev td = kt[i];
                     const InstDev &I = inst[td.inst];
-                    k1_tile<T, kPThreads>(src + I.off, dst + I.off, I.G, I.P, K, td.ob,
-                                          kPThreads - 2 * K,
+                    k1_tile<T, kPThreads>(src + I.off, dst + I.off, I.G, I.P, K, td.ob - K,
+                                          td.ob, kPThreads - 2 * K,
                                           reinterpret_cast<T (*)[4][kPThreads]>(lds));
                 }
             }

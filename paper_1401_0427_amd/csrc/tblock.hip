@@ -435,10 +435,12 @@ hipError_t launch_step2k(bool f32, const void *src, void *dst, const Geo &G, con
 
 template <typename T>
 __global__ void __launch_bounds__(kK1Threads)
-    k_step1d_k(const T *__restrict__ src, T *__restrict__ dst, Geo G, Phys P, int K, int nout)
+    k_step1d_k(const T *__restrict__ src, T *__restrict__ dst, Geo G, Phys P, int K, int nout,
+               int whole)
 {
     __shared__ T sh[2][4][kK1Threads];
-    k1_tile<T, kK1Threads>(src, dst, G, P, K, (int)blockIdx.x * nout, nout, sh);
+    const int ob = (int)blockIdx.x * nout;
+    k1_tile<T, kK1Threads>(src, dst, G, P, K, whole ? 0 : ob - K, ob, nout, sh);
 }
 
 // Batched form: workgroup b takes 1D tile b of a table spanning many 1D instances.
@@ -450,21 +452,26 @@ __global__ void __launch_bounds__(kK1Threads)
     __shared__ T sh[2][4][kK1Threads];
     const K1TileDev td = tiles[blockIdx.x];
     const InstDev &I = inst[td.inst];
-    k1_tile<T, kK1Threads>(src + I.off, dst + I.off, I.G, I.P, K, td.ob, kK1Threads - 2 * K,
-                           sh);
+    k1_tile<T, kK1Threads>(src + I.off, dst + I.off, I.G, I.P, K, td.ob - K, td.ob,
+                           kK1Threads - 2 * K, sh);
 }
+
+bool step1k_whole(const Geo &G) { return G.bc[0] != BC_PERIODIC && G.nx <= kK1Threads; }
 
 hipError_t launch_step1k(bool f32, const void *src, void *dst, const Geo &G, const Phys &P,
                          int K, hipStream_t st)
 {
-    const int nout = kK1Threads - 2 * K;
-    const int nb = (G.nx + nout - 1) / nout;
+    // a domain with non-periodic ends that fits one tile: one workgroup, any K
+    const int whole = step1k_whole(G) ? 1 : 0;
+    if (!whole && 2 * K >= kK1Threads) return hipErrorInvalidValue;
+    const int nout = whole ? G.nx : kK1Threads - 2 * K;
+    const int nb = whole ? 1 : (G.nx + nout - 1) / nout;
     if (f32)
         hipLaunchKernelGGL(k_step1d_k<float>, dim3(nb), dim3(kK1Threads), 0, st,
-                           (const float *)src, (float *)dst, G, P, K, nout);
+                           (const float *)src, (float *)dst, G, P, K, nout, whole);
     else
         hipLaunchKernelGGL(k_step1d_k<double>, dim3(nb), dim3(kK1Threads), 0, st,
-                           (const double *)src, (double *)dst, G, P, K, nout);
+                           (const double *)src, (double *)dst, G, P, K, nout, whole);
     return hipGetLastError();
 }
 

@@ -907,13 +907,16 @@ constexpr int kXkbDepth = 1;
 // A workgroup of NT threads (1024 in the 1D launches, 256 in the persistent
 // batched kernel) holds a tile of NT consecutive nodes in LDS (four planes,
 // double-buffered) and advances it K steps, one node per thread, one barrier per
-// step.  The tile starts K nodes before its NT - 2K output nodes: each step invalidates one more node at each tile edge inside the
-// domain, so the outputs are exact after K steps.  At a non-periodic domain end
-// the face rule (Neumann / wall / inflow, as in the one-step kernel) is applied
-// to the node's own previous-level values, so nothing is lost there; with
-// periodic faces the tile simply wraps.  Each level is rounded to the storage
-// type, as a store and a reload would round it: K steps in one launch equal K
-// single steps bit for bit.
+// step.  The tile (first node x0) starts K nodes before its NT - 2K output nodes
+// [ob, ob + nout): each step invalidates one more node at each tile edge inside
+// the domain, so the outputs are exact after K steps.  At a non-periodic domain
+// end the face rule (Neumann / wall / inflow, as in the one-step kernel) is
+// applied to the node's own previous-level values, so nothing is lost there; with
+// periodic faces the tile simply wraps.  A domain with non-periodic ends that fits
+// in one tile (x0 = ob = 0, nout = nx <= NT) loses nothing at either end, so it
+// stays exact for any K.  Each level is rounded to the storage type, as a store
+// and a reload would round it: K steps in one launch equal K single steps bit for
+// bit.
 constexpr int kK1Threads = 1024;
 
 // Ghost value of plane pl beyond face (0: x-, 1: x+) of a non-periodic end, from
@@ -937,15 +940,15 @@ __device__ __forceinline__ double k1_face(const Geo &G, int pl, int face, const 
 // the workgroup's LDS array sh (NT threads, nout <= NT - 2K).
 template <typename T, int NT>
 __device__ __forceinline__ void k1_tile(const T *__restrict__ src, T *__restrict__ dst,
-                                        const Geo &G, const Phys &P, int K, int ob, int nout,
-                                        T (*sh)[4][NT])
+                                        const Geo &G, const Phys &P, int K, int x0, int ob,
+                                        int nout, T (*sh)[4][NT])
 {
     const int t = threadIdx.x;
     const int nx = G.nx;
     const long ps = G.ps;
     const bool per = G.bc[0] == BC_PERIODIC;  // the two 1D faces are periodic together
     const int oe = min(ob + nout, nx);         // output nodes [ob, oe)
-    const int x = ob - K + t;                  // this thread's node, unwrapped
+    const int x = x0 + t;                      // this thread's node, unwrapped
     const bool in = per || (x >= 0 && x < nx);
     const int xw = per ? ((x % nx) + nx) % nx : x;
     const int tl = t > 0 ? t - 1 : t;          // clamped neighbours (edge values are

@@ -45,8 +45,8 @@ def test_layout_pads_planes(L):
 
 @pytest.mark.parametrize("bad", [dict(s=2.0), dict(s=0.0), dict(lam=-1.0), dict(g=0.0),
                                  dict(nx=1), dict(bc=("periodic", "wall", "periodic", "periodic")),
-                                 dict(block=100), dict(npt=3), dict(fuse_steps=17),
-                                 dict(fuse_steps=32), dict(fuse_steps=-1),
+                                 dict(block=100), dict(npt=3), dict(fuse_steps=1025),
+                                 dict(fuse_steps=4096), dict(fuse_steps=-1),
                                  dict(bc=("inflow", "wall", "periodic", "periodic"), inflow={0: (0.0, 0, 0)}),
                                  dict(adjoint_storage="f32"), dict(adjoint_storage=16)])
 def test_init_rejects_bad_parameters_without_touching_memory(L, bad):

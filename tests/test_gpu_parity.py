@@ -319,12 +319,41 @@ def test_fused_1d_launch_equals_single_steps(storage, fuse, n, bc, inflow, steps
         assert per_plane_rel(b, ref) <= TOL64
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("n,bc,inflow", [
+    (1000, ("neumann", "neumann"), {}),
+    (1024, ("inflow", "wall"), {0: (1.5, 0.75, 0.0)}),
+    (333, ("wall", "inflow"), {1: (1.2, -0.3, 0.0)}),
+])
+def test_whole_domain_1d_launch_equals_single_steps(storage, n, bc, inflow):
+    """A 1D domain with non-periodic ends that fits one LDS tile (at most 1024 nodes)
+    loses nothing at the tile's ends, so it takes up to 1024 steps per launch by
+    default (400 steps: one launch; 1500: 1024 + 476); the state equals single steps
+    bit for bit and, in FP64, the oracle.  1025 nodes fall back to 16 steps."""
+    case = _case_1d(n, bc, inflow, seed=n)
+    A = gpu_solver(case, storage=storage, fuse_steps=1)
+    B = gpu_solver(case, storage=storage)
+    assert B.launch_info()["steps_per_launch"] == 1024
+    assert B.launch_plan(400) == [400] and B.launch_plan(1500) == [1024, 476]
+    for steps in (400, 1500):
+        A.step(steps)
+        B.step(steps)
+        a, b = to_np(A.planes()), to_np(B.planes())
+        assert np.array_equal(a, b), steps
+    if storage == "f64":
+        ref, _ = orc_state(case, 1900)
+        assert per_plane_rel(b, ref) <= TOL64
+    big = gpu_solver(_case_1d(1025, bc, inflow, seed=3), storage=storage)
+    assert big.launch_info()["steps_per_launch"] == 16
+
+
 def test_default_launch_plans():
     """lbm_launch_info reports the plan chosen at init: the wave-strip multi-step
     launch on grids it can fill (8 steps per launch; FP32 6 on grids below about
     three workgroups per resident slot, such as 1024^2), with a segment length and
     the resident workgroups it was chosen against; one step per launch on a
-    small FP32 grid; 16 steps per launch in 1D; with non-periodic 2D faces 7
+    small FP32 grid; 16 steps per launch in 1D (1024 on a domain with non-periodic ends that
+    fits one tile); with non-periodic 2D faces 7
     (FP64) / 8 (FP32) steps, or fewer where that launch cannot fill the device;
     an explicit request is honoured up to 8 steps."""
     big64 = gpu_solver(smooth_random_2d(1024, 1024, seed=8), storage="f64").launch_info()
@@ -336,8 +365,10 @@ def test_default_launch_plans():
     assert huge32["steps_per_launch"] == 8
     small32 = gpu_solver(smooth_random_2d(256, 256, seed=8), storage="f32").launch_info()
     assert small32["steps_per_launch"] == 1
-    one_d = gpu_solver(W.dam_break_1d(1000)).launch_info()
+    one_d = gpu_solver(W.dam_break_1d(5000)).launch_info()
     assert one_d["steps_per_launch"] == 16 and one_d["segment_rows"] == 0
+    small_1d = gpu_solver(W.dam_break_1d(1000)).launch_info()
+    assert small_1d["steps_per_launch"] == 1024
     walls = gpu_solver(W.oblique_shock_2d(20, steps=10), fuse_steps=4).launch_info()
     assert walls["steps_per_launch"] == 4 and walls["segment_rows"] >= 16
     walls8 = gpu_solver(W.oblique_shock_2d(20, steps=10), fuse_steps=8).launch_info()
@@ -377,7 +408,8 @@ def test_launch_plan_spreads_the_remainder_and_keeps_the_state():
     assert (len(long_plan) == 251 and sum(long_plan) == 2002
             and set(long_plan) == {7, 8} and long_plan[:200] == [8] * 200)
     assert S.launch_plan(0) == [] and S.launch_plan(1) == [1] and S.launch_plan(8) == [8]
-    assert gpu_solver(W.dam_break_1d(1000)).launch_plan(20) == [16, 4]
+    assert gpu_solver(W.dam_break_1d(5000)).launch_plan(20) == [16, 4]
+    assert gpu_solver(W.dam_break_1d(1000)).launch_plan(400) == [400]
     # state checks every 9 steps split a run into windows, each planned on its own
     # (a 9-step window: 8 + 1, the remainder of one step in the one-step kernel)
     Sc = gpu_solver(per, fuse_steps=8, check_every=9)
