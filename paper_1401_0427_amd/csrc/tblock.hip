@@ -149,8 +149,8 @@ __global__ void __launch_bounds__(64 * kXkWaves)
         const int tile = xk_tile(blockIdx.x, nstrips * nseg, true);
         const int strip = tile % nstrips;
         const int y0 = (tile / nstrips) * seg;
-        xk_wave<T, K, D, false, SW>(src, dst, G, P, strip, y0, min(y0 + seg, G.ny), lds,
-                                       rows);
+        xk_wave<T, K, D, false, SW, true>(src, dst, G, P, strip, y0, min(y0 + seg, G.ny), lds,
+                                          rows);
     } else {
         __shared__ T xs[kXkWaves][xk_lds_elems<T, K>()];
         const int ngroups = (nstrips + kXkWaves - 1) / kXkWaves;
@@ -158,7 +158,8 @@ __global__ void __launch_bounds__(64 * kXkWaves)
         const int strip = (tile % ngroups) * kXkWaves + (threadIdx.x >> 6);
         if (strip >= nstrips) return;  // whole wavefront; nothing here waits on others
         const int y0 = (tile / ngroups) * seg;
-        xk_wave<T, K, D>(src, dst, G, P, strip, y0, min(y0 + seg, G.ny), xs[threadIdx.x >> 6]);
+        xk_wave<T, K, D, false, 1, true>(src, dst, G, P, strip, y0, min(y0 + seg, G.ny),
+                                         xs[threadIdx.x >> 6]);
     }
 }
 
@@ -176,7 +177,8 @@ __global__ void __launch_bounds__(64 * kXkWaves)
     const int strip = (tile % ngroups) * kXkWaves + (threadIdx.x >> 6);
     if (strip >= nstrips) return;  // whole wavefront; nothing here waits on others
     const int y0 = (tile / ngroups) * seg;
-    xk_wave<T, K, D, true>(src, dst, G, P, strip, y0, min(y0 + seg, G.ny), xs[threadIdx.x >> 6]);
+    xk_wave<T, K, D, true, 1, true>(src, dst, G, P, strip, y0, min(y0 + seg, G.ny),
+                                    xs[threadIdx.x >> 6]);
 }
 
 // Batched form: workgroup b takes tile b' (the XCD-contiguous order of b) of a
