@@ -18,12 +18,12 @@ Beside it on the same JSON line:
   forms.dam_break_1d  the 1D dam break as stated (1000 nodes, 400 steps, FP64): the
                  whole run's time, set by launch latency
   forms.batched  256 mixed 1D / 2D Riemann problems, FP32 storage, 1000 steps, in
-                 the tuned mode (K steps per launch over every instance, graph
-                 replayed); beside it the three single-launch persistent modes
-                 (the same tiles with one pass per K steps, dataflow,
-                 step-synchronous), the FP64 reference of the FP32 L1 error, the
-                 committed DRAM counters of the batched kernels and the plain path
-                 launched per instance
+                 the tuned mode (the fused tiles of K steps over every instance in
+                 ONE persistent launch for the run, replayed from a captured graph);
+                 beside it the other forms (the same tiles as two launches per K
+                 steps, the persistent dataflow and step-synchronous modes), the
+                 FP64 reference of the FP32 L1 error, the committed DRAM counters of
+                 the batched kernels and the plain path launched per instance
   forms.adjoint  2D 1024^2 gradient rollout (T = 500, checkpoints every 23 steps)
   roofline       the dominant kernel (the FP64 launches of the timed region's most
                  frequent steps per launch) against its binding roof -- FP64 VALU issue or HBM, named
@@ -233,11 +233,12 @@ def _time_batch(torch, insts, storage, steps, tune):
 
 
 def time_batched(torch, steps=1000, tuned_only=False, direct=False, mode=-1):
-    """The 256-instance manifest (FP32 storage): the tuned mode (fused launches of K
-    steps over every instance), the three persistent single-launch modes
-    (dataflow, step-synchronous, and the fused tiles with a grid barrier per K-step
-    pass), the same manifest with FP64 storage (the reference of the FP32 L1 error,
-    same steps and mode), and the plain path per instance."""
+    """The 256-instance manifest (FP32 storage): the tuned mode (the fused tiles of K
+    steps over every instance, in one persistent launch for the whole run with a
+    grid-wide close per K-step pass, or two launches per K steps), the other modes
+    beside it (the persistent dataflow and step-synchronous modes, and the fused
+    mode's other form), the same manifest with FP64 storage (the reference of the
+    FP32 L1 error, same steps and mode), and the plain path per instance."""
     from paper_1401_0427_amd.lbm import Solver
 
     insts = _manifest_instances()
@@ -269,11 +270,17 @@ def time_batched(torch, steps=1000, tuned_only=False, direct=False, mode=-1):
     out["l1_rel_h_vs_fp64"] = float((h32 - h64).abs().sum() / h64.abs().sum())
     out["l1_ok"] = out["l1_rel_h_vs_fp64"] <= 1e-5
     del h64
-    # the persistent forms: every step of every instance in ONE kernel launch
+    # the persistent forms (every step of every instance in ONE kernel launch) not
+    # tuned, and the fused tiles' other form
+    fk = tune.get("fuse_steps") or 8
+    others = [("dataflow", dict(mode=0, block=512, tile_nodes=32768, pass_nodes=1)),
+              ("step_synchronous", dict(mode=1, block=256))]
+    if tune.get("mode") == 4:
+        others.append(("fused_launch_pairs", dict(mode=3, fuse_steps=fk)))
+    else:
+        others.append(("fused_passes", dict(mode=4, fuse_steps=fk)))
     pers = {}
-    for name, t in (("dataflow", dict(mode=0, block=512, tile_nodes=32768, pass_nodes=1)),
-                    ("step_synchronous", dict(mode=1, block=256)),
-                    ("fused_passes", dict(mode=4, fuse_steps=tune.get("fuse_steps") or 8))):
+    for name, t in others:
         log(f"[bench] batched persistent {name}")
         pms, pnt, pgrid, ph, _ = _time_batch(torch, insts, "f32", steps, t)
         pers[name] = dict(ms_per_step=pms / steps, mlups=nodes * steps / (pms * 1e-3) / 1e6,

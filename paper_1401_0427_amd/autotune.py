@@ -172,6 +172,9 @@ def main():
     ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--skip-forward", action="store_true")
     ap.add_argument("--skip-batch", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=0,
+                    help="steps per timed batch run (0: --steps); the manifest runs 1000")
+    ap.add_argument("--modes", default="0,2,3,4", help="batch modes to sweep")
     args = ap.parse_args()
 
     def log(s):
@@ -191,7 +194,8 @@ def main():
         out["forward"] = fw
         out["sweeps"] = sweeps
     if not args.skip_batch:
-        best, rows = tune_batch(steps=args.steps, log=log)
+        modes = tuple(int(m) for m in args.modes.split(","))
+        best, rows = tune_batch(steps=args.batch_steps or args.steps, modes=modes, log=log)
         out["batch"] = {k: best[k] for k in ("mode", "block", "tile_nodes", "grid", "pass_nodes")}
         if best.get("fuse_steps"):
             out["batch"]["fuse_steps"] = best["fuse_steps"]
