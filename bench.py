@@ -440,7 +440,7 @@ def kernel_kind(form):
 
 
 def _summary(kind, which, n, K):
-    """A committed rocprofv3 summary (JSON) of the FP64 step kernel -- ``which`` 1
+    """A committed rocprofv3 summary (JSON) of the step kernel (both storages) -- ``which`` 1
     = traffic, 2 = SQ instruction counters -- if it was taken for this grid,
     launch depth and the current kernel source; else None."""
     prof = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
@@ -459,28 +459,35 @@ def _summary(kind, which, n, K):
     return None
 
 
-def _measured_traffic(n, kind, K):
-    """HBM bytes per launch of the FP64 step kernel (FETCH_SIZE + WRITE_SIZE, each
-    scaled by what the counter reads for a plain copy of known size)."""
+def _measured_traffic(n, kind, K, storage="f64"):
+    """HBM bytes per launch of the step kernel of the given storage (FETCH_SIZE +
+    WRITE_SIZE, each scaled by what the counter reads for a plain copy of known
+    size)."""
     d = _summary(kind, 1, n, K)
-    return None if d is None else d.get("traffic_bytes_per_launch_f64")
+    if d is None:
+        return None
+    if storage == "f64":
+        return d.get("traffic_bytes_per_launch_f64")
+    e = d.get(storage)
+    return None if e is None else e["read_bytes"] + e["write_bytes"]
 
 
-def roofline(f64, n, kind):
-    """Roofline object of the dominant kernel (the FP64 launches of the timed
-    region's most frequent depth K).  Both roofs are computed from the live launch time; the bound
-    named is the one the kernel uses more of: the FP64 VALU issue (busy fraction
-    from the committed SQ counter summary) or HBM (DRAM bytes from the committed
-    traffic summary, else the algorithmic bytes)."""
-    K = f64["dominant_steps"]
-    ms_launch = f64["ms_per_launch"]
+def roofline(form, n, kind, storage="f64"):
+    """Roofline object of the dominant kernel (the launches of the timed region's
+    most frequent depth K, in the storage that was timed).  Both roofs are computed
+    from the live launch time; the bound named is the one the kernel uses more of:
+    the FP64 VALU issue (busy fraction from the committed SQ counter summary; FP32
+    storage computes in FP64 too) or HBM (DRAM bytes from the committed traffic
+    summary, else the algorithmic bytes)."""
+    K = form["dominant_steps"]
+    ms_launch = form["ms_per_launch"]
     nodes = n * n
-    alg_bytes = nodes * f64["bytes_per_lu"]
+    alg_bytes = nodes * form["bytes_per_lu"]
     hbm_gbs = alg_bytes / (ms_launch * 1e-3) / 1e9
     tflops = ALG_FLOPS_2D * nodes * K / (ms_launch * 1e-3) / 1e12
-    traffic = _measured_traffic(n, kind, K)
+    traffic = _measured_traffic(n, kind, K, storage)
     sq = _summary(kind, 2, n, K)
-    valu_busy = sq["f64"]["valu_busy"] if sq else None
+    valu_busy = sq[storage]["valu_busy"] if sq and storage in sq else None
     dram_frac = (traffic if traffic else alg_bytes) / (ms_launch * 1e-3) / 1e9 / HBM_PEAK_GBS
     if valu_busy is not None:
         bound = "alu" if valu_busy > dram_frac else "hbm"
@@ -494,8 +501,9 @@ def roofline(f64, n, kind):
     main = alu if bound == "alu" else hbm
     return {"bound": bound, "achieved": main["achieved"], "peak": main["peak"],
             "unit": main["unit"], "frac": main["frac"], "traffic": traffic,
-            "kernel": KERNELS[kind][3].format(K=K), "steps_per_launch": K,
-            "launches_timed": f64["full_launches"], "ms_per_launch": round(ms_launch, 5),
+            "kernel": KERNELS[kind][3].format(K=K).replace(
+                "<double", "<double" if storage == "f64" else "<float"), "steps_per_launch": K,
+            "launches_timed": form["full_launches"], "ms_per_launch": round(ms_launch, 5),
             "bytes_per_launch": alg_bytes, "hbm": hbm, "alu": alu,
             "valu_busy": valu_busy, "dram_frac": round(dram_frac, 4),
             "per_step_equivalent_gbs": round(hbm_gbs * K, 1)}
@@ -700,7 +708,9 @@ def main():
             forms[a]["l1_ok"] = e <= 1e-5
     for f in forms.values():
         f.pop("h", None)
-    f64 = forms.get("fp64") or forms["fp32"]
+    # the headline form: FP64 storage, else (``--storage f32``) FP32 storage
+    head_storage = "f64" if "fp64" in forms else "f32"
+    f64 = forms["fp" + head_storage[1:]]
     if not args.quick and not args.no_batched:
         log("[bench] batched 256 instances x 1000 steps")
         forms["batched"] = time_batched(torch, steps=args.batched_steps,
@@ -710,7 +720,7 @@ def main():
         log("[bench] adjoint rollout 1024^2 x 500")
         forms["adjoint"] = time_adjoint(torch)
     kind = kernel_kind(f64)
-    roof = roofline(f64, n, kind)
+    roof = roofline(f64, n, kind, head_storage)
     cpu = None
     if not args.quick and not args.no_cpu:
         log("[bench] CPU oracle baseline")
@@ -729,7 +739,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"2D shallow-water radial dam break, D2Q4 x3, {n}x{n} periodic, "
-                               f"lambda=6, s=1.8, FP64 storage",
+                               f"lambda=6, s=1.8, {head_storage.upper()} storage",
                    "nodes": n * n, "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -111,6 +111,27 @@ def test_roofline_bound_follows_the_counters(monkeypatch):
     assert r["bound"] == "alu" and r["unit"] == "TFLOP/s" and r["valu_busy"] == 0.9
 
 
+def test_roofline_of_fp32_storage_uses_the_fp32_counters(monkeypatch):
+    """With only FP32 storage timed (``--storage f32``) the roofline takes the FP32
+    kernel's bytes, DRAM traffic and VALU busy fraction, and names the float kernel."""
+    def fake(kind, which, n, K):
+        if which == 1:
+            return {"traffic_bytes_per_launch_f64": 3.6e9,
+                    "f32": {"read_bytes": 1.0e9, "write_bytes": 0.8e9}}
+        return {"f64": {"valu_busy": 0.7}, "f32": {"valu_busy": 0.85}}
+
+    monkeypatch.setattr(bench, "_summary", fake)
+    f = dict(_form(8, 250, 250, 0.5), bytes_per_lu=96)
+    r = bench.roofline(f, 4096, "wave_strip", "f32")
+    assert r["bytes_per_launch"] == 4096 * 4096 * 96
+    assert r["traffic"] == pytest.approx(1.8e9)
+    # 1.8e9 B in 0.5 ms = 3.6 TB/s = 0.45 of the peak, below 0.85 VALU busy
+    assert r["dram_frac"] == pytest.approx(0.45, rel=1e-4) and r["valu_busy"] == 0.85
+    assert r["bound"] == "alu" and "<float, 8>" in r["kernel"]
+    r64 = bench.roofline(_form(8, 250, 250, 0.5), 4096, "wave_strip")
+    assert r64["traffic"] == 3.6e9 and r64["valu_busy"] == 0.7 and "<double, 8>" in r64["kernel"]
+
+
 def test_batched_counter_summary_is_self_consistent_and_keyed_to_the_sources():
     """The batched kernels' DRAM summary: bytes = counter x 1024 / copy-probe scale,
     compulsory bytes = every instance's state read and written once per pass (FP32:

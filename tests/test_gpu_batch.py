@@ -46,8 +46,8 @@ def oracle_moments(d, steps):
     return oracle.moments(P, f)
 
 
-TUNES = [dict(block=256, tile_nodes=256), dict(block=64, tile_nodes=100),
-         dict(block=512, tile_nodes=4096, grid=7),
+TUNES = [dict(block=256, tile_nodes=256, mode=0), dict(block=64, tile_nodes=100, mode=0),
+         dict(block=512, tile_nodes=4096, grid=7, mode=0),
          dict(block=256, mode=1),
          dict(block=64, mode=1, grid=5),
          dict(block=512, mode=1),
