@@ -35,13 +35,17 @@ namespace lbm {
 // instead of cross-lane permutes into registers; 0 levels = off.  At K = 8 this
 // takes the kernel from 332 registers (one wavefront per SIMD) to 231 (two):
 // 171 vs 157 GLUPS at 4096^2 (4, 5 or 6 levels alike; 6 uses 72 KiB of LDS per
-// workgroup, two workgroups per compute unit).
+// workgroup, two workgroups per compute unit).  At K = 6 the permutes hold 256
+// registers plus spills (one wavefront per SIMD) and the LDS rows 170 (two):
+// 0.710 against 0.716 ms per 4096^2 launch; at K = 4 and 5 the permute form,
+// already at two wavefronts per SIMD, is the faster one (0.725 / 0.734 ms against
+// 0.734 / 0.747 with LDS rows at three).
 constexpr int kXkLdsLevelsF64 = 6;
 // LDS exchange levels read one level ahead, for FP32 launches of at most this
 // many steps (0: never).  Measured at 2048^2, FP32 K = 6: 159-160 GLUPS against
 // 151; FP32 K = 8 at 4096^2: 221 against 224; FP64 K = 8 unchanged (177).
 constexpr int kXkLdsPrefetchF32MaxK = 6;
-constexpr int kXkLdsMinK = 7;
+constexpr int kXkLdsMinK = 6;
 constexpr int kXkLdsLevelsF32 = 0;  // the same for FP32 launches (0 = off)
 // Output strips start and end on this many bytes (0: no alignment), and the
 // stores are non-temporal (1) or not (0), per storage type.  Measured at 4096^2:
