@@ -24,6 +24,11 @@ Beside it on the same JSON line:
                  steps, the persistent dataflow and step-synchronous modes), the
                  FP64 reference of the FP32 L1 error, the committed DRAM counters of
                  the batched kernels and the plain path launched per instance
+  forms.rest_mrt_*  the paper's rest-population schemes with one relaxation rate per
+                 non-conserved moment: D2Q5Q4Q4 on the headline grid (FP64 and FP32
+                 storage, one step per launch, with the FP32 L1 error of h) and
+                 D1Q3Q2 on the 1D wall reflection
+  forms.entropy_2d_f64  the discrete entropy diagnostic of the headline state
   forms.adjoint  2D 1024^2 gradient rollout (T = 500, checkpoints every 23 steps)
   roofline       the dominant kernel (the FP64 launches of the timed region's most
                  frequent steps per launch) against its binding roof -- FP64 VALU issue or HBM, named
@@ -53,6 +58,8 @@ def _parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-1d", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-rest", action="store_true",
+                    help="skip the rest-population (MRT) and entropy forms")
     ap.add_argument("--no-faces", action="store_true",
                     help="skip the forward run with inflow / Neumann / wall faces")
     ap.add_argument("--batched-steps", type=int, default=1000,
@@ -193,6 +200,97 @@ def time_dam_break_1d(torch, reps=20):
     return dict(nodes=c.nx, steps=c.steps, ms_run=best, ms_per_step=best / c.steps,
                 mlups=c.nx * c.steps / (best * 1e-3) / 1e6,
                 launches=len(S.launch_plan(c.steps)))
+
+
+# Rest weight and moment rates of the timed rest-population runs (one rate per
+# non-conserved moment, Sec. 2 / Sec. 3): 2D (J_x, J_y, eps, XX_rho, f_xx, f_xy, XX_u,
+# f_yx, f_yy, XX_v), 1D (J_rho, eps_rho, J_q).
+REST_A = 0.05
+REST_RATES_2D = (1.7, 1.6, 1.2, 1.9, 1.5, 1.3, 1.1, 1.45, 1.55, 1.8)
+REST_RATES_1D = (1.7, 1.3, 1.9)
+
+
+def time_rest_2d(torch, n, storage, steps=200, warmup=10):
+    """D2Q5Q4Q4 with moment-space MRT (the rest-population scheme of Sec. 3) on the
+    headline radial dam break, one step per launch: 13 planes, 208 B (FP64) / 104 B
+    (FP32) of state read and written per node update, HBM-bound like the one-step
+    kernel of the hot path."""
+    from paper_1401_0427_amd import workloads as W
+    from paper_1401_0427_amd.lbm import Solver
+
+    c = W.radial_dam_break_2d(n, lam=6.0)
+    S = Solver(2, n, n, lam=c.lam, s=c.s, h0=c.h0, qx0=c.qx0, qy0=c.qy0, storage=storage,
+               rest=True, a=REST_A, rates=list(REST_RATES_2D))
+    S.step(warmup)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(st)
+    for i in range(steps):
+        S.step(1)
+        ev[i + 1].record(st)
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[-1])
+    dur = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
+    (h, _, _), tot = S.moments(totals=True)
+    bpl = 13 * 2 * (8 if storage == "f64" else 4)
+    gbs = n * n * bpl / (ms / steps * 1e-3) / 1e9
+    return dict(ms_per_step=ms / steps, median_launch_ms=dur[steps // 2],
+                mlups=n * n * steps / (ms * 1e-3) / 1e6, bytes_per_lu=bpl, gbs=gbs,
+                hbm_frac=gbs / HBM_PEAK_GBS, a=REST_A, rates=list(REST_RATES_2D),
+                finite=bool(torch.isfinite(h).all().item()), mass=tot[0], h=h.clone())
+
+
+def time_rest_1d(torch, storage="f64", steps=2000, warmup=64):
+    """D1Q3Q2 with moment-space MRT (Sec. 2) on the 1D wall reflection (2^20 nodes):
+    5 planes, 80 B (FP64) of state per node update; 40 MiB per buffer, so it runs out
+    of the MALL and the rate is an effective bandwidth."""
+    from paper_1401_0427_amd import workloads as W
+    from paper_1401_0427_amd.lbm import Solver
+
+    c = W.wall_reflection_1d()
+    S = Solver(1, c.nx, 1, lam=c.lam, s=c.s, bc=c.bc, inflow=c.inflow, h0=c.h0, qx0=c.qx0,
+               storage=storage, rest=True, a=0.1, rates=list(REST_RATES_1D))
+    S.step(warmup)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    S.step(steps)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    h = S.moments()[0]
+    bpl = 5 * 2 * (8 if storage == "f64" else 4)
+    return dict(nodes=c.nx, steps=steps, ms_per_step=ms / steps,
+                mlups=c.nx * steps / (ms * 1e-3) / 1e6,
+                effective_gbs=c.nx * bpl * steps / (ms * 1e-3) / 1e9, bytes_per_lu=bpl,
+                a=0.1, rates=list(REST_RATES_1D), finite=bool(torch.isfinite(h).all().item()))
+
+
+def time_entropy_2d(torch, n, calls=20):
+    """The discrete entropy diagnostic (Sec. 1) of the headline state after 16 steps,
+    FP64: one pass over the 12 planes (96 B per node) with per-node entropies written
+    (8 B per node) and per-block partial sums, then the FP64 totals; each call ends with
+    the host reading the totals, so a call is a kernel, a small sum and a copy."""
+    from paper_1401_0427_amd import workloads as W
+    from paper_1401_0427_amd.lbm import Solver
+
+    c = W.radial_dam_break_2d(n, lam=6.0)
+    S = Solver(2, n, n, lam=c.lam, s=c.s, h0=c.h0, qx0=c.qx0, qy0=c.qy0, storage="f64")
+    S.step(16)
+    H0, bad0 = S.entropy()
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(calls):
+        t0 = time.perf_counter()
+        H, bad, hn = S.entropy(per_node=True)
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    byt = n * n * (96 + 8)
+    return dict(ms_per_call=best * 1e3, bytes_per_call=byt, gbs=byt / best / 1e9,
+                hbm_frac=byt / best / 1e9 / HBM_PEAK_GBS, total=H, invalid=bad,
+                equals_without_per_node=bool(H == H0 and bad == bad0))
 
 
 def _manifest_instances():
@@ -716,6 +814,18 @@ def main():
         forms["batched"] = time_batched(torch, steps=args.batched_steps,
                                         tuned_only=args.batched_tuned_only,
                                         direct=args.direct_batch, mode=args.batch_mode)
+    if not args.quick and not args.no_rest:
+        for storage in ("f64", "f32"):
+            log(f"[bench] rest-population MRT 2D {n}^2 {storage.upper()}")
+            forms["rest_mrt_2d_" + storage] = time_rest_2d(torch, n, storage)
+        h64, h32 = forms["rest_mrt_2d_f64"].pop("h"), forms["rest_mrt_2d_f32"].pop("h")
+        e = float((h32 - h64).abs().sum() / h64.abs().sum())
+        forms["rest_mrt_2d_f32"]["l1_rel_h_vs_fp64"] = e
+        forms["rest_mrt_2d_f32"]["l1_ok"] = e <= 1e-5
+        log("[bench] rest-population MRT 1D 2^20 FP64")
+        forms["rest_mrt_1d_f64"] = time_rest_1d(torch)
+        log(f"[bench] entropy diagnostic {n}^2 FP64")
+        forms["entropy_2d_f64"] = time_entropy_2d(torch, n)
     if not args.quick and not args.no_adjoint:
         log("[bench] adjoint rollout 1024^2 x 500")
         forms["adjoint"] = time_adjoint(torch)

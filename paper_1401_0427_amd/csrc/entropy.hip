@@ -30,50 +30,59 @@ struct EntPop {
     int ok;
 };
 
+// cA = kappa / (4 w K) and ik = 1 / kappa are per-lattice constants (A = cA f^2).
+// Each Newton iteration takes one reciprocal of D and one quotient; the step
+// tests compare |dz| with (1 + |z|) by multiplication instead of dividing.
 __device__ __forceinline__ EntPop ent_pop(double f, double gxi, double gom, double sigma,
-                                          double w, double kappa, double K)
+                                          double cA, double kappa, double ik)
 {
     EntPop r = {0.0, 0};
     if (!(f > 0.0)) return r;
-    const double om = gom / f;
-    const double A = kappa * f * f / (4.0 * w * K);
+    const double rf = 1.0 / f;
+    const double om = gom * rf;
+    const double A = cA * (f * f);
+    const double tkA = 2.0 * kappa * A;
     const double gs = sigma * gxi;
-    const double Dc = cbrt(2.0 * kappa * A / f);
-    const double zc = (Dc - 1.0) / kappa;
+    const double Dc = cbrt(tkA * rf);
+    const double zc = (Dc - 1.0) * ik;
     // start right of the root: from max(zc, first-order guess), then outwards
-    double z = fmax(zc, (gs - A) / f);
-    double step = fmax(fabs(z), 1.0 / kappa);
+    double z = fmax(zc, (gs - A) * rf);
+    double step = fmax(fabs(z), ik);
     double S = 0.0;
-    int k = 0;
-    for (; k < 200; ++k) {
-        const double D = 1.0 + kappa * z;
-        S = z * f + A / (D * D) - gs;
+    for (int k = 0; k < 200; ++k) {
+        const double iD = 1.0 / (1.0 + kappa * z);
+        S = z * f + A * (iD * iD) - gs;
         if (S > 0.0) break;
         z += step;
         step *= 2.0;
     }
     if (!(S > 0.0)) return r;
-    double prev = 1e300;
+    // relative step |dz| / (1 + |z|) of the previous iteration, as the pair (a, b)
+    double pa = 1.0, pb = 0.0;
     int conv = 0;
     for (int it = 0; it < 100; ++it) {
-        const double D = 1.0 + kappa * z;
-        const double Sz = z * f + A / (D * D) - gs;
-        const double dS = f - 2.0 * kappa * A / (D * D * D);
+        const double iD = 1.0 / (1.0 + kappa * z);
+        const double iD2 = iD * iD;
+        const double Sz = z * f + A * iD2 - gs;
+        const double dS = f - tkA * (iD2 * iD);
         if (!(dS > 0.0)) break;
         const double dz = Sz / dS;
         z -= dz;
         if (!(z > zc)) break;  // no root with D > Dc
-        const double rel = fabs(dz) / (1.0 + fabs(z));
-        if (rel <= 1e-15 || (rel < 1e-10 && rel >= prev)) {
+        const double a = fabs(dz), b = 1.0 + fabs(z);
+        // converged: relative step <= 1e-15, or below 1e-10 and no longer shrinking
+        if (a <= 1e-15 * b || (a < 1e-10 * b && a * pb >= pa * b)) {
             conv = 1;
             break;
         }
-        prev = rel;
+        pa = a;
+        pb = b;
     }
     if (!conv) return r;
-    const double D = 1.0 + kappa * z;
-    if (!(f - 2.0 * kappa * A / (D * D * D) > 0.0)) return r;
-    r.h = A * (1.0 + 2.0 * kappa * z) / (kappa * D * D) + 0.5 * (z * z + om * om) * f;
+    const double iD = 1.0 / (1.0 + kappa * z);
+    const double iD2 = iD * iD;
+    if (!(f - tkA * (iD2 * iD) > 0.0)) return r;
+    r.h = A * (1.0 + 2.0 * kappa * z) * iD2 * ik + 0.5 * (z * z + om * om) * f;
     r.ok = 1;
     return r;
 }
@@ -113,17 +122,19 @@ __global__ void __launch_bounds__(256) k_entropy(int dim, const T *__restrict__ 
         if (dim == 1) {
             // planes f+, f-, g+, g-
             const double kappa = 1.0 / lambda;
+            const double cA = kappa / (4.0 * 0.5 * K);
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 const double f = ld(state + j * G.ps + i);
                 const double q = ld(state + (2 + j) * G.ps + i);
-                const EntPop e = ent_pop(f, q, 0.0, j == 0 ? 1.0 : -1.0, 0.5, kappa, K);
+                const EntPop e = ent_pop(f, q, 0.0, j == 0 ? 1.0 : -1.0, cA, kappa, lambda);
                 H += e.h;
                 bad += 1 - e.ok;
             }
         } else {
             // planes (h: e1..e4, qx: e1..e4, qy: e1..e4); e1 = +x, e2 = +y, e3 = -x, e4 = -y
             const double kappa = 2.0 / lambda;
+            const double cA = kappa / (4.0 * 0.25 * K);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const double f = ld(state + j * G.ps + i);
@@ -131,7 +142,7 @@ __global__ void __launch_bounds__(256) k_entropy(int dim, const T *__restrict__ 
                 const double gy = ld(state + (8 + j) * G.ps + i);
                 const bool xaxis = (j & 1) == 0;
                 const EntPop e = ent_pop(f, xaxis ? gx : gy, xaxis ? gy : gx, j < 2 ? 1.0 : -1.0,
-                                         0.25, kappa, K);
+                                         cA, kappa, 0.5 * lambda);
                 H += e.h;
                 bad += 1 - e.ok;
             }
