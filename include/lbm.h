@@ -119,8 +119,11 @@ typedef struct {
                              take 16; default 16), except a 1D domain with
                              non-periodic ends of at most 1024 nodes (one LDS
                              tile, nothing lost at its ends), which takes any up
-                             to 1024 (default 1024).  lbm_launch_info reports
-                             the choice. */
+                             to 1024 (default 1024).  D2Q5Q4Q4 (rest
+                             population, MRT) on all-periodic grids at most 6
+                             (default 5 when that launch fills a third of the
+                             device, else 1); the other rest-population grids
+                             take 1.  lbm_launch_info reports the choice. */
     void *f_a, *f_b;      /* caller-owned device state buffers (ping-pong) */
     void *stream;         /* hipStream_t; NULL = default stream */
     int adjoint_storage;  /* element type of adjoint buffers: 0 = the state's,
@@ -159,9 +162,10 @@ int lbm_current(lbm_ctx *ctx, void **state, long *steps_done);
 
 /* Launch plan chosen at init (any output may be NULL): steps per launch
  * (temporal blocking depth, see fuse_steps); rows per workgroup (LDS two-step
- * kernel) or per wavefront (wave-strip K-step kernel) segment, 0 for one-step
- * and 1D launches; and, for the wave-strip kernel, the workgroups resident on
- * the device at once, which the segment length was chosen against (0 otherwise). */
+ * kernel) or per wavefront (wave-strip K-step kernel, and the D2Q5Q4Q4 K-step
+ * kernel) segment, 0 for one-step and 1D launches; and, for those K-step
+ * kernels, the workgroups resident on the device at once, which the segment
+ * length was chosen against (0 otherwise). */
 int lbm_launch_info(lbm_ctx *ctx, int *steps_per_launch, int *segment_rows,
                     long *resident_blocks);
 

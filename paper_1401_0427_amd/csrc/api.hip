@@ -166,6 +166,8 @@ struct lbm_ctx {
     int xk_seg;     // rows per segment of the wave-strip K-step launch
     long xk_slots;  // its resident workgroups on the device
     int xk_seg_k[17];  // rows per segment of a wave-strip launch of k <= fuse steps
+    int rest_seg_k[kMaxFuseRest2d + 1];  // the same for the D2Q5Q4Q4 multi-step launch
+    long rest_slots;                     // its resident workgroups at the full depth
 };
 
 // Steps per captured graph: the smallest multiple of twice the steps per launch that is
@@ -209,6 +211,11 @@ static const int kDefaultFuse2dF32Small = 6;
 static const int kXkMinSeg = 16;
 // 2D all-periodic: steps per launch at most (wave-strip kernel: K = 2 .. 8)
 static const int kMaxFuse2d = 8;
+// D2Q5Q4Q4 on all-periodic grids: steps per launch by default (at most
+// kMaxFuseRest2d); other rest-population grids take one step per launch.
+// Measured at 4096^2 (GLUPS for K = 2 .. 6): FP64 36.6, 56.5, 69.3, 105.1, 102.9;
+// FP32 53.8, 81.9, 102.4, 124.3, 120.6 (one step per launch: 26.9 / 57.5).
+static const int kDefaultFuseRest2d = 5;
 
 extern "C" void lbm_destroy(lbm_ctx *c)
 {
@@ -298,8 +305,27 @@ extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0
         const bool allper = p->bc[0] == LBM_BC_PERIODIC && p->bc[1] == LBM_BC_PERIODIC &&
                             p->bc[2] == LBM_BC_PERIODIC && p->bc[3] == LBM_BC_PERIODIC;
         int want = p->fuse_steps;
-        c->x2 = allper;  // two steps per launch: the LDS strip kernel (faster at K = 2)
-        if (rest)
+        c->x2 = allper && !rest;  // two steps per launch: the LDS strip kernel (K = 2)
+        c->rest_slots = 0;
+        for (int k = 0; k <= kMaxFuseRest2d; ++k) c->rest_seg_k[k] = 0;
+        if (rest && dim == 2 && allper) {
+            // D2Q5Q4Q4: the multi-step launch at the depth asked for (at most
+            // kMaxFuseRest2d), by default kDefaultFuseRest2d when its launch fills a
+            // third of the device's resident workgroups, else one step per launch
+            int k = want ? (want > kMaxFuseRest2d ? kMaxFuseRest2d : want) : kDefaultFuseRest2d;
+            long slots = 0;
+            const int seg = k >= 2 ? rest2k_seg(c->G, c->f32, k, &slots) : 0;
+            if (k >= 2 && seg > 0 && (want || 3 * rest2k_blocks(c->G, k, seg) >= slots)) {
+                c->fuse = k;
+                c->rest_slots = slots;
+                for (int kk = 2; kk <= k; ++kk) {
+                    const int sk = kk == k ? seg : rest2k_seg(c->G, c->f32, kk, nullptr);
+                    c->rest_seg_k[kk] = sk > 0 ? sk : seg;
+                }
+            } else {
+                c->fuse = 1;
+            }
+        } else if (rest)
             c->fuse = 1;
         else if (dim == 1 && step1k_whole(c->G))
             c->fuse = want ? want : kFuse1dWhole;
@@ -422,6 +448,7 @@ static hipError_t step_once(lbm_ctx *c, const void *src, void *dst, hipStream_t 
 static hipError_t step_k(lbm_ctx *c, int k, const void *src, void *dst, hipStream_t st)
 {
     if (k == 1) return step_once(c, src, dst, st);
+    if (c->rest) return launch_step_rest2k(c->f32, src, dst, c->G, c->M, k, c->rest_seg_k[k], st);
     if (c->dim == 2) {
         if (c->x2 && k == 2)
             return launch_step2x(c->f32, src, dst, c->G, c->P, kFuseSeg, st);
@@ -620,6 +647,11 @@ extern "C" int lbm_launch_info(lbm_ctx *c, int *steps_per_launch, int *segment_r
     if (rc) return rc;
     const bool xk = c->dim == 2 && c->fuse >= 2 && !(c->x2 && c->fuse == 2);
     if (steps_per_launch) *steps_per_launch = c->fuse;
+    if (c->rest) {
+        if (segment_rows) *segment_rows = c->fuse >= 2 ? c->rest_seg_k[c->fuse] : 0;
+        if (resident_blocks) *resident_blocks = c->rest_slots;
+        return LBM_OK;
+    }
     if (segment_rows) *segment_rows = xk ? c->xk_seg : (c->fuse == 2 ? kFuseSeg : 0);
     if (resident_blocks) *resident_blocks = xk ? c->xk_slots : 0;
     return LBM_OK;

@@ -21,6 +21,7 @@
 //   f_xy^eq = f_yx^eq = rho u v, f_yy^eq = rho v^2 + p.
 // Plane order: rest population first, then the a = 0 order.
 #include "internal.h"
+#include "xk_wave.h"
 
 namespace lbm {
 
@@ -272,6 +273,188 @@ __global__ void __launch_bounds__(256) k_step_rest1d(const T *__restrict__ src, 
     collide_mrt1d(f, M);
 #pragma unroll
     for (int pl = 0; pl < 5; ++pl) sth<2>(dst + pl * ps + x, f[pl]);
+}
+
+// ---- D2Q5Q4Q4, K steps per launch on all-periodic grids ----------------------------
+// One wavefront per column strip of 64 lanes (lane l at column x0 - (K - 1) + l,
+// wrapped), walking down a segment of rows.  Iteration j computes level 1 of row
+// i = y0 - (K - 1) + j from the level-n pulls of that row (loaded one iteration
+// ahead), then level k + 1 of row i - k from level k for k = 1 .. K - 1, so the
+// levels are skewed one row apart and only level K leaves the wavefront (row
+// i - (K - 1), stored when it lies in the segment).  Level k + 1 of row r pulls
+// from level k: e1 / e3 of row r from lanes l - 1 / l + 1 (cross-lane, kept from
+// the previous iteration), e2 of row r - 1 (kept two iterations, two arrays used
+// alternately), e4 of row r + 1 (just computed), and the rest population of row r
+// (kept one iteration).  Every level is rounded to the storage type, as the
+// one-step kernel's store and load round it, and the collision is the same
+// function, so the result equals K single steps bit for bit.  The K - 1 lanes at
+// each strip edge and the first 2 (K - 1) iterations take values from outside the
+// valid range and are not stored.
+template <typename T, int K>
+__device__ __forceinline__ void rest2k_load(const T *__restrict__ src, long ps, int nx, int ny,
+                                            int r, int xm, int xw, int xp, T (&b)[13])
+{
+    const long row = (long)r * nx;
+    const long rm = r == 0 ? (long)(ny - 1) * nx : row - nx;
+    const long rp = r == ny - 1 ? 0 : row + nx;
+    b[0] = src[row + xw];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const T *q = src + (1 + 4 * c) * ps;
+        b[1 + 4 * c] = q[row + xm];
+        b[2 + 4 * c] = q[ps + rm + xw];
+        b[3 + 4 * c] = q[2 * ps + row + xp];
+        b[4 + 4 * c] = q[3 * ps + rp + xw];
+    }
+}
+
+template <typename T, int K>
+__global__ void __launch_bounds__(256) k_step_rest2d_k(const T *__restrict__ src,
+                                                       T *__restrict__ dst, Geo G, Mrt M,
+                                                       int nsb, int seg)
+{
+    constexpr int H = K - 1, WO = 64 - 2 * H;
+    const int nx = G.nx, ny = G.ny;
+    const long ps = G.ps;
+    const int lane = threadIdx.x & 63;
+    const int strip = (blockIdx.x % nsb) * 4 + (int)(threadIdx.x >> 6);
+    const int y0 = (blockIdx.x / nsb) * seg;
+    if (strip * WO >= nx || y0 >= ny) return;  // whole wavefronts only
+    const int y1 = y0 + seg < ny ? y0 + seg : ny;
+    const int xc = strip * WO - H + lane;
+    const int xw = ((xc % nx) + nx) % nx;
+    const int xm = xw == 0 ? nx - 1 : xw - 1, xp = xw == nx - 1 ? 0 : xw + 1;
+    const bool olane = lane >= H && lane < H + WO && xc < nx;
+    T e2[2][K - 1][3], s1[K - 1][3], s3[K - 1][3], r0[K - 1];
+#pragma unroll
+    for (int k = 0; k < K - 1; ++k) {
+        r0[k] = (T)0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) e2[0][k][c] = e2[1][k][c] = s1[k][c] = s3[k][c] = (T)0;
+    }
+    const int niter = (y1 - y0) + 2 * H;
+    int rl = (((y0 - H) % ny) + ny) % ny;  // level-1 row of the last load, wrapped
+    T buf[2][13];
+    rest2k_load<T, K>(src, ps, nx, ny, rl, xm, xw, xp, buf[0]);
+    for (int j = 0; j < niter; j += 2) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int orow = y0 - 2 * H + j + u;
+            rl = rl == ny - 1 ? 0 : rl + 1;
+            rest2k_load<T, K>(src, ps, nx, ny, rl, xm, xw, xp, buf[1 - u]);
+            double v[13];
+#pragma unroll
+            for (int pl = 0; pl < 13; ++pl) v[pl] = (double)buf[u][pl];
+            collide_mrt2d(v, M);  // level 1
+#pragma unroll
+            for (int k = 1; k < K; ++k) {
+#pragma unroll
+                for (int pl = 0; pl < 13; ++pl) v[pl] = (double)(T)v[pl];
+                double o[13];
+                o[0] = (double)r0[k - 1];
+                r0[k - 1] = (T)v[0];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int b = 1 + 4 * c;
+                    o[b + 0] = (double)s1[k - 1][c];
+                    o[b + 1] = (double)e2[u][k - 1][c];
+                    o[b + 2] = (double)s3[k - 1][c];
+                    o[b + 3] = v[b + 3];
+                    e2[u][k - 1][c] = (T)v[b + 1];
+                    s1[k - 1][c] = xk_xch((T)v[b + 0], lane, 1);
+                    s3[k - 1][c] = xk_xch((T)v[b + 2], lane, -1);
+                }
+                collide_mrt2d(o, M);
+#pragma unroll
+                for (int pl = 0; pl < 13; ++pl) v[pl] = o[pl];
+            }
+            if (olane && orow >= y0 && orow < y1) {
+                T *q = dst + (long)orow * nx + xc;
+#pragma unroll
+                for (int pl = 0; pl < 13; ++pl) sth<2>(q + pl * ps, v[pl]);
+            }
+        }
+    }
+}
+
+template <typename T, int K>
+static int rest2k_resident()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_rest2d_k<T, K>, 256, 0) !=
+        hipSuccess)
+        return 0;
+    return nb;
+}
+
+int rest2k_seg(const Geo &G, bool f32, int K, long *slots_out)
+{
+    int dev = 0, ncu = 0, per = 0;
+    if (slots_out) *slots_out = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    switch (K) {
+#define LBM_REST_OCC(KK) \
+    case KK: per = f32 ? rest2k_resident<float, KK>() : rest2k_resident<double, KK>(); break;
+        LBM_REST_OCC(2) LBM_REST_OCC(3) LBM_REST_OCC(4) LBM_REST_OCC(5) LBM_REST_OCC(6)
+#undef LBM_REST_OCC
+    default: return 0;
+    }
+    const long slots = (long)ncu * per;
+    if (slots_out) *slots_out = slots;
+    if (slots <= 0) return 0;
+    const int WO = 64 - 2 * (K - 1);
+    const long ngroups = ((G.nx + WO - 1) / WO + 3) / 4;
+    // segment length of the fewest rows computed per wavefront over whole rounds of
+    // resident workgroups (halo rows: 2 (K - 1) per segment)
+    int best = 0;
+    double best_cost = 0.0;
+    for (int nseg = 1; nseg <= G.ny; ++nseg) {
+        const int sg = (G.ny + nseg - 1) / nseg;
+        if (sg < kRestMinSeg && nseg > 1) break;  // short grids: one segment
+        if ((G.ny + sg - 1) / sg != nseg) continue;
+        const long blocks = ngroups * nseg;
+        const long rounds = (blocks + slots - 1) / slots;
+        double cost = (double)rounds * (sg + 2 * (K - 1));
+        if (blocks < slots) cost *= (double)slots / (double)blocks;
+        if (best == 0 || cost < best_cost) {
+            best = sg;
+            best_cost = cost;
+        }
+    }
+    return best;
+}
+
+long rest2k_blocks(const Geo &G, int K, int seg)
+{
+    const int WO = 64 - 2 * (K - 1);
+    return (long)(((G.nx + WO - 1) / WO + 3) / 4) * ((G.ny + seg - 1) / seg);
+}
+
+hipError_t launch_step_rest2k(bool f32, const void *src, void *dst, const Geo &G, const Mrt &M,
+                              int K, int seg, hipStream_t st)
+{
+    if (seg <= 0) return hipErrorInvalidValue;
+    const int WO = 64 - 2 * (K - 1);
+    const int nsb = ((G.nx + WO - 1) / WO + 3) / 4;
+    const dim3 grid((unsigned)rest2k_blocks(G, K, seg)), block(256);
+    switch (K) {
+#define LBM_REST_K(KK)                                                                       \
+    case KK:                                                                                 \
+        if (f32)                                                                             \
+            hipLaunchKernelGGL((k_step_rest2d_k<float, KK>), grid, block, 0, st,            \
+                               (const float *)src, (float *)dst, G, M, nsb, seg);            \
+        else                                                                                 \
+            hipLaunchKernelGGL((k_step_rest2d_k<double, KK>), grid, block, 0, st,           \
+                               (const double *)src, (double *)dst, G, M, nsb, seg);          \
+        break;
+        LBM_REST_K(2) LBM_REST_K(3) LBM_REST_K(4) LBM_REST_K(5) LBM_REST_K(6)
+#undef LBM_REST_K
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 // f*(0) = C(f^eq(W0)) with the same checks as the a = 0 initialisation.
