@@ -27,7 +27,8 @@ Beside it on the same JSON line:
   forms.rest_mrt_*  the paper's rest-population schemes with one relaxation rate per
                  non-conserved moment: D2Q5Q4Q4 on the headline grid (FP64 and FP32
                  storage, several steps per launch, the FP32 L1 error of h; FP64 one
-                 step per launch beside it) and D1Q3Q2 on the 1D wall reflection
+                 step per launch beside it), D1Q3Q2 on the 1D wall reflection (16
+                 steps per launch; one step beside it) and on the Sec. 2 setup
   forms.entropy_2d_f64  the discrete entropy diagnostic of the headline state
   forms.adjoint  2D 1024^2 gradient rollout (T = 500, checkpoints every 23 steps)
   roofline       the dominant kernel (the FP64 launches of the timed region's most
@@ -253,16 +254,18 @@ def time_rest_2d(torch, n, storage, steps=200, warmup=10, fuse=0):
                 h_copy_consistent=copy_ok)
 
 
-def time_rest_1d(torch, storage="f64", steps=2000, warmup=64):
+def time_rest_1d(torch, storage="f64", steps=2000, warmup=64, fuse=0):
     """D1Q3Q2 with moment-space MRT (Sec. 2) on the 1D wall reflection (2^20 nodes):
     5 planes, 80 B (FP64) of state per node update; 40 MiB per buffer, so it runs out
-    of the MALL and the rate is an effective bandwidth."""
+    of the MALL and the rate is an effective bandwidth.  ``fuse`` = steps per launch
+    (0 = library default, 16 here)."""
     from paper_1401_0427_amd import workloads as W
     from paper_1401_0427_amd.lbm import Solver
 
     c = W.wall_reflection_1d()
     S = Solver(1, c.nx, 1, lam=c.lam, s=c.s, bc=c.bc, inflow=c.inflow, h0=c.h0, qx0=c.qx0,
-               storage=storage, rest=True, a=0.1, rates=list(REST_RATES_1D))
+               storage=storage, rest=True, a=0.1, rates=list(REST_RATES_1D), fuse_steps=fuse)
+    K = S.launch_info()["steps_per_launch"]
     S.step(warmup)
     torch.cuda.synchronize()
     st = torch.cuda.current_stream()
@@ -274,10 +277,42 @@ def time_rest_1d(torch, storage="f64", steps=2000, warmup=64):
     ms = e0.elapsed_time(e1)
     h = S.moments()[0]
     bpl = 5 * 2 * (8 if storage == "f64" else 4)
-    return dict(nodes=c.nx, steps=steps, ms_per_step=ms / steps,
+    return dict(nodes=c.nx, steps=steps, steps_per_launch=K, ms_per_step=ms / steps,
                 mlups=c.nx * steps / (ms * 1e-3) / 1e6,
                 effective_gbs=c.nx * bpl * steps / (ms * 1e-3) / 1e9, bytes_per_lu=bpl,
                 a=0.1, rates=list(REST_RATES_1D), finite=bool(torch.isfinite(h).all().item()))
+
+
+def time_fig1_rest_1d(torch, reps=20):
+    """The Sec. 2 experiment with the rest population: D1Q3Q2, 80 points, a = 0.15,
+    lambda = 8, s = 1.8 on every moment, Neumann ends, 96 steps (the end time is not
+    stated; 96 steps of dt = dx / lambda reach t = 0.15), FP64; the whole run timed
+    from its initial state ``reps`` times (one launch: the domain fits one tile)."""
+    import numpy as np
+    from paper_1401_0427_amd import workloads as W
+    from paper_1401_0427_amd.lbm import Solver
+
+    n, steps = 80, 96
+    x = W.cell_centres(n)
+    S = Solver(1, n, 1, lam=8.0, s=1.8, bc=("neumann", "neumann", "periodic", "periodic"),
+               h0=np.where(x < 0.5, 2.0, 0.5), qx0=np.zeros(n), storage="f64", rest=True,
+               a=0.15, rates=[1.8, 1.8, 1.8])
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    init = S.current()[0].clone()
+    S.step(steps)  # untimed: first launches
+    best = None
+    for _ in range(reps):
+        S.import_(init)
+        torch.cuda.synchronize()
+        e0.record(st)
+        S.step(steps)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    return dict(nodes=n, steps=steps, ms_run=best, ms_per_step=best / steps,
+                mlups=n * steps / (best * 1e-3) / 1e6, launches=len(S.launch_plan(steps)))
 
 
 def time_entropy_2d(torch, n, calls=20):
@@ -846,6 +881,10 @@ def main():
             forms["rest_mrt_2d_f32"]["l1_ok"] = None
         log("[bench] rest-population MRT 1D 2^20 FP64")
         forms["rest_mrt_1d_f64"] = time_rest_1d(torch)
+        log("[bench] rest-population MRT 1D 2^20 FP64, one step per launch")
+        forms["rest_mrt_1d_f64_one_step_per_launch"] = time_rest_1d(torch, fuse=1)
+        log("[bench] D1Q3Q2 Sec. 2 setup (80 points, 96 steps)")
+        forms["rest_mrt_fig1_1d"] = time_fig1_rest_1d(torch)
         log(f"[bench] entropy diagnostic {n}^2 FP64")
         forms["entropy_2d_f64"] = time_entropy_2d(torch, n)
     if not args.quick and not args.no_adjoint:

@@ -122,8 +122,8 @@ typedef struct {
                              to 1024 (default 1024).  D2Q5Q4Q4 (rest
                              population, MRT) on all-periodic grids at most 6
                              (default 5 when that launch fills a third of the
-                             device, else 1); the other rest-population grids
-                             take 1.  lbm_launch_info reports the choice. */
+                             device, else 1), with faces 1; D1Q3Q2 as the 1D
+                             grids above.  lbm_launch_info reports the choice. */
     void *f_a, *f_b;      /* caller-owned device state buffers (ping-pong) */
     void *stream;         /* hipStream_t; NULL = default stream */
     int adjoint_storage;  /* element type of adjoint buffers: 0 = the state's,

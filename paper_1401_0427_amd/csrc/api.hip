@@ -325,9 +325,9 @@ extern "C" int lbm_init(const lbm_params *p, const double *h0, const double *qx0
             } else {
                 c->fuse = 1;
             }
-        } else if (rest)
+        } else if (rest && dim == 2)
             c->fuse = 1;
-        else if (dim == 1 && step1k_whole(c->G))
+        else if (dim == 1 && step1k_whole(c->G))  // D1Q2x2 and D1Q3Q2 alike
             c->fuse = want ? want : kFuse1dWhole;
         else if (dim == 1)
             c->fuse = want ? (want > kMaxFuse1d ? kMaxFuse1d : want) : kDefaultFuse1d;
@@ -448,7 +448,10 @@ static hipError_t step_once(lbm_ctx *c, const void *src, void *dst, hipStream_t 
 static hipError_t step_k(lbm_ctx *c, int k, const void *src, void *dst, hipStream_t st)
 {
     if (k == 1) return step_once(c, src, dst, st);
-    if (c->rest) return launch_step_rest2k(c->f32, src, dst, c->G, c->M, k, c->rest_seg_k[k], st);
+    if (c->rest)
+        return c->dim == 1
+                   ? launch_step_rest1k(c->f32, src, dst, c->G, c->M, k, st)
+                   : launch_step_rest2k(c->f32, src, dst, c->G, c->M, k, c->rest_seg_k[k], st);
     if (c->dim == 2) {
         if (c->x2 && k == 2)
             return launch_step2x(c->f32, src, dst, c->G, c->P, kFuseSeg, st);

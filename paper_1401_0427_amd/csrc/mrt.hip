@@ -377,6 +377,113 @@ __global__ void __launch_bounds__(256) k_step_rest2d_k(const T *__restrict__ src
     }
 }
 
+// ---- D1Q3Q2, K steps per launch ------------------------------------------------------
+// A workgroup of kK1Threads threads holds a tile of consecutive nodes, one per thread,
+// and advances it K steps with one barrier per step: the four moving planes go
+// through LDS (double-buffered), the rest population stays in the thread.  The tile
+// starts K nodes before its output nodes (each step invalidates one more node at
+// each tile edge), or, for a domain with non-periodic ends that fits one tile
+// (step1k_whole), covers the whole domain, whose ends apply the face rules, for any
+// K.  Faces as in the one-step kernel: Neumann takes the node's own value of the
+// plane, a wall its own opposite plane (momentum negated), an inflow face the
+// equilibrium of its state; levels rounded to the storage type, so a launch equals K
+// single steps bit for bit.
+__device__ __forceinline__ double rest1k_face(const Geo &G, int pl, int face, const double *own,
+                                              const double *weq)
+{
+    switch (G.bc[face]) {
+    case BC_NEUMANN:
+        return own[pl];
+    case BC_WALL: {
+        const int opp = pl == 1 ? 2 : pl == 2 ? 1 : pl == 3 ? 4 : 3;
+        const double v = own[opp];
+        return pl >= 3 ? -v : v;
+    }
+    default:  // BC_INFLOW
+        return weq[face * 5 + pl];
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kK1Threads)
+    k_step_rest1d_k(const T *__restrict__ src, T *__restrict__ dst, Geo G, Mrt M, int K,
+                    int nout, int whole)
+{
+    constexpr int NT = kK1Threads;
+    __shared__ T sh[2][4][NT];
+    const int t = threadIdx.x;
+    const int nx = G.nx;
+    const long ps = G.ps;
+    const int ob = (int)blockIdx.x * nout;
+    const int x0 = whole ? 0 : ob - K;
+    const bool per = G.bc[0] == BC_PERIODIC;  // the two 1D faces are periodic together
+    const int oe = min(ob + nout, nx);         // output nodes [ob, oe)
+    const int x = x0 + t;                      // this thread's node, unwrapped
+    const bool in = per || (x >= 0 && x < nx);
+    const int xw = per ? ((x % nx) + nx) % nx : x;
+    const int tl = t > 0 ? t - 1 : t;  // clamped neighbours (edge values are invalid anyway)
+    const int tr = t < NT - 1 ? t + 1 : t;
+    double weq[10];
+#pragma unroll
+    for (int face = 0; face < 2; ++face)
+        if (G.bc[face] == BC_INFLOW) feq_rest1d(G.win[face][0], G.win[face][1], M, weq + 5 * face);
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (in) {
+#pragma unroll
+        for (int pl = 0; pl < 5; ++pl) v[pl] = ld(src + pl * ps + xw);
+    }
+#pragma unroll
+    for (int pl = 1; pl < 5; ++pl) sh[0][pl - 1][t] = (T)v[pl];
+    __syncthreads();
+    int b = 0;
+    for (int k = 0; k < K; ++k) {
+        double f[5];
+        f[0] = v[0];
+        // f+ and g+ (planes 1, 3) from x - 1, f- and g- (planes 2, 4) from x + 1
+        if (!per && x == 0) {
+            f[1] = rest1k_face(G, 1, 0, v, weq);
+            f[3] = rest1k_face(G, 3, 0, v, weq);
+        } else {
+            f[1] = (double)sh[b][0][tl];
+            f[3] = (double)sh[b][2][tl];
+        }
+        if (!per && x == nx - 1) {
+            f[2] = rest1k_face(G, 2, 1, v, weq);
+            f[4] = rest1k_face(G, 4, 1, v, weq);
+        } else {
+            f[2] = (double)sh[b][1][tr];
+            f[4] = (double)sh[b][3][tr];
+        }
+        collide_mrt1d(f, M);
+        b ^= 1;
+#pragma unroll
+        for (int pl = 0; pl < 5; ++pl) v[pl] = (double)(T)f[pl];
+#pragma unroll
+        for (int pl = 1; pl < 5; ++pl) sh[b][pl - 1][t] = (T)v[pl];
+        __syncthreads();
+    }
+    if (in && x >= ob && x < oe) {
+#pragma unroll
+        for (int pl = 0; pl < 5; ++pl) sth<2>(dst + pl * ps + xw, v[pl]);
+    }
+}
+
+hipError_t launch_step_rest1k(bool f32, const void *src, void *dst, const Geo &G, const Mrt &M,
+                              int K, hipStream_t st)
+{
+    const int whole = step1k_whole(G) ? 1 : 0;
+    if (K < 1 || (!whole && 2 * K >= kK1Threads)) return hipErrorInvalidValue;
+    const int nout = whole ? G.nx : kK1Threads - 2 * K;
+    const int nb = whole ? 1 : (G.nx + nout - 1) / nout;
+    if (f32)
+        hipLaunchKernelGGL(k_step_rest1d_k<float>, dim3(nb), dim3(kK1Threads), 0, st,
+                           (const float *)src, (float *)dst, G, M, K, nout, whole);
+    else
+        hipLaunchKernelGGL(k_step_rest1d_k<double>, dim3(nb), dim3(kK1Threads), 0, st,
+                           (const double *)src, (double *)dst, G, M, K, nout, whole);
+    return hipGetLastError();
+}
+
 template <typename T, int K>
 static int rest2k_resident()
 {

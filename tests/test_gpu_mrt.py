@@ -179,3 +179,60 @@ def test_d2q5q4q4_default_launch_on_a_large_periodic_grid():
     walls = smooth_random_2d(1024, 1024, seed=2, lam=6.0, s=1.8,
                              bc=("wall", "wall", "periodic", "periodic"))
     assert _rest_solver(walls, "f64", 0).launch_info()["steps_per_launch"] == 1
+
+
+def _rest1d_solver(case, storage, fuse, a=0.1, rates=(1.7, 1.3, 1.9)):
+    from paper_1401_0427_amd.lbm import Solver
+
+    return Solver(1, case.nx, 1, lam=case.lam, s=case.s, g=case.g, bc=case.bc, inflow=case.inflow,
+                  h0=case.h0, qx0=case.qx0, storage=storage, rest=True, a=a, rates=list(rates),
+                  fuse_steps=fuse)
+
+
+def _riemann_1d(n, bc, inflow=None, lam=4.0):
+    x = W.cell_centres(n)
+    rng = np.random.default_rng(n)
+    h0 = np.where(x < 0.5, 1.6, 0.7) + 0.01 * rng.random(n)
+    q0 = 0.1 * np.sin(2 * np.pi * x)
+    return W.Case(1, n, 1, lam, 1.7, 0, bc=bc, inflow=inflow or {}, h0=h0, qx0=q0)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("n,bc,inflow,ks", [
+    (3000, ("periodic",) * 4, None, (2, 5, 16)),
+    (2500, ("inflow", "wall", "periodic", "periodic"), {0: (1.4, 0.35, 0.0)}, (3, 16)),
+    (900, ("wall", "inflow", "periodic", "periodic"), {1: (1.1, -0.2, 0.0)}, (7, 64, 300)),
+    (80, ("neumann", "neumann", "periodic", "periodic"), None, (96,)),
+])
+def test_d1q3q2_multistep_launch_equals_single_steps(storage, n, bc, inflow, ks):
+    """K steps per launch of D1Q3Q2 with distinct rates equal single steps bit for bit:
+    periodic tiles with a ragged last one, wall and inflow ends across tiles, and
+    domains that fit one tile (any K, the whole run in few launches)."""
+    import torch
+
+    case = _riemann_1d(n, bc, inflow)
+    steps = 300 if n > 100 else 96
+    A = _rest1d_solver(case, storage, 1)
+    A.step(steps)
+    ref = A.planes()
+    for K in ks:
+        B = _rest1d_solver(case, storage, K)
+        assert B.launch_info()["steps_per_launch"] == K
+        B.step(steps)
+        torch.cuda.synchronize()
+        say(f"[mrt 1D multistep] {storage} n={n} {bc[:2]} K={K} launches={len(B.launch_plan(steps))}")
+        assert torch.equal(B.planes(), ref), f"K={K}"
+
+
+def test_d1q3q2_default_launches():
+    """By default D1Q3Q2 takes the 1D launch plan of the hot path: 16 steps per launch,
+    and the whole run in one launch for a domain with non-periodic ends that fits one
+    tile (the Fig. 1 setup: 80 points, 96 steps)."""
+    big = _rest1d_solver(_riemann_1d(5000, ("periodic",) * 4), "f64", 0)
+    assert big.launch_info()["steps_per_launch"] == 16
+    n = 80
+    x = W.cell_centres(n)
+    case = W.Case(1, n, 1, 8.0, 1.8, 96, bc=("neumann", "neumann", "periodic", "periodic"),
+                  h0=np.where(x < 0.5, 2.0, 0.5), qx0=np.zeros(n))
+    S = _rest1d_solver(case, "f64", 0, a=0.15, rates=(1.8, 1.8, 1.8))
+    assert S.launch_plan(96) == [96]
