@@ -290,7 +290,7 @@ __global__ void __launch_bounds__(256) k_step_rest1d(const T *__restrict__ src, 
 // function, so the result equals K single steps bit for bit.  The K - 1 lanes at
 // each strip edge and the first 2 (K - 1) iterations take values from outside the
 // valid range and are not stored.
-template <typename T, int K>
+template <typename T>
 __device__ __forceinline__ void rest2k_load(const T *__restrict__ src, long ps, int nx, int ny,
                                             int r, int xm, int xw, int xp, T (&b)[13])
 {
@@ -335,13 +335,13 @@ __global__ void __launch_bounds__(256) k_step_rest2d_k(const T *__restrict__ src
     const int niter = (y1 - y0) + 2 * H;
     int rl = (((y0 - H) % ny) + ny) % ny;  // level-1 row of the last load, wrapped
     T buf[2][13];
-    rest2k_load<T, K>(src, ps, nx, ny, rl, xm, xw, xp, buf[0]);
+    rest2k_load<T>(src, ps, nx, ny, rl, xm, xw, xp, buf[0]);
     for (int j = 0; j < niter; j += 2) {
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const int orow = y0 - 2 * H + j + u;
             rl = rl == ny - 1 ? 0 : rl + 1;
-            rest2k_load<T, K>(src, ps, nx, ny, rl, xm, xw, xp, buf[1 - u]);
+            rest2k_load<T>(src, ps, nx, ny, rl, xm, xw, xp, buf[1 - u]);
             double v[13];
 #pragma unroll
             for (int pl = 0; pl < 13; ++pl) v[pl] = (double)buf[u][pl];
