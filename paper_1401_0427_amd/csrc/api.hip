@@ -10,6 +10,7 @@
 
 #include "lbm.h"
 #include "internal.h"
+#include "multistep.h"
 
 using namespace lbm;
 

@@ -22,6 +22,7 @@
 // Plane order: rest population first, then the a = 0 order.
 #include "internal.h"
 #include "xk_wave.h"
+#include "multistep.h"
 
 namespace lbm {
 

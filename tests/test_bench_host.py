@@ -151,3 +151,21 @@ def test_batched_counter_summary_is_self_consistent_and_keyed_to_the_sources():
         assert set(t["kernels"]) == set(d["kernels"])
     else:
         assert t is None
+
+
+def test_committed_counter_summaries_match_the_present_sources():
+    """The counter summaries bench.py carries (DRAM traffic and SQ issue of the
+    default-depth and 7-step wave-strip launches, the one-step kernel and the batched
+    kernels) were taken on the kernel sources as they are now; a change to those
+    sources needs the summaries retaken, else the bench line loses them."""
+    prof = os.path.join(ROOT, "profiles")
+    names = {"wave_strip": ["k_step2d_xk_fwd_4096_traffic.json", "k_step2d_xk_fwd_4096_sq.json",
+                            "k_step2d_xk_fwd_4096_k7_traffic.json",
+                            "k_step2d_xk_fwd_4096_k7_sq.json"],
+             "one_step": ["k_step2d_fwd_4096_traffic.json", "k_step2d_fwd_4096_sq.json"]}
+    for kind, files in names.items():
+        for f in files:
+            d = json.load(open(os.path.join(prof, f)))
+            assert d["kernel_source_sha"] == bench._kernel_sha(kind), f
+    d = json.load(open(os.path.join(prof, "k_batch_manifest256_traffic.json")))
+    assert d["kernel_source_sha"] == bench._sources_sha(bench.BATCH_SOURCES)

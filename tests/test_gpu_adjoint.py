@@ -339,3 +339,27 @@ def test_rollout_gradient_with_faces_matches_oracle(dim, faces, K):
         f"grad_h0 rel {e_h:.3e}; grad_s rel {e_s:.3e}")
     assert abs(float(loss) - l_ref) <= 1e-12 * l_ref
     assert e_h <= 1e-10 and e_s <= 1e-10
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("nx,ny", [(300, 70), (40, 37)])
+def test_step_levels_on_periodic_grids_equal_single_steps(storage, nx, ny):
+    """On all-periodic grids each level lbm_step_levels stores equals the single
+    steps' bit for bit, for runs of 1 .. 23 levels, on a grid wider than one 64-lane
+    strip and on a narrower one."""
+    import torch
+
+    case = smooth_random_2d(nx, ny, seed=8)
+    S = gpu_solver(case, storage=storage)
+    S.step(3)
+    ck = S.current()[0].clone()
+    nb = S.nplanes * S.ps
+    for n in (1, 2, 3, 4, 5, 11, 23):
+        levels = S.new_state(n)
+        S.step_levels(ck, n, levels)
+        prev = ck
+        for i in range(n):
+            nxt = S.new_state()
+            S.step_buffers(prev, nxt)
+            assert torch.equal(nxt, levels[i * nb:(i + 1) * nb]), (n, i)
+            prev = nxt
