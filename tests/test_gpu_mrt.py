@@ -236,3 +236,30 @@ def test_d1q3q2_default_launches():
                   h0=np.where(x < 0.5, 2.0, 0.5), qx0=np.zeros(n))
     S = _rest1d_solver(case, "f64", 0, a=0.15, rates=(1.8, 1.8, 1.8))
     assert S.launch_plan(96) == [96]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_rest_multistep_launches_on_degenerate_grids(storage):
+    """Tiny grids where a launch's strips and halo rows wrap the grid several times
+    (D2Q5Q4Q4 5 x 3 and 2 x 2 periodic, K = 2 .. 6) and a two-node D1Q3Q2 domain with
+    wall / Neumann ends (one tile, 40 steps per launch) equal single steps bit for bit."""
+    import torch
+
+    for nx, ny in ((5, 3), (2, 2)):
+        case = smooth_random_2d(nx, ny, seed=13, lam=6.0, s=1.7)
+        A = _rest_solver(case, storage, 1)
+        A.step(17)
+        for K in range(2, 7):
+            B = _rest_solver(case, storage, K)
+            assert B.launch_info()["steps_per_launch"] == K
+            B.step(17)
+            torch.cuda.synchronize()
+            assert torch.equal(B.planes(), A.planes()), (nx, ny, K)
+    case = _riemann_1d(2, ("wall", "neumann", "periodic", "periodic"))
+    A = _rest1d_solver(case, storage, 1)
+    A.step(80)
+    B = _rest1d_solver(case, storage, 40)
+    assert B.launch_plan(80) == [40, 40]
+    B.step(80)
+    torch.cuda.synchronize()
+    assert torch.equal(B.planes(), A.planes())
